@@ -1,0 +1,137 @@
+/*
+ * amg.h -- C ABI of libamg.so: unsmoothed-aggregation algebraic multigrid on one
+ * AMD MI355X (gfx950), after Brannick, Chen, Hu, Zikatanov, "Parallel Unsmoothed
+ * Aggregation Algebraic Multigrid Algorithms on GPUs".
+ *
+ * Problem (Sec. 2, eq. (2.1)): solve A u = f for a symmetric positive definite
+ * weighted graph Laplacian A given in CSR.
+ *
+ * Conventions for every entry point:
+ *   - Pointers to matrices and vectors are DEVICE pointers (for example
+ *     torch.Tensor.data_ptr() of a CUDA/HIP tensor) unless the name ends in
+ *     _host.  Indices are 0-based int32; values are IEEE binary64.
+ *   - Calls are ordered on the stream given in amg_options.stream (NULL: the
+ *     library creates its own blocking stream, which is ordered after work on the
+ *     legacy default stream).  Calls that return data or status to the host block
+ *     until that data is ready.
+ *   - No C++ exception crosses this boundary; failures are reported as amg_status.
+ *   - A hierarchy must not be used by two host threads at once.
+ */
+#ifndef UA_AMG_H
+#define UA_AMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMG_OK = 0,
+    AMG_ERR_INVALID_ARGUMENT = 1, /* NULL pointer, bad option, non-finite b          */
+    AMG_ERR_INVALID_MATRIX = 2,   /* CSR malformed, diagonal missing or <= 0        */
+    AMG_ERR_OUT_OF_MEMORY = 3,    /* device allocation failed or mem_budget exceeded */
+    AMG_ERR_DEVICE = 4,           /* a HIP runtime call failed                       */
+    AMG_ERR_NOT_CONVERGED = 5,    /* max_iters reached; info holds the last residual */
+    AMG_ERR_BREAKDOWN = 6,        /* a Krylov step met p^T A p <= 0: A is not SPD     */
+    AMG_ERR_UNSUPPORTED = 7       /* option value outside what is implemented         */
+} amg_status;
+
+typedef enum {
+    AMG_PREC_FP64 = 0,       /* every level and the K-cycle in binary64                 */
+    AMG_PREC_FP32_INNER = 1  /* K-cycle in binary32 inside the binary64 outer iteration */
+} amg_precision;
+
+/* Opaque hierarchy: owns copies of every level and all its device memory. */
+typedef struct amg_hierarchy amg_hierarchy;
+
+/* Square n x n matrix in CSR (device pointers).  Columns strictly ascending in
+ * every row, diagonal entry present and > 0 (Sec. 2: positive weights). */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t *row_ptr; /* n + 1 */
+    const int32_t *col_idx; /* nnz   */
+    const double *values;   /* nnz   */
+} amg_csr;
+
+typedef struct {
+    int32_t coarsest_size;      /* n_0 of Alg. 1: coarsen while n_l > n_0 (default 64)       */
+    int32_t max_levels;         /* L of Alg. 1 (default 40, at most 64)                      */
+    double stall_ratio;         /* stop when an aggregation keeps > ratio*n_l (default 0.9)  */
+    int32_t max_aggregate;      /* size limit t of Sec. 3.3 / 5.1; 0 = unlimited (default)   */
+    uint64_t seed;              /* seed of rand() in eq. (3.2)                               */
+    int32_t kcycle_inner;       /* inner flexible-CG steps per coarse visit, 1 or 2 (def. 2) */
+    int32_t precision;          /* amg_precision (default AMG_PREC_FP64)                     */
+    int32_t max_iters;          /* outer iterations (default 200)                            */
+    int32_t max_coarsest;       /* largest coarsest level factored densely (default 4096)   */
+    size_t mem_budget;          /* device bytes the hierarchy may hold; 0 = no limit        */
+    void *stream;               /* hipStream_t, or NULL                                      */
+} amg_options;
+
+typedef struct {
+    int32_t iterations;   /* outer flexible-CG iterations                     */
+    double rel_residual;  /* true ||b - A x||_2 / ||b||_2 at return (binary64) */
+    double setup_ms;      /* device time of amg_setup for this hierarchy       */
+    double solve_ms;      /* device time of this amg_solve                     */
+} amg_solve_info;
+
+/* Fills *opt with the defaults listed above. */
+void amg_default_options(amg_options *opt);
+
+/* Setup phase of Alg. 1: builds the level hierarchy of A.  Per level: priorities
+ * of eq. (3.2), the parallel aggregation of Alg. 2 (Sec. 3.1-3.2), aggregates
+ * numbered by increasing coarse-vertex index (Sec. 5.1), the coarse matrix of
+ * eq. (2.4) and the l1-Jacobi diagonal (Sec. 4.1); the coarsest level is factored
+ * densely.  A is copied: the caller may free its arrays on return.  opt may be
+ * NULL (defaults).  On AMG_OK *out receives a hierarchy to release with amg_free;
+ * on any error *out is set to NULL and nothing stays allocated. */
+amg_status amg_setup(const amg_csr *A, const amg_options *opt, amg_hierarchy **out);
+
+/* Solve phase: outer nonlinear (flexible) preconditioned CG preconditioned by
+ * the K-cycle of Sec. 4.3-4.4, stopping when the true relative residual
+ * ||b - A x|| / ||b|| <= tol.  b and x are device vectors of length n; x holds the
+ * initial guess on entry and the solution on return (written on AMG_OK and
+ * AMG_ERR_NOT_CONVERGED).  info (may be NULL) is filled on those two statuses. */
+amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, amg_solve_info *info);
+
+/* Releases every resource of h.  NULL is accepted. */
+void amg_free(amg_hierarchy *h);
+
+/* Number of levels (finest = 0, coarsest = levels - 1). */
+amg_status amg_num_levels(const amg_hierarchy *h, int32_t *levels);
+
+/* Size of level `level`: unknowns, stored entries, and the number of passes of
+ * Alg. 2 that aggregated it (0 on the coarsest level).  NULL outputs are skipped. */
+amg_status amg_level_sizes(const amg_hierarchy *h, int32_t level, int32_t *n, int32_t *nnz, int32_t *passes);
+
+/* Copies level `level` to host arrays in the natural (aggregation) numbering:
+ * agg_host[n] = coarse index of each unknown (column of P, eq. (2.2); -1 on the
+ * coarsest level), row_ptr_host[n+1], col_host[nnz], val_host[nnz].  Any output
+ * may be NULL. */
+amg_status amg_export_level(const amg_hierarchy *h, int32_t level, int32_t *agg_host, int32_t *row_ptr_host,
+                            int32_t *col_host, double *val_host);
+
+/* y = A_level x for device vectors in the natural numbering of that level (the
+ * sparse product of Sec. 4.4). */
+amg_status amg_spmv(amg_hierarchy *h, int32_t level, const double *x, double *y);
+
+/* z = B r: one application of the K-cycle preconditioner on the finest level
+ * (Sec. 4.3), device vectors of length n in the natural numbering. */
+amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z);
+
+/* Average device time in microseconds of the finest-level post-smoothing kernel
+ * (the fused prolongation + l1-Jacobi sweep, the solve's dominant kernel),
+ * measured with events over `reps` back-to-back launches on the hierarchy's
+ * stream; *bytes receives its algorithmic DRAM traffic per launch. */
+amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, double *bytes);
+
+/* Human-readable name of a status code (static storage). */
+const char *amg_status_string(amg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UA_AMG_H */

@@ -1,0 +1,189 @@
+"""ctypes binding of libamg.so (include/amg.h): argument marshalling only.
+
+Every function of the C ABI is exposed under its own name; ``Hierarchy`` is a
+thin owner of an ``amg_hierarchy*`` that takes torch device tensors (or raw
+device pointers) and forwards them.  There is no fallback: if the HIP library is
+missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamg.so")
+
+AMG_OK = 0
+AMG_ERR_INVALID_ARGUMENT = 1
+AMG_ERR_INVALID_MATRIX = 2
+AMG_ERR_OUT_OF_MEMORY = 3
+AMG_ERR_DEVICE = 4
+AMG_ERR_NOT_CONVERGED = 5
+AMG_ERR_BREAKDOWN = 6
+AMG_ERR_UNSUPPORTED = 7
+AMG_PREC_FP64 = 0
+AMG_PREC_FP32_INNER = 1
+
+
+class amg_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("values", ctypes.c_void_p)]
+
+
+class amg_options(ctypes.Structure):
+    _fields_ = [("coarsest_size", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("stall_ratio", ctypes.c_double),
+                ("max_aggregate", ctypes.c_int32), ("seed", ctypes.c_uint64), ("kcycle_inner", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("max_coarsest", ctypes.c_int32),
+                ("mem_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
+
+
+class amg_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("setup_ms", ctypes.c_double),
+                ("solve_ms", ctypes.c_double)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1302_2547_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_sig = {
+    "amg_default_options": (None, [ctypes.POINTER(amg_options)]),
+    "amg_setup": (ctypes.c_int, [ctypes.POINTER(amg_csr), ctypes.POINTER(amg_options), ctypes.POINTER(_P)]),
+    "amg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(amg_solve_info)]),
+    "amg_free": (None, [_P]),
+    "amg_num_levels": (ctypes.c_int, [_P, _I32P]),
+    "amg_level_sizes": (ctypes.c_int, [_P, ctypes.c_int32, _I32P, _I32P, _I32P]),
+    "amg_export_level": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
+    "amg_spmv": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "amg_kcycle": (ctypes.c_int, [_P, _P, _P]),
+    "amg_time_smoother": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]),
+    "amg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+
+class AmgError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {amg_status_string(status).decode()} ({status})")
+
+
+def _ptr(t) -> int:
+    """Raw device pointer of a torch tensor (must be on the GPU) or an int."""
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError("libamg takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libamg takes contiguous tensors")
+    return t.data_ptr()
+
+
+def default_options(**kw) -> amg_options:
+    o = amg_options()
+    amg_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class LevelExport:
+    n: int
+    nnz: int
+    passes: int
+    agg: np.ndarray
+    row_ptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+
+class Hierarchy:
+    """Owns one amg_hierarchy*; tensors are int32/float64 CUDA tensors."""
+
+    def __init__(self, row_ptr, col, val, n: int | None = None, **options):
+        import torch
+        for t, dt in ((row_ptr, torch.int32), (col, torch.int32), (val, torch.float64)):
+            if t.dtype != dt:
+                raise TypeError(f"expected {dt}, got {t.dtype}")
+        n = row_ptr.numel() - 1 if n is None else n
+        self._csr = amg_csr(n, col.numel(), _ptr(row_ptr), _ptr(col), _ptr(val))
+        self.options = default_options(**options)
+        self._h = _P()
+        st = amg_setup(ctypes.byref(self._csr), ctypes.byref(self.options), ctypes.byref(self._h))
+        if st != AMG_OK:
+            raise AmgError(st, "amg_setup")
+        self.n = n
+
+    @property
+    def num_levels(self) -> int:
+        v = ctypes.c_int32()
+        self._check(amg_num_levels(self._h, ctypes.byref(v)), "amg_num_levels")
+        return v.value
+
+    def level_sizes(self, level: int):
+        n, nnz, passes = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(amg_level_sizes(self._h, level, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(passes)),
+                    "amg_level_sizes")
+        return n.value, nnz.value, passes.value
+
+    def export_level(self, level: int) -> LevelExport:
+        n, nnz, passes = self.level_sizes(level)
+        agg = np.empty(n, np.int32)
+        rp = np.empty(n + 1, np.int32)
+        ci = np.empty(nnz, np.int32)
+        va = np.empty(nnz, np.float64)
+        self._check(amg_export_level(self._h, level, agg.ctypes.data, rp.ctypes.data, ci.ctypes.data, va.ctypes.data),
+                    "amg_export_level")
+        return LevelExport(n, nnz, passes, agg, rp, ci, va)
+
+    def solve(self, b, x, tol: float = 1e-8, raise_on_error: bool = True):
+        info = amg_solve_info()
+        st = amg_solve(self._h, _ptr(b), _ptr(x), tol, ctypes.byref(info))
+        if raise_on_error and st not in (AMG_OK,):
+            raise AmgError(st, "amg_solve")
+        return st, info
+
+    def spmv(self, level: int, x, y):
+        self._check(amg_spmv(self._h, level, _ptr(x), _ptr(y)), "amg_spmv")
+
+    def kcycle(self, r, z):
+        self._check(amg_kcycle(self._h, _ptr(r), _ptr(z)), "amg_kcycle")
+
+    def time_smoother(self, reps: int = 20):
+        us, by = ctypes.c_double(), ctypes.c_double()
+        self._check(amg_time_smoother(self._h, reps, ctypes.byref(us), ctypes.byref(by)), "amg_time_smoother")
+        return us.value, by.value
+
+    def _check(self, st, where):
+        if st != AMG_OK:
+            raise AmgError(st, where)
+
+    def close(self):
+        if self._h:
+            amg_free(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,118 @@
+// amg_internal.h -- internal declarations of libamg (gfx950 only).
+//
+// Kernels live in setup_kernels.hip, solve_kernels.hip and scan.hip; each file
+// exports host-side launch functions declared here.  The host engine
+// (engine.hip) owns all orchestration.  Every launch takes the stream it runs on.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+
+namespace amg {
+
+constexpr int kWave = 64;    // CDNA wavefront width
+constexpr int kBlock = 256;  // threads per block for every kernel below
+constexpr int kMaxDotBlocks = 2048;
+constexpr int kMaxDots = 5;
+
+struct Error : std::runtime_error {
+    int status;
+    Error(int s, const char *what) : std::runtime_error(what), status(s) {}
+};
+
+void hip_check(hipError_t e, const char *what);
+#define AMG_HIP(call) ::amg::hip_check((call), #call)
+
+// Device reduction workspace shared by the kernels of one solve context: per-block
+// partial sums, an arrival counter for the last-block pattern, and an error flag.
+struct DotWork {
+    double *partials;   // kMaxDots * kMaxDotBlocks
+    unsigned *counter;  // 1 (kept at 0 between launches)
+    int *flag;          // 1: bit 0 = Krylov breakdown
+};
+
+// ---------------------------------------------------------------- scan.hip
+// out[i] = sum_{k<i} in[i] (in may alias out); *total_dev = sum of all (device).
+// tmp must hold scan_tmp_ints(n) ints.
+size_t scan_tmp_ints(int64_t n);
+void scan_exclusive(const int *in, int *out, int64_t n, int *total_dev, int *tmp, hipStream_t s);
+
+// ---------------------------------------------------------------- setup_kernels.hip
+void launch_validate_csr(int n, int nnz, const int *rp, const int *ci, const double *va, int *err, hipStream_t s);
+void launch_l1_inverse_diagonal(int n, const int *rp, const int *ci, const double *va, double *minv, hipStream_t s);
+void launch_priorities(int n, const int *rp, uint32_t s_l, uint64_t *key, int *owner, hipStream_t s);
+void launch_mis_pass(int n, const int *rp, const int *ci, uint64_t *key, uint64_t *m1, int *owner, int cap, int G,
+                     unsigned *done_counter, hipStream_t s);
+void launch_centre_flags(int n, const int *owner, int *flag, hipStream_t s);
+void launch_assign_aggregates(int n, const int *owner, const int *cid, int *agg, int *centre_of, hipStream_t s);
+void launch_member_counts(int nc, const int *rp, const int *ci, const int *owner, const int *centre_of, int *size,
+                          int *pairs, hipStream_t s);
+void launch_member_fill(int nc, const int *rp, const int *ci, const int *owner, const int *centre_of,
+                        const int *aptr, int *members, hipStream_t s);
+void launch_coarse_rows(int nc, const int *rp, const int *ci, const double *va, const int *agg, const int *aptr,
+                        const int *members, const int *tptr, int *tcol, double *tval, int *cnt, int *big_rows,
+                        unsigned *big_count, hipStream_t s);
+int coarse_wave_capacity();
+void launch_coarse_big_rows(int nbig, const int *big_rows, const int64_t *scratch_off, uint64_t *skey,
+                            const int *rp, const int *ci, const double *va, const int *agg, const int *aptr,
+                            const int *members, const int *tptr, int *tcol, double *tval, int *cnt,
+                            hipStream_t s);
+void launch_coarse_compact(int nc, const int *tptr, const int *tcol, const double *tval, const int *crp, int *cci,
+                           double *cva, double *cminv, hipStream_t s);
+void launch_dense_from_csr(int n, const int *rp, const int *ci, const double *va, double *dense, hipStream_t s);
+void launch_cholesky_inverse(int n, double *a, double *inv, int *err, hipStream_t s);
+// solve-layout permutation
+void launch_identity(int n, int *v, hipStream_t s);
+void launch_sizes_in_position_order(int nc, const int *aptr_nat, const int *perm_c, int *size_pos, hipStream_t s);
+void launch_positions_from_segments(int nc, const int *aptr_nat, const int *members_nat, const int *pos_c,
+                                    const int *seg_ptr, int *pos_f, int *perm_f, hipStream_t s);
+void launch_permuted_row_lengths(int n, const int *rp_nat, const int *perm, int *len, hipStream_t s);
+void launch_permute_rows(int n, const int *rp_nat, const int *ci_nat, const double *va_nat, const double *minv_nat,
+                         const int *perm, const int *pos, const int *rp, int *ci, double *va, double *minv,
+                         hipStream_t s);
+void launch_agg_positions(int n, const int *perm_f, const int *agg_nat, const int *pos_c, int *agg_pos,
+                          hipStream_t s);
+void launch_gather_int(int n, const int *src, const int *idx, int *dst, hipStream_t s);
+
+// ---------------------------------------------------------------- solve_kernels.hip
+int lanes_for(double avg_row_len);
+// y = A x; dots: d[0] = (x, y), d[1] = (x, w)   (w may be NULL -> d[1] = 0)
+void launch_spmv_dot2(int n, const int *rp, const int *ci, const double *va, const double *x, double *y,
+                      const double *w, int G, DotWork dw, double *out, hipStream_t s);
+// dots only: d[0] = (x, A x), d[1] = (x, w1), d[2] = (x, w2)
+void launch_spmv_dot3(int n, const int *rp, const int *ci, const double *va, const double *x, const double *w1,
+                      const double *w2, int G, DotWork dw, double *out, hipStream_t s);
+// plain y = A x
+void launch_spmv(int n, const int *rp, const int *ci, const double *va, const double *x, double *y, int G,
+                 hipStream_t s);
+// rc[Q] = sum_{q in seg Q} r_q - sum_{e in super-row Q} a_e minv[col_e] r[col_e]
+void launch_pre_restrict(int nc, const int *seg_ptr, const int *srp, const int *ci, const double *va,
+                         const double *minv, const double *r, double *rc, int G, hipStream_t s);
+// rt = rc - (alpha1/rho1) v1, scalars d[0] = rho1, d[1] = alpha1
+void launch_inner_residual(int n, const double *rc, const double *v1, const double *d, double *rt, int *flag,
+                           hipStream_t s);
+// post-smoothing with the coarse correction folded in.  mode 0: e = edirect;
+// mode 1: e = (alpha1/rho1) c1; mode 2: e = a1 c1 + a2 c2 from the 5 dots of d.
+// Optionally dots (out, wdot) into dw/out_dot.
+void launch_post_smooth(int n, const int *rp, const int *ci, const double *va, const double *minv, const double *r,
+                        const int *agg_pos, int mode, const double *edirect, const double *c1, const double *c2,
+                        const double *d, double *xout, const double *wdot, DotWork dw, double *out_dot, int G,
+                        hipStream_t s);
+void launch_dense_gemv(int n, const double *a, const double *x, double *y, hipStream_t s);
+// outer flexible CG
+// r = b - A x; out[0] = (b, b), out[1] = (r, r)
+void launch_residual(int n, const int *rp, const int *ci, const double *va, const double *b, const double *x,
+                     double *r, int G, DotWork dw, double *out, hipStream_t s);
+// alpha = pr/pq; x += alpha p; r -= alpha q; out = (r, r)
+void launch_fcg_update(int n, const double *pq_pr, double *x, double *r, const double *p, const double *q,
+                       DotWork dw, double *out, hipStream_t s);
+// beta = -zq/pq; p = z + beta p
+void launch_fcg_direction(int n, const double *pq, const double *zq, const double *z, double *p, int *flag,
+                          hipStream_t s);
+void launch_dot(int n, const double *a, const double *b, DotWork dw, double *out, hipStream_t s);  // out = (a, b)
+void launch_gather(int n, const double *src, const int *idx, double *dst, hipStream_t s);   // dst[i] = src[idx[i]]
+void launch_scatter(int n, const double *src, const int *idx, double *dst, hipStream_t s);  // dst[idx[i]] = src[i]
+
+}  // namespace amg

@@ -1,0 +1,661 @@
+// engine.hip -- host engine of libamg: hierarchy construction (Alg. 1 setup),
+// K-cycle and outer flexible CG orchestration (Sec. 4), and the C ABI of amg.h.
+//
+// Device memory is owned by one pool per hierarchy; a failed setup releases
+// everything it allocated.  All work is ordered on one HIP stream; the host
+// waits on it only where it needs a value: the per-pass count of processed
+// vertices, level sizes, and the outer residual norm.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "amg.h"
+#include "amg_internal.h"
+
+namespace amg {
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) throw Error(AMG_ERR_OUT_OF_MEMORY, what);
+    throw Error(AMG_ERR_DEVICE, what);
+}
+
+namespace {
+
+// SplitMix64 (Steele, Lea, Flood 2014): k-th output of the stream seeded with seed.
+uint64_t splitmix64(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (k + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Device allocations of one hierarchy, with an optional byte budget.
+struct Pool {
+    size_t used = 0, peak = 0, budget = 0;
+    std::vector<std::pair<void *, size_t>> blocks;
+
+    template <class T>
+    T *alloc(size_t count)
+    {
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (budget && used + bytes > budget) throw Error(AMG_ERR_OUT_OF_MEMORY, "mem_budget exceeded");
+        void *p = nullptr;
+        const hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(AMG_ERR_OUT_OF_MEMORY, "hipMalloc");
+        }
+        blocks.emplace_back(p, bytes);
+        used += bytes;
+        peak = std::max(peak, used);
+        return static_cast<T *>(p);
+    }
+    void release(void *p)
+    {
+        if (!p) return;
+        for (size_t k = 0; k < blocks.size(); k++) {
+            if (blocks[k].first == p) {
+                (void)hipFree(p);
+                used -= blocks[k].second;
+                blocks.erase(blocks.begin() + (long)k);
+                return;
+            }
+        }
+    }
+    void release_all()
+    {
+        for (auto &b : blocks) (void)hipFree(b.first);
+        blocks.clear();
+        used = 0;
+    }
+};
+
+struct Level {
+    int n = 0, nnz = 0, passes = 0;
+    // natural numbering (setup result)
+    int *rp_nat = nullptr, *ci_nat = nullptr;
+    double *va_nat = nullptr, *minv_nat = nullptr;
+    int *agg_nat = nullptr, *aptr_nat = nullptr, *members_nat = nullptr;  // all but the coarsest level
+    // solve layout (nested aggregate order)
+    int *rp = nullptr, *ci = nullptr;
+    double *va = nullptr, *minv = nullptr;
+    int *perm = nullptr, *pos = nullptr;                        // position -> natural, natural -> position
+    int *agg_pos = nullptr, *seg_ptr = nullptr, *srp = nullptr;  // all but the coarsest level
+    int G = 2, Gs = 2;
+    // work vectors when this level is a coarse level of a K-cycle visit
+    double *rc = nullptr, *rt = nullptr, *c1 = nullptr, *c2 = nullptr, *v1 = nullptr;
+    double *dots = nullptr;  // rho1, alpha1, beta, gamma, alpha2
+};
+
+}  // namespace
+}  // namespace amg
+
+using amg::Error;
+using amg::Level;
+
+struct amg_hierarchy {
+    amg_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    amg::Pool pool;
+    std::vector<Level> lev;
+    double *ainv = nullptr;  // dense inverse of the coarsest matrix
+    // outer iteration vectors (finest level, solve layout)
+    double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    double *outer = nullptr;  // 8 device scalars: pq, pr, rr, zq, bb, rr0
+    amg::DotWork dw{};
+    double *host = nullptr;  // pinned: readbacks
+    int *host_i = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double setup_ms = 0.0;
+
+    ~amg_hierarchy()
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        pool.release_all();
+        if (host) (void)hipHostFree(host);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+
+    int levels() const { return (int)lev.size(); }
+    void sync() { AMG_HIP(hipStreamSynchronize(stream)); }
+
+    template <class T>
+    void to_host(T *dst, const T *src, size_t count)
+    {
+        AMG_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, stream));
+        sync();
+    }
+    int read_int(const int *dev)
+    {
+        AMG_HIP(hipMemcpyAsync(host_i, dev, sizeof(int), hipMemcpyDeviceToHost, stream));
+        sync();
+        return host_i[0];
+    }
+    void scan(const int *in, int *out, int64_t count, int *total_dev, int *tmp)
+    {
+        amg::scan_exclusive(in, out, count, total_dev, tmp, stream);
+    }
+
+    void build(const amg_csr &A);
+    void finalize_layout();
+    void kcycle(int k, const double *r, double *x, const double *wdot, double *out_dot);
+    amg_status solve(const double *b_user, double *x_user, double tol, amg_solve_info *info);
+};
+
+void amg_hierarchy::build(const amg_csr &A)
+{
+    using namespace amg;
+    AMG_HIP(hipEventCreate(&ev0));
+    AMG_HIP(hipEventCreate(&ev1));
+    AMG_HIP(hipHostMalloc((void **)&host, 64 * sizeof(double), hipHostMallocDefault));
+    host_i = reinterpret_cast<int *>(host + 32);
+    AMG_HIP(hipEventRecord(ev0, stream));
+
+    const int n0 = A.n, nnz0 = A.nnz;
+    lev.reserve(opt.max_levels);
+    lev.emplace_back();
+    {
+        Level &L0 = lev[0];
+        L0.n = n0;
+        L0.nnz = nnz0;
+        L0.rp_nat = pool.alloc<int>(n0 + 1);
+        L0.ci_nat = pool.alloc<int>(nnz0);
+        L0.va_nat = pool.alloc<double>(nnz0);
+        L0.minv_nat = pool.alloc<double>(n0);
+        AMG_HIP(hipMemcpyAsync(L0.rp_nat, A.row_ptr, sizeof(int) * (n0 + 1), hipMemcpyDeviceToDevice, stream));
+        AMG_HIP(hipMemcpyAsync(L0.ci_nat, A.col_idx, sizeof(int) * (size_t)nnz0, hipMemcpyDeviceToDevice, stream));
+        AMG_HIP(hipMemcpyAsync(L0.va_nat, A.values, sizeof(double) * (size_t)nnz0, hipMemcpyDeviceToDevice, stream));
+    }
+    // setup scratch, sized by the finest level and released at the end of setup
+    int *ibuf = pool.alloc<int>(16);  // 0 err, 1 done, 2 big_count, 3 nc, 4 total, 5 nnz_c
+    uint64_t *key = pool.alloc<uint64_t>(n0);
+    uint64_t *m1 = pool.alloc<uint64_t>(n0);
+    int *owner = pool.alloc<int>(n0);
+    int *cid = pool.alloc<int>(n0 + 1);
+    int *centre_of = pool.alloc<int>(n0);
+    int *size = pool.alloc<int>(n0);
+    int *pairs = pool.alloc<int>(n0);
+    int *cnt = pool.alloc<int>(n0);
+    int *tptr = pool.alloc<int>(n0 + 1);
+    int *tcol = pool.alloc<int>(nnz0);
+    double *tval = pool.alloc<double>(nnz0);
+    int *big_rows = pool.alloc<int>(n0);
+    int *scan_tmp = pool.alloc<int>(scan_tmp_ints((int64_t)nnz0 + 1));
+    unsigned *done = reinterpret_cast<unsigned *>(ibuf + 1);
+    unsigned *big_count = reinterpret_cast<unsigned *>(ibuf + 2);
+
+    AMG_HIP(hipMemsetAsync(ibuf, 0, 16 * sizeof(int), stream));
+    launch_validate_csr(n0, nnz0, lev[0].rp_nat, lev[0].ci_nat, lev[0].va_nat, ibuf, stream);
+    if (read_int(ibuf) != 0) throw Error(AMG_ERR_INVALID_MATRIX, "invalid CSR");
+    launch_l1_inverse_diagonal(n0, lev[0].rp_nat, lev[0].ci_nat, lev[0].va_nat, lev[0].minv_nat, stream);
+
+    // Alg. 1: coarsen while n_l > n_0 and fewer than L levels exist
+    int l = 0;
+    while (lev[l].n > opt.coarsest_size && l + 1 < opt.max_levels) {
+        const int n = lev[l].n, nnz = lev[l].nnz;
+        const int G = lanes_for((double)nnz / n);
+        const uint32_t s_l = (uint32_t)splitmix64(opt.seed, (uint64_t)l);
+        launch_priorities(n, lev[l].rp_nat, s_l, key, owner, stream);
+        AMG_HIP(hipMemsetAsync(done, 0, sizeof(unsigned), stream));
+        int passes = 0;
+        unsigned processed = 0;
+        while (processed < (unsigned)n) {
+            launch_mis_pass(n, lev[l].rp_nat, lev[l].ci_nat, key, m1, owner, opt.max_aggregate, G, done, stream);
+            passes++;
+            const unsigned now = (unsigned)read_int(reinterpret_cast<int *>(done));
+            if (now <= processed || now > (unsigned)n) throw Error(AMG_ERR_DEVICE, "aggregation made no progress");
+            processed = now;
+        }
+        // Sec. 5.1: aggregates numbered by increasing coarse-vertex index
+        launch_centre_flags(n, owner, cid, stream);
+        scan(cid, cid, n, ibuf + 3, scan_tmp);
+        const int nc = read_int(ibuf + 3);
+        if ((double)nc > opt.stall_ratio * (double)n) break;  // coarsening stalled: level l is the coarsest
+        Level &F = lev[l];
+        F.passes = passes;
+        F.agg_nat = pool.alloc<int>(n);
+        launch_assign_aggregates(n, owner, cid, F.agg_nat, centre_of, stream);
+        launch_member_counts(nc, F.rp_nat, F.ci_nat, owner, centre_of, size, pairs, stream);
+        F.aptr_nat = pool.alloc<int>(nc + 1);
+        scan(size, F.aptr_nat, nc, F.aptr_nat + nc, scan_tmp);
+        F.members_nat = pool.alloc<int>(n);
+        launch_member_fill(nc, F.rp_nat, F.ci_nat, owner, centre_of, F.aptr_nat, F.members_nat, stream);
+        scan(pairs, tptr, nc, tptr + nc, scan_tmp);
+        AMG_HIP(hipMemsetAsync(big_count, 0, sizeof(unsigned), stream));
+        launch_coarse_rows(nc, F.rp_nat, F.ci_nat, F.va_nat, F.agg_nat, F.aptr_nat, F.members_nat, tptr, tcol, tval,
+                           cnt, big_rows, big_count, stream);
+        const int nbig = read_int(reinterpret_cast<int *>(big_count));
+        if (nbig > 0) {
+            std::vector<int> rows(nbig), tp(nc + 1);
+            to_host(rows.data(), big_rows, nbig);
+            to_host(tp.data(), tptr, nc + 1);
+            std::vector<int64_t> off(nbig + 1, 0);
+            for (int k = 0; k < nbig; k++) {
+                int64_t pc = tp[rows[k] + 1] - tp[rows[k]], P = 1;
+                while (P < pc) P <<= 1;
+                off[k + 1] = off[k] + P;
+            }
+            int64_t *off_dev = pool.alloc<int64_t>(nbig + 1);
+            int *rows_dev = pool.alloc<int>(nbig);
+            uint64_t *scratch = pool.alloc<uint64_t>(2 * off[nbig]);
+            AMG_HIP(hipMemcpyAsync(off_dev, off.data(), sizeof(int64_t) * (nbig + 1), hipMemcpyHostToDevice, stream));
+            AMG_HIP(hipMemcpyAsync(rows_dev, rows.data(), sizeof(int) * nbig, hipMemcpyHostToDevice, stream));
+            launch_coarse_big_rows(nbig, rows_dev, off_dev, scratch, F.rp_nat, F.ci_nat, F.va_nat, F.agg_nat,
+                                   F.aptr_nat, F.members_nat, tptr, tcol, tval, cnt, stream);
+            sync();
+            pool.release(scratch);
+            pool.release(rows_dev);
+            pool.release(off_dev);
+        }
+        Level C;
+        C.n = nc;
+        C.rp_nat = pool.alloc<int>(nc + 1);
+        scan(cnt, C.rp_nat, nc, C.rp_nat + nc, scan_tmp);
+        C.nnz = read_int(C.rp_nat + nc);
+        C.ci_nat = pool.alloc<int>(C.nnz);
+        C.va_nat = pool.alloc<double>(C.nnz);
+        C.minv_nat = pool.alloc<double>(nc);
+        launch_coarse_compact(nc, tptr, tcol, tval, C.rp_nat, C.ci_nat, C.va_nat, C.minv_nat, stream);
+        lev.push_back(C);
+        l++;
+    }
+    sync();
+    for (void *ptr : std::initializer_list<void *>{key, m1, owner, cid, centre_of, size, pairs, cnt, tptr, tcol, tval,
+                                                  big_rows, scan_tmp})
+        pool.release(ptr);
+
+    // coarsest level: dense Cholesky factorisation and explicit inverse
+    Level &Lc = lev.back();
+    if (Lc.n > opt.max_coarsest) throw Error(AMG_ERR_UNSUPPORTED, "coarsest level larger than max_coarsest");
+    {
+        const size_t nn = (size_t)Lc.n * Lc.n;
+        double *dense = pool.alloc<double>(nn);
+        ainv = pool.alloc<double>(nn);
+        AMG_HIP(hipMemsetAsync(dense, 0, nn * sizeof(double), stream));
+        AMG_HIP(hipMemsetAsync(ibuf, 0, sizeof(int), stream));
+        launch_dense_from_csr(Lc.n, Lc.rp_nat, Lc.ci_nat, Lc.va_nat, dense, stream);
+        launch_cholesky_inverse(Lc.n, dense, ainv, ibuf, stream);
+        const int err = read_int(ibuf);
+        pool.release(dense);
+        if (err) throw Error(AMG_ERR_BREAKDOWN, "coarsest matrix is not positive definite");
+    }
+    finalize_layout();
+    pool.release(ibuf);
+    AMG_HIP(hipEventRecord(ev1, stream));
+    sync();
+    float ms = 0.f;
+    AMG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    setup_ms = ms;
+}
+
+// Nested aggregate order, built from the coarsest level down (see setup_kernels.hip).
+void amg_hierarchy::finalize_layout()
+{
+    using namespace amg;
+    const int L = levels() - 1;
+    int *tmp = pool.alloc<int>(lev[0].n + 1);
+    int *scan_tmp = pool.alloc<int>(scan_tmp_ints((int64_t)lev[0].nnz + 1));
+    lev[L].perm = pool.alloc<int>(lev[L].n);
+    lev[L].pos = pool.alloc<int>(lev[L].n);
+    launch_identity(lev[L].n, lev[L].perm, stream);
+    launch_identity(lev[L].n, lev[L].pos, stream);
+    for (int l = L - 1; l >= 0; l--) {
+        Level &F = lev[l], &C = lev[l + 1];
+        launch_sizes_in_position_order(C.n, F.aptr_nat, C.perm, tmp, stream);
+        F.seg_ptr = pool.alloc<int>(C.n + 1);
+        scan(tmp, F.seg_ptr, C.n, F.seg_ptr + C.n, scan_tmp);
+        F.pos = pool.alloc<int>(F.n);
+        F.perm = pool.alloc<int>(F.n);
+        launch_positions_from_segments(C.n, F.aptr_nat, F.members_nat, C.pos, F.seg_ptr, F.pos, F.perm, stream);
+        F.agg_pos = pool.alloc<int>(F.n);
+        launch_agg_positions(F.n, F.perm, F.agg_nat, C.pos, F.agg_pos, stream);
+    }
+    for (int l = 0; l <= L; l++) {
+        Level &F = lev[l];
+        launch_permuted_row_lengths(F.n, F.rp_nat, F.perm, tmp, stream);
+        F.rp = pool.alloc<int>(F.n + 1);
+        scan(tmp, F.rp, F.n, F.rp + F.n, scan_tmp);
+        F.ci = pool.alloc<int>(F.nnz);
+        F.va = pool.alloc<double>(F.nnz);
+        F.minv = pool.alloc<double>(F.n);
+        launch_permute_rows(F.n, F.rp_nat, F.ci_nat, F.va_nat, F.minv_nat, F.perm, F.pos, F.rp, F.ci, F.va, F.minv,
+                            stream);
+        F.G = lanes_for((double)F.nnz / F.n);
+        if (l < L) {
+            const int nc = lev[l + 1].n;
+            F.srp = pool.alloc<int>(nc + 1);
+            launch_gather_int(nc + 1, F.rp, F.seg_ptr, F.srp, stream);
+            F.Gs = lanes_for((double)F.nnz / nc);
+        }
+        if (l >= 1) {
+            F.rc = pool.alloc<double>(F.n);
+            F.rt = pool.alloc<double>(F.n);
+            F.c1 = pool.alloc<double>(F.n);
+            F.c2 = pool.alloc<double>(F.n);
+            F.v1 = pool.alloc<double>(F.n);
+            F.dots = pool.alloc<double>(8);
+        }
+    }
+    const int n = lev[0].n;
+    b = pool.alloc<double>(n);
+    x = pool.alloc<double>(n);
+    r = pool.alloc<double>(n);
+    z = pool.alloc<double>(n);
+    p = pool.alloc<double>(n);
+    q = pool.alloc<double>(n);
+    outer = pool.alloc<double>(8);
+    dw.partials = pool.alloc<double>((size_t)kMaxDots * kMaxDotBlocks);
+    dw.counter = pool.alloc<unsigned>(1);
+    dw.flag = pool.alloc<int>(1);
+    AMG_HIP(hipMemsetAsync(dw.counter, 0, sizeof(unsigned), stream));
+    AMG_HIP(hipMemsetAsync(dw.flag, 0, sizeof(int), stream));
+    sync();
+    pool.release(tmp);
+    pool.release(scan_tmp);
+}
+
+// x = K_k(r) on level k (solve layout).  When wdot is given, (x, wdot) is written
+// to *out_dot (the outer iteration needs (z, A p)).
+void amg_hierarchy::kcycle(int k, const double *rr, double *xx, const double *wdot, double *out_dot)
+{
+    using namespace amg;
+    const int L = levels() - 1;
+    Level &F = lev[k];
+    if (k == L) {  // single-level hierarchy: the exact solve is the preconditioner
+        launch_dense_gemv(F.n, ainv, rr, xx, stream);
+        if (wdot) launch_dot(F.n, xx, wdot, dw, out_dot, stream);
+        return;
+    }
+    Level &C = lev[k + 1];
+    launch_pre_restrict(C.n, F.seg_ptr, F.srp, F.ci, F.va, F.minv, rr, C.rc, F.Gs, stream);
+    if (k + 1 == L) {
+        launch_dense_gemv(C.n, ainv, C.rc, C.c1, stream);
+        launch_post_smooth(F.n, F.rp, F.ci, F.va, F.minv, rr, F.agg_pos, 0, C.c1, nullptr, nullptr, nullptr, xx, wdot,
+                           dw, out_dot, F.G, stream);
+        return;
+    }
+    kcycle(k + 1, C.rc, C.c1, nullptr, nullptr);
+    launch_spmv_dot2(C.n, C.rp, C.ci, C.va, C.c1, C.v1, C.rc, C.G, dw, C.dots, stream);  // rho1, alpha1
+    if (opt.kcycle_inner == 1) {
+        launch_post_smooth(F.n, F.rp, F.ci, F.va, F.minv, rr, F.agg_pos, 1, nullptr, C.c1, nullptr, C.dots, xx, wdot,
+                           dw, out_dot, F.G, stream);
+        return;
+    }
+    launch_inner_residual(C.n, C.rc, C.v1, C.dots, C.rt, dw.flag, stream);
+    kcycle(k + 1, C.rt, C.c2, nullptr, nullptr);
+    launch_spmv_dot3(C.n, C.rp, C.ci, C.va, C.c2, C.v1, C.rt, C.G, dw, C.dots + 2, stream);  // beta, gamma, alpha2
+    launch_post_smooth(F.n, F.rp, F.ci, F.va, F.minv, rr, F.agg_pos, 2, nullptr, C.c1, C.c2, C.dots, xx, wdot, dw,
+                       out_dot, F.G, stream);
+}
+
+amg_status amg_hierarchy::solve(const double *b_user, double *x_user, double tol, amg_solve_info *info)
+{
+    using namespace amg;
+    Level &F = lev[0];
+    const int n = F.n;
+    AMG_HIP(hipEventRecord(ev0, stream));
+    AMG_HIP(hipMemsetAsync(dw.flag, 0, sizeof(int), stream));
+    launch_gather(n, b_user, F.perm, b, stream);
+    launch_gather(n, x_user, F.perm, x, stream);
+    launch_residual(n, F.rp, F.ci, F.va, b, x, r, F.G, dw, outer + 4, stream);
+    AMG_HIP(hipMemcpyAsync(host, outer + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    sync();
+    const double bb = host[0];
+    double rel = std::sqrt(host[1] / bb);
+    if (!std::isfinite(bb) || !std::isfinite(host[1])) return AMG_ERR_INVALID_ARGUMENT;
+    int it = 0;
+    amg_status st = AMG_ERR_NOT_CONVERGED;
+    if (bb == 0.0) {
+        AMG_HIP(hipMemsetAsync(x_user, 0, sizeof(double) * n, stream));
+        rel = 0.0;
+        st = AMG_OK;
+    } else {
+        const double bnorm = std::sqrt(bb);
+        bool restart = true;
+        if (rel <= tol) st = AMG_OK;
+        while (st != AMG_OK && it < opt.max_iters) {
+            if (restart) {  // z = B r, p = z
+                kcycle(0, r, z, nullptr, nullptr);
+                AMG_HIP(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
+                restart = false;
+            }
+            launch_spmv_dot2(n, F.rp, F.ci, F.va, p, q, r, F.G, dw, outer + 0, stream);  // q = A p; pq, pr
+            launch_fcg_update(n, outer + 0, x, r, p, q, dw, outer + 2, stream);          // x, r; rr
+            AMG_HIP(hipMemcpyAsync(host, outer + 2, sizeof(double), hipMemcpyDeviceToHost, stream));
+            AMG_HIP(hipMemcpyAsync(host_i, dw.flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+            sync();
+            it++;
+            if (host_i[0]) {
+                st = AMG_ERR_BREAKDOWN;
+                break;
+            }
+            rel = std::sqrt(host[0]) / bnorm;
+            if (rel <= tol) {  // confirm with the true residual
+                launch_residual(n, F.rp, F.ci, F.va, b, x, r, F.G, dw, outer + 4, stream);
+                AMG_HIP(hipMemcpyAsync(host, outer + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+                sync();
+                rel = std::sqrt(host[1]) / bnorm;
+                if (rel <= tol) {
+                    st = AMG_OK;
+                    break;
+                }
+                restart = true;
+                continue;
+            }
+            kcycle(0, r, z, q, outer + 3);                                       // z = B r; zq
+            launch_fcg_direction(n, outer + 0, outer + 3, z, p, dw.flag, stream);  // p = z + beta p
+        }
+        launch_scatter(n, x, F.perm, x_user, stream);
+        // the reported residual is always the true one
+        launch_residual(n, F.rp, F.ci, F.va, b, x, r, F.G, dw, outer + 4, stream);
+        AMG_HIP(hipMemcpyAsync(host, outer + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    }
+    AMG_HIP(hipEventRecord(ev1, stream));
+    sync();
+    if (bb != 0.0) rel = std::sqrt(host[1] / host[0]);
+    float ms = 0.f;
+    AMG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    if (info) {
+        info->iterations = it;
+        info->rel_residual = rel;
+        info->setup_ms = setup_ms;
+        info->solve_ms = ms;
+    }
+    return st;
+}
+
+// ====================================================================== C ABI
+
+namespace {
+
+template <class F>
+amg_status guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const Error &e) {
+        return (amg_status)e.status;
+    } catch (const std::bad_alloc &) {
+        return AMG_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        return AMG_ERR_DEVICE;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void amg_default_options(amg_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->coarsest_size = 64;
+    opt->max_levels = 40;
+    opt->stall_ratio = 0.9;
+    opt->max_aggregate = 0;
+    opt->seed = 0x5EED5EEDull;
+    opt->kcycle_inner = 2;
+    opt->precision = AMG_PREC_FP64;
+    opt->max_iters = 200;
+    opt->max_coarsest = 4096;
+    opt->mem_budget = 0;
+    opt->stream = nullptr;
+}
+
+amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy **out)
+{
+    if (!out) return AMG_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    if (!A || !A->row_ptr || !A->col_idx || !A->values || A->n < 1 || A->nnz < A->n) return AMG_ERR_INVALID_ARGUMENT;
+    amg_options opt;
+    if (opt_in) opt = *opt_in;
+    else amg_default_options(&opt);
+    if (opt.coarsest_size < 1 || opt.max_levels < 1 || opt.max_levels > 64 || !(opt.stall_ratio > 0.0) ||
+        !(opt.stall_ratio <= 1.0) || opt.max_aggregate < 0 || opt.max_aggregate == 1 || opt.max_iters < 0 ||
+        opt.max_coarsest < 1)
+        return AMG_ERR_INVALID_ARGUMENT;
+    if (opt.kcycle_inner != 1 && opt.kcycle_inner != 2) return AMG_ERR_UNSUPPORTED;
+    if (opt.precision != AMG_PREC_FP64) return AMG_ERR_UNSUPPORTED;
+    amg_hierarchy *h = new (std::nothrow) amg_hierarchy();
+    if (!h) return AMG_ERR_OUT_OF_MEMORY;
+    h->opt = opt;
+    h->pool.budget = opt.mem_budget;
+    amg_status st = guarded([&]() -> amg_status {
+        if (opt.stream) {
+            h->stream = (hipStream_t)opt.stream;
+        } else {
+            AMG_HIP(hipStreamCreate(&h->stream));
+            h->own_stream = true;
+        }
+        h->build(*A);
+        return AMG_OK;
+    });
+    if (st != AMG_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return AMG_OK;
+}
+
+amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, amg_solve_info *info)
+{
+    if (!h || !b || !x || !(tol > 0.0) || !std::isfinite(tol)) return AMG_ERR_INVALID_ARGUMENT;
+    return guarded([&]() { return h->solve(b, x, tol, info); });
+}
+
+void amg_free(amg_hierarchy *h) { delete h; }
+
+amg_status amg_num_levels(const amg_hierarchy *h, int32_t *levels)
+{
+    if (!h || !levels) return AMG_ERR_INVALID_ARGUMENT;
+    *levels = h->levels();
+    return AMG_OK;
+}
+
+amg_status amg_level_sizes(const amg_hierarchy *h, int32_t level, int32_t *n, int32_t *nnz, int32_t *passes)
+{
+    if (!h || level < 0 || level >= h->levels()) return AMG_ERR_INVALID_ARGUMENT;
+    const Level &L = h->lev[level];
+    if (n) *n = L.n;
+    if (nnz) *nnz = L.nnz;
+    if (passes) *passes = L.passes;
+    return AMG_OK;
+}
+
+amg_status amg_export_level(const amg_hierarchy *h_c, int32_t level, int32_t *agg_host, int32_t *row_ptr_host,
+                            int32_t *col_host, double *val_host)
+{
+    amg_hierarchy *h = const_cast<amg_hierarchy *>(h_c);
+    if (!h || level < 0 || level >= h->levels()) return AMG_ERR_INVALID_ARGUMENT;
+    return guarded([&]() {
+        const Level &L = h->lev[level];
+        if (agg_host) {
+            if (L.agg_nat) h->to_host(agg_host, L.agg_nat, L.n);
+            else std::fill(agg_host, agg_host + L.n, -1);
+        }
+        if (row_ptr_host) h->to_host(row_ptr_host, L.rp_nat, L.n + 1);
+        if (col_host) h->to_host(col_host, L.ci_nat, L.nnz);
+        if (val_host) h->to_host(val_host, L.va_nat, L.nnz);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_spmv(amg_hierarchy *h, int32_t level, const double *x, double *y)
+{
+    if (!h || !x || !y || level < 0 || level >= h->levels()) return AMG_ERR_INVALID_ARGUMENT;
+    return guarded([&]() {
+        const Level &L = h->lev[level];
+        amg::launch_spmv(L.n, L.rp_nat, L.ci_nat, L.va_nat, x, y, L.G, h->stream);
+        h->sync();
+        return AMG_OK;
+    });
+}
+
+amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z)
+{
+    if (!h || !r || !z) return AMG_ERR_INVALID_ARGUMENT;
+    return guarded([&]() {
+        const Level &F = h->lev[0];
+        AMG_HIP(hipMemsetAsync(h->dw.flag, 0, sizeof(int), h->stream));
+        amg::launch_gather(F.n, r, F.perm, h->r, h->stream);
+        h->kcycle(0, h->r, h->z, nullptr, nullptr);
+        amg::launch_scatter(F.n, h->z, F.perm, z, h->stream);
+        AMG_HIP(hipMemcpyAsync(h->host_i, h->dw.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        h->sync();
+        return h->host_i[0] ? AMG_ERR_BREAKDOWN : AMG_OK;
+    });
+}
+
+amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, double *bytes)
+{
+    if (!h || reps < 1 || !avg_us) return AMG_ERR_INVALID_ARGUMENT;
+    if (h->levels() < 3) return AMG_ERR_UNSUPPORTED;
+    return guarded([&]() {
+        const Level &F = h->lev[0], &C = h->lev[1];
+        auto launch = [&]() {
+            amg::launch_post_smooth(F.n, F.rp, F.ci, F.va, F.minv, h->r, F.agg_pos, h->opt.kcycle_inner == 1 ? 1 : 2,
+                                    nullptr, C.c1, C.c2, C.dots, h->z, nullptr, h->dw, nullptr, F.G, h->stream);
+        };
+        launch();
+        AMG_HIP(hipEventRecord(h->ev0, h->stream));
+        for (int k = 0; k < reps; k++) launch();
+        AMG_HIP(hipEventRecord(h->ev1, h->stream));
+        h->sync();
+        float ms = 0.f;
+        AMG_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        *avg_us = 1000.0 * ms / reps;
+        if (bytes)
+            *bytes = 12.0 * F.nnz + 4.0 * (F.n + 1) + 32.0 * F.n + 16.0 * C.n;
+        return AMG_OK;
+    });
+}
+
+const char *amg_status_string(amg_status s)
+{
+    switch (s) {
+    case AMG_OK: return "AMG_OK";
+    case AMG_ERR_INVALID_ARGUMENT: return "AMG_ERR_INVALID_ARGUMENT";
+    case AMG_ERR_INVALID_MATRIX: return "AMG_ERR_INVALID_MATRIX";
+    case AMG_ERR_OUT_OF_MEMORY: return "AMG_ERR_OUT_OF_MEMORY";
+    case AMG_ERR_DEVICE: return "AMG_ERR_DEVICE";
+    case AMG_ERR_NOT_CONVERGED: return "AMG_ERR_NOT_CONVERGED";
+    case AMG_ERR_BREAKDOWN: return "AMG_ERR_BREAKDOWN";
+    case AMG_ERR_UNSUPPORTED: return "AMG_ERR_UNSUPPORTED";
+    }
+    return "AMG_ERR_UNKNOWN";
+}
+
+}  // extern "C"

@@ -1,0 +1,765 @@
+// setup_kernels.hip -- gfx950 kernels of the setup phase (Alg. 1 setup loop).
+//
+//   priorities (eq. (3.2))            k_priorities
+//   parallel aggregation (Alg. 2)     k_mis_max1 + k_mis_select_claim, one pair per pass
+//   numbering by coarse vertex (Sec. 5.1)   scan of centre flags, k_assign_aggregates
+//   P^T member lists                  k_member_counts / k_member_fill
+//   A_c = P^T A P as sums (eq. (2.4))  k_coarse_rows (one wavefront per coarse row,
+//                                     LDS bitonic sort + ordered segmented sums),
+//                                     k_coarse_big_rows (rows beyond LDS capacity)
+//   l1-Jacobi diagonal (Sec. 4.1)     k_l1_inverse_diagonal / k_coarse_compact
+//   coarsest level                    dense Cholesky and explicit inverse
+//   solve layout                      nested aggregate order for every level
+//
+// Every result is independent of the schedule: priorities are unique, a pass
+// only claims conflict-free stars, integer counts are exact, and every
+// floating-point sum runs in a fixed order.
+#include "amg_internal.h"
+
+namespace amg {
+namespace {
+
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+inline int grid_for(int64_t threads)
+{
+    int64_t b = (threads + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > (1 << 20)) b = 1 << 20;
+    return (int)b;
+}
+
+// MurmurHash3 32-bit finaliser (Appleby): a bijection on 32-bit words.
+__device__ inline uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// ------------------------------------------------------------------ input checks
+
+__global__ void __launch_bounds__(kBlock) k_validate_csr(int n, int nnz, const int *__restrict__ rp,
+                                                         const int *__restrict__ ci, const double *__restrict__ va,
+                                                         int *__restrict__ err)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicOr(err, 1);
+    if (i >= n) return;
+    const int b = rp[i], e = rp[i + 1];
+    if (b < 0 || e < b || e > nnz) {
+        atomicOr(err, 2);
+        return;
+    }
+    int prev = -1;
+    bool diag = false;
+    for (int p = b; p < e; p++) {
+        const int c = ci[p];
+        if (c < 0 || c >= n || c <= prev) {
+            atomicOr(err, 4);
+            return;
+        }
+        prev = c;
+        const double v = va[p];
+        if (!isfinite(v)) atomicOr(err, 8);
+        if (c == i) {
+            diag = true;
+            if (!(v > 0.0)) atomicOr(err, 16);
+        }
+    }
+    if (!diag) atomicOr(err, 32);
+}
+
+// minv_i = 1 / (a_ii + sum_{j != i} |a_ij|), the row summed in column order.
+__global__ void __launch_bounds__(kBlock) k_l1_inverse_diagonal(int n, const int *__restrict__ rp,
+                                                                const int *__restrict__ ci,
+                                                                const double *__restrict__ va,
+                                                                double *__restrict__ minv)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double diag = 0.0, off = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; p++) {
+        if (ci[p] == i) diag += va[p];
+        else off += fabs(va[p]);
+    }
+    minv[i] = 1.0 / (diag + off);
+}
+
+// ------------------------------------------------------------------ eq. (3.2)
+
+// key_i = (12 d_i + (i mod 12) + 1) * 2^32 + fmix32(i XOR s_l): 12 * 2^32 * v_i
+// shifted by 2^32 so that 0 can mark "processed".  d_i = row length - 1 (the
+// diagonal is present in every row of every level).
+__global__ void __launch_bounds__(kBlock) k_priorities(int n, const int *__restrict__ rp, uint32_t s_l,
+                                                       uint64_t *__restrict__ key, int *__restrict__ owner)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t deg = (uint64_t)(rp[i + 1] - rp[i] - 1);
+    const uint64_t whole = 12u * deg + (uint64_t)(i % 12) + 1u;
+    key[i] = (whole << 32) | (uint64_t)fmix32((uint32_t)i ^ s_l);
+    owner[i] = -1;
+}
+
+// ------------------------------------------------------------------ Alg. 2, one pass
+//
+// Step (2b) with distances measured among unprocessed vertices: i is a coarse
+// vertex of the pass iff its key is the maximum over unprocessed vertices within
+// distance 2 through unprocessed vertices.  Two sweeps of max-propagation give
+// that maximum: m1_i = max over the closed neighbourhood (processed keys are 0),
+// m2_i = max over the closed neighbourhood of m1.  A group of G lanes serves one row.
+
+template <int G>
+__device__ inline uint64_t group_max(uint64_t v)
+{
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        const uint64_t w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_mis_max1(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                     const uint64_t *__restrict__ key, uint64_t *__restrict__ m1)
+{
+    const int sub = threadIdx.x % G;
+    const int ngroups = gridDim.x * (kBlock / G);
+    for (int i = (blockIdx.x * kBlock + threadIdx.x) / G; i < n; i += ngroups) {
+        const uint64_t ki = key[i];
+        uint64_t m = 0;
+        if (ki != 0) {
+            for (int p = rp[i] + sub; p < rp[i + 1]; p += G) {
+                const uint64_t kj = key[ci[p]];
+                m = kj > m ? kj : m;
+            }
+        }
+        m = group_max<G>(m);
+        if (sub == 0) m1[i] = m;
+    }
+}
+
+// Step (2b) decision (m2 == key) and step (2c): the coarse vertex takes itself and
+// its unprocessed neighbours in ascending order, at most cap-1 of them (cap = 0:
+// all).  Coarse vertices of one pass are at distance >= 3 among unprocessed
+// vertices, so no two of them touch the same neighbour.
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_mis_select_claim(int n, const int *__restrict__ rp,
+                                                             const int *__restrict__ ci, uint64_t *key,
+                                                             const uint64_t *__restrict__ m1, int *owner, int cap,
+                                                             unsigned *__restrict__ done)
+{
+    __shared__ unsigned block_done;
+    if (threadIdx.x == 0) block_done = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int sub = threadIdx.x % G;
+    const int gbase = lane - sub;  // first lane of this group within the wave
+    const uint64_t gmask = (G == kWave) ? ~0ull : (((1ull << G) - 1ull) << gbase);
+    const int ngroups = gridDim.x * (kBlock / G);
+    for (int i = (blockIdx.x * kBlock + threadIdx.x) / G; i < n; i += ngroups) {
+        // key[i] may be zeroed concurrently by a neighbouring coarse vertex that
+        // claims i; one lane reads it and the group shares that value, so the
+        // group decides as one.  (If i is claimed, i cannot be a local maximum.)
+        uint64_t ki = (sub == 0) ? key[i] : 0;
+        ki = __shfl(ki, gbase, kWave);
+        if (ki == 0) continue;  // processed (uniform within the group)
+        uint64_t m = 0;
+        const int b = rp[i], e = rp[i + 1];
+        for (int p = b + sub; p < e; p += G) {
+            const uint64_t v = m1[ci[p]];
+            m = v > m ? v : m;
+        }
+        m = group_max<G>(m);
+        if (m != ki) continue;  // not a local maximum (uniform within the group)
+        int taken = 1;
+        for (int p0 = b; p0 < e; p0 += G) {
+            if (cap > 0 && taken >= cap) break;
+            const int p = p0 + sub;
+            int j = -1;
+            bool cand = false;
+            if (p < e) {
+                j = ci[p];
+                cand = (j != i) && (key[j] != 0);
+            }
+            const uint64_t bal = __ballot(cand) & gmask;
+            const int rank = __popcll(bal & ((1ull << lane) - 1ull) & gmask);
+            if (cand && (cap == 0 || taken + rank < cap)) {
+                owner[j] = i;
+                key[j] = 0;
+            }
+            const int c = __popcll(bal);
+            taken += (cap > 0 && taken + c > cap) ? (cap - taken) : c;
+        }
+        if (sub == 0) {
+            owner[i] = i;
+            key[i] = 0;
+            atomicAdd(&block_done, (unsigned)taken);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && block_done) atomicAdd(done, block_done);
+}
+
+// ------------------------------------------------------------------ numbering (Sec. 5.1)
+
+__global__ void __launch_bounds__(kBlock) k_centre_flags(int n, const int *__restrict__ owner, int *__restrict__ flag)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) flag[i] = owner[i] == i ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_assign_aggregates(int n, const int *__restrict__ owner,
+                                                              const int *__restrict__ cid, int *__restrict__ agg,
+                                                              int *__restrict__ centre_of)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int o = owner[i];
+    agg[i] = cid[o];
+    if (o == i) centre_of[cid[i]] = i;
+}
+
+// Members of aggregate I are its coarse vertex c and the neighbours j of c with
+// owner j = c; walking row c (ascending columns, diagonal included) lists them in
+// ascending order.
+__global__ void __launch_bounds__(kBlock) k_member_counts(int nc, const int *__restrict__ rp,
+                                                          const int *__restrict__ ci, const int *__restrict__ owner,
+                                                          const int *__restrict__ centre_of, int *__restrict__ size,
+                                                          int *__restrict__ pairs)
+{
+    const int I = blockIdx.x * kBlock + threadIdx.x;
+    if (I >= nc) return;
+    const int c = centre_of[I];
+    int s = 0, pc = 0;
+    for (int p = rp[c]; p < rp[c + 1]; p++) {
+        const int j = ci[p];
+        if (owner[j] == c) {
+            s++;
+            pc += rp[j + 1] - rp[j];
+        }
+    }
+    size[I] = s;
+    pairs[I] = pc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_member_fill(int nc, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                        const int *__restrict__ owner,
+                                                        const int *__restrict__ centre_of,
+                                                        const int *__restrict__ aptr, int *__restrict__ members)
+{
+    const int I = blockIdx.x * kBlock + threadIdx.x;
+    if (I >= nc) return;
+    const int c = centre_of[I];
+    int k = aptr[I];
+    for (int p = rp[c]; p < rp[c + 1]; p++) {
+        const int j = ci[p];
+        if (owner[j] == c) members[k++] = j;
+    }
+}
+
+// ------------------------------------------------------------------ eq. (2.4)
+//
+// Coarse row I gathers the pairs (agg[t], a_st) of its members' rows, in member
+// order and column order; key = (J << 32) | position makes the sort stable, and
+// each segment of equal J is summed sequentially in position order, which is the
+// order of a row-by-row accumulation over (s, t).
+
+constexpr int kWaveCap = 1024;  // pairs one wavefront sorts in LDS
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+__global__ void __launch_bounds__(kBlock) k_coarse_rows(int nc, const int *__restrict__ rp,
+                                                        const int *__restrict__ ci, const double *__restrict__ va,
+                                                        const int *__restrict__ agg, const int *__restrict__ aptr,
+                                                        const int *__restrict__ members, const int *__restrict__ tptr,
+                                                        int *__restrict__ tcol, double *__restrict__ tval,
+                                                        int *__restrict__ cnt, int *__restrict__ big_rows,
+                                                        unsigned *__restrict__ big_count)
+{
+    __shared__ uint64_t skey[kWavesPerBlock][kWaveCap];
+    __shared__ double sval[kWavesPerBlock][kWaveCap];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint64_t *key = skey[w];
+    double *val = sval[w];
+    const int total_waves = gridDim.x * kWavesPerBlock;
+    for (int I = blockIdx.x * kWavesPerBlock + w; I < nc; I += total_waves) {
+        const int base = tptr[I];
+        const int pc = tptr[I + 1] - base;
+        if (pc > kWaveCap) {
+            if (lane == 0) big_rows[atomicAdd(big_count, 1u)] = I;
+            continue;
+        }
+        int fill = 0;
+        for (int m = aptr[I]; m < aptr[I + 1]; m++) {
+            const int s = members[m];
+            const int b = rp[s], e = rp[s + 1];
+            for (int p = b + lane; p < e; p += kWave) {
+                const int k = fill + (p - b);
+                key[k] = ((uint64_t)(uint32_t)agg[ci[p]] << 32) | (uint32_t)k;
+                val[k] = va[p];
+            }
+            fill += e - b;
+        }
+        int P = 1;
+        while (P < pc) P <<= 1;
+        for (int k = pc + lane; k < P; k += kWave) key[k] = ~0ull;
+        wave_sync();
+        for (int size = 2; size <= P; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int t = lane; t < P / 2; t += kWave) {
+                    const int lo = 2 * stride * (t / stride) + (t % stride);
+                    const int hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const uint64_t a = key[lo], c = key[hi];
+                    if ((a > c) == up) {
+                        key[lo] = c;
+                        key[hi] = a;
+                    }
+                }
+                wave_sync();
+            }
+        }
+        int out = 0;
+        for (int q0 = 0; q0 < pc; q0 += kWave) {
+            const int q = q0 + lane;
+            bool head = false;
+            uint32_t J = 0;
+            if (q < pc) {
+                J = (uint32_t)(key[q] >> 32);
+                head = (q == 0) || ((uint32_t)(key[q - 1] >> 32) != J);
+            }
+            const uint64_t hm = __ballot(head);
+            if (head) {
+                const int rank = out + __popcll(hm & ((1ull << lane) - 1ull));
+                double s = 0.0;
+                for (int r = q; r < pc && (uint32_t)(key[r] >> 32) == J; r++) s += val[(uint32_t)key[r]];
+                tcol[base + rank] = (int)J;
+                tval[base + rank] = s;
+            }
+            out += __popcll(hm);
+        }
+        if (lane == 0) cnt[I] = out;
+        wave_sync();
+    }
+}
+
+// Rows with more pairs than one wavefront's LDS holds: one block per row, the
+// same stable sort in global scratch (keys only; values are re-read by position).
+__global__ void __launch_bounds__(kBlock) k_coarse_big_rows(const int *__restrict__ big_rows,
+                                                            const int64_t *__restrict__ scratch_off, uint64_t *skey,
+                                                            const int *__restrict__ rp, const int *__restrict__ ci,
+                                                            const double *__restrict__ va, const int *__restrict__ agg,
+                                                            const int *__restrict__ aptr,
+                                                            const int *__restrict__ members,
+                                                            const int *__restrict__ tptr, int *__restrict__ tcol,
+                                                            double *__restrict__ tval, int *__restrict__ cnt)
+{
+    __shared__ int sh_count[kWavesPerBlock];
+    __shared__ int sh_out;
+    const int I = big_rows[blockIdx.x];
+    uint64_t *key = skey + scratch_off[blockIdx.x];
+    double *val = reinterpret_cast<double *>(skey + scratch_off[gridDim.x]) + scratch_off[blockIdx.x];
+    const int base = tptr[I];
+    const int pc = tptr[I + 1] - base;
+    int fill = 0;
+    for (int m = aptr[I]; m < aptr[I + 1]; m++) {
+        const int s = members[m];
+        const int b = rp[s], e = rp[s + 1];
+        for (int p = b + (int)threadIdx.x; p < e; p += kBlock) {
+            const int k = fill + (p - b);
+            key[k] = ((uint64_t)(uint32_t)agg[ci[p]] << 32) | (uint32_t)k;
+            val[k] = va[p];
+        }
+        fill += e - b;
+    }
+    int P = 1;
+    while (P < pc) P <<= 1;
+    for (int k = pc + threadIdx.x; k < P; k += kBlock) key[k] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < P / 2; t += kBlock) {
+                const int lo = 2 * stride * (t / stride) + (t % stride);
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint64_t a = key[lo], c = key[hi];
+                if ((a > c) == up) {
+                    key[lo] = c;
+                    key[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (threadIdx.x == 0) sh_out = 0;
+    __syncthreads();
+    for (int q0 = 0; q0 < pc; q0 += kBlock) {
+        const int q = q0 + (int)threadIdx.x;
+        bool head = false;
+        uint32_t J = 0;
+        if (q < pc) {
+            J = (uint32_t)(key[q] >> 32);
+            head = (q == 0) || ((uint32_t)(key[q - 1] >> 32) != J);
+        }
+        const uint64_t hm = __ballot(head);
+        if (lane == 0) sh_count[w] = __popcll(hm);
+        __syncthreads();
+        int before = sh_out;
+        for (int k = 0; k < w; k++) before += sh_count[k];
+        if (head) {
+            const int rank = before + __popcll(hm & ((1ull << lane) - 1ull));
+            double s = 0.0;
+            for (int r = q; r < pc && (uint32_t)(key[r] >> 32) == J; r++) s += val[(uint32_t)key[r]];
+            tcol[base + rank] = (int)J;
+            tval[base + rank] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int add = 0;
+            for (int k = 0; k < kWavesPerBlock; k++) add += sh_count[k];
+            sh_out += add;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[I] = sh_out;
+}
+
+// Copy the unique entries of every coarse row into the final CSR and form the
+// coarse l1 diagonal (row summed in column order).
+__global__ void __launch_bounds__(kBlock) k_coarse_compact(int nc, const int *__restrict__ tptr,
+                                                           const int *__restrict__ tcol,
+                                                           const double *__restrict__ tval,
+                                                           const int *__restrict__ crp, int *__restrict__ cci,
+                                                           double *__restrict__ cva, double *__restrict__ cminv)
+{
+    const int I = blockIdx.x * kBlock + threadIdx.x;
+    if (I >= nc) return;
+    const int src = tptr[I], dst = crp[I], len = crp[I + 1] - crp[I];
+    double diag = 0.0, off = 0.0;
+    for (int k = 0; k < len; k++) {
+        const int J = tcol[src + k];
+        const double v = tval[src + k];
+        cci[dst + k] = J;
+        cva[dst + k] = v;
+        if (J == I) diag += v;
+        else off += fabs(v);
+    }
+    cminv[I] = 1.0 / (diag + off);
+}
+
+// ------------------------------------------------------------------ coarsest level
+
+__global__ void __launch_bounds__(kBlock) k_dense_from_csr(int n, const int *__restrict__ rp,
+                                                           const int *__restrict__ ci, const double *__restrict__ va,
+                                                           double *__restrict__ dense)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    for (int p = rp[i]; p < rp[i + 1]; p++) dense[(size_t)i * n + ci[p]] = va[p];
+}
+
+// One block: right-looking Cholesky A = L L^T in place (lower triangle of a), then
+// inv = L^-T L^-1 column by column (forward then backward substitution).
+constexpr int kCholThreads = 1024;
+
+__global__ void __launch_bounds__(kCholThreads) k_cholesky_inverse(int n, double *a, double *inv, int *err)
+{
+    __shared__ double piv;
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int k = 0; k < n; k++) {
+        if (threadIdx.x == 0) {
+            const double d = a[(size_t)k * n + k];
+            if (!(d > 0.0)) {
+                bad = 1;
+                *err = 1;
+            } else {
+                piv = sqrt(d);
+                a[(size_t)k * n + k] = piv;
+            }
+        }
+        __syncthreads();
+        if (bad) return;
+        for (int i = k + 1 + threadIdx.x; i < n; i += kCholThreads) a[(size_t)i * n + k] /= piv;
+        __syncthreads();
+        const int m = n - k - 1;
+        for (int64_t t = threadIdx.x; t < (int64_t)m * m; t += kCholThreads) {
+            const int ii = (int)(t / m), jj = (int)(t % m);
+            if (jj <= ii) {
+                const int i = k + 1 + ii, j = k + 1 + jj;
+                a[(size_t)i * n + j] -= a[(size_t)i * n + k] * a[(size_t)j * n + k];
+            }
+        }
+        __syncthreads();
+    }
+    for (int j = threadIdx.x; j < n; j += kCholThreads) {
+        // forward: L y = e_j, y_i = 0 for i < j
+        for (int i = 0; i < j; i++) inv[(size_t)i * n + j] = 0.0;
+        for (int i = j; i < n; i++) {
+            double s = (i == j) ? 1.0 : 0.0;
+            for (int k = j; k < i; k++) s -= a[(size_t)i * n + k] * inv[(size_t)k * n + j];
+            inv[(size_t)i * n + j] = s / a[(size_t)i * n + i];
+        }
+        // backward: L^T x = y
+        for (int i = n - 1; i >= 0; i--) {
+            double s = inv[(size_t)i * n + j];
+            for (int k = i + 1; k < n; k++) s -= a[(size_t)k * n + i] * inv[(size_t)k * n + j];
+            inv[(size_t)i * n + j] = s / a[(size_t)i * n + i];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ solve layout
+//
+// Every level is stored in nested aggregate order: the coarsest level in its own
+// order, and level l as the concatenation of its aggregates in the order their
+// coarse unknowns have on level l+1, members ascending inside an aggregate.  Then
+// restriction sums contiguous segments and prolongation broadcasts over them.
+
+__global__ void __launch_bounds__(kBlock) k_identity(int n, int *__restrict__ v)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) v[i] = i;
+}
+
+__global__ void __launch_bounds__(kBlock) k_sizes_in_position_order(int nc, const int *__restrict__ aptr_nat,
+                                                                    const int *__restrict__ perm_c,
+                                                                    int *__restrict__ size_pos)
+{
+    const int Q = blockIdx.x * kBlock + threadIdx.x;
+    if (Q >= nc) return;
+    const int J = perm_c[Q];
+    size_pos[Q] = aptr_nat[J + 1] - aptr_nat[J];
+}
+
+__global__ void __launch_bounds__(kBlock) k_positions_from_segments(int nc, const int *__restrict__ aptr_nat,
+                                                                    const int *__restrict__ members_nat,
+                                                                    const int *__restrict__ pos_c,
+                                                                    const int *__restrict__ seg_ptr,
+                                                                    int *__restrict__ pos_f, int *__restrict__ perm_f)
+{
+    const int J = blockIdx.x * kBlock + threadIdx.x;
+    if (J >= nc) return;
+    const int start = seg_ptr[pos_c[J]];
+    const int b = aptr_nat[J], e = aptr_nat[J + 1];
+    for (int k = 0; k < e - b; k++) {
+        const int i = members_nat[b + k];
+        pos_f[i] = start + k;
+        perm_f[start + k] = i;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_permuted_row_lengths(int n, const int *__restrict__ rp_nat,
+                                                                 const int *__restrict__ perm, int *__restrict__ len)
+{
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    const int i = perm[q];
+    len[q] = rp_nat[i + 1] - rp_nat[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_permute_rows(int n, const int *__restrict__ rp_nat,
+                                                         const int *__restrict__ ci_nat,
+                                                         const double *__restrict__ va_nat,
+                                                         const double *__restrict__ minv_nat,
+                                                         const int *__restrict__ perm, const int *__restrict__ pos,
+                                                         const int *__restrict__ rp, int *__restrict__ ci,
+                                                         double *__restrict__ va, double *__restrict__ minv)
+{
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    const int i = perm[q];
+    const int b = rp_nat[i], len = rp_nat[i + 1] - b, d = rp[q];
+    for (int k = 0; k < len; k++) {
+        ci[d + k] = pos[ci_nat[b + k]];
+        va[d + k] = va_nat[b + k];
+    }
+    minv[q] = minv_nat[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_agg_positions(int n, const int *__restrict__ perm_f,
+                                                          const int *__restrict__ agg_nat,
+                                                          const int *__restrict__ pos_c, int *__restrict__ agg_pos)
+{
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q < n) agg_pos[q] = pos_c[agg_nat[perm_f[q]]];
+}
+
+__global__ void __launch_bounds__(kBlock) k_gather_int(int n, const int *__restrict__ src, const int *__restrict__ idx,
+                                                       int *__restrict__ dst)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+#define AMG_LAUNCH_G(G, KERNEL, GRID, STREAM, ...)                                      \
+    switch (G) {                                                                        \
+    case 1: KERNEL<1><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;                 \
+    case 2: KERNEL<2><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;                 \
+    case 4: KERNEL<4><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;                 \
+    case 8: KERNEL<8><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;                 \
+    case 16: KERNEL<16><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;               \
+    case 32: KERNEL<32><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;               \
+    default: KERNEL<64><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;               \
+    }
+
+void launch_validate_csr(int n, int nnz, const int *rp, const int *ci, const double *va, int *err, hipStream_t s)
+{
+    k_validate_csr<<<grid_for(n), kBlock, 0, s>>>(n, nnz, rp, ci, va, err);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_l1_inverse_diagonal(int n, const int *rp, const int *ci, const double *va, double *minv, hipStream_t s)
+{
+    k_l1_inverse_diagonal<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, va, minv);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_priorities(int n, const int *rp, uint32_t s_l, uint64_t *key, int *owner, hipStream_t s)
+{
+    k_priorities<<<grid_for(n), kBlock, 0, s>>>(n, rp, s_l, key, owner);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_mis_pass(int n, const int *rp, const int *ci, uint64_t *key, uint64_t *m1, int *owner, int cap, int G,
+                     unsigned *done_counter, hipStream_t s)
+{
+    const int grid = grid_for((int64_t)n * G);
+    AMG_LAUNCH_G(G, k_mis_max1, grid, s, n, rp, ci, key, m1);
+    AMG_LAUNCH_G(G, k_mis_select_claim, grid, s, n, rp, ci, key, m1, owner, cap, done_counter);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_centre_flags(int n, const int *owner, int *flag, hipStream_t s)
+{
+    k_centre_flags<<<grid_for(n), kBlock, 0, s>>>(n, owner, flag);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_assign_aggregates(int n, const int *owner, const int *cid, int *agg, int *centre_of, hipStream_t s)
+{
+    k_assign_aggregates<<<grid_for(n), kBlock, 0, s>>>(n, owner, cid, agg, centre_of);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_member_counts(int nc, const int *rp, const int *ci, const int *owner, const int *centre_of, int *size,
+                          int *pairs, hipStream_t s)
+{
+    k_member_counts<<<grid_for(nc), kBlock, 0, s>>>(nc, rp, ci, owner, centre_of, size, pairs);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_member_fill(int nc, const int *rp, const int *ci, const int *owner, const int *centre_of,
+                        const int *aptr, int *members, hipStream_t s)
+{
+    k_member_fill<<<grid_for(nc), kBlock, 0, s>>>(nc, rp, ci, owner, centre_of, aptr, members);
+    AMG_HIP(hipGetLastError());
+}
+
+int coarse_wave_capacity() { return kWaveCap; }
+
+void launch_coarse_rows(int nc, const int *rp, const int *ci, const double *va, const int *agg, const int *aptr,
+                        const int *members, const int *tptr, int *tcol, double *tval, int *cnt, int *big_rows,
+                        unsigned *big_count, hipStream_t s)
+{
+    int64_t blocks = ((int64_t)nc + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    k_coarse_rows<<<(int)blocks, kBlock, 0, s>>>(nc, rp, ci, va, agg, aptr, members, tptr, tcol, tval, cnt, big_rows,
+                                                 big_count);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_coarse_big_rows(int nbig, const int *big_rows, const int64_t *scratch_off, uint64_t *skey,
+                            const int *rp, const int *ci, const double *va, const int *agg, const int *aptr,
+                            const int *members, const int *tptr, int *tcol, double *tval, int *cnt, hipStream_t s)
+{
+    if (nbig <= 0) return;
+    k_coarse_big_rows<<<nbig, kBlock, 0, s>>>(big_rows, scratch_off, skey, rp, ci, va, agg, aptr, members, tptr, tcol,
+                                             tval, cnt);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_coarse_compact(int nc, const int *tptr, const int *tcol, const double *tval, const int *crp, int *cci,
+                           double *cva, double *cminv, hipStream_t s)
+{
+    k_coarse_compact<<<grid_for(nc), kBlock, 0, s>>>(nc, tptr, tcol, tval, crp, cci, cva, cminv);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_dense_from_csr(int n, const int *rp, const int *ci, const double *va, double *dense, hipStream_t s)
+{
+    k_dense_from_csr<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, va, dense);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_cholesky_inverse(int n, double *a, double *inv, int *err, hipStream_t s)
+{
+    k_cholesky_inverse<<<1, kCholThreads, 0, s>>>(n, a, inv, err);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_identity(int n, int *v, hipStream_t s)
+{
+    k_identity<<<grid_for(n), kBlock, 0, s>>>(n, v);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_sizes_in_position_order(int nc, const int *aptr_nat, const int *perm_c, int *size_pos, hipStream_t s)
+{
+    k_sizes_in_position_order<<<grid_for(nc), kBlock, 0, s>>>(nc, aptr_nat, perm_c, size_pos);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_positions_from_segments(int nc, const int *aptr_nat, const int *members_nat, const int *pos_c,
+                                    const int *seg_ptr, int *pos_f, int *perm_f, hipStream_t s)
+{
+    k_positions_from_segments<<<grid_for(nc), kBlock, 0, s>>>(nc, aptr_nat, members_nat, pos_c, seg_ptr, pos_f,
+                                                             perm_f);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_permuted_row_lengths(int n, const int *rp_nat, const int *perm, int *len, hipStream_t s)
+{
+    k_permuted_row_lengths<<<grid_for(n), kBlock, 0, s>>>(n, rp_nat, perm, len);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_permute_rows(int n, const int *rp_nat, const int *ci_nat, const double *va_nat, const double *minv_nat,
+                         const int *perm, const int *pos, const int *rp, int *ci, double *va, double *minv,
+                         hipStream_t s)
+{
+    k_permute_rows<<<grid_for(n), kBlock, 0, s>>>(n, rp_nat, ci_nat, va_nat, minv_nat, perm, pos, rp, ci, va, minv);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_agg_positions(int n, const int *perm_f, const int *agg_nat, const int *pos_c, int *agg_pos,
+                          hipStream_t s)
+{
+    k_agg_positions<<<grid_for(n), kBlock, 0, s>>>(n, perm_f, agg_nat, pos_c, agg_pos);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_gather_int(int n, const int *src, const int *idx, int *dst, hipStream_t s)
+{
+    k_gather_int<<<grid_for(n), kBlock, 0, s>>>(n, src, idx, dst);
+    AMG_HIP(hipGetLastError());
+}
+
+}  // namespace amg

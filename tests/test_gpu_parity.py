@@ -1,0 +1,114 @@
+"""GPU parity: the HIP library against the oracle, through the C ABI.
+
+Hierarchies (aggregates, coarse sparsity, coarse values) must equal the oracle's
+exactly; solutions must reach the requested true relative residual.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1302_2547_amd import inputs  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def amg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1302_2547_amd import amg as mod
+    return mod
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def setup_both(amg, rp, ci, va, **opt):
+    print(f"[parity] n={len(rp) - 1} nnz={len(ci)} opt={opt}", flush=True)
+    h = amg.Hierarchy(dev(rp), dev(ci), dev(va), **opt)
+    oopt = {k: v for k, v in opt.items() if k in ("coarsest_size", "max_levels", "stall_ratio", "max_aggregate",
+                                                   "seed", "kcycle_inner")}
+    ref = oracle.Hierarchy(rp, ci, va, **oopt)
+    return h, ref
+
+
+def assert_same_hierarchy(h, ref, value_rtol=0.0):
+    assert h.num_levels == ref.num_levels
+    for l in range(h.num_levels):
+        g, o = h.export_level(l), ref.level(l)
+        assert (g.n, g.nnz, g.passes) == (o.n, o.nnz, o.passes), l
+        np.testing.assert_array_equal(g.agg, o.agg, err_msg=f"level {l} aggregates")
+        np.testing.assert_array_equal(g.row_ptr, o.row_ptr, err_msg=f"level {l} row_ptr")
+        np.testing.assert_array_equal(g.col, o.col, err_msg=f"level {l} columns")
+        if value_rtol == 0.0:
+            np.testing.assert_array_equal(g.val, o.val, err_msg=f"level {l} values")
+        else:
+            np.testing.assert_allclose(g.val, o.val, rtol=value_rtol, atol=0, err_msg=f"level {l} values")
+
+
+CASES = {
+    "grid2d_64": lambda: inputs.grid_laplacian((64, 64)),
+    "grid2d_77x50_jitter": lambda: inputs.grid_laplacian((77, 50), jitter=0.3, seed=5),
+    "grid3d_24_jitter": lambda: inputs.grid_laplacian((24, 24, 24), jitter=0.1, seed=2),
+    "grid3d_31x17x9": lambda: inputs.grid_laplacian((31, 17, 9), jitter=0.1, seed=7),
+    "rgg_20k": lambda: inputs.rgg_laplacian(20000, seed=3, weight_range=(0.5, 1.5)),
+    "random_int_300": lambda: inputs.random_graph_laplacian(300, 0.02, seed=4, integer_weights=True, shift=1.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_hierarchy_bit_identical(amg, case):
+    rp, ci, va = CASES[case]()
+    h, ref = setup_both(amg, rp, ci, va)
+    assert_same_hierarchy(h, ref)
+    h.close()
+
+
+@pytest.mark.parametrize("t", [2, 3, 4, 5])
+def test_aggregate_cap_and_paper_ratio(amg, t, golden):
+    rp, ci, va = inputs.grid_laplacian((128, 128))
+    h, ref = setup_both(amg, rp, ci, va, max_aggregate=t, coarsest_size=99)
+    assert_same_hierarchy(h, ref)
+    paper = {r[1]: r[2] for r in golden("table_5_1_ratios.txt") if r[0] == 128}
+    n0, n1 = h.level_sizes(0)[0], h.level_sizes(1)[0]
+    assert f"{n0 / n1:.2f}" == f"{paper[t]:.2f}"
+
+
+@pytest.mark.parametrize("case", ["grid2d_64", "grid3d_24_jitter", "rgg_20k"])
+def test_solve_reaches_tolerance(amg, case):
+    rp, ci, va = CASES[case]()
+    n = len(rp) - 1
+    b = inputs.rhs(n, 11)
+    h, ref = setup_both(amg, rp, ci, va)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, info = h.solve(dev(b), x, tol=1e-8)
+    xo, st_o, it_o, rel_o, _ = ref.solve(b, tol=1e-8)
+    xg = x.cpu().numpy()
+    r = b - oracle.spmv(rp, ci, va, xg)
+    rel = np.linalg.norm(r) / np.linalg.norm(b)
+    print(f"[parity] {case}: gpu iters={info.iterations} rel={info.rel_residual:.3e} (host {rel:.3e}); "
+          f"oracle iters={it_o} rel={rel_o:.3e}")
+    assert st == amg.AMG_OK and rel <= 1e-8 and abs(rel - info.rel_residual) <= 1e-12
+    assert abs(info.iterations - it_o) <= 2
+    np.testing.assert_allclose(xg, xo, rtol=0, atol=1e-6 * np.abs(xo).max())
+
+
+def test_spmv_and_kcycle_match_oracle(amg):
+    rp, ci, va = CASES["grid3d_24_jitter"]()
+    n = len(rp) - 1
+    h, ref = setup_both(amg, rp, ci, va)
+    xv = inputs.rhs(n, 3)
+    for l in range(h.num_levels):
+        lv = ref.level(l)
+        xl = xv[:lv.n]
+        y = torch.empty(lv.n, dtype=torch.float64, device="cuda")
+        h.spmv(l, dev(xl), y)
+        yo = oracle.spmv(lv.row_ptr, lv.col, lv.val, xl)
+        np.testing.assert_allclose(y.cpu().numpy(), yo, rtol=1e-13, atol=1e-13 * np.abs(yo).max())
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.kcycle(dev(xv), z)
+    zo = ref.kcycle(xv)
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-10 * np.abs(zo).max())
