@@ -1,0 +1,145 @@
+"""Benchmark: UA-AMG setup + K-cycle/FCG solve on one MI355X.
+
+Workload (the headline metric): 3D 7-point finite-difference Laplacian on a
+128^3 interior grid (2,097,152 unknowns, 14,581,760 stored entries), edge weights
+1 + 0.1 U[-1,1] from seed 2, Dirichlet boundary, FP64 CSR, right-hand side
+U[-1,1] from seed 1, zero initial guess, stop at true relative residual 1e-8.
+A step is amg_setup + amg_solve + amg_free from a CSR already resident in HBM.
+
+Prints one JSON line.  ``roofline`` is the finest-level post-smoothing kernel
+(fused prolongation + l1-Jacobi sweep) timed with HIP events on the library's
+stream; ``cpu_baseline`` is the serial FP64 oracle on the host, same input.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "setup+solve ms to 1e-8 rel-res, 128^3 Laplacian; served solves/s + p99 ms"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=128, help="grid side (128 = the headline workload)")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--smoother-reps", type=int, default=50)
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "post_smooth_128cubed_traffic.json"))
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1302_2547_amd import amg, inputs
+
+    dev = torch.device("cuda:0")
+    N = args.grid
+    t0 = time.perf_counter()
+    rp, ci, va = inputs.grid_laplacian((N, N, N), jitter=0.1, seed=2)
+    n, nnz = len(rp) - 1, len(ci)
+    b = inputs.rhs(n, 1)
+    gen_s = time.perf_counter() - t0
+    d_rp, d_ci, d_va = (torch.from_numpy(a).to(dev) for a in (rp, ci, va))
+    d_b = torch.from_numpy(b).to(dev)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    print(f"[bench] generated n={n} nnz={nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    def step():
+        x.zero_()
+        h = amg.Hierarchy(d_rp, d_ci, d_va)
+        st, info = h.solve(d_b, x, tol=args.tol)
+        levels = h.num_levels
+        sizes = [h.level_sizes(l) for l in range(levels)]
+        h.close()
+        return info, levels, sizes
+
+    for w in range(args.warmup):
+        info, levels, sizes = step()
+        print(f"[bench] warmup {w}: setup {info.setup_ms:.2f} ms solve {info.solve_ms:.2f} ms "
+              f"iters {info.iterations} rel {info.rel_residual:.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    walls, setups, solves, iters, rels = [], [], [], [], []
+    t_all = time.perf_counter()
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        info, levels, sizes = step()
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - ts) * 1e3)
+        setups.append(info.setup_ms)
+        solves.append(info.solve_ms)
+        iters.append(info.iterations)
+        rels.append(info.rel_residual)
+        print(f"[bench] step {k}: wall {walls[-1]:.2f} ms setup {info.setup_ms:.2f} solve {info.solve_ms:.2f} "
+              f"iters {info.iterations} rel {info.rel_residual:.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t_all
+    assert max(rels) <= args.tol, rels
+
+    # dominant kernel, timed live on the library's stream
+    h = amg.Hierarchy(d_rp, d_ci, d_va)
+    h.solve(d_b, x, tol=args.tol)
+    avg_us, alg_bytes = h.time_smoother(args.smoother_reps)
+    h.close()
+    achieved = alg_bytes / (avg_us * 1e-6) / 1e9
+    traffic = None
+    if os.path.exists(args.traffic_file):
+        with open(args.traffic_file) as f:
+            tr = json.load(f)
+        if tr.get("grid") == N:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": "k_post_smooth (finest level)", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "avg_us": round(avg_us, 2), "alg_bytes_per_launch": alg_bytes}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        tc = time.perf_counter()
+        ref = oracle.Hierarchy(rp, ci, va)
+        _, st, it_o, rel_o, solve_ms = ref.solve(b, tol=args.tol)
+        cpu_ms = ref.setup_ms + solve_ms
+        ref.close()
+        cpu = {"value": round(cpu_ms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+               "sample": f"one full setup+solve of the same {N}^3 workload (serial FP64 C, {it_o} iterations, "
+                         f"rel {rel_o:.1e}); wall {time.perf_counter() - tc:.1f}s",
+               "host_cpus": os.cpu_count()}
+
+    ms = statistics.median(walls)
+    out = {
+        "metric": METRIC, "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"3D 7-point Laplacian {N}^3 (n={n}), weights 1+0.1U[-1,1] seed 2, Dirichlet, "
+                               f"FP64 CSR, rhs U[-1,1] seed 1, x0=0, tol {args.tol:g}; UA-AMG K-cycle (nu=2) "
+                               f"+ flexible CG, l1-Jacobi 1+1, coarsest <= 64",
+                   "n": n, "nnz": nnz, "levels": levels, "level_sizes": [s[0] for s in sizes],
+                   "passes": [s[2] for s in sizes], "parallelism": "single GPU"},
+        "setup_ms": round(statistics.median(setups), 3), "solve_ms": round(statistics.median(solves), 3),
+        "iterations": int(statistics.median(iters)), "rel_residual": max(rels),
+        "timed_region_s": round(total_s, 3),
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -66,6 +66,8 @@ typedef struct {
     int32_t precision;          /* amg_precision (default AMG_PREC_FP64)                     */
     int32_t max_iters;          /* outer iterations (default 200)                            */
     int32_t max_coarsest;       /* largest coarsest level factored densely (default 4096)   */
+    int32_t use_graph;          /* 1: replay the K-cycle as a captured HIP graph (default); */
+                                /* 0: launch its kernels one by one (same results)          */
     size_t mem_budget;          /* device bytes the hierarchy may hold; 0 = no limit        */
     void *stream;               /* hipStream_t, or NULL                                      */
 } amg_options;

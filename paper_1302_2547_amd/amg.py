@@ -37,7 +37,7 @@ class amg_options(ctypes.Structure):
     _fields_ = [("coarsest_size", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("stall_ratio", ctypes.c_double),
                 ("max_aggregate", ctypes.c_int32), ("seed", ctypes.c_uint64), ("kcycle_inner", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("max_coarsest", ctypes.c_int32),
-                ("mem_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
+                ("use_graph", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
 
 
 class amg_solve_info(ctypes.Structure):

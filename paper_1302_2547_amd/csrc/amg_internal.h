@@ -27,10 +27,49 @@ void hip_check(hipError_t e, const char *what);
 
 // Device reduction workspace shared by the kernels of one solve context: per-block
 // partial sums, an arrival counter for the last-block pattern, and an error flag.
-struct DotWork {
-    double *partials;   // kMaxDots * kMaxDotBlocks
-    unsigned *counter;  // 1 (kept at 0 between launches)
-    int *flag;          // 1: bit 0 = Krylov breakdown
+// Rows of a CSR-like operator: row r has entries ptr[r] .. ptr[r+1].  Rows with
+// more than lim entries ("hub" rows) are cut into chunks of at most kChunk
+// entries, each served by one block; long_first[k] .. long_first[k+1] are the
+// chunks of hub row k.  chunk_sum / arrive are device workspaces (arrive is zero
+// between launches).
+constexpr int kChunk = 1024;
+constexpr int kLongBlocks = 1024;  // blocks that serve chunks
+constexpr int kMaxLong = 2048;     // hub rows per operator (the threshold is raised beyond)
+constexpr int kSmallLevel = 100000;
+constexpr int kPartStride = kMaxDotBlocks + kMaxLong;
+
+struct Chunk {
+    int row, beg, end, k;
+};
+
+struct Rows {
+    int n;
+    const int *ptr;
+    int lim;
+    int nchunks;
+    const Chunk *chunks;
+    int nlong;
+    const int *long_first;
+    double *chunk_sum;
+    unsigned *arrive;
+};
+
+// A dot product as a set of partial sums (count 1: already reduced).
+struct DotRef {
+    const double *part;
+    int count;
+};
+struct DotSet {
+    DotRef d[3];
+};
+// Storage of one dot-product site: partials (3 * kPartStride) and 3 reduced values.
+struct DotBuf {
+    double *part;
+    double *final_out;
+};
+// The five inner products of one K-cycle coarse correction.
+struct KDots {
+    DotRef rho1, alpha1, beta, gamma, alpha2;
 };
 
 // ---------------------------------------------------------------- scan.hip
@@ -75,44 +114,43 @@ void launch_permute_rows(int n, const int *rp_nat, const int *ci_nat, const doub
 void launch_agg_positions(int n, const int *perm_f, const int *agg_nat, const int *pos_c, int *agg_pos,
                           hipStream_t s);
 void launch_gather_int(int n, const int *src, const int *idx, int *dst, hipStream_t s);
+// Rows of ptr longer than lim, ascending.  Call first with list == NULL: flags
+// (n ints) receive exclusive offsets and *count_dev the count; then call again with
+// the same flags and a list of that many ints.
+void launch_long_rows(int n, const int *ptr, int lim, int *flags, int *list, int *count_dev, int *scan_tmp,
+                      hipStream_t s);
 
 // ---------------------------------------------------------------- solve_kernels.hip
-int lanes_for(double avg_row_len);
-// y = A x; dots: d[0] = (x, y), d[1] = (x, w)   (w may be NULL -> d[1] = 0)
-void launch_spmv_dot2(int n, const int *rp, const int *ci, const double *va, const double *x, double *y,
-                      const double *w, int G, DotWork dw, double *out, hipStream_t s);
-// dots only: d[0] = (x, A x), d[1] = (x, w1), d[2] = (x, w2)
-void launch_spmv_dot3(int n, const int *rp, const int *ci, const double *va, const double *x, const double *w1,
-                      const double *w2, int G, DotWork dw, double *out, hipStream_t s);
+int lanes_for(double avg_row_len, int n);
 // plain y = A x
-void launch_spmv(int n, const int *rp, const int *ci, const double *va, const double *x, double *y, int G,
-                 hipStream_t s);
-// rc[Q] = sum_{q in seg Q} r_q - sum_{e in super-row Q} a_e minv[col_e] r[col_e]
-void launch_pre_restrict(int nc, const int *seg_ptr, const int *srp, const int *ci, const double *va,
-                         const double *minv, const double *r, double *rc, int G, hipStream_t s);
-// rt = rc - (alpha1/rho1) v1, scalars d[0] = rho1, d[1] = alpha1
-void launch_inner_residual(int n, const double *rc, const double *v1, const double *d, double *rt, int *flag,
-                           hipStream_t s);
-// post-smoothing with the coarse correction folded in.  mode 0: e = edirect;
-// mode 1: e = (alpha1/rho1) c1; mode 2: e = a1 c1 + a2 c2 from the 5 dots of d.
-// Optionally dots (out, wdot) into dw/out_dot.
-void launch_post_smooth(int n, const int *rp, const int *ci, const double *va, const double *minv, const double *r,
-                        const int *agg_pos, int mode, const double *edirect, const double *c1, const double *c2,
-                        const double *d, double *xout, const double *wdot, DotWork dw, double *out_dot, int G,
-                        hipStream_t s);
+void launch_spmv(Rows R, const int *ci, const double *va, const double *x, double *y, int G, hipStream_t s);
+// y = A x (y may be NULL); d[0] = (x, A x), d[1] = (x, w1) if w1, d[2] = (x, w2) if w2
+DotSet launch_spmv_dots(Rows R, const int *ci, const double *va, const double *x, double *y, const double *w1,
+                        const double *w2, int G, DotBuf buf, hipStream_t s);
+// r = b - A x; d[0] = (b, b), d[1] = (r, r)
+DotSet launch_residual(Rows R, const int *ci, const double *va, const double *b, const double *x, double *r, int G,
+                       DotBuf buf, hipStream_t s);
+// *out = value of ref (one block)
+void launch_reduce(const DotRef &ref, double *out, hipStream_t s);
+// rc = W r over the super-rows S, W = P^T (I - A M^-1) stored per entry
+void launch_restrict(Rows S, const int *ci, const double *wv, const double *r, double *rc, int G, hipStream_t s);
+// rt = rc - (alpha1/rho1) v1
+void launch_inner_residual(int n, const double *rc, const double *v1, KDots kd, double *rt, int *flag, hipStream_t s);
+// post-smoothing with the coarse correction folded in (mode 0: e = edirect;
+// 1: e = (alpha1/rho1) c1; 2: e = a1 c1 + a2 c2); returns (out, wdot) if wdot
+DotRef launch_post_smooth(Rows R, const int *ci, const double *va, const double *minv, const double *r,
+                          const int *agg_pos, int mode, const double *edirect, const double *c1, const double *c2,
+                          KDots kd, double *xout, const double *wdot, DotBuf buf, int *flag, int G, hipStream_t s);
 void launch_dense_gemv(int n, const double *a, const double *x, double *y, hipStream_t s);
-// outer flexible CG
-// r = b - A x; out[0] = (b, b), out[1] = (r, r)
-void launch_residual(int n, const int *rp, const int *ci, const double *va, const double *b, const double *x,
-                     double *r, int G, DotWork dw, double *out, hipStream_t s);
-// alpha = pr/pq; x += alpha p; r -= alpha q; out = (r, r)
-void launch_fcg_update(int n, const double *pq_pr, double *x, double *r, const double *p, const double *q,
-                       DotWork dw, double *out, hipStream_t s);
+// alpha = pr/pq; x += alpha p; r -= alpha q; returns (r, r)
+DotRef launch_fcg_update(int n, DotRef pq, DotRef pr, double *x, double *r, const double *p, const double *q,
+                         DotBuf buf, int *flag, hipStream_t s);
 // beta = -zq/pq; p = z + beta p
-void launch_fcg_direction(int n, const double *pq, const double *zq, const double *z, double *p, int *flag,
-                          hipStream_t s);
-void launch_dot(int n, const double *a, const double *b, DotWork dw, double *out, hipStream_t s);  // out = (a, b)
+void launch_fcg_direction(int n, DotRef pq, DotRef zq, const double *z, double *p, int *flag, hipStream_t s);
+DotRef launch_dot(int n, const double *a, const double *b, DotBuf buf, hipStream_t s);
 void launch_gather(int n, const double *src, const int *idx, double *dst, hipStream_t s);   // dst[i] = src[idx[i]]
 void launch_scatter(int n, const double *src, const int *idx, double *dst, hipStream_t s);  // dst[idx[i]] = src[i]
+void launch_restriction_weights(int n, const int *rp, const int *ci, const double *va, const double *minv, double *wv,
+                                hipStream_t s);
 
 }  // namespace amg

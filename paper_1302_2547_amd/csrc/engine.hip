@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -25,6 +26,31 @@ void hip_check(hipError_t e, const char *what)
     if (e == hipErrorOutOfMemory) throw Error(AMG_ERR_OUT_OF_MEMORY, what);
     throw Error(AMG_ERR_DEVICE, what);
 }
+
+namespace {
+
+using amg::DotBuf;
+using amg::Rows;
+
+}  // namespace
+
+// Stage trace on stderr when the environment sets AMG_TRACE=1.
+bool trace_on()
+{
+    static const bool on = [] {
+        const char *v = std::getenv("AMG_TRACE");
+        return v && v[0] == '1';
+    }();
+    return on;
+}
+#define AMG_TRACE_MSG(...)                          \
+    do {                                            \
+        if (::amg::trace_on()) {                    \
+            std::fprintf(stderr, "[amg] " __VA_ARGS__); \
+            std::fputc('\n', stderr);                \
+            std::fflush(stderr);                    \
+        }                                           \
+    } while (0)
 
 namespace {
 
@@ -87,19 +113,25 @@ struct Level {
     // solve layout (nested aggregate order)
     int *rp = nullptr, *ci = nullptr;
     double *va = nullptr, *minv = nullptr;
+    double *wv = nullptr;                                        // restriction weights P^T (I - A M^-1)
     int *perm = nullptr, *pos = nullptr;                        // position -> natural, natural -> position
     int *agg_pos = nullptr, *seg_ptr = nullptr, *srp = nullptr;  // all but the coarsest level
     int G = 2, Gs = 2;
-    // work vectors when this level is a coarse level of a K-cycle visit
+    Rows A{}, S{};  // rows of A and super-rows of P^T A, each with its hub-row chunks
+    // work vectors and dot sites when this level is the coarse level of a visit
     double *rc = nullptr, *rt = nullptr, *c1 = nullptr, *c2 = nullptr, *v1 = nullptr;
-    double *dots = nullptr;  // rho1, alpha1, beta, gamma, alpha2
+    DotBuf d_c1{}, d_c2{};  // (c1, A c1), (c1, rc) and (c2, A c2), (c2, v1), (c2, rt)
 };
 
 }  // namespace
 }  // namespace amg
 
+using amg::DotBuf;
+using amg::DotRef;
 using amg::Error;
+using amg::KDots;
 using amg::Level;
+using amg::Rows;
 
 struct amg_hierarchy {
     amg_options opt{};
@@ -110,8 +142,14 @@ struct amg_hierarchy {
     double *ainv = nullptr;  // dense inverse of the coarsest matrix
     // outer iteration vectors (finest level, solve layout)
     double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
-    double *outer = nullptr;  // 8 device scalars: pq, pr, rr, zq, bb, rr0
-    amg::DotWork dw{};
+    DotBuf d_pq{}, d_rr{}, d_zq{}, d_res{};
+    DotRef dr_pq{}, dr_pr{}, dr_rr{}, dr_zq{};
+    double *scal = nullptr;  // device scalars read by the host: rr, bb, rr0
+    KDots kd0{};             // dots of the finest visit's coarse correction (for timing)
+    int *flag = nullptr;     // bit 0: Krylov breakdown
+    hipGraphExec_t g_kcycle = nullptr, g_first = nullptr, g_iter = nullptr;
+    bool graphs_tried = false;
+    static constexpr int kMaxGraphDepth = 12;
     double *host = nullptr;  // pinned: readbacks
     int *host_i = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -120,6 +158,8 @@ struct amg_hierarchy {
     ~amg_hierarchy()
     {
         if (stream) (void)hipStreamSynchronize(stream);
+        for (hipGraphExec_t g : {g_kcycle, g_first, g_iter})
+            if (g) (void)hipGraphExecDestroy(g);
         pool.release_all();
         if (host) (void)hipHostFree(host);
         if (ev0) (void)hipEventDestroy(ev0);
@@ -147,9 +187,68 @@ struct amg_hierarchy {
         amg::scan_exclusive(in, out, count, total_dev, tmp, stream);
     }
 
+    DotBuf dot_buf()
+    {
+        return DotBuf{pool.alloc<double>(3 * (size_t)amg::kPartStride), pool.alloc<double>(4)};
+    }
+
+    // Rows descriptor of a CSR-like operator: rows longer than lim = 8 G entries
+    // are hub rows, cut into chunks of at most kChunk entries (raised if there
+    // would be more than kMaxLong hub rows).
+    Rows make_rows(int n, const int *ptr, int G, int *flags, int *scan_tmp)
+    {
+        Rows R{};
+        R.n = n;
+        R.ptr = ptr;
+        R.lim = 8 * G;
+        for (;;) {
+            amg::launch_long_rows(n, ptr, R.lim, flags, nullptr, flags + n, scan_tmp, stream);
+            R.nlong = read_int(flags + n);
+            if (R.nlong <= amg::kMaxLong) break;
+            R.lim *= 2;
+        }
+        if (R.nlong == 0) return R;
+        int *list = pool.alloc<int>(R.nlong);
+        amg::launch_long_rows(n, ptr, R.lim, flags, list, nullptr, scan_tmp, stream);
+        std::vector<int> rows(R.nlong), beg(R.nlong), end(R.nlong);
+        int *bounds = pool.alloc<int>(2 * (size_t)R.nlong);
+        amg::launch_gather_int(R.nlong, ptr, list, bounds, stream);
+        amg::launch_gather_int(R.nlong, ptr + 1, list, bounds + R.nlong, stream);
+        to_host(rows.data(), list, R.nlong);
+        to_host(beg.data(), bounds, R.nlong);
+        to_host(end.data(), bounds + R.nlong, R.nlong);
+        pool.release(bounds);
+        pool.release(list);
+        std::vector<amg::Chunk> chunks;
+        std::vector<int> first(R.nlong + 1, 0);
+        for (int k = 0; k < R.nlong; k++) {
+            first[k] = (int)chunks.size();
+            for (int b0 = beg[k]; b0 < end[k]; b0 += amg::kChunk)
+                chunks.push_back(amg::Chunk{rows[k], b0, std::min(end[k], b0 + amg::kChunk), k});
+        }
+        first[R.nlong] = (int)chunks.size();
+        R.nchunks = (int)chunks.size();
+        amg::Chunk *dchunks = pool.alloc<amg::Chunk>(chunks.size());
+        int *dfirst = pool.alloc<int>(first.size());
+        R.chunk_sum = pool.alloc<double>(chunks.size());
+        R.arrive = pool.alloc<unsigned>(R.nlong);
+        AMG_HIP(hipMemcpyAsync(dchunks, chunks.data(), sizeof(amg::Chunk) * chunks.size(), hipMemcpyHostToDevice,
+                               stream));
+        AMG_HIP(hipMemcpyAsync(dfirst, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, stream));
+        AMG_HIP(hipMemsetAsync(R.arrive, 0, sizeof(unsigned) * R.nlong, stream));
+        sync();
+        R.chunks = dchunks;
+        R.long_first = dfirst;
+        return R;
+    }
+
     void build(const amg_csr &A);
     void finalize_layout();
-    void kcycle(int k, const double *r, double *x, const double *wdot, double *out_dot);
+    DotRef kcycle(int k, const double *r, double *x, const double *wdot);
+    void run_kcycle();
+    void run_first();
+    void run_iter();
+    void capture_graphs();
     amg_status solve(const double *b_user, double *x_user, double tol, amg_solve_info *info);
 };
 
@@ -204,7 +303,8 @@ void amg_hierarchy::build(const amg_csr &A)
     int l = 0;
     while (lev[l].n > opt.coarsest_size && l + 1 < opt.max_levels) {
         const int n = lev[l].n, nnz = lev[l].nnz;
-        const int G = lanes_for((double)nnz / n);
+        const int G = lanes_for((double)nnz / n, n);
+        AMG_TRACE_MSG("level %d: n=%d nnz=%d G=%d aggregation", l, n, nnz, G);
         const uint32_t s_l = (uint32_t)splitmix64(opt.seed, (uint64_t)l);
         launch_priorities(n, lev[l].rp_nat, s_l, key, owner, stream);
         AMG_HIP(hipMemsetAsync(done, 0, sizeof(unsigned), stream));
@@ -236,6 +336,7 @@ void amg_hierarchy::build(const amg_csr &A)
         launch_coarse_rows(nc, F.rp_nat, F.ci_nat, F.va_nat, F.agg_nat, F.aptr_nat, F.members_nat, tptr, tcol, tval,
                            cnt, big_rows, big_count, stream);
         const int nbig = read_int(reinterpret_cast<int *>(big_count));
+        AMG_TRACE_MSG("level %d: passes=%d nc=%d big rows=%d", l, passes, nc, nbig);
         if (nbig > 0) {
             std::vector<int> rows(nbig), tp(nc + 1);
             to_host(rows.data(), big_rows, nbig);
@@ -277,6 +378,7 @@ void amg_hierarchy::build(const amg_csr &A)
 
     // coarsest level: dense Cholesky factorisation and explicit inverse
     Level &Lc = lev.back();
+    AMG_TRACE_MSG("coarsest level %d: n=%d", levels() - 1, Lc.n);
     if (Lc.n > opt.max_coarsest) throw Error(AMG_ERR_UNSUPPORTED, "coarsest level larger than max_coarsest");
     {
         const size_t nn = (size_t)Lc.n * Lc.n;
@@ -331,12 +433,18 @@ void amg_hierarchy::finalize_layout()
         F.minv = pool.alloc<double>(F.n);
         launch_permute_rows(F.n, F.rp_nat, F.ci_nat, F.va_nat, F.minv_nat, F.perm, F.pos, F.rp, F.ci, F.va, F.minv,
                             stream);
-        F.G = lanes_for((double)F.nnz / F.n);
+        F.G = lanes_for((double)F.nnz / F.n, F.n);
+        F.A = make_rows(F.n, F.rp, F.G, tmp, scan_tmp);
+        AMG_TRACE_MSG("layout level %d: G=%d hub rows=%d chunks=%d", l, F.G, F.A.nlong, F.A.nchunks);
         if (l < L) {
             const int nc = lev[l + 1].n;
             F.srp = pool.alloc<int>(nc + 1);
             launch_gather_int(nc + 1, F.rp, F.seg_ptr, F.srp, stream);
-            F.Gs = lanes_for((double)F.nnz / nc);
+            F.Gs = lanes_for((double)F.nnz / nc, nc);
+            F.S = make_rows(nc, F.srp, F.Gs, tmp, scan_tmp);
+            AMG_TRACE_MSG("layout level %d: super-rows Gs=%d hub rows=%d chunks=%d", l, F.Gs, F.S.nlong, F.S.nchunks);
+            F.wv = pool.alloc<double>(F.nnz);
+            launch_restriction_weights(F.n, F.rp, F.ci, F.va, F.minv, F.wv, stream);
         }
         if (l >= 1) {
             F.rc = pool.alloc<double>(F.n);
@@ -344,7 +452,8 @@ void amg_hierarchy::finalize_layout()
             F.c1 = pool.alloc<double>(F.n);
             F.c2 = pool.alloc<double>(F.n);
             F.v1 = pool.alloc<double>(F.n);
-            F.dots = pool.alloc<double>(8);
+            F.d_c1 = dot_buf();
+            F.d_c2 = dot_buf();
         }
     }
     const int n = lev[0].n;
@@ -354,49 +463,140 @@ void amg_hierarchy::finalize_layout()
     z = pool.alloc<double>(n);
     p = pool.alloc<double>(n);
     q = pool.alloc<double>(n);
-    outer = pool.alloc<double>(8);
-    dw.partials = pool.alloc<double>((size_t)kMaxDots * kMaxDotBlocks);
-    dw.counter = pool.alloc<unsigned>(1);
-    dw.flag = pool.alloc<int>(1);
-    AMG_HIP(hipMemsetAsync(dw.counter, 0, sizeof(unsigned), stream));
-    AMG_HIP(hipMemsetAsync(dw.flag, 0, sizeof(int), stream));
+    AMG_HIP(hipMemsetAsync(q, 0, sizeof(double) * n, stream));
+    AMG_HIP(hipMemsetAsync(p, 0, sizeof(double) * n, stream));
+    d_pq = dot_buf();
+    d_rr = dot_buf();
+    d_zq = dot_buf();
+    d_res = dot_buf();
+    scal = pool.alloc<double>(8);
+    flag = pool.alloc<int>(1);
+    AMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
     sync();
     pool.release(tmp);
     pool.release(scan_tmp);
 }
 
-// x = K_k(r) on level k (solve layout).  When wdot is given, (x, wdot) is written
-// to *out_dot (the outer iteration needs (z, A p)).
-void amg_hierarchy::kcycle(int k, const double *rr, double *xx, const double *wdot, double *out_dot)
+// x = K_k(r) on level k (solve layout): pre-smoothing from zero + restriction,
+// coarse correction (exact on the coarsest level, else two flexible-CG steps
+// preconditioned by K_{k+1}), prolongation + post-smoothing.  When wdot is given
+// the returned reference holds (x, wdot).
+DotRef amg_hierarchy::kcycle(int k, const double *rr, double *xx, const double *wdot)
 {
     using namespace amg;
     const int L = levels() - 1;
     Level &F = lev[k];
     if (k == L) {  // single-level hierarchy: the exact solve is the preconditioner
         launch_dense_gemv(F.n, ainv, rr, xx, stream);
-        if (wdot) launch_dot(F.n, xx, wdot, dw, out_dot, stream);
-        return;
+        return wdot ? launch_dot(F.n, xx, wdot, d_zq, stream) : DotRef{nullptr, 0};
     }
     Level &C = lev[k + 1];
-    launch_pre_restrict(C.n, F.seg_ptr, F.srp, F.ci, F.va, F.minv, rr, C.rc, F.Gs, stream);
+    launch_restrict(F.S, F.ci, F.wv, rr, C.rc, F.Gs, stream);
+    KDots kd{};
+    int mode;
+    const double *edirect = nullptr;
     if (k + 1 == L) {
         launch_dense_gemv(C.n, ainv, C.rc, C.c1, stream);
-        launch_post_smooth(F.n, F.rp, F.ci, F.va, F.minv, rr, F.agg_pos, 0, C.c1, nullptr, nullptr, nullptr, xx, wdot,
-                           dw, out_dot, F.G, stream);
+        mode = 0;
+        edirect = C.c1;
+    } else {
+        kcycle(k + 1, C.rc, C.c1, nullptr);
+        const DotSet s1 = launch_spmv_dots(C.A, C.ci, C.va, C.c1, C.v1, C.rc, nullptr, C.G, C.d_c1, stream);
+        kd.rho1 = s1.d[0];
+        kd.alpha1 = s1.d[1];
+        mode = 1;
+        if (opt.kcycle_inner == 2) {
+            launch_inner_residual(C.n, C.rc, C.v1, kd, C.rt, flag, stream);
+            kcycle(k + 1, C.rt, C.c2, nullptr);
+            const DotSet s2 = launch_spmv_dots(C.A, C.ci, C.va, C.c2, nullptr, C.v1, C.rt, C.G, C.d_c2, stream);
+            kd.beta = s2.d[0];
+            kd.gamma = s2.d[1];
+            kd.alpha2 = s2.d[2];
+            mode = 2;
+        }
+    }
+    if (k == 0) kd0 = kd;
+    return launch_post_smooth(F.A, F.ci, F.va, F.minv, rr, F.agg_pos, mode, edirect, C.c1, C.c2, kd, xx, wdot,
+                              k == 0 ? d_zq : DotBuf{}, flag, F.G, stream);
+}
+
+// One outer iteration is split in three replayable pieces:
+//   K     : z = B r, with (z, A p) for the direction update
+//   first : p = z; q = A p, (p, q), (p, r); x += alpha p, r -= alpha q; (r, r)
+//   iter  : p = z + beta p; then as in first
+void amg_hierarchy::run_kcycle()
+{
+    if (g_kcycle) AMG_HIP(hipGraphLaunch(g_kcycle, stream));
+    else dr_zq = kcycle(0, r, z, q);
+}
+
+void amg_hierarchy::run_first()
+{
+    using namespace amg;
+    if (g_first) {
+        AMG_HIP(hipGraphLaunch(g_first, stream));
         return;
     }
-    kcycle(k + 1, C.rc, C.c1, nullptr, nullptr);
-    launch_spmv_dot2(C.n, C.rp, C.ci, C.va, C.c1, C.v1, C.rc, C.G, dw, C.dots, stream);  // rho1, alpha1
-    if (opt.kcycle_inner == 1) {
-        launch_post_smooth(F.n, F.rp, F.ci, F.va, F.minv, rr, F.agg_pos, 1, nullptr, C.c1, nullptr, C.dots, xx, wdot,
-                           dw, out_dot, F.G, stream);
+    Level &F = lev[0];
+    AMG_HIP(hipMemcpyAsync(p, z, sizeof(double) * F.n, hipMemcpyDeviceToDevice, stream));
+    const DotSet s1 = launch_spmv_dots(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream);
+    dr_pq = s1.d[0];
+    dr_pr = s1.d[1];
+    dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream);
+    launch_reduce(dr_rr, scal, stream);
+}
+
+void amg_hierarchy::run_iter()
+{
+    using namespace amg;
+    if (g_iter) {
+        AMG_HIP(hipGraphLaunch(g_iter, stream));
         return;
     }
-    launch_inner_residual(C.n, C.rc, C.v1, C.dots, C.rt, dw.flag, stream);
-    kcycle(k + 1, C.rt, C.c2, nullptr, nullptr);
-    launch_spmv_dot3(C.n, C.rp, C.ci, C.va, C.c2, C.v1, C.rt, C.G, dw, C.dots + 2, stream);  // beta, gamma, alpha2
-    launch_post_smooth(F.n, F.rp, F.ci, F.va, F.minv, rr, F.agg_pos, 2, nullptr, C.c1, C.c2, C.dots, xx, wdot, dw,
-                       out_dot, F.G, stream);
+    Level &F = lev[0];
+    launch_fcg_direction(F.n, dr_pq, dr_zq, z, p, flag, stream);
+    const DotSet s1 = launch_spmv_dots(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream);
+    dr_pq = s1.d[0];
+    dr_pr = s1.d[1];
+    dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream);
+    launch_reduce(dr_rr, scal, stream);
+}
+
+// Records the three pieces once per hierarchy; every launch argument (buffers,
+// partial-set sizes) is fixed by the level sizes, so the graphs stay valid.
+void amg_hierarchy::capture_graphs()
+{
+    // The K-cycle visits level k 2^k times, so its graph has about 6 (2^L - 1)
+    // nodes; deep hierarchies (small aggregates) are launched eagerly instead.
+    if (!opt.use_graph || graphs_tried) return;
+    graphs_tried = true;
+    const int L = levels() - 1;
+    if (L > kMaxGraphDepth) return;
+    auto capture = [&](auto &&body, hipGraphExec_t *out) {
+        hipGraph_t g = nullptr;
+        AMG_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        try {
+            body();
+        } catch (...) {
+            (void)hipStreamEndCapture(stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        AMG_HIP(hipStreamEndCapture(stream, &g));
+        const hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        AMG_HIP(e);
+    };
+    hipGraphExec_t gk = nullptr, gf = nullptr, gi = nullptr;
+    AMG_TRACE_MSG("capturing K-cycle graph");
+    capture([&] { run_kcycle(); }, &gk);
+    AMG_TRACE_MSG("capturing outer-iteration graphs");
+    capture([&] { run_first(); }, &gf);
+    capture([&] { run_iter(); }, &gi);
+    AMG_TRACE_MSG("graphs ready");
+    g_kcycle = gk;
+    g_first = gf;
+    g_iter = gi;
 }
 
 amg_status amg_hierarchy::solve(const double *b_user, double *x_user, double tol, amg_solve_info *info)
@@ -405,35 +605,37 @@ amg_status amg_hierarchy::solve(const double *b_user, double *x_user, double tol
     Level &F = lev[0];
     const int n = F.n;
     AMG_HIP(hipEventRecord(ev0, stream));
-    AMG_HIP(hipMemsetAsync(dw.flag, 0, sizeof(int), stream));
+    capture_graphs();
+    AMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
     launch_gather(n, b_user, F.perm, b, stream);
     launch_gather(n, x_user, F.perm, x, stream);
-    launch_residual(n, F.rp, F.ci, F.va, b, x, r, F.G, dw, outer + 4, stream);
-    AMG_HIP(hipMemcpyAsync(host, outer + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
-    sync();
-    const double bb = host[0];
-    double rel = std::sqrt(host[1] / bb);
-    if (!std::isfinite(bb) || !std::isfinite(host[1])) return AMG_ERR_INVALID_ARGUMENT;
+    auto true_residual = [&]() {  // r = b - A x; scal[1] = (b, b), scal[2] = (r, r)
+        const DotSet s0 = launch_residual(F.A, F.ci, F.va, b, x, r, F.G, d_res, stream);
+        launch_reduce(s0.d[0], scal + 1, stream);
+        launch_reduce(s0.d[1], scal + 2, stream);
+        AMG_HIP(hipMemcpyAsync(host, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
+        sync();
+    };
+    true_residual();
+    const double bb = host[1];
+    if (!std::isfinite(bb) || !std::isfinite(host[2])) return AMG_ERR_INVALID_ARGUMENT;
+    double rel = bb > 0.0 ? std::sqrt(host[2] / bb) : 0.0;
     int it = 0;
     amg_status st = AMG_ERR_NOT_CONVERGED;
     if (bb == 0.0) {
         AMG_HIP(hipMemsetAsync(x_user, 0, sizeof(double) * n, stream));
-        rel = 0.0;
         st = AMG_OK;
     } else {
         const double bnorm = std::sqrt(bb);
         bool restart = true;
         if (rel <= tol) st = AMG_OK;
         while (st != AMG_OK && it < opt.max_iters) {
-            if (restart) {  // z = B r, p = z
-                kcycle(0, r, z, nullptr, nullptr);
-                AMG_HIP(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
-                restart = false;
-            }
-            launch_spmv_dot2(n, F.rp, F.ci, F.va, p, q, r, F.G, dw, outer + 0, stream);  // q = A p; pq, pr
-            launch_fcg_update(n, outer + 0, x, r, p, q, dw, outer + 2, stream);          // x, r; rr
-            AMG_HIP(hipMemcpyAsync(host, outer + 2, sizeof(double), hipMemcpyDeviceToHost, stream));
-            AMG_HIP(hipMemcpyAsync(host_i, dw.flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+            run_kcycle();  // z = B r
+            if (restart) run_first();
+            else run_iter();
+            restart = false;
+            AMG_HIP(hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, stream));
+            AMG_HIP(hipMemcpyAsync(host_i, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
             sync();
             it++;
             if (host_i[0]) {
@@ -441,29 +643,19 @@ amg_status amg_hierarchy::solve(const double *b_user, double *x_user, double tol
                 break;
             }
             rel = std::sqrt(host[0]) / bnorm;
-            if (rel <= tol) {  // confirm with the true residual
-                launch_residual(n, F.rp, F.ci, F.va, b, x, r, F.G, dw, outer + 4, stream);
-                AMG_HIP(hipMemcpyAsync(host, outer + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
-                sync();
-                rel = std::sqrt(host[1]) / bnorm;
-                if (rel <= tol) {
-                    st = AMG_OK;
-                    break;
-                }
-                restart = true;
-                continue;
+            if (rel <= tol) {  // confirm with the true residual; restart from it if they disagree
+                true_residual();
+                rel = std::sqrt(host[2]) / bnorm;
+                if (rel <= tol) st = AMG_OK;
+                else restart = true;
             }
-            kcycle(0, r, z, q, outer + 3);                                       // z = B r; zq
-            launch_fcg_direction(n, outer + 0, outer + 3, z, p, dw.flag, stream);  // p = z + beta p
         }
         launch_scatter(n, x, F.perm, x_user, stream);
-        // the reported residual is always the true one
-        launch_residual(n, F.rp, F.ci, F.va, b, x, r, F.G, dw, outer + 4, stream);
-        AMG_HIP(hipMemcpyAsync(host, outer + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+        true_residual();  // the reported residual is always the true one
+        rel = std::sqrt(host[2] / host[1]);
     }
     AMG_HIP(hipEventRecord(ev1, stream));
     sync();
-    if (bb != 0.0) rel = std::sqrt(host[1] / host[0]);
     float ms = 0.f;
     AMG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     if (info) {
@@ -510,6 +702,7 @@ void amg_default_options(amg_options *opt)
     opt->precision = AMG_PREC_FP64;
     opt->max_iters = 200;
     opt->max_coarsest = 4096;
+    opt->use_graph = 1;
     opt->mem_budget = 0;
     opt->stream = nullptr;
 }
@@ -598,7 +791,12 @@ amg_status amg_spmv(amg_hierarchy *h, int32_t level, const double *x, double *y)
     if (!h || !x || !y || level < 0 || level >= h->levels()) return AMG_ERR_INVALID_ARGUMENT;
     return guarded([&]() {
         const Level &L = h->lev[level];
-        amg::launch_spmv(L.n, L.rp_nat, L.ci_nat, L.va_nat, x, y, L.G, h->stream);
+        // natural numbering, no hub-row table: one wavefront per row
+        Rows R{};
+        R.n = L.n;
+        R.ptr = L.rp_nat;
+        R.lim = 1 << 30;
+        amg::launch_spmv(R, L.ci_nat, L.va_nat, x, y, amg::kWave, h->stream);
         h->sync();
         return AMG_OK;
     });
@@ -609,11 +807,12 @@ amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z)
     if (!h || !r || !z) return AMG_ERR_INVALID_ARGUMENT;
     return guarded([&]() {
         const Level &F = h->lev[0];
-        AMG_HIP(hipMemsetAsync(h->dw.flag, 0, sizeof(int), h->stream));
+        h->capture_graphs();
+        AMG_HIP(hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
         amg::launch_gather(F.n, r, F.perm, h->r, h->stream);
-        h->kcycle(0, h->r, h->z, nullptr, nullptr);
+        h->run_kcycle();
         amg::launch_scatter(F.n, h->z, F.perm, z, h->stream);
-        AMG_HIP(hipMemcpyAsync(h->host_i, h->dw.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        AMG_HIP(hipMemcpyAsync(h->host_i, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         h->sync();
         return h->host_i[0] ? AMG_ERR_BREAKDOWN : AMG_OK;
     });
@@ -625,9 +824,10 @@ amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, dou
     if (h->levels() < 3) return AMG_ERR_UNSUPPORTED;
     return guarded([&]() {
         const Level &F = h->lev[0], &C = h->lev[1];
+        const int mode = h->opt.kcycle_inner == 1 ? 1 : 2;
         auto launch = [&]() {
-            amg::launch_post_smooth(F.n, F.rp, F.ci, F.va, F.minv, h->r, F.agg_pos, h->opt.kcycle_inner == 1 ? 1 : 2,
-                                    nullptr, C.c1, C.c2, C.dots, h->z, nullptr, h->dw, nullptr, F.G, h->stream);
+            amg::launch_post_smooth(F.A, F.ci, F.va, F.minv, h->r, F.agg_pos, mode, nullptr, C.c1, C.c2, h->kd0, h->z,
+                                    nullptr, DotBuf{}, h->flag, F.G, h->stream);
         };
         launch();
         AMG_HIP(hipEventRecord(h->ev0, h->stream));
@@ -637,8 +837,7 @@ amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, dou
         float ms = 0.f;
         AMG_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
         *avg_us = 1000.0 * ms / reps;
-        if (bytes)
-            *bytes = 12.0 * F.nnz + 4.0 * (F.n + 1) + 32.0 * F.n + 16.0 * C.n;
+        if (bytes) *bytes = 12.0 * F.nnz + 4.0 * (F.n + 1) + 32.0 * F.n + 16.0 * C.n;
         return AMG_OK;
     });
 }

@@ -604,9 +604,37 @@ __global__ void __launch_bounds__(kBlock) k_gather_int(int n, const int *__restr
     if (i < n) dst[i] = src[idx[i]];
 }
 
+__global__ void __launch_bounds__(kBlock) k_long_flags(int n, const int *__restrict__ ptr, int lim,
+                                                       int *__restrict__ flags)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) flags[i] = (ptr[i + 1] - ptr[i] > lim) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_long_compact(int n, const int *__restrict__ ptr, int lim,
+                                                         const int *__restrict__ offs, int *__restrict__ list)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n && ptr[i + 1] - ptr[i] > lim) list[offs[i]] = i;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+
+void launch_long_rows(int n, const int *ptr, int lim, int *flags, int *list, int *count_dev, int *scan_tmp,
+                      hipStream_t s)
+{
+    // list == nullptr: count only (flags are left as exclusive offsets)
+    if (list == nullptr) {
+        k_long_flags<<<grid_for(n), kBlock, 0, s>>>(n, ptr, lim, flags);
+        AMG_HIP(hipGetLastError());
+        scan_exclusive(flags, flags, n, count_dev, scan_tmp, s);
+        return;
+    }
+    k_long_compact<<<grid_for(n), kBlock, 0, s>>>(n, ptr, lim, flags, list);
+    AMG_HIP(hipGetLastError());
+}
 
 #define AMG_LAUNCH_G(G, KERNEL, GRID, STREAM, ...)                                      \
     switch (G) {                                                                        \

@@ -1,15 +1,22 @@
 // solve_kernels.hip -- gfx950 kernels of the solve phase (Sec. 4).
 //
-// All matrices are CSR in the nested aggregate order of their level, so that the
-// aggregate of every coarse unknown Q is the contiguous range seg_ptr[Q] ..
-// seg_ptr[Q+1] of fine rows and its rows' entries are the contiguous range
-// srp[Q] .. srp[Q+1] (a "super-row" of P^T A).  A group of G lanes (G | 64)
-// serves one row; G is chosen per level from the mean row length so the column
-// and value streams stay coalesced.
+// All matrices are CSR in the nested aggregate order of their level, so the
+// aggregate of coarse unknown Q is the contiguous range seg_ptr[Q] .. seg_ptr[Q+1]
+// of fine rows, and its rows' entries form the contiguous "super-row" srp[Q] ..
+// srp[Q+1] of P^T A.
 //
-// Inner products use a fixed grid, per-block partial sums and the last-arriving
-// block to add the partials in block order: results are identical run to run and
-// never leave the device (the K-cycle reads its scalars from device memory).
+// Row mapping.  A group of G lanes (G | 64) serves one ordinary row, G chosen per
+// level from the mean row length so the column/value streams stay coalesced.
+// Coarse levels of 3D problems contain hub rows with thousands of entries; rows
+// longer than R.lim are cut into chunks of at most kChunk entries, one block per
+// chunk; the last chunk of a row to finish adds the chunk sums in chunk order and
+// runs the row's epilogue.
+//
+// Inner products.  A producing kernel writes one partial sum per block (plus one
+// per hub row) -- no fences; a consumer reduces the partials in a fixed order.  Small
+// partial sets are reduced by every consumer block itself; large ones by one
+// extra block (k_reduce_partials).  Results are identical run to run and never
+// leave the device, so the K-cycle has no host round trip.
 #include "amg_internal.h"
 
 namespace amg {
@@ -38,251 +45,287 @@ __device__ inline double group_sum(double v)
     return v;
 }
 
-// Block partial sums of ND values -> partials[d * gridDim.x + block]; the last
-// block to arrive adds the partials in block order and writes out[0..ND).
-template <int ND>
-__device__ void finish_dots(double (&v)[ND], const DotWork &dw, double *out)
+// Sum over the block; every thread receives the same value (fixed order).
+__device__ inline double block_sum(double v)
 {
-    __shared__ double sh[ND][kBlock / kWave];
-    __shared__ int last;
+    __shared__ double sh[kBlock / kWave];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    v = wave_sum(v);
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double s = 0.0;
 #pragma unroll
-    for (int d = 0; d < ND; d++) {
-        const double s = wave_sum(v[d]);
-        if (lane == 0) sh[d][wid] = s;
-    }
+    for (int w = 0; w < kBlock / kWave; w++) s += sh[w];
     __syncthreads();
-    if (threadIdx.x < ND) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kBlock / kWave; w++) s += sh[threadIdx.x][w];
-        __hip_atomic_store(&dw.partials[threadIdx.x * kMaxDotBlocks + blockIdx.x], s, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = __hip_atomic_fetch_add(dw.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (prev == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    for (int d = wid; d < ND; d += kBlock / kWave) {
-        double s = 0.0;
-        for (int b = lane; b < (int)gridDim.x; b += kWave)
-            s += __hip_atomic_load(&dw.partials[d * kMaxDotBlocks + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s = wave_sum(s);
-        if (lane == 0) out[d] = s;
-    }
-    if (threadIdx.x == 0) __hip_atomic_store(dw.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return s;
 }
 
-template <int G>
-__device__ inline double row_product(const int *__restrict__ rp, const int *__restrict__ ci,
-                                     const double *__restrict__ va, const double *__restrict__ x, int row, int sub)
+// Value of a dot product from its partials (same value in every thread).
+__device__ inline double dot_value(DotRef r)
 {
+    if (r.count == 1) return r.part[0];
     double s = 0.0;
-    const int e = rp[row + 1];
-    for (int p = rp[row] + sub; p < e; p += G) s += va[p] * x[ci[p]];
-    return group_sum<G>(s);
+    for (int b = threadIdx.x; b < r.count; b += kBlock) s += r.part[b];
+    return block_sum(s);
+}
+
+// Writes this block's partials of ND dot products: part[d * kPartStride + block].
+template <int ND>
+__device__ inline void store_partials(const double (&v)[ND], double *part)
+{
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+        const double s = block_sum(v[d]);
+        if (threadIdx.x == 0) part[d * kPartStride + blockIdx.x] = s;
+    }
+}
+
+// Visits every row of R once and calls epi(row, sum, k) with the row's reduced
+// sum; k = -1 for an ordinary row, else the index of the hub row (0 .. nlong).
+// range(beg, end, lane, width) returns one lane's share of entries [beg, end).
+template <int G, class Range, class Epi>
+__device__ inline void visit_rows(const Rows &R, Range range, Epi epi)
+{
+    const int nlb = R.nchunks < kLongBlocks ? R.nchunks : kLongBlocks;
+    if ((int)blockIdx.x < nlb) {
+        for (int c = blockIdx.x; c < R.nchunks; c += nlb) {
+            const Chunk ch = R.chunks[c];
+            const double s = block_sum(range(ch.beg, ch.end, (int)threadIdx.x, kBlock));
+            const int first = R.long_first[ch.k], m = R.long_first[ch.k + 1] - first;
+            if (threadIdx.x == 0) {
+                if (m == 1) {
+                    epi(ch.row, s, ch.k);
+                } else {
+                    __hip_atomic_store(&R.chunk_sum[c], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const unsigned prev =
+                        __hip_atomic_fetch_add(&R.arrive[ch.k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                    if (prev == (unsigned)(m - 1)) {  // last chunk of this row to finish
+                        double t = 0.0;
+                        for (int j = first; j < first + m; j++)
+                            t += __hip_atomic_load(&R.chunk_sum[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&R.arrive[ch.k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        epi(ch.row, t, ch.k);
+                    }
+                }
+            }
+        }
+        return;
+    }
+    const int sub = threadIdx.x % G;
+    const int ngroups = (gridDim.x - nlb) * (kBlock / G);
+    for (int row = ((blockIdx.x - nlb) * kBlock + threadIdx.x) / G; row < R.n; row += ngroups) {
+        const int b = R.ptr[row], e = R.ptr[row + 1];
+        if (e - b > R.lim) continue;  // hub row: served by the chunk blocks (uniform within the group)
+        const double s = group_sum<G>(range(b, e, sub, G));
+        if (sub == 0) epi(row, s, -1);
+    }
 }
 
 // ------------------------------------------------------------------ SpMV family
 
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                 const double *__restrict__ va, const double *__restrict__ x,
-                                                 double *__restrict__ y)
+__global__ void __launch_bounds__(kBlock) k_spmv(Rows R, const int *__restrict__ ci, const double *__restrict__ va,
+                                                 const double *__restrict__ x, double *__restrict__ y)
 {
-    const int sub = threadIdx.x % G;
-    const int ngroups = gridDim.x * (kBlock / G);
-    for (int row = (blockIdx.x * kBlock + threadIdx.x) / G; row < n; row += ngroups) {
-        const double s = row_product<G>(rp, ci, va, x, row, sub);
-        if (sub == 0) y[row] = s;
-    }
+    visit_rows<G>(
+        R,
+        [&](int b, int e, int lane, int width) {
+            double s = 0.0;
+            for (int p = b + lane; p < e; p += width) s += va[p] * x[ci[p]];
+            return s;
+        },
+        [&](int row, double s, int) { y[row] = s; });
 }
 
-template <int G>
-__global__ void __launch_bounds__(kBlock) k_spmv_dot2(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+// y = A x (y may be NULL); dots (x, Ax) and, for each non-NULL w_j, (x, w_j).
+template <int G, int ND>
+__global__ void __launch_bounds__(kBlock) k_spmv_dots(Rows R, const int *__restrict__ ci,
                                                       const double *__restrict__ va, const double *__restrict__ x,
-                                                      double *__restrict__ y, const double *__restrict__ w,
-                                                      DotWork dw, double *__restrict__ out)
+                                                      double *__restrict__ y, const double *__restrict__ w1,
+                                                      const double *__restrict__ w2, double *__restrict__ part)
 {
-    const int sub = threadIdx.x % G;
-    const int ngroups = gridDim.x * (kBlock / G);
-    double d[2] = {0.0, 0.0};
-    for (int row = (blockIdx.x * kBlock + threadIdx.x) / G; row < n; row += ngroups) {
-        const double s = row_product<G>(rp, ci, va, x, row, sub);
-        if (sub == 0) {
-            y[row] = s;
+    double d[ND] = {};
+    const int nb = gridDim.x;
+    visit_rows<G>(
+        R,
+        [&](int b, int e, int lane, int width) {
+            double s = 0.0;
+            for (int p = b + lane; p < e; p += width) s += va[p] * x[ci[p]];
+            return s;
+        },
+        [&](int row, double s, int k) {
+            if (y) y[row] = s;
             const double xr = x[row];
-            d[0] += xr * s;
-            if (w) d[1] += xr * w[row];
-        }
-    }
-    finish_dots<2>(d, dw, out);
+            double t[ND];
+            t[0] = xr * s;
+            if (ND > 1) t[1] = xr * w1[row];
+            if (ND > 2) t[2] = xr * w2[row];
+            if (k < 0) {
+#pragma unroll
+                for (int j = 0; j < ND; j++) d[j] += t[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < ND; j++) part[j * kPartStride + nb + k] = t[j];
+            }
+        });
+    store_partials<ND>(d, part);
 }
 
+// r = b - A x; partials of (b, b) and (r, r)
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_spmv_dot3(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                      const double *__restrict__ va, const double *__restrict__ x,
-                                                      const double *__restrict__ w1, const double *__restrict__ w2,
-                                                      DotWork dw, double *__restrict__ out)
-{
-    const int sub = threadIdx.x % G;
-    const int ngroups = gridDim.x * (kBlock / G);
-    double d[3] = {0.0, 0.0, 0.0};
-    for (int row = (blockIdx.x * kBlock + threadIdx.x) / G; row < n; row += ngroups) {
-        const double s = row_product<G>(rp, ci, va, x, row, sub);
-        if (sub == 0) {
-            const double xr = x[row];
-            d[0] += xr * s;
-            d[1] += xr * w1[row];
-            d[2] += xr * w2[row];
-        }
-    }
-    finish_dots<3>(d, dw, out);
-}
-
-// r = b - A x; out[0] = (b, b), out[1] = (r, r)
-template <int G>
-__global__ void __launch_bounds__(kBlock) k_residual(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+__global__ void __launch_bounds__(kBlock) k_residual(Rows R, const int *__restrict__ ci,
                                                      const double *__restrict__ va, const double *__restrict__ b,
-                                                     const double *__restrict__ x, double *__restrict__ r, DotWork dw,
-                                                     double *__restrict__ out)
+                                                     const double *__restrict__ x, double *__restrict__ r,
+                                                     double *__restrict__ part)
 {
-    const int sub = threadIdx.x % G;
-    const int ngroups = gridDim.x * (kBlock / G);
     double d[2] = {0.0, 0.0};
-    for (int row = (blockIdx.x * kBlock + threadIdx.x) / G; row < n; row += ngroups) {
-        const double s = row_product<G>(rp, ci, va, x, row, sub);
-        if (sub == 0) {
+    const int nb = gridDim.x;
+    visit_rows<G>(
+        R,
+        [&](int beg, int end, int lane, int width) {
+            double s = 0.0;
+            for (int p = beg + lane; p < end; p += width) s += va[p] * x[ci[p]];
+            return s;
+        },
+        [&](int row, double s, int k) {
             const double br = b[row], rr = br - s;
             r[row] = rr;
-            d[0] += br * br;
-            d[1] += rr * rr;
-        }
+            if (k < 0) {
+                d[0] += br * br;
+                d[1] += rr * rr;
+            } else {
+                part[nb + k] = br * br;
+                part[kPartStride + nb + k] = rr * rr;
+            }
+        });
+    store_partials<2>(d, part);
+}
+
+__global__ void __launch_bounds__(kBlock) k_reduce_partials(int nd, const double *__restrict__ part, int count,
+                                                            double *__restrict__ out)
+{
+    for (int d = 0; d < nd; d++) {
+        const double v = dot_value(DotRef{part + d * kPartStride, count});
+        if (threadIdx.x == 0) out[d] = v;
     }
-    finish_dots<2>(d, dw, out);
 }
 
 // ------------------------------------------------------------------ K-cycle pieces
 
-// Pre-smoothing from zero (x = M^-1 r) fused with residual and restriction:
-// rc_Q = sum_{q in G_Q} (r_q - (A x)_q) = sum_{seg} r_q - sum_{super-row} a_e minv_t r_t.
+// Pre-smoothing from zero fused with residual and restriction.  With x = M^-1 r,
+// rc_Q = sum_{q in G_Q} (r - A x)_q = sum_{e in super-row Q} w_e r_{col(e)} where
+// w = P^T (I - A M^-1) is stored per entry (w_e = [diagonal] - a_e minv_col).
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_pre_restrict(int nc, const int *__restrict__ seg_ptr,
-                                                         const int *__restrict__ srp, const int *__restrict__ ci,
-                                                         const double *__restrict__ va,
-                                                         const double *__restrict__ minv,
-                                                         const double *__restrict__ r, double *__restrict__ rc)
+__global__ void __launch_bounds__(kBlock) k_restrict(Rows S, const int *__restrict__ ci,
+                                                     const double *__restrict__ wv, const double *__restrict__ r,
+                                                     double *__restrict__ rc)
 {
-    const int sub = threadIdx.x % G;
-    const int ngroups = gridDim.x * (kBlock / G);
-    for (int Q = (blockIdx.x * kBlock + threadIdx.x) / G; Q < nc; Q += ngroups) {
-        double s = 0.0;
-        const int e = srp[Q + 1];
-        for (int p = srp[Q] + sub; p < e; p += G) {
-            const int t = ci[p];
-            s -= va[p] * (minv[t] * r[t]);
-        }
-        const int qe = seg_ptr[Q + 1];
-        for (int q = seg_ptr[Q] + sub; q < qe; q += G) s += r[q];
-        s = group_sum<G>(s);
-        if (sub == 0) rc[Q] = s;
-    }
+    visit_rows<G>(
+        S,
+        [&](int b, int e, int lane, int width) {
+            double s = 0.0;
+            for (int p = b + lane; p < e; p += width) s += wv[p] * r[ci[p]];
+            return s;
+        },
+        [&](int Q, double s, int) { rc[Q] = s; });
 }
 
-// K-cycle coefficients.  d = [rho1, alpha1, beta, gamma, alpha2] with
-// rho1 = (c1, A c1), alpha1 = (c1, rc), beta = (c2, A c2), gamma = (c2, A c1),
-// alpha2 = (c2, rt): two flexible-CG steps from zero give
+// K-cycle coefficients.  rho1 = (c1, A c1), alpha1 = (c1, rc), beta = (c2, A c2),
+// gamma = (c2, A c1), alpha2 = (c2, rt): two flexible-CG steps from zero give
 // e = (alpha1/rho1 - (gamma/rho1)(alpha2/rho2)) c1 + (alpha2/rho2) c2,
-// rho2 = beta - gamma^2/rho1.  A non-positive rho means A is not SPD: flag it and
-// drop the correction.
-__device__ inline void kcycle_coefficients(int mode, const double *__restrict__ d, double &a1, double &a2, bool &bad)
+// rho2 = beta - gamma^2/rho1.  A non-positive rho means A is not SPD: the flag is
+// raised and the correction dropped.
+struct KCoef {
+    double a1, a2;
+    bool bad;
+};
+
+__device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd)
 {
-    a1 = 0.0;
-    a2 = 0.0;
-    bad = false;
-    if (mode == 0) return;
-    const double rho1 = d[0];
+    KCoef c{0.0, 0.0, false};
+    if (mode == 0) return c;
+    const double rho1 = dot_value(kd.rho1), alpha1 = dot_value(kd.alpha1);
+    double beta = 0.0, gamma = 0.0, alpha2 = 0.0;
+    if (mode == 2) {
+        beta = dot_value(kd.beta);
+        gamma = dot_value(kd.gamma);
+        alpha2 = dot_value(kd.alpha2);
+    }
     if (!(rho1 > 0.0)) {
-        bad = true;
-        return;
+        c.bad = true;
+        return c;
     }
-    const double q1 = d[1] / rho1;
-    if (mode == 1) {
-        a1 = q1;
-        return;
-    }
-    const double g1 = d[3] / rho1;
-    const double rho2 = d[2] - d[3] * g1;
+    const double q1 = alpha1 / rho1;
+    c.a1 = q1;
+    if (mode == 1) return c;
+    const double g1 = gamma / rho1;
+    const double rho2 = beta - gamma * g1;
     if (!(rho2 > 0.0)) {
-        bad = true;
-        a1 = q1;
-        return;
+        c.bad = true;
+        return c;
     }
-    a2 = d[4] / rho2;
-    a1 = q1 - g1 * a2;
+    c.a2 = alpha2 / rho2;
+    c.a1 = q1 - g1 * c.a2;
+    return c;
 }
 
+// rt = rc - (alpha1/rho1) v1
 __global__ void __launch_bounds__(kBlock) k_inner_residual(int n, const double *__restrict__ rc,
-                                                           const double *__restrict__ v1,
-                                                           const double *__restrict__ d, double *__restrict__ rt,
-                                                           int *__restrict__ flag)
+                                                           const double *__restrict__ v1, KDots kd,
+                                                           double *__restrict__ rt, int *__restrict__ flag)
 {
-    const double rho1 = d[0];
-    const bool bad = !(rho1 > 0.0);
-    const double s = bad ? 0.0 : d[1] / rho1;
-    if (bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) rt[i] = rc[i] - s * v1[i];
+    const KCoef c = kcycle_coefficients(1, kd);
+    if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) rt[i] = rc[i] - c.a1 * v1[i];
 }
 
-// Prolongation + post-smoothing (Alg. 1 lines "prolongation", "post-smoothing"):
-// x = M^-1 r + P e (the pre-smoothed iterate plus the coarse correction) is formed
-// on the fly for every column, then out = x + M^-1 (r - A x).
+// Prolongation + post-smoothing: x = M^-1 r + P e (the pre-smoothed iterate plus
+// the coarse correction) is formed on the fly for every column, then
+// out = x + M^-1 (r - A x).  mode 0: e = edirect; mode 1: e = a1 c1;
+// mode 2: e = a1 c1 + a2 c2.  DOT adds partials of (out, wdot).
 template <int G, int MODE, bool DOT>
-__global__ void __launch_bounds__(kBlock) k_post_smooth(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+__global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__restrict__ ci,
                                                         const double *__restrict__ va,
                                                         const double *__restrict__ minv,
                                                         const double *__restrict__ r,
                                                         const int *__restrict__ agg_pos,
                                                         const double *__restrict__ edirect,
                                                         const double *__restrict__ c1,
-                                                        const double *__restrict__ c2, const double *__restrict__ d,
+                                                        const double *__restrict__ c2, KDots kd,
                                                         double *__restrict__ xout, const double *__restrict__ wdot,
-                                                        DotWork dw, double *__restrict__ out_dot)
+                                                        double *__restrict__ part, int *__restrict__ flag)
 {
-    double a1 = 0.0, a2 = 0.0;
-    bool bad = false;
-    if (MODE != 0) kcycle_coefficients(MODE, d, a1, a2, bad);
-    if (bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(dw.flag, 1);
+    const KCoef c = kcycle_coefficients(MODE, kd);
+    if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
+    const double a1 = c.a1, a2 = c.a2;
     auto corr = [&](int J) -> double {
         if (MODE == 0) return edirect[J];
         if (MODE == 1) return a1 * c1[J];
         return a1 * c1[J] + a2 * c2[J];
     };
-    const int sub = threadIdx.x % G;
-    const int ngroups = gridDim.x * (kBlock / G);
     double dsum[1] = {0.0};
-    for (int row = (blockIdx.x * kBlock + threadIdx.x) / G; row < n; row += ngroups) {
-        double s = 0.0;
-        const int e = rp[row + 1];
-        for (int p = rp[row] + sub; p < e; p += G) {
-            const int t = ci[p];
-            s += va[p] * (minv[t] * r[t] + corr(agg_pos[t]));
-        }
-        s = group_sum<G>(s);
-        if (sub == 0) {
+    const int nb = gridDim.x;
+    visit_rows<G>(
+        R,
+        [&](int b, int e, int lane, int width) {
+            double s = 0.0;
+            for (int p = b + lane; p < e; p += width) {
+                const int t = ci[p];
+                s += va[p] * (minv[t] * r[t] + corr(agg_pos[t]));
+            }
+            return s;
+        },
+        [&](int row, double s, int k) {
             const double mr = minv[row], rr = r[row];
             const double x = mr * rr + corr(agg_pos[row]);
             const double o = x + mr * (rr - s);
             xout[row] = o;
-            if (DOT) dsum[0] += o * wdot[row];
-        }
-    }
-    if (DOT) finish_dots<1>(dsum, dw, out_dot);
+            if (DOT) {
+                if (k < 0) dsum[0] += o * wdot[row];
+                else part[nb + k] = o * wdot[row];
+            }
+        });
+    if (DOT) store_partials<1>(dsum, part);
 }
 
 // y = A x for a dense row-major n x n matrix: one wavefront per row.
@@ -302,16 +345,16 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemv(int n, const double *__re
 
 // ------------------------------------------------------------------ outer flexible CG
 
-// alpha = (p, r) / (p, A p); x += alpha p; r -= alpha q; out = (r, r)
-__global__ void __launch_bounds__(kBlock) k_fcg_update(int n, const double *__restrict__ pq_pr,
-                                                       double *__restrict__ x, double *__restrict__ r,
-                                                       const double *__restrict__ p, const double *__restrict__ q,
-                                                       DotWork dw, double *__restrict__ out)
+// alpha = (p, r) / (p, A p); x += alpha p; r -= alpha q; partials of (r, r)
+__global__ void __launch_bounds__(kBlock) k_fcg_update(int n, DotRef pq, DotRef pr, double *__restrict__ x,
+                                                       double *__restrict__ r, const double *__restrict__ p,
+                                                       const double *__restrict__ q, double *__restrict__ part,
+                                                       int *__restrict__ flag)
 {
-    const double pq = pq_pr[0];
-    const bool bad = !(pq > 0.0);
-    const double alpha = bad ? 0.0 : pq_pr[1] / pq;
-    if (bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(dw.flag, 1);
+    const double vpq = dot_value(pq), vpr = dot_value(pr);
+    const bool bad = !(vpq > 0.0);
+    const double alpha = bad ? 0.0 : vpr / vpq;
+    if (bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
     double d[1] = {0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         x[i] += alpha * p[i];
@@ -319,27 +362,26 @@ __global__ void __launch_bounds__(kBlock) k_fcg_update(int n, const double *__re
         r[i] = ri;
         d[0] += ri * ri;
     }
-    finish_dots<1>(d, dw, out);
+    store_partials<1>(d, part);
 }
 
 // beta = -(z, A p) / (p, A p); p = z + beta p
-__global__ void __launch_bounds__(kBlock) k_fcg_direction(int n, const double *__restrict__ pq,
-                                                          const double *__restrict__ zq,
-                                                          const double *__restrict__ z, double *__restrict__ p,
-                                                          int *__restrict__ flag)
+__global__ void __launch_bounds__(kBlock) k_fcg_direction(int n, DotRef pq, DotRef zq, const double *__restrict__ z,
+                                                          double *__restrict__ p, int *__restrict__ flag)
 {
-    const bool bad = !(pq[0] > 0.0);
-    const double beta = bad ? 0.0 : -zq[0] / pq[0];
+    const double vpq = dot_value(pq), vzq = dot_value(zq);
+    const bool bad = !(vpq > 0.0);
+    const double beta = bad ? 0.0 : -vzq / vpq;
     if (bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i] + beta * p[i];
 }
 
 __global__ void __launch_bounds__(kBlock) k_dot(int n, const double *__restrict__ a, const double *__restrict__ b,
-                                                DotWork dw, double *__restrict__ out)
+                                                double *__restrict__ part)
 {
     double d[1] = {0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) d[0] += a[i] * b[i];
-    finish_dots<1>(d, dw, out);
+    store_partials<1>(d, part);
 }
 
 __global__ void __launch_bounds__(kBlock) k_gather(int n, const double *__restrict__ src, const int *__restrict__ idx,
@@ -354,20 +396,62 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int n, const double *__restr
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[idx[i]] = src[i];
 }
 
+// w_e = [col(e) is the row's diagonal] - a_e minv_col(e) for every entry (solve layout)
+__global__ void __launch_bounds__(kBlock) k_restriction_weights(int n, const int *__restrict__ rp,
+                                                                const int *__restrict__ ci,
+                                                                const double *__restrict__ va,
+                                                                const double *__restrict__ minv,
+                                                                double *__restrict__ wv)
+{
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    for (int p = rp[q]; p < rp[q + 1]; p++) {
+        const int t = ci[p];
+        wv[p] = (t == q ? 1.0 : 0.0) - va[p] * minv[t];
+    }
+}
+
+inline int rows_grid(const Rows &R, int G, int cap)
+{
+    const int nlb = R.nchunks < kLongBlocks ? R.nchunks : kLongBlocks;
+    return nlb + grid_for((int64_t)R.n * G, cap - nlb);
+}
+
+// Partial sets larger than this are reduced by one extra block instead of by
+// every consumer block.
+constexpr int kConsumerReduceMax = 96;
+
+void reduce_if_large(int nd, double *part, int count, double *final_out, hipStream_t s)
+{
+    if (count > kConsumerReduceMax && final_out) {
+        k_reduce_partials<<<1, kBlock, 0, s>>>(nd, part, count, final_out);
+        AMG_HIP(hipGetLastError());
+    }
+}
+
+DotRef finished(double *part, int count, double *final_out, int d)
+{
+    if (count <= kConsumerReduceMax || final_out == nullptr) return DotRef{part + d * kPartStride, count};
+    return DotRef{final_out + d, 1};
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
 
-int lanes_for(double avg_row_len)
+int lanes_for(double avg_row_len, int n)
 {
-    int g = 2;
-    while (g < avg_row_len && g < kWave) g <<= 1;
+    // largest power of two not above the mean row length; at least 8 lanes on
+    // small (latency-bound) levels so that ordinary rows take one step
+    int g = 1;
+    while (2 * g <= avg_row_len && g < kWave) g <<= 1;
+    if (n < kSmallLevel && g < 8) g = 8;
+    if (g < 2) g = 2;
     return g;
 }
 
 #define AMG_SWITCH_G(G, BODY)                          \
     switch (G) {                                       \
-    case 1: { constexpr int kG = 1; BODY; } break;     \
     case 2: { constexpr int kG = 2; BODY; } break;     \
     case 4: { constexpr int kG = 4; BODY; } break;     \
     case 8: { constexpr int kG = 8; BODY; } break;     \
@@ -376,63 +460,74 @@ int lanes_for(double avg_row_len)
     default: { constexpr int kG = 64; BODY; } break;   \
     }
 
-void launch_spmv(int n, const int *rp, const int *ci, const double *va, const double *x, double *y, int G,
-                 hipStream_t s)
+void launch_spmv(Rows R, const int *ci, const double *va, const double *x, double *y, int G, hipStream_t s)
 {
-    const int grid = grid_for((int64_t)n * G);
-    AMG_SWITCH_G(G, (k_spmv<kG><<<grid, kBlock, 0, s>>>(n, rp, ci, va, x, y)));
+    const int grid = rows_grid(R, G, 1 << 20);
+    AMG_SWITCH_G(G, (k_spmv<kG><<<grid, kBlock, 0, s>>>(R, ci, va, x, y)));
     AMG_HIP(hipGetLastError());
 }
 
-void launch_spmv_dot2(int n, const int *rp, const int *ci, const double *va, const double *x, double *y,
-                      const double *w, int G, DotWork dw, double *out, hipStream_t s)
+DotSet launch_spmv_dots(Rows R, const int *ci, const double *va, const double *x, double *y, const double *w1,
+                        const double *w2, int G, DotBuf buf, hipStream_t s)
 {
-    const int grid = grid_for((int64_t)n * G, kMaxDotBlocks);
-    AMG_SWITCH_G(G, (k_spmv_dot2<kG><<<grid, kBlock, 0, s>>>(n, rp, ci, va, x, y, w, dw, out)));
+    const int grid = rows_grid(R, G, kMaxDotBlocks);
+    const int nd = w2 ? 3 : (w1 ? 2 : 1);
+    if (nd == 1) {
+        AMG_SWITCH_G(G, (k_spmv_dots<kG, 1><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, buf.part)));
+    } else if (nd == 2) {
+        AMG_SWITCH_G(G, (k_spmv_dots<kG, 2><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, buf.part)));
+    } else {
+        AMG_SWITCH_G(G, (k_spmv_dots<kG, 3><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, buf.part)));
+    }
+    AMG_HIP(hipGetLastError());
+    const int count = grid + R.nlong;
+    reduce_if_large(nd, buf.part, count, buf.final_out, s);
+    DotSet out{};
+    for (int d = 0; d < nd; d++) out.d[d] = finished(buf.part, count, buf.final_out, d);
+    return out;
+}
+
+DotSet launch_residual(Rows R, const int *ci, const double *va, const double *b, const double *x, double *r, int G,
+                       DotBuf buf, hipStream_t s)
+{
+    const int grid = rows_grid(R, G, kMaxDotBlocks);
+    AMG_SWITCH_G(G, (k_residual<kG><<<grid, kBlock, 0, s>>>(R, ci, va, b, x, r, buf.part)));
+    AMG_HIP(hipGetLastError());
+    const int count = grid + R.nlong;
+    reduce_if_large(2, buf.part, count, buf.final_out, s);
+    DotSet out{};
+    for (int d = 0; d < 2; d++) out.d[d] = finished(buf.part, count, buf.final_out, d);
+    return out;
+}
+
+void launch_reduce(const DotRef &ref, double *out, hipStream_t s)
+{
+    k_reduce_partials<<<1, kBlock, 0, s>>>(1, ref.part, ref.count, out);
     AMG_HIP(hipGetLastError());
 }
 
-void launch_spmv_dot3(int n, const int *rp, const int *ci, const double *va, const double *x, const double *w1,
-                      const double *w2, int G, DotWork dw, double *out, hipStream_t s)
+void launch_restrict(Rows S, const int *ci, const double *wv, const double *r, double *rc, int G, hipStream_t s)
 {
-    const int grid = grid_for((int64_t)n * G, kMaxDotBlocks);
-    AMG_SWITCH_G(G, (k_spmv_dot3<kG><<<grid, kBlock, 0, s>>>(n, rp, ci, va, x, w1, w2, dw, out)));
+    const int grid = rows_grid(S, G, 1 << 20);
+    AMG_SWITCH_G(G, (k_restrict<kG><<<grid, kBlock, 0, s>>>(S, ci, wv, r, rc)));
     AMG_HIP(hipGetLastError());
 }
 
-void launch_residual(int n, const int *rp, const int *ci, const double *va, const double *b, const double *x,
-                     double *r, int G, DotWork dw, double *out, hipStream_t s)
+void launch_inner_residual(int n, const double *rc, const double *v1, KDots kd, double *rt, int *flag, hipStream_t s)
 {
-    const int grid = grid_for((int64_t)n * G, kMaxDotBlocks);
-    AMG_SWITCH_G(G, (k_residual<kG><<<grid, kBlock, 0, s>>>(n, rp, ci, va, b, x, r, dw, out)));
+    k_inner_residual<<<grid_for(n, 4096), kBlock, 0, s>>>(n, rc, v1, kd, rt, flag);
     AMG_HIP(hipGetLastError());
 }
 
-void launch_pre_restrict(int nc, const int *seg_ptr, const int *srp, const int *ci, const double *va,
-                         const double *minv, const double *r, double *rc, int G, hipStream_t s)
-{
-    const int grid = grid_for((int64_t)nc * G);
-    AMG_SWITCH_G(G, (k_pre_restrict<kG><<<grid, kBlock, 0, s>>>(nc, seg_ptr, srp, ci, va, minv, r, rc)));
-    AMG_HIP(hipGetLastError());
-}
-
-void launch_inner_residual(int n, const double *rc, const double *v1, const double *d, double *rt, int *flag,
-                           hipStream_t s)
-{
-    k_inner_residual<<<grid_for(n, 4096), kBlock, 0, s>>>(n, rc, v1, d, rt, flag);
-    AMG_HIP(hipGetLastError());
-}
-
-void launch_post_smooth(int n, const int *rp, const int *ci, const double *va, const double *minv, const double *r,
-                        const int *agg_pos, int mode, const double *edirect, const double *c1, const double *c2,
-                        const double *d, double *xout, const double *wdot, DotWork dw, double *out_dot, int G,
-                        hipStream_t s)
+DotRef launch_post_smooth(Rows R, const int *ci, const double *va, const double *minv, const double *r,
+                          const int *agg_pos, int mode, const double *edirect, const double *c1, const double *c2,
+                          KDots kd, double *xout, const double *wdot, DotBuf buf, int *flag, int G, hipStream_t s)
 {
     const bool dot = wdot != nullptr;
-    const int grid = grid_for((int64_t)n * G, dot ? kMaxDotBlocks : (1 << 20));
-#define AMG_POST(M, D)                                                                                        \
-    AMG_SWITCH_G(G, (k_post_smooth<kG, M, D><<<grid, kBlock, 0, s>>>(n, rp, ci, va, minv, r, agg_pos, edirect, \
-                                                                      c1, c2, d, xout, wdot, dw, out_dot)))
+    const int grid = rows_grid(R, G, dot ? kMaxDotBlocks : (1 << 20));
+#define AMG_POST(M, D)                                                                                      \
+    AMG_SWITCH_G(G, (k_post_smooth<kG, M, D><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, agg_pos, edirect, \
+                                                                      c1, c2, kd, xout, wdot, buf.part, flag)))
     if (mode == 0) {
         if (dot) { AMG_POST(0, true); } else { AMG_POST(0, false); }
     } else if (mode == 1) {
@@ -442,6 +537,10 @@ void launch_post_smooth(int n, const int *rp, const int *ci, const double *va, c
     }
 #undef AMG_POST
     AMG_HIP(hipGetLastError());
+    if (!dot) return DotRef{nullptr, 0};
+    const int count = grid + R.nlong;
+    reduce_if_large(1, buf.part, count, buf.final_out, s);
+    return finished(buf.part, count, buf.final_out, 0);
 }
 
 void launch_dense_gemv(int n, const double *a, const double *x, double *y, hipStream_t s)
@@ -450,24 +549,29 @@ void launch_dense_gemv(int n, const double *a, const double *x, double *y, hipSt
     AMG_HIP(hipGetLastError());
 }
 
-void launch_fcg_update(int n, const double *pq_pr, double *x, double *r, const double *p, const double *q,
-                       DotWork dw, double *out, hipStream_t s)
+DotRef launch_fcg_update(int n, DotRef pq, DotRef pr, double *x, double *r, const double *p, const double *q,
+                         DotBuf buf, int *flag, hipStream_t s)
 {
-    k_fcg_update<<<grid_for(n, kMaxDotBlocks), kBlock, 0, s>>>(n, pq_pr, x, r, p, q, dw, out);
+    const int grid = grid_for(n, kMaxDotBlocks);
+    k_fcg_update<<<grid, kBlock, 0, s>>>(n, pq, pr, x, r, p, q, buf.part, flag);
     AMG_HIP(hipGetLastError());
+    reduce_if_large(1, buf.part, grid, buf.final_out, s);
+    return finished(buf.part, grid, buf.final_out, 0);
 }
 
-void launch_fcg_direction(int n, const double *pq, const double *zq, const double *z, double *p, int *flag,
-                          hipStream_t s)
+void launch_fcg_direction(int n, DotRef pq, DotRef zq, const double *z, double *p, int *flag, hipStream_t s)
 {
     k_fcg_direction<<<grid_for(n, 4096), kBlock, 0, s>>>(n, pq, zq, z, p, flag);
     AMG_HIP(hipGetLastError());
 }
 
-void launch_dot(int n, const double *a, const double *b, DotWork dw, double *out, hipStream_t s)
+DotRef launch_dot(int n, const double *a, const double *b, DotBuf buf, hipStream_t s)
 {
-    k_dot<<<grid_for(n, kMaxDotBlocks), kBlock, 0, s>>>(n, a, b, dw, out);
+    const int grid = grid_for(n, kMaxDotBlocks);
+    k_dot<<<grid, kBlock, 0, s>>>(n, a, b, buf.part);
     AMG_HIP(hipGetLastError());
+    reduce_if_large(1, buf.part, grid, buf.final_out, s);
+    return finished(buf.part, grid, buf.final_out, 0);
 }
 
 void launch_gather(int n, const double *src, const int *idx, double *dst, hipStream_t s)
@@ -479,6 +583,13 @@ void launch_gather(int n, const double *src, const int *idx, double *dst, hipStr
 void launch_scatter(int n, const double *src, const int *idx, double *dst, hipStream_t s)
 {
     k_scatter<<<grid_for(n, 4096), kBlock, 0, s>>>(n, src, idx, dst);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_restriction_weights(int n, const int *rp, const int *ci, const double *va, const double *minv, double *wv,
+                                hipStream_t s)
+{
+    k_restriction_weights<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, va, minv, wv);
     AMG_HIP(hipGetLastError());
 }
 

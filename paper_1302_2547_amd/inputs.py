@@ -85,31 +85,36 @@ def grid_laplacian(dims, jitter: float = 0.0, seed: int = 0, bc: str = "dirichle
     # weights of the edge in direction a from each node to its +a neighbour (and -a)
     w_plus = [weight(ext_index, a) for a in range(d)]
     w_minus = [weight(ext_index - ext_stride[a], a) for a in range(d)]
+    valid_minus = [coords[a] > 0 for a in range(d)]
+    valid_plus = [coords[a] < dims[a] - 1 for a in range(d)]
+    # slots in ascending column order: -z, -y, -x, diagonal, +x, +y, +z
+    slots = [(valid_minus[a], -stride[a], w_minus[a]) for a in reversed(range(d))] + [None] + \
+            [(valid_plus[a], stride[a], w_plus[a]) for a in range(d)]
+    # diagonal: incident edge weights added in slot order (boundary edges only for Dirichlet)
     diag = np.zeros(n)
-    slots = []  # (valid mask, column, value), in ascending column order
-    for a in reversed(range(d)):  # -z, -y, -x
-        valid = coords[a] > 0
-        if bc == "dirichlet":
-            diag += w_minus[a]
-        else:
-            diag += np.where(valid, w_minus[a], 0.0)
-        slots.append((valid, np.arange(n) - stride[a], -w_minus[a]))
-    slots.append(None)  # diagonal
-    for a in range(d):  # +x, +y, +z
-        valid = coords[a] < dims[a] - 1
-        if bc == "dirichlet":
-            diag += w_plus[a]
-        else:
-            diag += np.where(valid, w_plus[a], 0.0)
-        slots.append((valid, np.arange(n) + stride[a], -w_plus[a]))
-    all_valid = np.stack([np.ones(n, bool) if s is None else s[0] for s in slots], axis=1)
-    all_col = np.stack([np.arange(n) if s is None else s[1] for s in slots], axis=1)
-    all_val = np.stack([diag if s is None else s[2] for s in slots], axis=1)
-    counts = all_valid.sum(axis=1)
+    counts = np.ones(n, np.int64)
+    for slot in slots:
+        if slot is not None:
+            m, _, w = slot
+            diag += w if bc == "dirichlet" else np.where(m, w, 0.0)
+            counts += m
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
-    col = all_col[all_valid].astype(np.int32)
-    val = all_val[all_valid].astype(np.float64)
+    col = np.empty(int(row_ptr[-1]), np.int32)
+    val = np.empty(int(row_ptr[-1]), np.float64)
+    cursor = row_ptr[:-1].copy()
+    ids = np.arange(n, dtype=np.int32)
+    for slot in slots:
+        if slot is None:
+            col[cursor] = ids
+            val[cursor] = diag
+            cursor += 1
+            continue
+        m, off, w = slot
+        at = cursor[m]
+        col[at] = ids[m] + off
+        val[at] = -w[m]
+        cursor[m] += 1
     return row_ptr.astype(np.int32), col, val
 
 

@@ -112,3 +112,128 @@ def test_spmv_and_kcycle_match_oracle(amg):
     h.kcycle(dev(xv), z)
     zo = ref.kcycle(xv)
     np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-10 * np.abs(zo).max())
+
+
+def hub_graph(n=6000, seed=9):
+    """Graph Laplacian with a hub joined to every vertex plus a ring: row 0 has n
+    entries (several chunks of the hub-row path) on the finest level."""
+    hub = np.zeros(n - 1, np.int64)
+    leaves = np.arange(1, n)
+    ring_a = np.arange(1, n)
+    ring_b = np.roll(ring_a, -1)
+    i = np.concatenate([hub, ring_a])
+    j = np.concatenate([leaves, ring_b])
+    w = 0.5 + inputs.uniform(seed, np.arange(len(i), dtype=np.uint64))
+    a = {}
+    for u, v, wt in zip(i.tolist(), j.tolist(), w.tolist()):
+        a[(min(u, v), max(u, v))] = wt
+    rows, cols, vals = [], [], []
+    diag = np.full(n, 1e-3)
+    for (u, v), wt in a.items():
+        rows += [u, v]
+        cols += [v, u]
+        vals += [-wt, -wt]
+        diag[u] += wt
+        diag[v] += wt
+    rows += list(range(n))
+    cols += list(range(n))
+    vals += diag.tolist()
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = np.array(rows)[order], np.array(cols)[order], np.array(vals)[order]
+    rp = np.zeros(n + 1, np.int32)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    return rp, cols.astype(np.int32), vals
+
+
+def test_hub_rows_chunked(amg):
+    rp, ci, va = hub_graph()
+    assert np.diff(rp).max() == 6000
+    n = len(rp) - 1
+    h, ref = setup_both(amg, rp, ci, va, coarsest_size=16)
+    assert_same_hierarchy(h, ref)
+    xv = inputs.rhs(n, 5)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.kcycle(dev(xv), z)
+    zo = ref.kcycle(xv)
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-10 * np.abs(zo).max())
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, info = h.solve(dev(xv), x, tol=1e-10)
+    r = xv - oracle.spmv(rp, ci, va, x.cpu().numpy())
+    assert st == amg.AMG_OK and np.linalg.norm(r) / np.linalg.norm(xv) <= 1e-10
+
+
+def test_graph_replay_matches_eager(amg):
+    rp, ci, va = CASES["grid3d_24_jitter"]()
+    n = len(rp) - 1
+    b = dev(inputs.rhs(n, 21))
+    hg = amg.Hierarchy(dev(rp), dev(ci), dev(va), use_graph=1)
+    he = amg.Hierarchy(dev(rp), dev(ci), dev(va), use_graph=0)
+    ref_x, ref_it = None, None
+    for rep in range(3):  # graph replays with eager work in between
+        for h in (he, hg):
+            x = torch.zeros(n, dtype=torch.float64, device="cuda")
+            st, info = h.solve(b, x, tol=1e-9)
+            assert st == amg.AMG_OK
+            xs = x.cpu().numpy()
+            if ref_x is None:
+                ref_x, ref_it = xs, info.iterations
+            assert info.iterations == ref_it
+            np.testing.assert_array_equal(xs, ref_x)  # deterministic reductions: bitwise equal
+            y = torch.empty(n, dtype=torch.float64, device="cuda")
+            h.spmv(0, x, y)  # eager work between replays
+
+
+def test_error_statuses(amg):
+    rp, ci, va = inputs.grid_laplacian((16, 16))
+    n = len(rp) - 1
+    # unsorted columns -> invalid matrix
+    bad = ci.copy()
+    bad[1], bad[2] = bad[2], bad[1]
+    with pytest.raises(amg.AmgError) as e:
+        amg.Hierarchy(dev(rp), dev(bad), dev(va))
+    assert e.value.status == amg.AMG_ERR_INVALID_MATRIX
+    # non-positive diagonal
+    vb = va.copy()
+    vb[np.nonzero(ci == 0)[0][0]] = -1.0
+    with pytest.raises(amg.AmgError) as e:
+        amg.Hierarchy(dev(rp), dev(ci), dev(vb))
+    assert e.value.status == amg.AMG_ERR_INVALID_MATRIX
+    # memory budget too small
+    with pytest.raises(amg.AmgError) as e:
+        amg.Hierarchy(dev(rp), dev(ci), dev(va), mem_budget=4096)
+    assert e.value.status == amg.AMG_ERR_OUT_OF_MEMORY
+    h = amg.Hierarchy(dev(rp), dev(ci), dev(va), coarsest_size=8, max_iters=1)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, info = h.solve(dev(inputs.rhs(n, 1)), x, tol=1e-12, raise_on_error=False)
+    assert st == amg.AMG_ERR_NOT_CONVERGED and info.iterations == 1 and info.rel_residual > 1e-12
+    st, info = h.solve(torch.zeros(n, dtype=torch.float64, device="cuda"), x, raise_on_error=False)
+    assert st == amg.AMG_OK and info.iterations == 0 and not x.any()
+    bnan = dev(inputs.rhs(n, 1))
+    bnan[3] = float("nan")
+    st, info = h.solve(bnan, x, raise_on_error=False)
+    assert st == amg.AMG_ERR_INVALID_ARGUMENT
+    # indefinite matrix with positive diagonal: setup or solve reports the breakdown
+    vi = va.copy()
+    vi[ci == np.repeat(np.arange(n), np.diff(rp))] -= 1.0
+    try:
+        hi = amg.Hierarchy(dev(rp), dev(ci), dev(vi), coarsest_size=8)
+    except amg.AmgError as err:
+        assert err.status == amg.AMG_ERR_BREAKDOWN
+    else:
+        st, info = hi.solve(dev(inputs.rhs(n, 2)), x, tol=1e-10, raise_on_error=False)
+        assert st == amg.AMG_ERR_BREAKDOWN
+
+
+@pytest.mark.parametrize("opt", [dict(coarsest_size=1000), dict(kcycle_inner=1), dict(max_levels=2)])
+def test_option_variants_solve(amg, opt):
+    rp, ci, va = CASES["grid2d_77x50_jitter"]()
+    n = len(rp) - 1
+    b = inputs.rhs(n, 4)
+    h, ref = setup_both(amg, rp, ci, va, **opt)
+    assert_same_hierarchy(h, ref)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, info = h.solve(dev(b), x, tol=1e-9)
+    _, st_o, it_o, _, _ = ref.solve(b, tol=1e-9)
+    r = b - oracle.spmv(rp, ci, va, x.cpu().numpy())
+    assert st == amg.AMG_OK and np.linalg.norm(r) / np.linalg.norm(b) <= 1e-9
+    assert abs(info.iterations - it_o) <= 2
