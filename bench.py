@@ -36,11 +36,79 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--smoother-reps", type=int, default=50)
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "post_smooth_128cubed_traffic.json"))
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="launch a 256 MiB copy and the finest post-smoother only (run under rocprofv3 --pmc)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="turn two rocprofv3 --pmc databases of --traffic-probe into --traffic-file")
     return ap.parse_args()
+
+
+COPY_BYTES = 1 << 28  # 256 MiB read + 256 MiB written by the reference copy
+
+
+def traffic_probe(args):
+    """Reference copy of known size, then the dominant kernel, for PMC counting."""
+    import torch
+
+    from paper_1302_2547_amd import amg, inputs
+    dev = torch.device("cuda:0")
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    N = args.grid
+    rp, ci, va = inputs.grid_laplacian((N, N, N), jitter=0.1, seed=2)
+    b = inputs.rhs(len(rp) - 1, 1)
+    t = lambda a: torch.from_numpy(a).to(dev)
+    h = amg.Hierarchy(t(rp), t(ci), t(va))
+    x = torch.zeros(len(b), dtype=torch.float64, device=dev)
+    h.solve(t(b), x, tol=args.tol)
+    us, alg = h.time_smoother(5)
+    print(json.dumps({"probe": "done", "avg_us": us, "alg_bytes": alg}), flush=True)
+
+
+def traffic_from(args):
+    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the post-smoother by the
+    ratio the same counters show for the reference copy of known size."""
+    import sqlite3
+
+    def per_kernel(db, counter):
+        con = sqlite3.connect(db)
+        out = {}
+        for kname, cname, val in con.execute("select kernel_name, counter_name, value from counters_collection"):
+            if cname == counter:
+                out.setdefault(kname, []).append(val)
+        return out
+
+    fetch = per_kernel(args.traffic_from[0], "FETCH_SIZE")
+    write = per_kernel(args.traffic_from[1], "WRITE_SIZE")
+    pick = lambda d, key: [v for k, vs in d.items() if key(k) for v in vs]
+    copy_f = pick(fetch, lambda k: "copy" in k.lower() or "elementwise" in k.lower())
+    copy_w = pick(write, lambda k: "copy" in k.lower() or "elementwise" in k.lower())
+    post_f = pick(fetch, lambda k: "k_post_smooth" in k)
+    post_w = pick(write, lambda k: "k_post_smooth" in k)
+    med = lambda v: sorted(v)[len(v) // 2]
+    f_scale = COPY_BYTES / (med(copy_f) * 1024.0)
+    w_scale = COPY_BYTES / (med(copy_w) * 1024.0)
+    fetch_b = med(post_f) * 1024.0 * f_scale
+    write_b = med(post_w) * 1024.0 * w_scale
+    out = {"grid": args.grid, "kernel": "k_post_smooth (finest level)",
+           "fetch_kib_per_dispatch": med(post_f), "write_kib_per_dispatch": med(post_w),
+           "copy_fetch_kib": med(copy_f), "copy_write_kib": med(copy_w),
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "bytes_per_launch": fetch_b + write_b, "fetch_bytes": fetch_b, "write_bytes": write_b}
+    with open(args.traffic_file, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def main():
     args = parse()
+    if args.traffic_probe:
+        return traffic_probe(args)
+    if args.traffic_from:
+        return traffic_from(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))

@@ -14,7 +14,7 @@ namespace amg {
 
 constexpr int kWave = 64;    // CDNA wavefront width
 constexpr int kBlock = 256;  // threads per block for every kernel below
-constexpr int kMaxDotBlocks = 2048;
+constexpr int kMaxDotBlocks = 1 << 15;  // grid cap of kernels that write dot partials
 constexpr int kMaxDots = 5;
 
 struct Error : std::runtime_error {
@@ -35,7 +35,8 @@ void hip_check(hipError_t e, const char *what);
 constexpr int kChunk = 1024;
 constexpr int kLongBlocks = 1024;  // blocks that serve chunks
 constexpr int kMaxLong = 2048;     // hub rows per operator (the threshold is raised beyond)
-constexpr int kSmallLevel = 100000;
+constexpr int kSmallLevel = 100000;  // levels below this are latency-bound
+constexpr int kInlineCoarse = 64;    // coarsest levels up to this size are solved inside the post-smoother
 constexpr int kPartStride = kMaxDotBlocks + kMaxLong;
 
 struct Chunk {
@@ -82,8 +83,9 @@ void scan_exclusive(const int *in, int *out, int64_t n, int *total_dev, int *tmp
 void launch_validate_csr(int n, int nnz, const int *rp, const int *ci, const double *va, int *err, hipStream_t s);
 void launch_l1_inverse_diagonal(int n, const int *rp, const int *ci, const double *va, double *minv, hipStream_t s);
 void launch_priorities(int n, const int *rp, uint32_t s_l, uint64_t *key, int *owner, hipStream_t s);
+// one pass of Alg. 2; rows longer than lim (listed in hubs) are served by whole blocks
 void launch_mis_pass(int n, const int *rp, const int *ci, uint64_t *key, uint64_t *m1, int *owner, int cap, int G,
-                     unsigned *done_counter, hipStream_t s);
+                     unsigned *done_counter, const int *hubs, int nhub, int lim, hipStream_t s);
 void launch_centre_flags(int n, const int *owner, int *flag, hipStream_t s);
 void launch_assign_aggregates(int n, const int *owner, const int *cid, int *agg, int *centre_of, hipStream_t s);
 void launch_member_counts(int nc, const int *rp, const int *ci, const int *owner, const int *centre_of, int *size,
@@ -134,13 +136,20 @@ DotSet launch_residual(Rows R, const int *ci, const double *va, const double *b,
 void launch_reduce(const DotRef &ref, double *out, hipStream_t s);
 // rc = W r over the super-rows S, W = P^T (I - A M^-1) stored per entry
 void launch_restrict(Rows S, const int *ci, const double *wv, const double *r, double *rc, int G, hipStream_t s);
+// rc = W r with r = rt formed on the fly as rt = rcf - (alpha1/rho1) v1 (the
+// inner residual of the parent's first flexible-CG step), rt also stored
+void launch_restrict_rt(Rows S, int nf, const int *ci, const double *wv, const double *rcf, const double *v1,
+                        KDots kd, double *rt, double *rc, int *flag, int G, hipStream_t s);
 // rt = rc - (alpha1/rho1) v1
 void launch_inner_residual(int n, const double *rc, const double *v1, KDots kd, double *rt, int *flag, hipStream_t s);
 // post-smoothing with the coarse correction folded in (mode 0: e = edirect;
-// 1: e = (alpha1/rho1) c1; 2: e = a1 c1 + a2 c2); returns (out, wdot) if wdot
+// 1: e = (alpha1/rho1) c1; 2: e = a1 c1 + a2 c2; 3: e = ainv * edirect, a dense
+// coarsest solve of size nc <= kInlineCoarse done in the kernel); returns
+// (out, wdot) if wdot
 DotRef launch_post_smooth(Rows R, const int *ci, const double *va, const double *minv, const double *r,
-                          const int *agg_pos, int mode, const double *edirect, const double *c1, const double *c2,
-                          KDots kd, double *xout, const double *wdot, DotBuf buf, int *flag, int G, hipStream_t s);
+                          const int *agg_pos, const int *cagg, int mode, const double *edirect, const double *c1, const double *c2,
+                          KDots kd, double *xout, const double *wdot, DotBuf buf, int *flag, int G, hipStream_t s,
+                          const double *ainv = nullptr, int nc = 0);
 void launch_dense_gemv(int n, const double *a, const double *x, double *y, hipStream_t s);
 // alpha = pr/pq; x += alpha p; r -= alpha q; returns (r, r)
 DotRef launch_fcg_update(int n, DotRef pq, DotRef pr, double *x, double *r, const double *p, const double *q,
@@ -150,6 +159,8 @@ void launch_fcg_direction(int n, DotRef pq, DotRef zq, const double *z, double *
 DotRef launch_dot(int n, const double *a, const double *b, DotBuf buf, hipStream_t s);
 void launch_gather(int n, const double *src, const int *idx, double *dst, hipStream_t s);   // dst[i] = src[idx[i]]
 void launch_scatter(int n, const double *src, const int *idx, double *dst, hipStream_t s);  // dst[idx[i]] = src[i]
+// cagg[p] = agg_pos[ci[p]]: coarse unknown of every entry's column
+void launch_entry_coarse_column(int nnz, const int *ci, const int *agg_pos, int *cagg, hipStream_t s);
 void launch_restriction_weights(int n, const int *rp, const int *ci, const double *va, const double *minv, double *wv,
                                 hipStream_t s);
 

@@ -116,6 +116,7 @@ struct Level {
     double *wv = nullptr;                                        // restriction weights P^T (I - A M^-1)
     int *perm = nullptr, *pos = nullptr;                        // position -> natural, natural -> position
     int *agg_pos = nullptr, *seg_ptr = nullptr, *srp = nullptr;  // all but the coarsest level
+    int *cagg = nullptr;                                         // coarse unknown of each entry's column
     int G = 2, Gs = 2;
     Rows A{}, S{};  // rows of A and super-rows of P^T A, each with its hub-row chunks
     // work vectors and dot sites when this level is the coarse level of a visit
@@ -244,7 +245,12 @@ struct amg_hierarchy {
 
     void build(const amg_csr &A);
     void finalize_layout();
-    DotRef kcycle(int k, const double *r, double *x, const double *wdot);
+    // the inner residual rt = rcf - (alpha1/rho1) v1 of a parent's first step
+    struct RtSource {
+        const double *rcf, *v1;
+        KDots kd;
+    };
+    DotRef kcycle(int k, const double *r, double *x, const double *wdot, const RtSource *rts);
     void run_kcycle();
     void run_first();
     void run_iter();
@@ -308,10 +314,16 @@ void amg_hierarchy::build(const amg_csr &A)
         const uint32_t s_l = (uint32_t)splitmix64(opt.seed, (uint64_t)l);
         launch_priorities(n, lev[l].rp_nat, s_l, key, owner, stream);
         AMG_HIP(hipMemsetAsync(done, 0, sizeof(unsigned), stream));
+        // hub rows (longer than 8 G) of this level, served by whole blocks in the passes
+        const int lim = 8 * G;
+        launch_long_rows(n, lev[l].rp_nat, lim, tptr, nullptr, tptr + n, scan_tmp, stream);
+        const int nhub = read_int(tptr + n);
+        if (nhub > 0) launch_long_rows(n, lev[l].rp_nat, lim, tptr, big_rows, nullptr, scan_tmp, stream);
         int passes = 0;
         unsigned processed = 0;
         while (processed < (unsigned)n) {
-            launch_mis_pass(n, lev[l].rp_nat, lev[l].ci_nat, key, m1, owner, opt.max_aggregate, G, done, stream);
+            launch_mis_pass(n, lev[l].rp_nat, lev[l].ci_nat, key, m1, owner, opt.max_aggregate, G, done, big_rows,
+                            nhub, lim, stream);
             passes++;
             const unsigned now = (unsigned)read_int(reinterpret_cast<int *>(done));
             if (now <= processed || now > (unsigned)n) throw Error(AMG_ERR_DEVICE, "aggregation made no progress");
@@ -349,7 +361,8 @@ void amg_hierarchy::build(const amg_csr &A)
             }
             int64_t *off_dev = pool.alloc<int64_t>(nbig + 1);
             int *rows_dev = pool.alloc<int>(nbig);
-            uint64_t *scratch = pool.alloc<uint64_t>(2 * off[nbig]);
+            // per big row: keys, values by position, values in sorted order, segment heads
+            uint64_t *scratch = pool.alloc<uint64_t>(4 * off[nbig] + 1);
             AMG_HIP(hipMemcpyAsync(off_dev, off.data(), sizeof(int64_t) * (nbig + 1), hipMemcpyHostToDevice, stream));
             AMG_HIP(hipMemcpyAsync(rows_dev, rows.data(), sizeof(int) * nbig, hipMemcpyHostToDevice, stream));
             launch_coarse_big_rows(nbig, rows_dev, off_dev, scratch, F.rp_nat, F.ci_nat, F.va_nat, F.agg_nat,
@@ -445,6 +458,10 @@ void amg_hierarchy::finalize_layout()
             AMG_TRACE_MSG("layout level %d: super-rows Gs=%d hub rows=%d chunks=%d", l, F.Gs, F.S.nlong, F.S.nchunks);
             F.wv = pool.alloc<double>(F.nnz);
             launch_restriction_weights(F.n, F.rp, F.ci, F.va, F.minv, F.wv, stream);
+            if (F.n < kSmallLevel) {
+                F.cagg = pool.alloc<int>(F.nnz);
+                launch_entry_coarse_column(F.nnz, F.ci, F.agg_pos, F.cagg, stream);
+            }
         }
         if (l >= 1) {
             F.rc = pool.alloc<double>(F.n);
@@ -481,7 +498,7 @@ void amg_hierarchy::finalize_layout()
 // coarse correction (exact on the coarsest level, else two flexible-CG steps
 // preconditioned by K_{k+1}), prolongation + post-smoothing.  When wdot is given
 // the returned reference holds (x, wdot).
-DotRef amg_hierarchy::kcycle(int k, const double *rr, double *xx, const double *wdot)
+DotRef amg_hierarchy::kcycle(int k, const double *rr, double *xx, const double *wdot, const RtSource *rts)
 {
     using namespace amg;
     const int L = levels() - 1;
@@ -491,23 +508,38 @@ DotRef amg_hierarchy::kcycle(int k, const double *rr, double *xx, const double *
         return wdot ? launch_dot(F.n, xx, wdot, d_zq, stream) : DotRef{nullptr, 0};
     }
     Level &C = lev[k + 1];
-    launch_restrict(F.S, F.ci, F.wv, rr, C.rc, F.Gs, stream);
+    if (rts) {  // rr = rt is formed here from the parent's first inner step
+        launch_restrict_rt(F.S, F.n, F.ci, F.wv, rts->rcf, rts->v1, rts->kd, const_cast<double *>(rr), C.rc, flag,
+                           F.Gs, stream);
+    } else {
+        launch_restrict(F.S, F.ci, F.wv, rr, C.rc, F.Gs, stream);
+    }
     KDots kd{};
     int mode;
     const double *edirect = nullptr;
     if (k + 1 == L) {
-        launch_dense_gemv(C.n, ainv, C.rc, C.c1, stream);
-        mode = 0;
-        edirect = C.c1;
+        if (C.n <= kInlineCoarse) {
+            mode = 3;
+            edirect = C.rc;
+        } else {
+            launch_dense_gemv(C.n, ainv, C.rc, C.c1, stream);
+            mode = 0;
+            edirect = C.c1;
+        }
     } else {
-        kcycle(k + 1, C.rc, C.c1, nullptr);
+        kcycle(k + 1, C.rc, C.c1, nullptr, nullptr);
         const DotSet s1 = launch_spmv_dots(C.A, C.ci, C.va, C.c1, C.v1, C.rc, nullptr, C.G, C.d_c1, stream);
         kd.rho1 = s1.d[0];
         kd.alpha1 = s1.d[1];
         mode = 1;
         if (opt.kcycle_inner == 2) {
-            launch_inner_residual(C.n, C.rc, C.v1, kd, C.rt, flag, stream);
-            kcycle(k + 1, C.rt, C.c2, nullptr);
+            if (C.n < kSmallLevel) {  // fold the inner residual into the next restriction
+                const RtSource src{C.rc, C.v1, kd};
+                kcycle(k + 1, C.rt, C.c2, nullptr, &src);
+            } else {
+                launch_inner_residual(C.n, C.rc, C.v1, kd, C.rt, flag, stream);
+                kcycle(k + 1, C.rt, C.c2, nullptr, nullptr);
+            }
             const DotSet s2 = launch_spmv_dots(C.A, C.ci, C.va, C.c2, nullptr, C.v1, C.rt, C.G, C.d_c2, stream);
             kd.beta = s2.d[0];
             kd.gamma = s2.d[1];
@@ -516,8 +548,8 @@ DotRef amg_hierarchy::kcycle(int k, const double *rr, double *xx, const double *
         }
     }
     if (k == 0) kd0 = kd;
-    return launch_post_smooth(F.A, F.ci, F.va, F.minv, rr, F.agg_pos, mode, edirect, C.c1, C.c2, kd, xx, wdot,
-                              k == 0 ? d_zq : DotBuf{}, flag, F.G, stream);
+    return launch_post_smooth(F.A, F.ci, F.va, F.minv, rr, F.agg_pos, F.cagg, mode, edirect, C.c1, C.c2, kd, xx, wdot,
+                              k == 0 ? d_zq : DotBuf{}, flag, F.G, stream, ainv, C.n);
 }
 
 // One outer iteration is split in three replayable pieces:
@@ -527,7 +559,7 @@ DotRef amg_hierarchy::kcycle(int k, const double *rr, double *xx, const double *
 void amg_hierarchy::run_kcycle()
 {
     if (g_kcycle) AMG_HIP(hipGraphLaunch(g_kcycle, stream));
-    else dr_zq = kcycle(0, r, z, q);
+    else dr_zq = kcycle(0, r, z, q, nullptr);
 }
 
 void amg_hierarchy::run_first()
@@ -826,7 +858,7 @@ amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, dou
         const Level &F = h->lev[0], &C = h->lev[1];
         const int mode = h->opt.kcycle_inner == 1 ? 1 : 2;
         auto launch = [&]() {
-            amg::launch_post_smooth(F.A, F.ci, F.va, F.minv, h->r, F.agg_pos, mode, nullptr, C.c1, C.c2, h->kd0, h->z,
+            amg::launch_post_smooth(F.A, F.ci, F.va, F.minv, h->r, F.agg_pos, F.cagg, mode, nullptr, C.c1, C.c2, h->kd0, h->z,
                                     nullptr, DotBuf{}, h->flag, F.G, h->stream);
         };
         launch();
@@ -837,7 +869,9 @@ amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, dou
         float ms = 0.f;
         AMG_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
         *avg_us = 1000.0 * ms / reps;
-        if (bytes) *bytes = 12.0 * F.nnz + 4.0 * (F.n + 1) + 32.0 * F.n + 16.0 * C.n;
+        // per entry: column, value (+ coarse column on small levels); per row:
+        // row pointer, minv, r, coarse index, output; coarse c1, c2 once each
+        if (bytes) *bytes = (F.cagg ? 16.0 : 12.0) * F.nnz + 4.0 * (F.n + 1) + 32.0 * F.n + 16.0 * C.n;
         return AMG_OK;
     });
 }

@@ -6,14 +6,20 @@
 //   P^T member lists                  k_member_counts / k_member_fill
 //   A_c = P^T A P as sums (eq. (2.4))  k_coarse_rows (one wavefront per coarse row,
 //                                     LDS bitonic sort + ordered segmented sums),
-//                                     k_coarse_big_rows (rows beyond LDS capacity)
+//                                     k_coarse_big_rows (one block per row beyond
+//                                     LDS capacity, LDS-tiled bitonic sort)
 //   l1-Jacobi diagonal (Sec. 4.1)     k_l1_inverse_diagonal / k_coarse_compact
 //   coarsest level                    dense Cholesky and explicit inverse
 //   solve layout                      nested aggregate order for every level
 //
+// Coarse levels of 3D problems have hub rows with thousands of entries.  Row
+// kernels take a lane count: 1 (a thread per row, regular fine levels) or 64 (a
+// wavefront per row, small levels); the MIS passes serve rows longer than `lim`
+// with whole blocks.
+//
 // Every result is independent of the schedule: priorities are unique, a pass
-// only claims conflict-free stars, integer counts are exact, and every
-// floating-point sum runs in a fixed order.
+// only claims conflict-free stars, integer counts are exact, and the sums that
+// form A_c run in a fixed order.
 #include "amg_internal.h"
 
 namespace amg {
@@ -43,6 +49,48 @@ __device__ inline uint32_t fmix32(uint32_t h)
     h *= 0xC2B2AE35u;
     h ^= h >> 16;
     return h;
+}
+
+template <int G>
+__device__ inline uint64_t group_max(uint64_t v)
+{
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        const uint64_t w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+template <int G>
+__device__ inline int group_isum(int v)
+{
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <int G>
+__device__ inline double group_dsum(double v)
+{
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Block-wide max of a u64 (every thread receives it).
+__device__ inline uint64_t block_max(uint64_t v)
+{
+    __shared__ uint64_t sh[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    v = group_max<kWave>(v);
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    uint64_t m = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; w++) m = sh[w] > m ? sh[w] : m;
+    __syncthreads();
+    return m;
 }
 
 // ------------------------------------------------------------------ input checks
@@ -116,30 +164,40 @@ __global__ void __launch_bounds__(kBlock) k_priorities(int n, const int *__restr
 // vertex of the pass iff its key is the maximum over unprocessed vertices within
 // distance 2 through unprocessed vertices.  Two sweeps of max-propagation give
 // that maximum: m1_i = max over the closed neighbourhood (processed keys are 0),
-// m2_i = max over the closed neighbourhood of m1.  A group of G lanes serves one row.
-
-template <int G>
-__device__ inline uint64_t group_max(uint64_t v)
-{
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-        const uint64_t w = __shfl_xor(v, o, kWave);
-        v = w > v ? w : v;
-    }
-    return v;
-}
+// m2_i = max over the closed neighbourhood of m1.  A group of G lanes serves an
+// ordinary row; rows longer than lim (listed in hubs) are served by whole blocks,
+// from the first min(nhub, kLongBlocks) blocks.
 
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_mis_max1(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                     const uint64_t *__restrict__ key, uint64_t *__restrict__ m1)
+                                                     const uint64_t *__restrict__ key, uint64_t *__restrict__ m1,
+                                                     const int *__restrict__ hubs, int nhub, int lim)
 {
+    const int nhb = nhub < kLongBlocks ? nhub : kLongBlocks;
+    if ((int)blockIdx.x < nhb) {
+        for (int k = blockIdx.x; k < nhub; k += nhb) {
+            const int i = hubs[k];
+            uint64_t m = 0;
+            if (key[i] != 0) {
+                for (int p = rp[i] + threadIdx.x; p < rp[i + 1]; p += kBlock) {
+                    const uint64_t kj = key[ci[p]];
+                    m = kj > m ? kj : m;
+                }
+            }
+            m = block_max(m);
+            if (threadIdx.x == 0) m1[i] = m;
+        }
+        return;
+    }
     const int sub = threadIdx.x % G;
-    const int ngroups = gridDim.x * (kBlock / G);
-    for (int i = (blockIdx.x * kBlock + threadIdx.x) / G; i < n; i += ngroups) {
+    const int ngroups = (gridDim.x - nhb) * (kBlock / G);
+    for (int i = ((blockIdx.x - nhb) * kBlock + threadIdx.x) / G; i < n; i += ngroups) {
+        const int b = rp[i], e = rp[i + 1];
+        if (e - b > lim) continue;
         const uint64_t ki = key[i];
         uint64_t m = 0;
         if (ki != 0) {
-            for (int p = rp[i] + sub; p < rp[i + 1]; p += G) {
+            for (int p = b + sub; p < e; p += G) {
                 const uint64_t kj = key[ci[p]];
                 m = kj > m ? kj : m;
             }
@@ -152,59 +210,116 @@ __global__ void __launch_bounds__(kBlock) k_mis_max1(int n, const int *__restric
 // Step (2b) decision (m2 == key) and step (2c): the coarse vertex takes itself and
 // its unprocessed neighbours in ascending order, at most cap-1 of them (cap = 0:
 // all).  Coarse vertices of one pass are at distance >= 3 among unprocessed
-// vertices, so no two of them touch the same neighbour.
+// vertices, so no two of them touch the same neighbour.  key[i] may be zeroed
+// concurrently by a neighbouring coarse vertex that claims i; one lane reads it
+// and the group (or block) decides on that one value.  (If i is claimed it cannot
+// be a local maximum.)
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_mis_select_claim(int n, const int *__restrict__ rp,
                                                              const int *__restrict__ ci, uint64_t *key,
                                                              const uint64_t *__restrict__ m1, int *owner, int cap,
-                                                             unsigned *__restrict__ done)
+                                                             unsigned *__restrict__ done,
+                                                             const int *__restrict__ hubs, int nhub, int lim)
 {
     __shared__ unsigned block_done;
+    __shared__ uint64_t sh_key;
+    __shared__ int sh_cnt[kBlock / kWave];
     if (threadIdx.x == 0) block_done = 0;
     __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1);
-    const int sub = threadIdx.x % G;
-    const int gbase = lane - sub;  // first lane of this group within the wave
-    const uint64_t gmask = (G == kWave) ? ~0ull : (((1ull << G) - 1ull) << gbase);
-    const int ngroups = gridDim.x * (kBlock / G);
-    for (int i = (blockIdx.x * kBlock + threadIdx.x) / G; i < n; i += ngroups) {
-        // key[i] may be zeroed concurrently by a neighbouring coarse vertex that
-        // claims i; one lane reads it and the group shares that value, so the
-        // group decides as one.  (If i is claimed, i cannot be a local maximum.)
-        uint64_t ki = (sub == 0) ? key[i] : 0;
-        ki = __shfl(ki, gbase, kWave);
-        if (ki == 0) continue;  // processed (uniform within the group)
-        uint64_t m = 0;
-        const int b = rp[i], e = rp[i + 1];
-        for (int p = b + sub; p < e; p += G) {
-            const uint64_t v = m1[ci[p]];
-            m = v > m ? v : m;
-        }
-        m = group_max<G>(m);
-        if (m != ki) continue;  // not a local maximum (uniform within the group)
-        int taken = 1;
-        for (int p0 = b; p0 < e; p0 += G) {
-            if (cap > 0 && taken >= cap) break;
-            const int p = p0 + sub;
-            int j = -1;
-            bool cand = false;
-            if (p < e) {
-                j = ci[p];
-                cand = (j != i) && (key[j] != 0);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int nhb = nhub < kLongBlocks ? nhub : kLongBlocks;
+    if ((int)blockIdx.x < nhb) {
+        for (int k = blockIdx.x; k < nhub; k += nhb) {
+            const int i = hubs[k];
+            if (threadIdx.x == 0) sh_key = key[i];
+            __syncthreads();
+            const uint64_t ki = sh_key;
+            __syncthreads();
+            if (ki == 0) continue;  // uniform within the block
+            const int b = rp[i], e = rp[i + 1];
+            uint64_t m = 0;
+            for (int p = b + threadIdx.x; p < e; p += kBlock) {
+                const uint64_t v = m1[ci[p]];
+                m = v > m ? v : m;
             }
-            const uint64_t bal = __ballot(cand) & gmask;
-            const int rank = __popcll(bal & ((1ull << lane) - 1ull) & gmask);
-            if (cand && (cap == 0 || taken + rank < cap)) {
-                owner[j] = i;
-                key[j] = 0;
+            m = block_max(m);
+            if (m != ki) continue;
+            int taken = 1;
+            for (int p0 = b; p0 < e; p0 += kBlock) {
+                if (cap > 0 && taken >= cap) break;
+                const int p = p0 + threadIdx.x;
+                int j = -1;
+                bool cand = false;
+                if (p < e) {
+                    j = ci[p];
+                    cand = (j != i) && (key[j] != 0);
+                }
+                const uint64_t bal = __ballot(cand);
+                if (lane == 0) sh_cnt[wid] = __popcll(bal);
+                __syncthreads();
+                int before = 0, total = 0;
+#pragma unroll
+                for (int w = 0; w < kBlock / kWave; w++) {
+                    if (w < wid) before += sh_cnt[w];
+                    total += sh_cnt[w];
+                }
+                __syncthreads();
+                const int rank = before + __popcll(bal & ((1ull << lane) - 1ull));
+                if (cand && (cap == 0 || taken + rank < cap)) {
+                    owner[j] = i;
+                    key[j] = 0;
+                }
+                taken += (cap > 0 && taken + total > cap) ? (cap - taken) : total;
             }
-            const int c = __popcll(bal);
-            taken += (cap > 0 && taken + c > cap) ? (cap - taken) : c;
+            if (threadIdx.x == 0) {
+                owner[i] = i;
+                key[i] = 0;
+                block_done += (unsigned)taken;
+            }
+            __syncthreads();
         }
-        if (sub == 0) {
-            owner[i] = i;
-            key[i] = 0;
-            atomicAdd(&block_done, (unsigned)taken);
+    } else {
+        const int sub = threadIdx.x % G;
+        const int gbase = lane - sub;  // first lane of this group within the wave
+        const uint64_t gmask = (G == kWave) ? ~0ull : (((1ull << G) - 1ull) << gbase);
+        const int ngroups = (gridDim.x - nhb) * (kBlock / G);
+        for (int i = ((blockIdx.x - nhb) * kBlock + threadIdx.x) / G; i < n; i += ngroups) {
+            const int b = rp[i], e = rp[i + 1];
+            if (e - b > lim) continue;
+            uint64_t ki = (sub == 0) ? key[i] : 0;
+            ki = __shfl(ki, gbase, kWave);
+            if (ki == 0) continue;  // processed (uniform within the group)
+            uint64_t m = 0;
+            for (int p = b + sub; p < e; p += G) {
+                const uint64_t v = m1[ci[p]];
+                m = v > m ? v : m;
+            }
+            m = group_max<G>(m);
+            if (m != ki) continue;  // not a local maximum (uniform within the group)
+            int taken = 1;
+            for (int p0 = b; p0 < e; p0 += G) {
+                if (cap > 0 && taken >= cap) break;
+                const int p = p0 + sub;
+                int j = -1;
+                bool cand = false;
+                if (p < e) {
+                    j = ci[p];
+                    cand = (j != i) && (key[j] != 0);
+                }
+                const uint64_t bal = __ballot(cand) & gmask;
+                const int rank = __popcll(bal & ((1ull << lane) - 1ull) & gmask);
+                if (cand && (cap == 0 || taken + rank < cap)) {
+                    owner[j] = i;
+                    key[j] = 0;
+                }
+                const int c = __popcll(bal);
+                taken += (cap > 0 && taken + c > cap) ? (cap - taken) : c;
+            }
+            if (sub == 0) {
+                owner[i] = i;
+                key[i] = 0;
+                atomicAdd(&block_done, (unsigned)taken);
+            }
         }
     }
     __syncthreads();
@@ -232,39 +347,60 @@ __global__ void __launch_bounds__(kBlock) k_assign_aggregates(int n, const int *
 
 // Members of aggregate I are its coarse vertex c and the neighbours j of c with
 // owner j = c; walking row c (ascending columns, diagonal included) lists them in
-// ascending order.
+// ascending order.  G lanes (1 or 64) serve one aggregate.
+template <int G>
 __global__ void __launch_bounds__(kBlock) k_member_counts(int nc, const int *__restrict__ rp,
                                                           const int *__restrict__ ci, const int *__restrict__ owner,
                                                           const int *__restrict__ centre_of, int *__restrict__ size,
                                                           int *__restrict__ pairs)
 {
-    const int I = blockIdx.x * kBlock + threadIdx.x;
-    if (I >= nc) return;
-    const int c = centre_of[I];
-    int s = 0, pc = 0;
-    for (int p = rp[c]; p < rp[c + 1]; p++) {
-        const int j = ci[p];
-        if (owner[j] == c) {
-            s++;
-            pc += rp[j + 1] - rp[j];
+    const int sub = threadIdx.x % G;
+    const int ngroups = gridDim.x * (kBlock / G);
+    for (int I = (blockIdx.x * kBlock + threadIdx.x) / G; I < nc; I += ngroups) {
+        const int c = centre_of[I];
+        int s = 0, pc = 0;
+        for (int p = rp[c] + sub; p < rp[c + 1]; p += G) {
+            const int j = ci[p];
+            if (owner[j] == c) {
+                s++;
+                pc += rp[j + 1] - rp[j];
+            }
+        }
+        s = group_isum<G>(s);
+        pc = group_isum<G>(pc);
+        if (sub == 0) {
+            size[I] = s;
+            pairs[I] = pc;
         }
     }
-    size[I] = s;
-    pairs[I] = pc;
 }
 
+template <int G>
 __global__ void __launch_bounds__(kBlock) k_member_fill(int nc, const int *__restrict__ rp, const int *__restrict__ ci,
                                                         const int *__restrict__ owner,
                                                         const int *__restrict__ centre_of,
                                                         const int *__restrict__ aptr, int *__restrict__ members)
 {
-    const int I = blockIdx.x * kBlock + threadIdx.x;
-    if (I >= nc) return;
-    const int c = centre_of[I];
-    int k = aptr[I];
-    for (int p = rp[c]; p < rp[c + 1]; p++) {
-        const int j = ci[p];
-        if (owner[j] == c) members[k++] = j;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int sub = threadIdx.x % G;
+    const int gbase = lane - sub;
+    const uint64_t gmask = (G == kWave) ? ~0ull : (((1ull << G) - 1ull) << gbase);
+    const int ngroups = gridDim.x * (kBlock / G);
+    for (int I = (blockIdx.x * kBlock + threadIdx.x) / G; I < nc; I += ngroups) {
+        const int c = centre_of[I];
+        int k = aptr[I];
+        for (int p0 = rp[c]; p0 < rp[c + 1]; p0 += G) {
+            const int p = p0 + sub;
+            int j = -1;
+            bool mem = false;
+            if (p < rp[c + 1]) {
+                j = ci[p];
+                mem = owner[j] == c;
+            }
+            const uint64_t bal = __ballot(mem) & gmask;
+            if (mem) members[k + __popcll(bal & ((1ull << lane) - 1ull))] = j;
+            k += __popcll(bal);
+        }
     }
 }
 
@@ -275,7 +411,7 @@ __global__ void __launch_bounds__(kBlock) k_member_fill(int nc, const int *__res
 // each segment of equal J is summed sequentially in position order, which is the
 // order of a row-by-row accumulation over (s, t).
 
-constexpr int kWaveCap = 1024;  // pairs one wavefront sorts in LDS
+constexpr int kWaveCap = 512;  // pairs one wavefront sorts in LDS
 constexpr int kWavesPerBlock = kBlock / kWave;
 
 __global__ void __launch_bounds__(kBlock) k_coarse_rows(int nc, const int *__restrict__ rp,
@@ -288,9 +424,11 @@ __global__ void __launch_bounds__(kBlock) k_coarse_rows(int nc, const int *__res
 {
     __shared__ uint64_t skey[kWavesPerBlock][kWaveCap];
     __shared__ double sval[kWavesPerBlock][kWaveCap];
+    __shared__ int smb[kWavesPerBlock][kWave], smx[kWavesPerBlock][kWave];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     uint64_t *key = skey[w];
     double *val = sval[w];
+    int *mbeg = smb[w], *mexcl = smx[w];
     const int total_waves = gridDim.x * kWavesPerBlock;
     for (int I = blockIdx.x * kWavesPerBlock + w; I < nc; I += total_waves) {
         const int base = tptr[I];
@@ -299,16 +437,42 @@ __global__ void __launch_bounds__(kBlock) k_coarse_rows(int nc, const int *__res
             if (lane == 0) big_rows[atomicAdd(big_count, 1u)] = I;
             continue;
         }
+        // gather: up to 64 members at a time, their rows spread over the lanes
         int fill = 0;
-        for (int m = aptr[I]; m < aptr[I + 1]; m++) {
-            const int s = members[m];
-            const int b = rp[s], e = rp[s + 1];
-            for (int p = b + lane; p < e; p += kWave) {
-                const int k = fill + (p - b);
-                key[k] = ((uint64_t)(uint32_t)agg[ci[p]] << 32) | (uint32_t)k;
-                val[k] = va[p];
+        const int me = aptr[I + 1];
+        for (int m0 = aptr[I]; m0 < me; m0 += kWave) {
+            const int m = m0 + lane;
+            int b = 0, len = 0;
+            if (m < me) {
+                const int s = members[m];
+                b = rp[s];
+                len = rp[s + 1] - b;
             }
-            fill += e - b;
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int y = __shfl_up(incl, o, kWave);
+                if (lane >= o) incl += y;
+            }
+            mbeg[lane] = b;
+            mexcl[lane] = incl - len;
+            const int tot = __shfl(incl, kWave - 1, kWave);
+            const int nm = (me - m0) < kWave ? (me - m0) : kWave;
+            wave_sync();
+            for (int k = lane; k < tot; k += kWave) {
+                int lo = 0, hi = nm - 1;  // last member with mexcl <= k
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (mexcl[mid] <= k) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int p = mbeg[lo] + (k - mexcl[lo]);
+                const int pos = fill + k;
+                key[pos] = ((uint64_t)(uint32_t)agg[ci[p]] << 32) | (uint32_t)pos;
+                val[pos] = va[p];
+            }
+            fill += tot;
+            wave_sync();
         }
         int P = 1;
         while (P < pc) P <<= 1;
@@ -353,44 +517,113 @@ __global__ void __launch_bounds__(kBlock) k_coarse_rows(int nc, const int *__res
     }
 }
 
-// Rows with more pairs than one wavefront's LDS holds: one block per row, the
-// same stable sort in global scratch (keys only; values are re-read by position).
-__global__ void __launch_bounds__(kBlock) k_coarse_big_rows(const int *__restrict__ big_rows,
-                                                            const int64_t *__restrict__ scratch_off, uint64_t *skey,
-                                                            const int *__restrict__ rp, const int *__restrict__ ci,
-                                                            const double *__restrict__ va, const int *__restrict__ agg,
-                                                            const int *__restrict__ aptr,
-                                                            const int *__restrict__ members,
-                                                            const int *__restrict__ tptr, int *__restrict__ tcol,
-                                                            double *__restrict__ tval, int *__restrict__ cnt)
+// Rows with more pairs than one wavefront's LDS holds: one block of kBigThreads
+// per row.  Keys live in global scratch; the bitonic network runs its strides
+// below kTile inside LDS tiles and only the longer strides as global passes.
+constexpr int kBigThreads = 1024;
+constexpr int kTile = 4096;
+
+__device__ void tile_steps(uint64_t *t, int64_t base, int64_t size, int stride0, int len)
 {
-    __shared__ int sh_count[kWavesPerBlock];
-    __shared__ int sh_out;
+    for (int stride = stride0; stride > 0; stride >>= 1) {
+        for (int u = threadIdx.x; u < len / 2; u += kBigThreads) {
+            const int lo = 2 * stride * (u / stride) + (u % stride);
+            const int hi = lo + stride;
+            const bool up = ((base + lo) & size) == 0;
+            const uint64_t a = t[lo], c = t[hi];
+            if ((a > c) == up) {
+                t[lo] = c;
+                t[hi] = a;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBigThreads) k_coarse_big_rows(const int *__restrict__ big_rows,
+                                                                 const int64_t *__restrict__ scratch_off,
+                                                                 uint64_t *skey, const int *__restrict__ rp,
+                                                                 const int *__restrict__ ci,
+                                                                 const double *__restrict__ va,
+                                                                 const int *__restrict__ agg,
+                                                                 const int *__restrict__ aptr,
+                                                                 const int *__restrict__ members,
+                                                                 const int *__restrict__ tptr, int *__restrict__ tcol,
+                                                                 double *__restrict__ tval, int *__restrict__ cnt)
+{
+    __shared__ uint64_t tile[kTile];
+    __shared__ int mbeg[kBigThreads], mexcl[kBigThreads];
+    __shared__ int sh_count[kBigThreads / kWave];
+    __shared__ int sh_tot, sh_out;
     const int I = big_rows[blockIdx.x];
     uint64_t *key = skey + scratch_off[blockIdx.x];
     double *val = reinterpret_cast<double *>(skey + scratch_off[gridDim.x]) + scratch_off[blockIdx.x];
     const int base = tptr[I];
     const int pc = tptr[I + 1] - base;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    // gather: up to kBigThreads members at a time, block-wide prefix of row lengths
     int fill = 0;
-    for (int m = aptr[I]; m < aptr[I + 1]; m++) {
-        const int s = members[m];
-        const int b = rp[s], e = rp[s + 1];
-        for (int p = b + (int)threadIdx.x; p < e; p += kBlock) {
-            const int k = fill + (p - b);
-            key[k] = ((uint64_t)(uint32_t)agg[ci[p]] << 32) | (uint32_t)k;
-            val[k] = va[p];
+    const int me = aptr[I + 1];
+    for (int m0 = aptr[I]; m0 < me; m0 += kBigThreads) {
+        const int m = m0 + threadIdx.x;
+        int b = 0, len = 0;
+        if (m < me) {
+            const int s = members[m];
+            b = rp[s];
+            len = rp[s + 1] - b;
         }
-        fill += e - b;
+        int incl = len;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += y;
+        }
+        if (lane == kWave - 1) sh_count[w] = incl;
+        __syncthreads();
+        int before = 0;
+        for (int k = 0; k < w; k++) before += sh_count[k];
+        incl += before;
+        mbeg[threadIdx.x] = b;
+        mexcl[threadIdx.x] = incl - len;
+        if (threadIdx.x == kBigThreads - 1) sh_tot = incl;
+        __syncthreads();
+        const int tot = sh_tot;
+        const int nm = (me - m0) < kBigThreads ? (me - m0) : kBigThreads;
+        for (int k = threadIdx.x; k < tot; k += kBigThreads) {
+            int lo = 0, hi = nm - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (mexcl[mid] <= k) lo = mid;
+                else hi = mid - 1;
+            }
+            const int p = mbeg[lo] + (k - mexcl[lo]);
+            const int pos = fill + k;
+            key[pos] = ((uint64_t)(uint32_t)agg[ci[p]] << 32) | (uint32_t)pos;
+            val[pos] = va[p];
+        }
+        fill += tot;
+        __syncthreads();
     }
-    int P = 1;
+    int64_t P = 1;
     while (P < pc) P <<= 1;
-    for (int k = pc + threadIdx.x; k < P; k += kBlock) key[k] = ~0ull;
+    for (int64_t k = pc + threadIdx.x; k < P; k += kBigThreads) key[k] = ~0ull;
     __syncthreads();
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < P / 2; t += kBlock) {
-                const int lo = 2 * stride * (t / stride) + (t % stride);
-                const int hi = lo + stride;
+    const int tl = P < kTile ? (int)P : kTile;
+    // 1) sort every tile completely (bitonic sizes up to the tile length)
+    for (int64_t t0 = 0; t0 < P; t0 += tl) {
+        for (int k = threadIdx.x; k < tl; k += kBigThreads) tile[k] = key[t0 + k];
+        __syncthreads();
+        for (int size = 2; size <= tl; size <<= 1) tile_steps(tile, t0, size, size >> 1, tl);
+        for (int k = threadIdx.x; k < tl; k += kBigThreads) key[t0 + k] = tile[k];
+        __syncthreads();
+    }
+    // 2) larger sizes: long strides in global memory, the rest inside tiles
+    for (int64_t size = 2 * (int64_t)tl; size <= P; size <<= 1) {
+        int64_t stride = size >> 1;
+        for (; stride >= tl; stride >>= 1) {
+            for (int64_t u = threadIdx.x; u < P / 2; u += kBigThreads) {
+                const int64_t lo = 2 * stride * (u / stride) + (u % stride);
+                const int64_t hi = lo + stride;
                 const bool up = (lo & size) == 0;
                 const uint64_t a = key[lo], c = key[hi];
                 if ((a > c) == up) {
@@ -400,62 +633,79 @@ __global__ void __launch_bounds__(kBlock) k_coarse_big_rows(const int *__restric
             }
             __syncthreads();
         }
+        for (int64_t t0 = 0; t0 < P; t0 += tl) {
+            for (int k = threadIdx.x; k < tl; k += kBigThreads) tile[k] = key[t0 + k];
+            __syncthreads();
+            tile_steps(tile, t0, size, (int)stride, tl);
+            for (int k = threadIdx.x; k < tl; k += kBigThreads) key[t0 + k] = tile[k];
+            __syncthreads();
+        }
     }
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    // 3) values in sorted order, head positions, then every segment of equal J
+    //    summed in position order over a contiguous range
+    double *sv = reinterpret_cast<double *>(skey + 2 * scratch_off[gridDim.x]) + scratch_off[blockIdx.x];
+    int *hp = reinterpret_cast<int *>(skey + 3 * scratch_off[gridDim.x] + scratch_off[blockIdx.x]);
+    for (int q = threadIdx.x; q < pc; q += kBigThreads) sv[q] = val[(uint32_t)key[q]];
     if (threadIdx.x == 0) sh_out = 0;
     __syncthreads();
-    for (int q0 = 0; q0 < pc; q0 += kBlock) {
+    for (int q0 = 0; q0 < pc; q0 += kBigThreads) {
         const int q = q0 + (int)threadIdx.x;
         bool head = false;
-        uint32_t J = 0;
-        if (q < pc) {
-            J = (uint32_t)(key[q] >> 32);
-            head = (q == 0) || ((uint32_t)(key[q - 1] >> 32) != J);
-        }
+        if (q < pc) head = (q == 0) || ((uint32_t)(key[q - 1] >> 32) != (uint32_t)(key[q] >> 32));
         const uint64_t hm = __ballot(head);
         if (lane == 0) sh_count[w] = __popcll(hm);
         __syncthreads();
         int before = sh_out;
         for (int k = 0; k < w; k++) before += sh_count[k];
-        if (head) {
-            const int rank = before + __popcll(hm & ((1ull << lane) - 1ull));
-            double s = 0.0;
-            for (int r = q; r < pc && (uint32_t)(key[r] >> 32) == J; r++) s += val[(uint32_t)key[r]];
-            tcol[base + rank] = (int)J;
-            tval[base + rank] = s;
-        }
+        if (head) hp[before + __popcll(hm & ((1ull << lane) - 1ull))] = q;
         __syncthreads();
         if (threadIdx.x == 0) {
             int add = 0;
-            for (int k = 0; k < kWavesPerBlock; k++) add += sh_count[k];
+            for (int k = 0; k < kBigThreads / kWave; k++) add += sh_count[k];
             sh_out += add;
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) cnt[I] = sh_out;
+    const int u = sh_out;
+    if (threadIdx.x == 0) hp[u] = pc;
+    __syncthreads();
+    for (int k = threadIdx.x; k < u; k += kBigThreads) {
+        const int q = hp[k], qe = hp[k + 1];
+        double s = 0.0;
+        for (int r = q; r < qe; r++) s += sv[r];
+        tcol[base + k] = (int)(uint32_t)(key[q] >> 32);
+        tval[base + k] = s;
+    }
+    if (threadIdx.x == 0) cnt[I] = u;
 }
 
 // Copy the unique entries of every coarse row into the final CSR and form the
-// coarse l1 diagonal (row summed in column order).
+// coarse l1 diagonal.  G = 1: the row is summed in column order; G = 64: lanes
+// share the row (used on small levels, whose hub rows are long).
+template <int G>
 __global__ void __launch_bounds__(kBlock) k_coarse_compact(int nc, const int *__restrict__ tptr,
                                                            const int *__restrict__ tcol,
                                                            const double *__restrict__ tval,
                                                            const int *__restrict__ crp, int *__restrict__ cci,
                                                            double *__restrict__ cva, double *__restrict__ cminv)
 {
-    const int I = blockIdx.x * kBlock + threadIdx.x;
-    if (I >= nc) return;
-    const int src = tptr[I], dst = crp[I], len = crp[I + 1] - crp[I];
-    double diag = 0.0, off = 0.0;
-    for (int k = 0; k < len; k++) {
-        const int J = tcol[src + k];
-        const double v = tval[src + k];
-        cci[dst + k] = J;
-        cva[dst + k] = v;
-        if (J == I) diag += v;
-        else off += fabs(v);
+    const int sub = threadIdx.x % G;
+    const int ngroups = gridDim.x * (kBlock / G);
+    for (int I = (blockIdx.x * kBlock + threadIdx.x) / G; I < nc; I += ngroups) {
+        const int src = tptr[I], dst = crp[I], len = crp[I + 1] - crp[I];
+        double diag = 0.0, off = 0.0;
+        for (int k = sub; k < len; k += G) {
+            const int J = tcol[src + k];
+            const double v = tval[src + k];
+            cci[dst + k] = J;
+            cva[dst + k] = v;
+            if (J == I) diag += v;
+            else off += fabs(v);
+        }
+        diag = group_dsum<G>(diag);
+        off = group_dsum<G>(off);
+        if (sub == 0) cminv[I] = 1.0 / (diag + off);
     }
-    cminv[I] = 1.0 / (diag + off);
 }
 
 // ------------------------------------------------------------------ coarsest level
@@ -544,20 +794,23 @@ __global__ void __launch_bounds__(kBlock) k_sizes_in_position_order(int nc, cons
     size_pos[Q] = aptr_nat[J + 1] - aptr_nat[J];
 }
 
+template <int G>
 __global__ void __launch_bounds__(kBlock) k_positions_from_segments(int nc, const int *__restrict__ aptr_nat,
                                                                     const int *__restrict__ members_nat,
                                                                     const int *__restrict__ pos_c,
                                                                     const int *__restrict__ seg_ptr,
                                                                     int *__restrict__ pos_f, int *__restrict__ perm_f)
 {
-    const int J = blockIdx.x * kBlock + threadIdx.x;
-    if (J >= nc) return;
-    const int start = seg_ptr[pos_c[J]];
-    const int b = aptr_nat[J], e = aptr_nat[J + 1];
-    for (int k = 0; k < e - b; k++) {
-        const int i = members_nat[b + k];
-        pos_f[i] = start + k;
-        perm_f[start + k] = i;
+    const int sub = threadIdx.x % G;
+    const int ngroups = gridDim.x * (kBlock / G);
+    for (int J = (blockIdx.x * kBlock + threadIdx.x) / G; J < nc; J += ngroups) {
+        const int start = seg_ptr[pos_c[J]];
+        const int b = aptr_nat[J], e = aptr_nat[J + 1];
+        for (int k = sub; k < e - b; k += G) {
+            const int i = members_nat[b + k];
+            pos_f[i] = start + k;
+            perm_f[start + k] = i;
+        }
     }
 }
 
@@ -570,6 +823,7 @@ __global__ void __launch_bounds__(kBlock) k_permuted_row_lengths(int n, const in
     len[q] = rp_nat[i + 1] - rp_nat[i];
 }
 
+template <int G>
 __global__ void __launch_bounds__(kBlock) k_permute_rows(int n, const int *__restrict__ rp_nat,
                                                          const int *__restrict__ ci_nat,
                                                          const double *__restrict__ va_nat,
@@ -578,15 +832,17 @@ __global__ void __launch_bounds__(kBlock) k_permute_rows(int n, const int *__res
                                                          const int *__restrict__ rp, int *__restrict__ ci,
                                                          double *__restrict__ va, double *__restrict__ minv)
 {
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= n) return;
-    const int i = perm[q];
-    const int b = rp_nat[i], len = rp_nat[i + 1] - b, d = rp[q];
-    for (int k = 0; k < len; k++) {
-        ci[d + k] = pos[ci_nat[b + k]];
-        va[d + k] = va_nat[b + k];
+    const int sub = threadIdx.x % G;
+    const int ngroups = gridDim.x * (kBlock / G);
+    for (int q = (blockIdx.x * kBlock + threadIdx.x) / G; q < n; q += ngroups) {
+        const int i = perm[q];
+        const int b = rp_nat[i], len = rp_nat[i + 1] - b, d = rp[q];
+        for (int k = sub; k < len; k += G) {
+            ci[d + k] = pos[ci_nat[b + k]];
+            va[d + k] = va_nat[b + k];
+        }
+        if (sub == 0) minv[q] = minv_nat[i];
     }
-    minv[q] = minv_nat[i];
 }
 
 __global__ void __launch_bounds__(kBlock) k_agg_positions(int n, const int *__restrict__ perm_f,
@@ -618,9 +874,23 @@ __global__ void __launch_bounds__(kBlock) k_long_compact(int n, const int *__res
     if (i < n && ptr[i + 1] - ptr[i] > lim) list[offs[i]] = i;
 }
 
+// Lanes per row/aggregate for the helper kernels: a wavefront on small levels.
+inline bool wide(int n) { return n < kSmallLevel; }
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+
+#define AMG_LAUNCH_G(G, KERNEL, GRID, STREAM, ...)                                      \
+    switch (G) {                                                                        \
+    case 1: KERNEL<1><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;                 \
+    case 2: KERNEL<2><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;                 \
+    case 4: KERNEL<4><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;                 \
+    case 8: KERNEL<8><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;                 \
+    case 16: KERNEL<16><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;               \
+    case 32: KERNEL<32><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;               \
+    default: KERNEL<64><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;               \
+    }
 
 void launch_long_rows(int n, const int *ptr, int lim, int *flags, int *list, int *count_dev, int *scan_tmp,
                       hipStream_t s)
@@ -635,17 +905,6 @@ void launch_long_rows(int n, const int *ptr, int lim, int *flags, int *list, int
     k_long_compact<<<grid_for(n), kBlock, 0, s>>>(n, ptr, lim, flags, list);
     AMG_HIP(hipGetLastError());
 }
-
-#define AMG_LAUNCH_G(G, KERNEL, GRID, STREAM, ...)                                      \
-    switch (G) {                                                                        \
-    case 1: KERNEL<1><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;                 \
-    case 2: KERNEL<2><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;                 \
-    case 4: KERNEL<4><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;                 \
-    case 8: KERNEL<8><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;                 \
-    case 16: KERNEL<16><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;               \
-    case 32: KERNEL<32><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;               \
-    default: KERNEL<64><<<GRID, kBlock, 0, STREAM>>>(__VA_ARGS__); break;               \
-    }
 
 void launch_validate_csr(int n, int nnz, const int *rp, const int *ci, const double *va, int *err, hipStream_t s)
 {
@@ -666,11 +925,12 @@ void launch_priorities(int n, const int *rp, uint32_t s_l, uint64_t *key, int *o
 }
 
 void launch_mis_pass(int n, const int *rp, const int *ci, uint64_t *key, uint64_t *m1, int *owner, int cap, int G,
-                     unsigned *done_counter, hipStream_t s)
+                     unsigned *done_counter, const int *hubs, int nhub, int lim, hipStream_t s)
 {
-    const int grid = grid_for((int64_t)n * G);
-    AMG_LAUNCH_G(G, k_mis_max1, grid, s, n, rp, ci, key, m1);
-    AMG_LAUNCH_G(G, k_mis_select_claim, grid, s, n, rp, ci, key, m1, owner, cap, done_counter);
+    const int nhb = nhub < kLongBlocks ? nhub : kLongBlocks;
+    const int grid = nhb + grid_for((int64_t)n * G);
+    AMG_LAUNCH_G(G, k_mis_max1, grid, s, n, rp, ci, key, m1, hubs, nhub, lim);
+    AMG_LAUNCH_G(G, k_mis_select_claim, grid, s, n, rp, ci, key, m1, owner, cap, done_counter, hubs, nhub, lim);
     AMG_HIP(hipGetLastError());
 }
 
@@ -689,14 +949,16 @@ void launch_assign_aggregates(int n, const int *owner, const int *cid, int *agg,
 void launch_member_counts(int nc, const int *rp, const int *ci, const int *owner, const int *centre_of, int *size,
                           int *pairs, hipStream_t s)
 {
-    k_member_counts<<<grid_for(nc), kBlock, 0, s>>>(nc, rp, ci, owner, centre_of, size, pairs);
+    const int G = wide(nc) ? kWave : 1;
+    AMG_LAUNCH_G(G, k_member_counts, grid_for((int64_t)nc * G), s, nc, rp, ci, owner, centre_of, size, pairs);
     AMG_HIP(hipGetLastError());
 }
 
 void launch_member_fill(int nc, const int *rp, const int *ci, const int *owner, const int *centre_of,
                         const int *aptr, int *members, hipStream_t s)
 {
-    k_member_fill<<<grid_for(nc), kBlock, 0, s>>>(nc, rp, ci, owner, centre_of, aptr, members);
+    const int G = wide(nc) ? kWave : 1;
+    AMG_LAUNCH_G(G, k_member_fill, grid_for((int64_t)nc * G), s, nc, rp, ci, owner, centre_of, aptr, members);
     AMG_HIP(hipGetLastError());
 }
 
@@ -719,15 +981,16 @@ void launch_coarse_big_rows(int nbig, const int *big_rows, const int64_t *scratc
                             const int *members, const int *tptr, int *tcol, double *tval, int *cnt, hipStream_t s)
 {
     if (nbig <= 0) return;
-    k_coarse_big_rows<<<nbig, kBlock, 0, s>>>(big_rows, scratch_off, skey, rp, ci, va, agg, aptr, members, tptr, tcol,
-                                             tval, cnt);
+    k_coarse_big_rows<<<nbig, kBigThreads, 0, s>>>(big_rows, scratch_off, skey, rp, ci, va, agg, aptr, members, tptr,
+                                                   tcol, tval, cnt);
     AMG_HIP(hipGetLastError());
 }
 
 void launch_coarse_compact(int nc, const int *tptr, const int *tcol, const double *tval, const int *crp, int *cci,
                            double *cva, double *cminv, hipStream_t s)
 {
-    k_coarse_compact<<<grid_for(nc), kBlock, 0, s>>>(nc, tptr, tcol, tval, crp, cci, cva, cminv);
+    const int G = wide(nc) ? kWave : 1;
+    AMG_LAUNCH_G(G, k_coarse_compact, grid_for((int64_t)nc * G), s, nc, tptr, tcol, tval, crp, cci, cva, cminv);
     AMG_HIP(hipGetLastError());
 }
 
@@ -758,8 +1021,9 @@ void launch_sizes_in_position_order(int nc, const int *aptr_nat, const int *perm
 void launch_positions_from_segments(int nc, const int *aptr_nat, const int *members_nat, const int *pos_c,
                                     const int *seg_ptr, int *pos_f, int *perm_f, hipStream_t s)
 {
-    k_positions_from_segments<<<grid_for(nc), kBlock, 0, s>>>(nc, aptr_nat, members_nat, pos_c, seg_ptr, pos_f,
-                                                             perm_f);
+    const int G = wide(nc) ? kWave : 1;
+    AMG_LAUNCH_G(G, k_positions_from_segments, grid_for((int64_t)nc * G), s, nc, aptr_nat, members_nat, pos_c,
+                 seg_ptr, pos_f, perm_f);
     AMG_HIP(hipGetLastError());
 }
 
@@ -773,7 +1037,9 @@ void launch_permute_rows(int n, const int *rp_nat, const int *ci_nat, const doub
                          const int *perm, const int *pos, const int *rp, int *ci, double *va, double *minv,
                          hipStream_t s)
 {
-    k_permute_rows<<<grid_for(n), kBlock, 0, s>>>(n, rp_nat, ci_nat, va_nat, minv_nat, perm, pos, rp, ci, va, minv);
+    const int G = wide(n) ? kWave : 8;
+    AMG_LAUNCH_G(G, k_permute_rows, grid_for((int64_t)n * G), s, n, rp_nat, ci_nat, va_nat, minv_nat, perm, pos, rp,
+                 ci, va, minv);
     AMG_HIP(hipGetLastError());
 }
 

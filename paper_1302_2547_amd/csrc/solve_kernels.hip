@@ -60,23 +60,68 @@ __device__ inline double block_sum(double v)
     return s;
 }
 
-// Value of a dot product from its partials (same value in every thread).
+// Sums N values over the block in one synchronisation round; every thread
+// receives the sums (fixed order).
+template <int N>
+__device__ inline void block_sums(double (&v)[N])
+{
+    __shared__ double sh[N][kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int d = 0; d < N; d++) {
+        const double t = wave_sum(v[d]);
+        if (lane == 0) sh[d][wid] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < N; d++) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; w++) t += sh[d][w];
+        v[d] = t;
+    }
+    __syncthreads();
+}
+
+// Values of N dot products from their partials (same values in every thread).
+template <int N>
+__device__ inline void dot_values(const DotRef *refs, double (&out)[N])
+{
+    bool all_final = true;
+#pragma unroll
+    for (int d = 0; d < N; d++) all_final = all_final && refs[d].count == 1;
+    if (all_final) {
+#pragma unroll
+        for (int d = 0; d < N; d++) out[d] = refs[d].part[0];
+        return;
+    }
+#pragma unroll
+    for (int d = 0; d < N; d++) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < refs[d].count; b += kBlock) t += refs[d].part[b];
+        out[d] = t;
+    }
+    block_sums<N>(out);
+}
+
 __device__ inline double dot_value(DotRef r)
 {
-    if (r.count == 1) return r.part[0];
-    double s = 0.0;
-    for (int b = threadIdx.x; b < r.count; b += kBlock) s += r.part[b];
-    return block_sum(s);
+    double v[1];
+    dot_values<1>(&r, v);
+    return v[0];
 }
 
 // Writes this block's partials of ND dot products: part[d * kPartStride + block].
 template <int ND>
 __device__ inline void store_partials(const double (&v)[ND], double *part)
 {
+    double t[ND];
 #pragma unroll
-    for (int d = 0; d < ND; d++) {
-        const double s = block_sum(v[d]);
-        if (threadIdx.x == 0) part[d * kPartStride + blockIdx.x] = s;
+    for (int d = 0; d < ND; d++) t[d] = v[d];
+    block_sums<ND>(t);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int d = 0; d < ND; d++) part[d * kPartStride + blockIdx.x] = t[d];
     }
 }
 
@@ -201,12 +246,31 @@ __global__ void __launch_bounds__(kBlock) k_residual(Rows R, const int *__restri
     store_partials<2>(d, part);
 }
 
-__global__ void __launch_bounds__(kBlock) k_reduce_partials(int nd, const double *__restrict__ part, int count,
-                                                            double *__restrict__ out)
+// One block of 1024 threads reduces large partial sets (fixed order).
+constexpr int kReduceThreads = 1024;
+__global__ void __launch_bounds__(kReduceThreads) k_reduce_partials(int nd, const double *__restrict__ part,
+                                                                    int count, double *__restrict__ out)
 {
+    __shared__ double sh[kReduceThreads / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     for (int d = 0; d < nd; d++) {
-        const double v = dot_value(DotRef{part + d * kPartStride, count});
-        if (threadIdx.x == 0) out[d] = v;
+        const double *src = part + d * kPartStride;
+        double t[4] = {0.0, 0.0, 0.0, 0.0};
+        int b = threadIdx.x;
+        for (; b + 3 * kReduceThreads < count; b += 4 * kReduceThreads) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) t[u] += src[b + u * kReduceThreads];
+        }
+        for (; b < count; b += kReduceThreads) t[0] += src[b];
+        double v = wave_sum((t[0] + t[1]) + (t[2] + t[3]));
+        if (lane == 0) sh[wid] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0.0;
+            for (int w = 0; w < kReduceThreads / kWave; w++) a += sh[w];
+            out[d] = a;
+        }
+        __syncthreads();
     }
 }
 
@@ -243,13 +307,23 @@ struct KCoef {
 __device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd)
 {
     KCoef c{0.0, 0.0, false};
-    if (mode == 0) return c;
-    const double rho1 = dot_value(kd.rho1), alpha1 = dot_value(kd.alpha1);
-    double beta = 0.0, gamma = 0.0, alpha2 = 0.0;
+    if (mode == 0 || mode == 3) return c;
+    double rho1, alpha1, beta = 0.0, gamma = 0.0, alpha2 = 0.0;
     if (mode == 2) {
-        beta = dot_value(kd.beta);
-        gamma = dot_value(kd.gamma);
-        alpha2 = dot_value(kd.alpha2);
+        const DotRef refs[5] = {kd.rho1, kd.alpha1, kd.beta, kd.gamma, kd.alpha2};
+        double v[5];
+        dot_values<5>(refs, v);
+        rho1 = v[0];
+        alpha1 = v[1];
+        beta = v[2];
+        gamma = v[3];
+        alpha2 = v[4];
+    } else {
+        const DotRef refs[2] = {kd.rho1, kd.alpha1};
+        double v[2];
+        dot_values<2>(refs, v);
+        rho1 = v[0];
+        alpha1 = v[1];
     }
     if (!(rho1 > 0.0)) {
         c.bad = true;
@@ -269,6 +343,34 @@ __device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd)
     return c;
 }
 
+// Restriction of the inner residual of the parent's first flexible-CG step:
+// rt = rcf - (alpha1/rho1) v1 is formed on the fly (and stored for the later
+// kernels of the visit), rc = W rt.
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_restrict_rt(Rows S, int nf, const int *__restrict__ ci,
+                                                        const double *__restrict__ wv,
+                                                        const double *__restrict__ rcf,
+                                                        const double *__restrict__ v1, KDots kd,
+                                                        double *__restrict__ rt, double *__restrict__ rc,
+                                                        int *__restrict__ flag)
+{
+    const KCoef c = kcycle_coefficients(1, kd);
+    if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
+    const double a = c.a1;
+    for (int q = blockIdx.x * kBlock + threadIdx.x; q < nf; q += gridDim.x * kBlock) rt[q] = rcf[q] - a * v1[q];
+    visit_rows<G>(
+        S,
+        [&](int b, int e, int lane, int width) {
+            double s = 0.0;
+            for (int p = b + lane; p < e; p += width) {
+                const int t = ci[p];
+                s += wv[p] * (rcf[t] - a * v1[t]);
+            }
+            return s;
+        },
+        [&](int Q, double s, int) { rc[Q] = s; });
+}
+
 // rt = rc - (alpha1/rho1) v1
 __global__ void __launch_bounds__(kBlock) k_inner_residual(int n, const double *__restrict__ rc,
                                                            const double *__restrict__ v1, KDots kd,
@@ -280,26 +382,41 @@ __global__ void __launch_bounds__(kBlock) k_inner_residual(int n, const double *
 }
 
 // Prolongation + post-smoothing: x = M^-1 r + P e (the pre-smoothed iterate plus
-// the coarse correction) is formed on the fly for every column, then
+// the coarse correction) is formed on the fly for every column (cagg[p], when
+// given, is the coarse unknown of column ci[p] stored per entry: on small,
+// latency-bound levels it saves a dependent gather), then
 // out = x + M^-1 (r - A x).  mode 0: e = edirect; mode 1: e = a1 c1;
-// mode 2: e = a1 c1 + a2 c2.  DOT adds partials of (out, wdot).
+// mode 2: e = a1 c1 + a2 c2; mode 3: e = ainv edirect (small dense coarsest level).
+// DOT adds partials of (out, wdot).
 template <int G, int MODE, bool DOT>
 __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__restrict__ ci,
                                                         const double *__restrict__ va,
                                                         const double *__restrict__ minv,
                                                         const double *__restrict__ r,
                                                         const int *__restrict__ agg_pos,
+                                                        const int *__restrict__ cagg,
                                                         const double *__restrict__ edirect,
                                                         const double *__restrict__ c1,
                                                         const double *__restrict__ c2, KDots kd,
                                                         double *__restrict__ xout, const double *__restrict__ wdot,
-                                                        double *__restrict__ part, int *__restrict__ flag)
+                                                        double *__restrict__ part, int *__restrict__ flag,
+                                                        const double *__restrict__ ainv, int nc)
 {
     const KCoef c = kcycle_coefficients(MODE, kd);
     if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
     const double a1 = c.a1, a2 = c.a2;
+    __shared__ double e_sh[MODE == 3 ? kInlineCoarse : 1];
+    if (MODE == 3) {  // e = A_coarsest^-1 rc, computed by every block into LDS
+        for (int i = threadIdx.x; i < nc; i += kBlock) {
+            double t = 0.0;
+            for (int j = 0; j < nc; j++) t += ainv[i * nc + j] * edirect[j];
+            e_sh[i] = t;
+        }
+        __syncthreads();
+    }
     auto corr = [&](int J) -> double {
         if (MODE == 0) return edirect[J];
+        if (MODE == 3) return e_sh[J];
         if (MODE == 1) return a1 * c1[J];
         return a1 * c1[J] + a2 * c2[J];
     };
@@ -311,7 +428,7 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
             double s = 0.0;
             for (int p = b + lane; p < e; p += width) {
                 const int t = ci[p];
-                s += va[p] * (minv[t] * r[t] + corr(agg_pos[t]));
+                s += va[p] * (minv[t] * r[t] + corr(cagg ? cagg[p] : agg_pos[t]));
             }
             return s;
         },
@@ -396,19 +513,30 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int n, const double *__restr
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[idx[i]] = src[i];
 }
 
-// w_e = [col(e) is the row's diagonal] - a_e minv_col(e) for every entry (solve layout)
+// w_e = [col(e) is the row's diagonal] - a_e minv_col(e) for every entry (solve
+// layout); G lanes per row
+template <int G>
 __global__ void __launch_bounds__(kBlock) k_restriction_weights(int n, const int *__restrict__ rp,
                                                                 const int *__restrict__ ci,
                                                                 const double *__restrict__ va,
                                                                 const double *__restrict__ minv,
                                                                 double *__restrict__ wv)
 {
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= n) return;
-    for (int p = rp[q]; p < rp[q + 1]; p++) {
-        const int t = ci[p];
-        wv[p] = (t == q ? 1.0 : 0.0) - va[p] * minv[t];
+    const int sub = threadIdx.x % G;
+    const int ngroups = gridDim.x * (kBlock / G);
+    for (int q = (blockIdx.x * kBlock + threadIdx.x) / G; q < n; q += ngroups) {
+        for (int p = rp[q] + sub; p < rp[q + 1]; p += G) {
+            const int t = ci[p];
+            wv[p] = (t == q ? 1.0 : 0.0) - va[p] * minv[t];
+        }
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_entry_coarse_column(int nnz, const int *__restrict__ ci,
+                                                                const int *__restrict__ agg_pos,
+                                                                int *__restrict__ cagg)
+{
+    for (int p = blockIdx.x * kBlock + threadIdx.x; p < nnz; p += gridDim.x * kBlock) cagg[p] = agg_pos[ci[p]];
 }
 
 inline int rows_grid(const Rows &R, int G, int cap)
@@ -419,12 +547,12 @@ inline int rows_grid(const Rows &R, int G, int cap)
 
 // Partial sets larger than this are reduced by one extra block instead of by
 // every consumer block.
-constexpr int kConsumerReduceMax = 96;
+constexpr int kConsumerReduceMax = 1024;
 
 void reduce_if_large(int nd, double *part, int count, double *final_out, hipStream_t s)
 {
     if (count > kConsumerReduceMax && final_out) {
-        k_reduce_partials<<<1, kBlock, 0, s>>>(nd, part, count, final_out);
+        k_reduce_partials<<<1, kReduceThreads, 0, s>>>(nd, part, count, final_out);
         AMG_HIP(hipGetLastError());
     }
 }
@@ -502,7 +630,7 @@ DotSet launch_residual(Rows R, const int *ci, const double *va, const double *b,
 
 void launch_reduce(const DotRef &ref, double *out, hipStream_t s)
 {
-    k_reduce_partials<<<1, kBlock, 0, s>>>(1, ref.part, ref.count, out);
+    k_reduce_partials<<<1, kReduceThreads, 0, s>>>(1, ref.part, ref.count, out);
     AMG_HIP(hipGetLastError());
 }
 
@@ -520,20 +648,24 @@ void launch_inner_residual(int n, const double *rc, const double *v1, KDots kd, 
 }
 
 DotRef launch_post_smooth(Rows R, const int *ci, const double *va, const double *minv, const double *r,
-                          const int *agg_pos, int mode, const double *edirect, const double *c1, const double *c2,
-                          KDots kd, double *xout, const double *wdot, DotBuf buf, int *flag, int G, hipStream_t s)
+                          const int *agg_pos, const int *cagg, int mode, const double *edirect, const double *c1, const double *c2,
+                          KDots kd, double *xout, const double *wdot, DotBuf buf, int *flag, int G, hipStream_t s,
+                          const double *ainv, int nc)
 {
     const bool dot = wdot != nullptr;
     const int grid = rows_grid(R, G, dot ? kMaxDotBlocks : (1 << 20));
 #define AMG_POST(M, D)                                                                                      \
-    AMG_SWITCH_G(G, (k_post_smooth<kG, M, D><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, agg_pos, edirect, \
-                                                                      c1, c2, kd, xout, wdot, buf.part, flag)))
-    if (mode == 0) {
-        if (dot) { AMG_POST(0, true); } else { AMG_POST(0, false); }
-    } else if (mode == 1) {
-        if (dot) { AMG_POST(1, true); } else { AMG_POST(1, false); }
-    } else {
-        if (dot) { AMG_POST(2, true); } else { AMG_POST(2, false); }
+    AMG_SWITCH_G(G, (k_post_smooth<kG, M, D><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, agg_pos, cagg, edirect, \
+                                                                      c1, c2, kd, xout, wdot, buf.part, flag, \
+                                                                      ainv, nc)))
+    switch (mode) {
+    case 0: if (dot) { AMG_POST(0, true); } else { AMG_POST(0, false); } break;
+    case 1: if (dot) { AMG_POST(1, true); } else { AMG_POST(1, false); } break;
+    case 2: if (dot) { AMG_POST(2, true); } else { AMG_POST(2, false); } break;
+    default:
+        if (nc < 1 || nc > kInlineCoarse || !ainv) throw Error(4, "inline coarsest solve out of range");
+        if (dot) { AMG_POST(3, true); } else { AMG_POST(3, false); }
+        break;
     }
 #undef AMG_POST
     AMG_HIP(hipGetLastError());
@@ -541,6 +673,14 @@ DotRef launch_post_smooth(Rows R, const int *ci, const double *va, const double 
     const int count = grid + R.nlong;
     reduce_if_large(1, buf.part, count, buf.final_out, s);
     return finished(buf.part, count, buf.final_out, 0);
+}
+
+void launch_restrict_rt(Rows S, int nf, const int *ci, const double *wv, const double *rcf, const double *v1,
+                        KDots kd, double *rt, double *rc, int *flag, int G, hipStream_t s)
+{
+    const int grid = rows_grid(S, G, 1 << 20);
+    AMG_SWITCH_G(G, (k_restrict_rt<kG><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, rcf, v1, kd, rt, rc, flag)));
+    AMG_HIP(hipGetLastError());
 }
 
 void launch_dense_gemv(int n, const double *a, const double *x, double *y, hipStream_t s)
@@ -586,10 +726,17 @@ void launch_scatter(int n, const double *src, const int *idx, double *dst, hipSt
     AMG_HIP(hipGetLastError());
 }
 
+void launch_entry_coarse_column(int nnz, const int *ci, const int *agg_pos, int *cagg, hipStream_t s)
+{
+    k_entry_coarse_column<<<grid_for(nnz, 8192), kBlock, 0, s>>>(nnz, ci, agg_pos, cagg);
+    AMG_HIP(hipGetLastError());
+}
+
 void launch_restriction_weights(int n, const int *rp, const int *ci, const double *va, const double *minv, double *wv,
                                 hipStream_t s)
 {
-    k_restriction_weights<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, va, minv, wv);
+    if (n < kSmallLevel) k_restriction_weights<kWave><<<grid_for((int64_t)n * kWave), kBlock, 0, s>>>(n, rp, ci, va, minv, wv);
+    else k_restriction_weights<8><<<grid_for((int64_t)n * 8), kBlock, 0, s>>>(n, rp, ci, va, minv, wv);
     AMG_HIP(hipGetLastError());
 }
 
