@@ -388,7 +388,7 @@ __global__ void __launch_bounds__(kBlock) k_inner_residual(int n, const double *
 // out = x + M^-1 (r - A x).  mode 0: e = edirect; mode 1: e = a1 c1;
 // mode 2: e = a1 c1 + a2 c2; mode 3: e = ainv edirect (small dense coarsest level).
 // DOT adds partials of (out, wdot).
-template <int G, int MODE, bool DOT>
+template <int G, int MODE, bool DOT, bool CAGG>
 __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__restrict__ ci,
                                                         const double *__restrict__ va,
                                                         const double *__restrict__ minv,
@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
             double s = 0.0;
             for (int p = b + lane; p < e; p += width) {
                 const int t = ci[p];
-                s += va[p] * (minv[t] * r[t] + corr(cagg ? cagg[p] : agg_pos[t]));
+                s += va[p] * (minv[t] * r[t] + corr(CAGG ? cagg[p] : agg_pos[t]));
             }
             return s;
         },
@@ -654,10 +654,18 @@ DotRef launch_post_smooth(Rows R, const int *ci, const double *va, const double 
 {
     const bool dot = wdot != nullptr;
     const int grid = rows_grid(R, G, dot ? kMaxDotBlocks : (1 << 20));
-#define AMG_POST(M, D)                                                                                      \
-    AMG_SWITCH_G(G, (k_post_smooth<kG, M, D><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, agg_pos, cagg, edirect, \
-                                                                      c1, c2, kd, xout, wdot, buf.part, flag, \
-                                                                      ainv, nc)))
+#define AMG_POST(M, D)                                                                                        \
+    do {                                                                                                      \
+        if (cagg) {                                                                                           \
+            AMG_SWITCH_G(G, (k_post_smooth<kG, M, D, true><<<grid, kBlock, 0, s>>>(                           \
+                                R, ci, va, minv, r, agg_pos, cagg, edirect, c1, c2, kd, xout, wdot, buf.part, flag, \
+                                ainv, nc)));                                                                  \
+        } else {                                                                                              \
+            AMG_SWITCH_G(G, (k_post_smooth<kG, M, D, false><<<grid, kBlock, 0, s>>>(                          \
+                                R, ci, va, minv, r, agg_pos, cagg, edirect, c1, c2, kd, xout, wdot, buf.part, flag, \
+                                ainv, nc)));                                                                  \
+        }                                                                                                     \
+    } while (0)
     switch (mode) {
     case 0: if (dot) { AMG_POST(0, true); } else { AMG_POST(0, false); } break;
     case 1: if (dot) { AMG_POST(1, true); } else { AMG_POST(1, false); } break;
