@@ -98,8 +98,16 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt, amg_hierarchy **o
  * AMG_ERR_NOT_CONVERGED).  info (may be NULL) is filled on those two statuses. */
 amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, amg_solve_info *info);
 
-/* Releases every resource of h.  NULL is accepted. */
+/* Releases every resource of h.  NULL is accepted.  Device blocks are kept in a
+ * process-wide cache (per device and size class) for later hierarchies, because
+ * returning memory to the driver synchronises the device; see
+ * amg_release_cached_memory. */
 void amg_free(amg_hierarchy *h);
+
+/* Returns every cached device block to the driver.  Blocks in use by live
+ * hierarchies are not affected.  An allocation that the driver refuses does this
+ * by itself before it fails.  Call it with no solve in flight on any stream. */
+void amg_release_cached_memory(void);
 
 /* Number of levels (finest = 0, coarsest = levels - 1). */
 amg_status amg_num_levels(const amg_hierarchy *h, int32_t *levels);

@@ -56,6 +56,7 @@ _sig = {
     "amg_setup": (ctypes.c_int, [ctypes.POINTER(amg_csr), ctypes.POINTER(amg_options), ctypes.POINTER(_P)]),
     "amg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(amg_solve_info)]),
     "amg_free": (None, [_P]),
+    "amg_release_cached_memory": (None, []),
     "amg_num_levels": (ctypes.c_int, [_P, _I32P]),
     "amg_level_sizes": (ctypes.c_int, [_P, ctypes.c_int32, _I32P, _I32P, _I32P]),
     "amg_export_level": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),

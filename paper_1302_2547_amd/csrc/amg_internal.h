@@ -96,6 +96,12 @@ void launch_coarse_rows(int nc, const int *rp, const int *ci, const double *va, 
                         const int *members, const int *tptr, int *tcol, double *tval, int *cnt, int *big_rows,
                         unsigned *big_count, hipStream_t s);
 int coarse_wave_capacity();
+// Largest coarse level size whose dense accumulator fits in LDS beside the big-row
+// kernel's other shared arrays; rows of such levels need no global scratch.
+int coarse_acc_capacity();
+void launch_coarse_big_rows_acc(int nbig, const int *big_rows, int nc, const int *rp, const int *ci, const double *va,
+                                const int *agg, const int *aptr, const int *members, const int *tptr, int *tcol,
+                                double *tval, int *cnt, hipStream_t s);
 void launch_coarse_big_rows(int nbig, const int *big_rows, const int64_t *scratch_off, uint64_t *skey,
                             const int *rp, const int *ci, const double *va, const int *agg, const int *aptr,
                             const int *members, const int *tptr, int *tcol, double *tval, int *cnt,

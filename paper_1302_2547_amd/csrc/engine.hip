@@ -8,10 +8,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -43,13 +46,20 @@ bool trace_on()
     }();
     return on;
 }
-#define AMG_TRACE_MSG(...)                          \
-    do {                                            \
-        if (::amg::trace_on()) {                    \
-            std::fprintf(stderr, "[amg] " __VA_ARGS__); \
-            std::fputc('\n', stderr);                \
-            std::fflush(stderr);                    \
-        }                                           \
+// Milliseconds since the first call (trace time stamps).
+double trace_ms()
+{
+    static const auto t0 = std::chrono::steady_clock::now();
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+#define AMG_TRACE_MSG(...)                                                \
+    do {                                                                  \
+        if (::amg::trace_on()) {                                          \
+            std::fprintf(stderr, "[amg %10.3f ms] ", ::amg::trace_ms());  \
+            std::fprintf(stderr, __VA_ARGS__);                            \
+            std::fputc('\n', stderr);                                     \
+            std::fflush(stderr);                                          \
+        }                                                                 \
     } while (0)
 
 namespace {
@@ -63,23 +73,108 @@ uint64_t splitmix64(uint64_t seed, uint64_t k)
     return z ^ (z >> 31);
 }
 
-// Device allocations of one hierarchy, with an optional byte budget.
+// Process-wide cache of device blocks.  hipFree synchronises the device and is
+// slow, so blocks a hierarchy releases are kept, per device and size class, for
+// the next allocation of the same class.  An allocation that the driver refuses
+// returns the cached blocks first and tries again; amg_release_cached_memory()
+// returns them on request.
+class BlockCache {
+public:
+    static BlockCache &get()
+    {
+        static BlockCache c;
+        return c;
+    }
+    // Bytes actually reserved for a request: 256 B classes up to 1 MiB, 64 KiB
+    // classes up to 64 MiB, 2 MiB classes above.
+    static size_t size_class(size_t bytes)
+    {
+        const size_t q = bytes <= (1u << 20) ? 256 : (bytes <= (64u << 20) ? (64u << 10) : (2u << 20));
+        return (bytes + q - 1) / q * q;
+    }
+    void *take(size_t cls)
+    {
+        int dev = 0;
+        AMG_HIP(hipGetDevice(&dev));
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = free_.find(Key{dev, cls});
+            if (it != free_.end()) {
+                void *p = it->second;
+                free_.erase(it);
+                cached_ -= cls;
+                return p;
+            }
+        }
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, cls);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            release_all();
+            e = hipMalloc(&p, cls);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        return p;
+    }
+    void give(void *p, size_t cls, int dev)
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        free_.emplace(Key{dev, cls}, p);
+        cached_ += cls;
+    }
+    void release_all()
+    {
+        std::multimap<Key, void *> out;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            out.swap(free_);
+            cached_ = 0;
+        }
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        for (auto &kv : out) {
+            (void)hipSetDevice(kv.first.dev);
+            (void)hipFree(kv.second);
+        }
+        (void)hipSetDevice(cur);
+    }
+
+private:
+    struct Key {
+        int dev;
+        size_t cls;
+        bool operator<(const Key &o) const { return dev != o.dev ? dev < o.dev : cls < o.cls; }
+    };
+    std::mutex mu_;
+    std::multimap<Key, void *> free_;
+    size_t cached_ = 0;
+};
+
+// Device allocations of one hierarchy, with an optional byte budget (counted in
+// requested bytes).  Blocks go back to the process-wide cache, not the driver.
 struct Pool {
+    struct Block {
+        void *p;
+        size_t bytes, cls;
+        int dev;
+    };
     size_t used = 0, peak = 0, budget = 0;
-    std::vector<std::pair<void *, size_t>> blocks;
+    std::vector<Block> blocks;
 
     template <class T>
     T *alloc(size_t count)
     {
         const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
         if (budget && used + bytes > budget) throw Error(AMG_ERR_OUT_OF_MEMORY, "mem_budget exceeded");
-        void *p = nullptr;
-        const hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            throw Error(AMG_ERR_OUT_OF_MEMORY, "hipMalloc");
-        }
-        blocks.emplace_back(p, bytes);
+        const size_t cls = BlockCache::size_class(bytes);
+        void *p = BlockCache::get().take(cls);
+        if (!p) throw Error(AMG_ERR_OUT_OF_MEMORY, "hipMalloc");
+        int dev = 0;
+        AMG_HIP(hipGetDevice(&dev));
+        blocks.push_back(Block{p, bytes, cls, dev});
         used += bytes;
         peak = std::max(peak, used);
         return static_cast<T *>(p);
@@ -87,10 +182,10 @@ struct Pool {
     void release(void *p)
     {
         if (!p) return;
-        for (size_t k = 0; k < blocks.size(); k++) {
-            if (blocks[k].first == p) {
-                (void)hipFree(p);
-                used -= blocks[k].second;
+        for (size_t k = blocks.size(); k-- > 0;) {
+            if (blocks[k].p == p) {
+                BlockCache::get().give(p, blocks[k].cls, blocks[k].dev);
+                used -= blocks[k].bytes;
                 blocks.erase(blocks.begin() + (long)k);
                 return;
             }
@@ -98,7 +193,7 @@ struct Pool {
     }
     void release_all()
     {
-        for (auto &b : blocks) (void)hipFree(b.first);
+        for (auto &b : blocks) BlockCache::get().give(b.p, b.cls, b.dev);
         blocks.clear();
         used = 0;
     }
@@ -158,10 +253,13 @@ struct amg_hierarchy {
 
     ~amg_hierarchy()
     {
+        AMG_TRACE_MSG("free: start");
         if (stream) (void)hipStreamSynchronize(stream);
         for (hipGraphExec_t g : {g_kcycle, g_first, g_iter})
             if (g) (void)hipGraphExecDestroy(g);
+        AMG_TRACE_MSG("free: graphs destroyed");
         pool.release_all();
+        AMG_TRACE_MSG("free: device memory released");
         if (host) (void)hipHostFree(host);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -305,6 +403,7 @@ void amg_hierarchy::build(const amg_csr &A)
     if (read_int(ibuf) != 0) throw Error(AMG_ERR_INVALID_MATRIX, "invalid CSR");
     launch_l1_inverse_diagonal(n0, lev[0].rp_nat, lev[0].ci_nat, lev[0].va_nat, lev[0].minv_nat, stream);
 
+    const int acc_cap = coarse_acc_capacity();
     // Alg. 1: coarsen while n_l > n_0 and fewer than L levels exist
     int l = 0;
     while (lev[l].n > opt.coarsest_size && l + 1 < opt.max_levels) {
@@ -329,6 +428,7 @@ void amg_hierarchy::build(const amg_csr &A)
             if (now <= processed || now > (unsigned)n) throw Error(AMG_ERR_DEVICE, "aggregation made no progress");
             processed = now;
         }
+        AMG_TRACE_MSG("level %d: %d aggregation passes", l, passes);
         // Sec. 5.1: aggregates numbered by increasing coarse-vertex index
         launch_centre_flags(n, owner, cid, stream);
         scan(cid, cid, n, ibuf + 3, scan_tmp);
@@ -349,7 +449,10 @@ void amg_hierarchy::build(const amg_csr &A)
                            cnt, big_rows, big_count, stream);
         const int nbig = read_int(reinterpret_cast<int *>(big_count));
         AMG_TRACE_MSG("level %d: passes=%d nc=%d big rows=%d", l, passes, nc, nbig);
-        if (nbig > 0) {
+        if (nbig > 0 && nc <= acc_cap) {  // dense accumulator in LDS, rows listed on the device
+            launch_coarse_big_rows_acc(nbig, big_rows, nc, F.rp_nat, F.ci_nat, F.va_nat, F.agg_nat, F.aptr_nat,
+                                       F.members_nat, tptr, tcol, tval, cnt, stream);
+        } else if (nbig > 0) {
             std::vector<int> rows(nbig), tp(nc + 1);
             to_host(rows.data(), big_rows, nbig);
             to_host(tp.data(), tptr, nc + 1);
@@ -405,10 +508,12 @@ void amg_hierarchy::build(const amg_csr &A)
         pool.release(dense);
         if (err) throw Error(AMG_ERR_BREAKDOWN, "coarsest matrix is not positive definite");
     }
+    AMG_TRACE_MSG("coarsest inverse done; solve layout");
     finalize_layout();
-    pool.release(ibuf);
+    AMG_TRACE_MSG("solve layout done");
     AMG_HIP(hipEventRecord(ev1, stream));
     sync();
+    pool.release(ibuf);
     float ms = 0.f;
     AMG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     setup_ms = ms;
@@ -636,6 +741,7 @@ amg_status amg_hierarchy::solve(const double *b_user, double *x_user, double tol
     using namespace amg;
     Level &F = lev[0];
     const int n = F.n;
+    AMG_TRACE_MSG("solve: start");
     AMG_HIP(hipEventRecord(ev0, stream));
     capture_graphs();
     AMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
@@ -688,6 +794,7 @@ amg_status amg_hierarchy::solve(const double *b_user, double *x_user, double tol
     }
     AMG_HIP(hipEventRecord(ev1, stream));
     sync();
+    AMG_TRACE_MSG("solve: done after %d iterations", it);
     float ms = 0.f;
     AMG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     if (info) {
@@ -758,6 +865,7 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy 
     h->opt = opt;
     h->pool.budget = opt.mem_budget;
     amg_status st = guarded([&]() -> amg_status {
+        AMG_TRACE_MSG("setup: start");
         if (opt.stream) {
             h->stream = (hipStream_t)opt.stream;
         } else {
@@ -765,6 +873,7 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy 
             h->own_stream = true;
         }
         h->build(*A);
+        AMG_TRACE_MSG("setup: done");
         return AMG_OK;
     });
     if (st != AMG_OK) {
@@ -782,6 +891,14 @@ amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, a
 }
 
 void amg_free(amg_hierarchy *h) { delete h; }
+
+void amg_release_cached_memory(void)
+{
+    try {
+        amg::BlockCache::get().release_all();
+    } catch (...) {
+    }
+}
 
 amg_status amg_num_levels(const amg_hierarchy *h, int32_t *levels)
 {

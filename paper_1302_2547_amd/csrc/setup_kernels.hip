@@ -679,6 +679,174 @@ __global__ void __launch_bounds__(kBigThreads) k_coarse_big_rows(const int *__re
     if (threadIdx.x == 0) cnt[I] = u;
 }
 
+// Big rows on coarse levels small enough for a dense accumulator in LDS: one
+// block of kBigThreads per row.  The row's pairs are taken in position order
+// (members ascending, each member's entries in column order), kBigThreads at a
+// time; every batch is sorted by (J, position) -- in registers for strides
+// inside a wavefront, through LDS for the longer ones -- and each run of equal J
+// is added to acc[J] in position order.  Every coarse entry is therefore summed
+// in the order of the sequential definition, and the row never leaves LDS.
+constexpr uint64_t kUntouched = 0x7FF4C0A75E000001ull;  // a NaN payload arithmetic never makes
+constexpr int kAccStaticBytes = 32 * 1024;              // LDS of the kernel besides acc[]
+
+__device__ inline uint64_t block_sort_keys(uint64_t v, uint64_t *sk)
+{
+    const int t = threadIdx.x;
+    for (int size = 2; size <= kBigThreads; size <<= 1) {
+        const bool up = (t & size) == 0;
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            uint64_t o;
+            if (stride >= kWave) {  // uniform over the block
+                __syncthreads();
+                sk[t] = v;
+                __syncthreads();
+                o = sk[t ^ stride];
+            } else {
+                o = __shfl_xor(v, stride, kWave);
+            }
+            const bool lower = (t & stride) == 0;
+            v = (lower == up) ? (v < o ? v : o) : (v > o ? v : o);
+        }
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(kBigThreads) k_coarse_big_rows_acc(const int *__restrict__ big_rows, int nc,
+                                                                     const int *__restrict__ rp,
+                                                                     const int *__restrict__ ci,
+                                                                     const double *__restrict__ va,
+                                                                     const int *__restrict__ agg,
+                                                                     const int *__restrict__ aptr,
+                                                                     const int *__restrict__ members,
+                                                                     const int *__restrict__ tptr,
+                                                                     int *__restrict__ tcol, double *__restrict__ tval,
+                                                                     int *__restrict__ cnt)
+{
+    extern __shared__ double acc[];  // nc entries
+    __shared__ uint64_t sk[kBigThreads];
+    __shared__ double cv[kBigThreads];
+    __shared__ int mbeg[kBigThreads], mexcl[kBigThreads], hp[kBigThreads + 1];
+    __shared__ int sh_count[kBigThreads / kWave];
+    __shared__ int sh_tot, sh_out;
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int I = big_rows[blockIdx.x];
+    for (int J = t; J < nc; J += kBigThreads) acc[J] = __longlong_as_double((long long)kUntouched);
+    const int me = aptr[I + 1];
+    for (int m0 = aptr[I]; m0 < me; m0 += kBigThreads) {
+        // block-wide prefix of the row lengths of up to kBigThreads members
+        const int m = m0 + t;
+        int b = 0, len = 0;
+        if (m < me) {
+            const int sidx = members[m];
+            b = rp[sidx];
+            len = rp[sidx + 1] - b;
+        }
+        int incl = len;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += y;
+        }
+        __syncthreads();  // the previous group's readers of mbeg / mexcl / sh_count are done
+        if (lane == kWave - 1) sh_count[w] = incl;
+        __syncthreads();
+        int before = 0;
+        for (int k = 0; k < w; k++) before += sh_count[k];
+        incl += before;
+        mbeg[t] = b;
+        mexcl[t] = incl - len;
+        if (t == kBigThreads - 1) sh_tot = incl;
+        __syncthreads();
+        const int tot = sh_tot;
+        const int nm = (me - m0) < kBigThreads ? (me - m0) : kBigThreads;
+        for (int k0 = 0; k0 < tot; k0 += kBigThreads) {
+            const int k = k0 + t;
+            uint64_t key = ~0ull;
+            double v = 0.0;
+            if (k < tot) {
+                int lo = 0, hi = nm - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (mexcl[mid] <= k) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int p = mbeg[lo] + (k - mexcl[lo]);
+                key = ((uint64_t)(uint32_t)agg[ci[p]] << 32) | (uint32_t)t;
+                v = va[p];
+            }
+            cv[t] = v;
+            key = block_sort_keys(key, sk);
+            const bool valid = key != ~0ull;
+            const uint32_t J = (uint32_t)(key >> 32);
+            __syncthreads();
+            const double mv = valid ? cv[(uint32_t)key] : 0.0;
+            sk[t] = key;
+            __syncthreads();
+            cv[t] = mv;  // values in sorted order
+            const bool head = valid && (t == 0 || (uint32_t)(sk[t - 1] >> 32) != J);
+            const uint64_t hm = __ballot(head);
+            if (lane == 0) sh_count[w] = __popcll(hm);
+            __syncthreads();
+            int hb = 0, nh = 0;
+            for (int q = 0; q < kBigThreads / kWave; q++) {
+                if (q < w) hb += sh_count[q];
+                nh += sh_count[q];
+            }
+            if (head) hp[hb + __popcll(hm & below)] = t;
+            if (t == 0) hp[nh] = (tot - k0) < kBigThreads ? (tot - k0) : kBigThreads;
+            __syncthreads();
+            if (t < nh) {  // run t: its values in position order onto acc[J]
+                const int q = hp[t], qe = hp[t + 1];
+                const uint32_t JJ = (uint32_t)(sk[q] >> 32);
+                double a = acc[JJ];
+                if ((uint64_t)__double_as_longlong(a) == kUntouched) a = 0.0;
+                int r = q;
+                for (; r + 16 <= qe; r += 16) {  // LDS reads in flight together, adds in order
+                    double v[16];
+#pragma unroll
+                    for (int u = 0; u < 16; u++) v[u] = cv[r + u];
+#pragma unroll
+                    for (int u = 0; u < 16; u++) a += v[u];
+                }
+                for (; r < qe; r++) a += cv[r];
+                acc[JJ] = a;
+            }
+            __syncthreads();
+        }
+    }
+    // the touched columns in ascending order
+    const int base = tptr[I];
+    if (t == 0) sh_out = 0;
+    for (int J0 = 0; J0 < nc; J0 += kBigThreads) {
+        const int J = J0 + t;
+        double a = 0.0;
+        bool on = false;
+        if (J < nc) {
+            a = acc[J];
+            on = (uint64_t)__double_as_longlong(a) != kUntouched;
+        }
+        const uint64_t hm = __ballot(on);
+        __syncthreads();  // sh_out / sh_count of the previous round are read
+        if (lane == 0) sh_count[w] = __popcll(hm);
+        __syncthreads();
+        int ob = sh_out, tot = 0;
+        for (int q = 0; q < kBigThreads / kWave; q++) {
+            if (q < w) ob += sh_count[q];
+            tot += sh_count[q];
+        }
+        if (on) {
+            const int o = ob + __popcll(hm & below);
+            tcol[base + o] = J;
+            tval[base + o] = a;
+        }
+        __syncthreads();
+        if (t == 0) sh_out += tot;
+    }
+    __syncthreads();
+    if (t == 0) cnt[I] = sh_out;
+}
+
 // Copy the unique entries of every coarse row into the final CSR and form the
 // coarse l1 diagonal.  G = 1: the row is summed in column order; G = 64: lanes
 // share the row (used on small levels, whose hub rows are long).
@@ -983,6 +1151,26 @@ void launch_coarse_big_rows(int nbig, const int *big_rows, const int64_t *scratc
     if (nbig <= 0) return;
     k_coarse_big_rows<<<nbig, kBigThreads, 0, s>>>(big_rows, scratch_off, skey, rp, ci, va, agg, aptr, members, tptr,
                                                    tcol, tval, cnt);
+    AMG_HIP(hipGetLastError());
+}
+
+int coarse_acc_capacity()
+{
+    int dev = 0, lds = 0;
+    AMG_HIP(hipGetDevice(&dev));
+    AMG_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int bytes = lds - kAccStaticBytes;
+    return bytes > 0 ? bytes / (int)sizeof(double) : 0;
+}
+
+void launch_coarse_big_rows_acc(int nbig, const int *big_rows, int nc, const int *rp, const int *ci, const double *va,
+                                const int *agg, const int *aptr, const int *members, const int *tptr, int *tcol,
+                                double *tval, int *cnt, hipStream_t s)
+{
+    if (nbig <= 0) return;
+    const size_t lds = sizeof(double) * (size_t)nc;
+    k_coarse_big_rows_acc<<<nbig, kBigThreads, lds, s>>>(big_rows, nc, rp, ci, va, agg, aptr, members, tptr, tcol,
+                                                         tval, cnt);
     AMG_HIP(hipGetLastError());
 }
 

@@ -84,22 +84,52 @@ __device__ inline void block_sums(double (&v)[N])
 }
 
 // Values of N dot products from their partials (same values in every thread).
-template <int N>
+// PREFETCH = true (small, latency-bound levels): the block shares the loads --
+// the first kBlock * 4 partials of every product are loaded in one unrolled step
+// with clamped indices, so they are all in flight together (and with any row
+// loads issued before), then summed through LDS; the barrier waits for LDS
+// traffic only.  PREFETCH = false (large levels, whose partial sets are normally
+// reduced already) keeps a plain per-wavefront loop and few registers.
+template <int N, bool PREFETCH = true>
 __device__ inline void dot_values(const DotRef *refs, double (&out)[N])
 {
     bool all_final = true;
 #pragma unroll
     for (int d = 0; d < N; d++) all_final = all_final && refs[d].count == 1;
-    if (all_final) {
+    if (all_final) {  // one load each, no reduction
 #pragma unroll
         for (int d = 0; d < N; d++) out[d] = refs[d].part[0];
         return;
     }
+    if (!PREFETCH) {
+        const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+        for (int d = 0; d < N; d++) {
+            double t = 0.0;
+            for (int b = lane; b < refs[d].count; b += kWave) t += refs[d].part[b];
+            out[d] = wave_sum(t);
+        }
+        return;
+    }
+    const int t = threadIdx.x;
+    double v[N][4];
 #pragma unroll
     for (int d = 0; d < N; d++) {
-        double t = 0.0;
-        for (int b = threadIdx.x; b < refs[d].count; b += kBlock) t += refs[d].part[b];
-        out[d] = t;
+        const int last = refs[d].count - 1;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int b = t + u * kBlock;
+            v[d][u] = refs[d].part[b < last ? b : last];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < N; d++) {
+        const int count = refs[d].count;
+        double a = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) a += t + u * kBlock < count ? v[d][u] : 0.0;
+        for (int b = t + 4 * kBlock; b < count; b += kBlock) a += refs[d].part[b];  // beyond kBlock * 4
+        out[d] = a;
     }
     block_sums<N>(out);
 }
@@ -107,7 +137,7 @@ __device__ inline void dot_values(const DotRef *refs, double (&out)[N])
 __device__ inline double dot_value(DotRef r)
 {
     double v[1];
-    dot_values<1>(&r, v);
+    dot_values<1, false>(&r, v);
     return v[0];
 }
 
@@ -125,65 +155,156 @@ __device__ inline void store_partials(const double (&v)[ND], double *part)
     }
 }
 
-// Visits every row of R once and calls epi(row, sum, k) with the row's reduced
-// sum; k = -1 for an ordinary row, else the index of the hub row (0 .. nlong).
-// range(beg, end, lane, width) returns one lane's share of entries [beg, end).
-template <int G, class Range, class Epi>
-__device__ inline void visit_rows(const Rows &R, Range range, Epi epi)
+// Completes chunk c of a hub row after the block has summed it (s in every
+// thread): a row of one chunk is finished at once; otherwise the chunk sum is
+// published and the last chunk of the row to arrive adds all of them (its first
+// wavefront loads them together) and finishes the row.  done(row, sum, k) runs
+// in one thread.
+template <class Done>
+__device__ inline void finish_chunk(const Rows &R, int c, const Chunk &ch, double s, Done done)
+{
+    if (threadIdx.x >= kWave) return;
+    const int lane = threadIdx.x;
+    const int first = R.long_first[ch.k], m = R.long_first[ch.k + 1] - first;
+    if (m == 1) {
+        if (lane == 0) done(ch.row, s, ch.k);
+        return;
+    }
+    unsigned prev = 0;
+    if (lane == 0) {
+        __hip_atomic_store(&R.chunk_sum[c], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        prev = __hip_atomic_fetch_add(&R.arrive[ch.k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    prev = __shfl(prev, 0, kWave);
+    if (prev != (unsigned)(m - 1)) return;  // not the last chunk of this row
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double t = 0.0;
+    for (int j = lane; j < m; j += kWave)
+        t += __hip_atomic_load(&R.chunk_sum[first + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    t = wave_sum(t);
+    if (lane == 0) {
+        __hip_atomic_store(&R.arrive[ch.k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        done(ch.row, t, ch.k);
+    }
+}
+
+// Visits every row of R once.  The callbacks are ordered for latency:
+//   pre(row)            loads that depend only on the row index (issued together
+//                       with the row-pointer loads);
+//   prologue()          once per thread, after the first row's loads are in flight
+//                       (typically the reduction of inner-product partials);
+//   late(pv)            loads that need the prologue's results;
+//   term(p)             contribution of entry p;
+//   fin(row, s, k, lv)  the row's reduced sum; k = -1 for an ordinary row, else
+//                       the index of the hub row (0 .. nlong).
+// Hub-row chunks take all of their entries in one unrolled step (clamped
+// indices, no branches), so every load of a chunk is in flight at once.
+//
+// LAT = false (large, bandwidth-bound levels) keeps the registers few instead: the
+// prologue runs first, entries are taken in a plain loop, and pre / late run at
+// the end of each row.
+template <int G, bool LAT, class Prologue, class Pre, class Late, class Term, class Fin>
+__device__ inline void visit_rows(const Rows &R, Prologue prologue, Pre pre, Late late, Term term, Fin fin)
 {
     const int nlb = R.nchunks < kLongBlocks ? R.nchunks : kLongBlocks;
-    if ((int)blockIdx.x < nlb) {
-        for (int c = blockIdx.x; c < R.nchunks; c += nlb) {
-            const Chunk ch = R.chunks[c];
-            const double s = block_sum(range(ch.beg, ch.end, (int)threadIdx.x, kBlock));
-            const int first = R.long_first[ch.k], m = R.long_first[ch.k + 1] - first;
-            if (threadIdx.x == 0) {
-                if (m == 1) {
-                    epi(ch.row, s, ch.k);
-                } else {
-                    __hip_atomic_store(&R.chunk_sum[c], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const unsigned prev =
-                        __hip_atomic_fetch_add(&R.arrive[ch.k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-                    if (prev == (unsigned)(m - 1)) {  // last chunk of this row to finish
-                        double t = 0.0;
-                        for (int j = first; j < first + m; j++)
-                            t += __hip_atomic_load(&R.chunk_sum[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(&R.arrive[ch.k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        epi(ch.row, t, ch.k);
-                    }
-                }
+    if (!LAT) {
+        prologue();
+        if ((int)blockIdx.x < nlb) {
+            for (int c = blockIdx.x; c < R.nchunks; c += nlb) {
+                const Chunk ch = R.chunks[c];
+                double s = 0.0;
+                for (int p = ch.beg + (int)threadIdx.x; p < ch.end; p += kBlock) s += term(p);
+                s = block_sum(s);
+                finish_chunk(R, c, ch, s, [&](int row, double t, int k) { fin(row, t, k, late(pre(row))); });
             }
+            return;
+        }
+        const int sub = threadIdx.x % G;
+        const int ngroups = (gridDim.x - nlb) * (kBlock / G);
+        for (int row = ((blockIdx.x - nlb) * kBlock + threadIdx.x) / G; row < R.n; row += ngroups) {
+            const int b = R.ptr[row], e = R.ptr[row + 1];
+            if (e - b > R.lim) continue;  // hub row: served by the chunk blocks (uniform within the group)
+            double s = 0.0;
+            for (int p = b + sub; p < e; p += G) s += term(p);
+            s = group_sum<G>(s);
+            if (sub == 0) fin(row, s, -1, late(pre(row)));
+        }
+        return;
+    }
+    if ((int)blockIdx.x < nlb) {
+        int c = blockIdx.x;
+        Chunk ch = R.chunks[c];
+        auto pv = pre(ch.row);
+        prologue();
+        for (;;) {
+            const auto lv = late(pv);
+            double s = 0.0;
+#pragma unroll
+            for (int u = 0; u < kChunk / kBlock; u++) {
+                const int p = ch.beg + (int)threadIdx.x + u * kBlock;
+                const double t = term(p < ch.end ? p : ch.end - 1);
+                s += p < ch.end ? t : 0.0;
+            }
+            s = block_sum(s);
+            finish_chunk(R, c, ch, s, [&](int row, double t, int k) { fin(row, t, k, lv); });
+            c += nlb;
+            if (c >= R.nchunks) break;
+            ch = R.chunks[c];
+            pv = pre(ch.row);
         }
         return;
     }
     const int sub = threadIdx.x % G;
     const int ngroups = (gridDim.x - nlb) * (kBlock / G);
-    for (int row = ((blockIdx.x - nlb) * kBlock + threadIdx.x) / G; row < R.n; row += ngroups) {
-        const int b = R.ptr[row], e = R.ptr[row + 1];
-        if (e - b > R.lim) continue;  // hub row: served by the chunk blocks (uniform within the group)
-        const double s = group_sum<G>(range(b, e, sub, G));
-        if (sub == 0) epi(row, s, -1);
+    int row = ((blockIdx.x - nlb) * kBlock + threadIdx.x) / G;
+    int b = 0, e = 0;
+    if (row < R.n) {
+        b = R.ptr[row];
+        e = R.ptr[row + 1];
+    }
+    auto pv = pre(row < R.n ? row : R.n - 1);
+    prologue();
+    while (row < R.n) {
+        if (e - b <= R.lim) {  // hub rows are served by the chunk blocks (uniform within the group)
+            const auto lv = late(pv);
+            double s = 0.0;
+            if (b < e) {  // first step without a branch: most rows fit in G lanes
+                const int p = b + sub;
+                const double t = term(p < e ? p : e - 1);
+                s = p < e ? t : 0.0;
+                for (int q = p + G; q < e; q += G) s += term(q);
+            }
+            s = group_sum<G>(s);
+            if (sub == 0) fin(row, s, -1, lv);
+        }
+        row += ngroups;
+        if (row < R.n) {
+            b = R.ptr[row];
+            e = R.ptr[row + 1];
+            pv = pre(row);
+        }
     }
 }
 
+// Callbacks for rows that need nothing before or after their sum.
+struct NoRow {};
+#define AMG_NO_PRE [&](int) { return NoRow{}; }
+#define AMG_NO_PROLOGUE [&]() {}
+#define AMG_SAME [&](const auto &v) { return v; }
+
 // ------------------------------------------------------------------ SpMV family
 
-template <int G>
+template <int G, bool LAT>
 __global__ void __launch_bounds__(kBlock) k_spmv(Rows R, const int *__restrict__ ci, const double *__restrict__ va,
                                                  const double *__restrict__ x, double *__restrict__ y)
 {
-    visit_rows<G>(
-        R,
-        [&](int b, int e, int lane, int width) {
-            double s = 0.0;
-            for (int p = b + lane; p < e; p += width) s += va[p] * x[ci[p]];
-            return s;
-        },
-        [&](int row, double s, int) { y[row] = s; });
+    visit_rows<G, LAT>(
+        R, AMG_NO_PROLOGUE, AMG_NO_PRE, AMG_SAME, [&](int p) { return va[p] * x[ci[p]]; },
+        [&](int row, double s, int, const NoRow &) { y[row] = s; });
 }
 
 // y = A x (y may be NULL); dots (x, Ax) and, for each non-NULL w_j, (x, w_j).
-template <int G, int ND>
+template <int G, int ND, bool LAT>
 __global__ void __launch_bounds__(kBlock) k_spmv_dots(Rows R, const int *__restrict__ ci,
                                                       const double *__restrict__ va, const double *__restrict__ x,
                                                       double *__restrict__ y, const double *__restrict__ w1,
@@ -191,20 +312,24 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dots(Rows R, const int *__restr
 {
     double d[ND] = {};
     const int nb = gridDim.x;
-    visit_rows<G>(
-        R,
-        [&](int b, int e, int lane, int width) {
-            double s = 0.0;
-            for (int p = b + lane; p < e; p += width) s += va[p] * x[ci[p]];
-            return s;
+    struct Pre {
+        double xr, w1r, w2r;
+    };
+    visit_rows<G, LAT>(
+        R, AMG_NO_PROLOGUE,
+        [&](int row) {
+            Pre v{x[row], 0.0, 0.0};
+            if (ND > 1) v.w1r = w1[row];
+            if (ND > 2) v.w2r = w2[row];
+            return v;
         },
-        [&](int row, double s, int k) {
+        AMG_SAME, [&](int p) { return va[p] * x[ci[p]]; },
+        [&](int row, double s, int k, const Pre &v) {
             if (y) y[row] = s;
-            const double xr = x[row];
             double t[ND];
-            t[0] = xr * s;
-            if (ND > 1) t[1] = xr * w1[row];
-            if (ND > 2) t[2] = xr * w2[row];
+            t[0] = v.xr * s;
+            if (ND > 1) t[1] = v.xr * v.w1r;
+            if (ND > 2) t[2] = v.xr * v.w2r;
             if (k < 0) {
 #pragma unroll
                 for (int j = 0; j < ND; j++) d[j] += t[j];
@@ -225,15 +350,10 @@ __global__ void __launch_bounds__(kBlock) k_residual(Rows R, const int *__restri
 {
     double d[2] = {0.0, 0.0};
     const int nb = gridDim.x;
-    visit_rows<G>(
-        R,
-        [&](int beg, int end, int lane, int width) {
-            double s = 0.0;
-            for (int p = beg + lane; p < end; p += width) s += va[p] * x[ci[p]];
-            return s;
-        },
-        [&](int row, double s, int k) {
-            const double br = b[row], rr = br - s;
+    visit_rows<G, false>(
+        R, AMG_NO_PROLOGUE, [&](int row) { return b[row]; }, AMG_SAME, [&](int p) { return va[p] * x[ci[p]]; },
+        [&](int row, double s, int k, double br) {
+            const double rr = br - s;
             r[row] = rr;
             if (k < 0) {
                 d[0] += br * br;
@@ -279,19 +399,14 @@ __global__ void __launch_bounds__(kReduceThreads) k_reduce_partials(int nd, cons
 // Pre-smoothing from zero fused with residual and restriction.  With x = M^-1 r,
 // rc_Q = sum_{q in G_Q} (r - A x)_q = sum_{e in super-row Q} w_e r_{col(e)} where
 // w = P^T (I - A M^-1) is stored per entry (w_e = [diagonal] - a_e minv_col).
-template <int G>
+template <int G, bool LAT>
 __global__ void __launch_bounds__(kBlock) k_restrict(Rows S, const int *__restrict__ ci,
                                                      const double *__restrict__ wv, const double *__restrict__ r,
                                                      double *__restrict__ rc)
 {
-    visit_rows<G>(
-        S,
-        [&](int b, int e, int lane, int width) {
-            double s = 0.0;
-            for (int p = b + lane; p < e; p += width) s += wv[p] * r[ci[p]];
-            return s;
-        },
-        [&](int Q, double s, int) { rc[Q] = s; });
+    visit_rows<G, LAT>(
+        S, AMG_NO_PROLOGUE, AMG_NO_PRE, AMG_SAME, [&](int p) { return wv[p] * r[ci[p]]; },
+        [&](int Q, double s, int, const NoRow &) { rc[Q] = s; });
 }
 
 // K-cycle coefficients.  rho1 = (c1, A c1), alpha1 = (c1, rc), beta = (c2, A c2),
@@ -304,6 +419,7 @@ struct KCoef {
     bool bad;
 };
 
+template <bool PREFETCH = true>
 __device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd)
 {
     KCoef c{0.0, 0.0, false};
@@ -312,7 +428,7 @@ __device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd)
     if (mode == 2) {
         const DotRef refs[5] = {kd.rho1, kd.alpha1, kd.beta, kd.gamma, kd.alpha2};
         double v[5];
-        dot_values<5>(refs, v);
+        dot_values<5, PREFETCH>(refs, v);
         rho1 = v[0];
         alpha1 = v[1];
         beta = v[2];
@@ -321,7 +437,7 @@ __device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd)
     } else {
         const DotRef refs[2] = {kd.rho1, kd.alpha1};
         double v[2];
-        dot_values<2>(refs, v);
+        dot_values<2, PREFETCH>(refs, v);
         rho1 = v[0];
         alpha1 = v[1];
     }
@@ -354,21 +470,28 @@ __global__ void __launch_bounds__(kBlock) k_restrict_rt(Rows S, int nf, const in
                                                         double *__restrict__ rt, double *__restrict__ rc,
                                                         int *__restrict__ flag)
 {
-    const KCoef c = kcycle_coefficients(1, kd);
-    if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
-    const double a = c.a1;
-    for (int q = blockIdx.x * kBlock + threadIdx.x; q < nf; q += gridDim.x * kBlock) rt[q] = rcf[q] - a * v1[q];
-    visit_rows<G>(
+    const int gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
+    double rq = 0.0, vq = 0.0;  // this thread's first element of rt, loaded before the coefficients
+    if (gt < nf) {
+        rq = rcf[gt];
+        vq = v1[gt];
+    }
+    double a = 0.0;
+    visit_rows<G, true>(
         S,
-        [&](int b, int e, int lane, int width) {
-            double s = 0.0;
-            for (int p = b + lane; p < e; p += width) {
-                const int t = ci[p];
-                s += wv[p] * (rcf[t] - a * v1[t]);
-            }
-            return s;
+        [&]() {
+            const KCoef c = kcycle_coefficients(1, kd);
+            if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
+            a = c.a1;
+            if (gt < nf) rt[gt] = rq - a * vq;
+            for (int q = gt + gs; q < nf; q += gs) rt[q] = rcf[q] - a * v1[q];
         },
-        [&](int Q, double s, int) { rc[Q] = s; });
+        AMG_NO_PRE, AMG_SAME,
+        [&](int p) {
+            const int t = ci[p];
+            return wv[p] * (rcf[t] - a * v1[t]);
+        },
+        [&](int Q, double s, int, const NoRow &) { rc[Q] = s; });
 }
 
 // rt = rc - (alpha1/rho1) v1
@@ -376,7 +499,7 @@ __global__ void __launch_bounds__(kBlock) k_inner_residual(int n, const double *
                                                            const double *__restrict__ v1, KDots kd,
                                                            double *__restrict__ rt, int *__restrict__ flag)
 {
-    const KCoef c = kcycle_coefficients(1, kd);
+    const KCoef c = kcycle_coefficients<false>(1, kd);  // large levels only
     if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) rt[i] = rc[i] - c.a1 * v1[i];
 }
@@ -402,44 +525,65 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
                                                         double *__restrict__ part, int *__restrict__ flag,
                                                         const double *__restrict__ ainv, int nc)
 {
-    const KCoef c = kcycle_coefficients(MODE, kd);
-    if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
-    const double a1 = c.a1, a2 = c.a2;
+    double a1 = 0.0, a2 = 0.0;
     __shared__ double e_sh[MODE == 3 ? kInlineCoarse : 1];
-    if (MODE == 3) {  // e = A_coarsest^-1 rc, computed by every block into LDS
-        for (int i = threadIdx.x; i < nc; i += kBlock) {
-            double t = 0.0;
-            for (int j = 0; j < nc; j++) t += ainv[i * nc + j] * edirect[j];
-            e_sh[i] = t;
-        }
-        __syncthreads();
-    }
     auto corr = [&](int J) -> double {
         if (MODE == 0) return edirect[J];
         if (MODE == 3) return e_sh[J];
         if (MODE == 1) return a1 * c1[J];
         return a1 * c1[J] + a2 * c2[J];
     };
+    struct Pre {
+        double mr, rr, wd;
+        int J;
+    };
+    struct Late {
+        double mr, rr, wd, cj;
+    };
     double dsum[1] = {0.0};
     const int nb = gridDim.x;
-    visit_rows<G>(
+    visit_rows<G, CAGG>(
         R,
-        [&](int b, int e, int lane, int width) {
-            double s = 0.0;
-            for (int p = b + lane; p < e; p += width) {
-                const int t = ci[p];
-                s += va[p] * (minv[t] * r[t] + corr(CAGG ? cagg[p] : agg_pos[t]));
+        [&]() {
+            const KCoef c = kcycle_coefficients<CAGG>(MODE, kd);  // CAGG marks small levels
+            if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
+            a1 = c.a1;
+            a2 = c.a2;
+            if (MODE == 3) {  // e = A_coarsest^-1 rc, computed by every block into LDS
+                // wavefront w forms rows w, w + 4, ...; lane j holds column j
+                constexpr int kRows = kInlineCoarse / (kBlock / kWave);
+                const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+                const double ej = lane < nc ? edirect[lane] : 0.0;
+                double aij[kRows];
+#pragma unroll
+                for (int u = 0; u < kRows; u++) {
+                    const int i = w + u * (kBlock / kWave);
+                    aij[u] = (i < nc && lane < nc) ? ainv[i * nc + lane] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kRows; u++) {
+                    const int i = w + u * (kBlock / kWave);
+                    if (i < nc) {  // uniform over the wavefront
+                        const double t = wave_sum(aij[u] * ej);
+                        if (lane == 0) e_sh[i] = t;
+                    }
+                }
+                __syncthreads();
             }
-            return s;
         },
-        [&](int row, double s, int k) {
-            const double mr = minv[row], rr = r[row];
-            const double x = mr * rr + corr(agg_pos[row]);
-            const double o = x + mr * (rr - s);
+        [&](int row) { return Pre{minv[row], r[row], DOT ? wdot[row] : 0.0, agg_pos[row]}; },
+        [&](const Pre &v) { return Late{v.mr, v.rr, v.wd, corr(v.J)}; },
+        [&](int p) {
+            const int t = ci[p];
+            return va[p] * (minv[t] * r[t] + corr(CAGG ? cagg[p] : agg_pos[t]));
+        },
+        [&](int row, double s, int k, const Late &v) {
+            const double x = v.mr * v.rr + v.cj;
+            const double o = x + v.mr * (v.rr - s);
             xout[row] = o;
             if (DOT) {
-                if (k < 0) dsum[0] += o * wdot[row];
-                else part[nb + k] = o * wdot[row];
+                if (k < 0) dsum[0] += o * v.wd;
+                else part[nb + k] = o * v.wd;
             }
         });
     if (DOT) store_partials<1>(dsum, part);
@@ -591,7 +735,11 @@ int lanes_for(double avg_row_len, int n)
 void launch_spmv(Rows R, const int *ci, const double *va, const double *x, double *y, int G, hipStream_t s)
 {
     const int grid = rows_grid(R, G, 1 << 20);
-    AMG_SWITCH_G(G, (k_spmv<kG><<<grid, kBlock, 0, s>>>(R, ci, va, x, y)));
+    if (R.n < kSmallLevel) {
+        AMG_SWITCH_G(G, (k_spmv<kG, true><<<grid, kBlock, 0, s>>>(R, ci, va, x, y)));
+    } else {
+        AMG_SWITCH_G(G, (k_spmv<kG, false><<<grid, kBlock, 0, s>>>(R, ci, va, x, y)));
+    }
     AMG_HIP(hipGetLastError());
 }
 
@@ -600,13 +748,29 @@ DotSet launch_spmv_dots(Rows R, const int *ci, const double *va, const double *x
 {
     const int grid = rows_grid(R, G, kMaxDotBlocks);
     const int nd = w2 ? 3 : (w1 ? 2 : 1);
+#define AMG_SPMV_DOTS(ND, LAT) \
+    AMG_SWITCH_G(G, (k_spmv_dots<kG, ND, LAT><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, buf.part)))
+    const bool lat = R.n < kSmallLevel;
     if (nd == 1) {
-        AMG_SWITCH_G(G, (k_spmv_dots<kG, 1><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, buf.part)));
+        if (lat) {
+            AMG_SPMV_DOTS(1, true);
+        } else {
+            AMG_SPMV_DOTS(1, false);
+        }
     } else if (nd == 2) {
-        AMG_SWITCH_G(G, (k_spmv_dots<kG, 2><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, buf.part)));
+        if (lat) {
+            AMG_SPMV_DOTS(2, true);
+        } else {
+            AMG_SPMV_DOTS(2, false);
+        }
     } else {
-        AMG_SWITCH_G(G, (k_spmv_dots<kG, 3><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, buf.part)));
+        if (lat) {
+            AMG_SPMV_DOTS(3, true);
+        } else {
+            AMG_SPMV_DOTS(3, false);
+        }
     }
+#undef AMG_SPMV_DOTS
     AMG_HIP(hipGetLastError());
     const int count = grid + R.nlong;
     reduce_if_large(nd, buf.part, count, buf.final_out, s);
@@ -637,7 +801,11 @@ void launch_reduce(const DotRef &ref, double *out, hipStream_t s)
 void launch_restrict(Rows S, const int *ci, const double *wv, const double *r, double *rc, int G, hipStream_t s)
 {
     const int grid = rows_grid(S, G, 1 << 20);
-    AMG_SWITCH_G(G, (k_restrict<kG><<<grid, kBlock, 0, s>>>(S, ci, wv, r, rc)));
+    if (S.n < kSmallLevel) {
+        AMG_SWITCH_G(G, (k_restrict<kG, true><<<grid, kBlock, 0, s>>>(S, ci, wv, r, rc)));
+    } else {
+        AMG_SWITCH_G(G, (k_restrict<kG, false><<<grid, kBlock, 0, s>>>(S, ci, wv, r, rc)));
+    }
     AMG_HIP(hipGetLastError());
 }
 
