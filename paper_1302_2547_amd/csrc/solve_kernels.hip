@@ -155,6 +155,17 @@ __device__ inline void store_partials(const double (&v)[ND], double *part)
     }
 }
 
+// Consecutive blocks are dispatched to the 8 XCDs in turn, each with its own L2.
+// Renumbering blocks so that XCD x serves the x-th eighth of the rows keeps the
+// gathers of neighbouring rows in one L2 (a bijection on the first multiple of 8
+// blocks, identity on the rest).
+constexpr int kXcds = 8;
+__device__ inline int xcd_block(int b, int nb)
+{
+    const int full = nb - nb % kXcds;
+    return b < full ? (b % kXcds) * (full / kXcds) + b / kXcds : b;
+}
+
 // Completes chunk c of a hub row after the block has summed it (s in every
 // thread): a row of one chunk is finished at once; otherwise the chunk sum is
 // published and the last chunk of the row to arrive adds all of them (its first
@@ -170,14 +181,19 @@ __device__ inline void finish_chunk(const Rows &R, int c, const Chunk &ch, doubl
         if (lane == 0) done(ch.row, s, ch.k);
         return;
     }
+    // The chunk sums are written and read only with device-coherent atomic
+    // accesses, so ordering the sum before the arrival count needs no cache
+    // write-back: the store's completion is awaited (vector memory counter) before
+    // the count is raised, and the last arrival reads the sums only after its
+    // count returned.  Nothing else is read afterwards, so no acquire either.
     unsigned prev = 0;
     if (lane == 0) {
         __hip_atomic_store(&R.chunk_sum[c], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        prev = __hip_atomic_fetch_add(&R.arrive[ch.k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        prev = __hip_atomic_fetch_add(&R.arrive[ch.k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     prev = __shfl(prev, 0, kWave);
     if (prev != (unsigned)(m - 1)) return;  // not the last chunk of this row
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     double t = 0.0;
     for (int j = lane; j < m; j += kWave)
         t += __hip_atomic_load(&R.chunk_sum[first + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -220,8 +236,10 @@ __device__ inline void visit_rows(const Rows &R, Prologue prologue, Pre pre, Lat
             return;
         }
         const int sub = threadIdx.x % G;
-        const int ngroups = (gridDim.x - nlb) * (kBlock / G);
-        for (int row = ((blockIdx.x - nlb) * kBlock + threadIdx.x) / G; row < R.n; row += ngroups) {
+        const int nrb = gridDim.x - nlb;
+        const int ngroups = nrb * (kBlock / G);
+        const int rb = xcd_block(blockIdx.x - nlb, nrb);
+        for (int row = (rb * kBlock + threadIdx.x) / G; row < R.n; row += ngroups) {
             const int b = R.ptr[row], e = R.ptr[row + 1];
             if (e - b > R.lim) continue;  // hub row: served by the chunk blocks (uniform within the group)
             double s = 0.0;
