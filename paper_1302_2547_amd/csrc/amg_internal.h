@@ -132,31 +132,55 @@ void launch_long_rows(int n, const int *ptr, int lim, int *flags, int *list, int
 int lanes_for(double avg_row_len, int n);
 // plain y = A x
 void launch_spmv(Rows R, const int *ci, const double *va, const double *x, double *y, int G, hipStream_t s);
+// The K-cycle launchers take the storage type T of values and vectors (double, or
+// float in the mixed-precision mode); arithmetic and inner products are FP64.
+//
 // y = A x (y may be NULL); d[0] = (x, A x), d[1] = (x, w1) if w1, d[2] = (x, w2) if w2
-DotSet launch_spmv_dots(Rows R, const int *ci, const double *va, const double *x, double *y, const double *w1,
-                        const double *w2, int G, DotBuf buf, hipStream_t s);
+// (omy, non-NULL only with at most two other products, adds (omy, A x) last.)
+template <class T>
+DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, const T *w1, const T *w2, int G,
+                        DotBuf buf, hipStream_t s, const double *omy = nullptr);
 // r = b - A x; d[0] = (b, b), d[1] = (r, r)
 DotSet launch_residual(Rows R, const int *ci, const double *va, const double *b, const double *x, double *r, int G,
                        DotBuf buf, hipStream_t s);
 // *out = value of ref (one block)
 void launch_reduce(const DotRef &ref, double *out, hipStream_t s);
 // rc = W r over the super-rows S, W = P^T (I - A M^-1) stored per entry
-void launch_restrict(Rows S, const int *ci, const double *wv, const double *r, double *rc, int G, hipStream_t s);
+// With om, also the partials of (om, rc) into buf (returned; else a null reference).
+template <class T>
+DotRef launch_restrict(Rows S, const int *ci, const T *wv, const T *r, T *rc, int G, hipStream_t s,
+                       const double *om = nullptr, DotBuf buf = DotBuf{});
 // rc = W r with r = rt formed on the fly as rt = rcf - (alpha1/rho1) v1 (the
 // inner residual of the parent's first flexible-CG step), rt also stored
-void launch_restrict_rt(Rows S, int nf, const int *ci, const double *wv, const double *rcf, const double *v1,
-                        KDots kd, double *rt, double *rc, int *flag, int G, hipStream_t s);
+template <class T>
+DotRef launch_restrict_rt(Rows S, int nf, const int *ci, const T *wv, const T *rcf, const T *v1, KDots kd, T *rt,
+                          T *rc, int *flag, int G, hipStream_t s, const double *om = nullptr, DotBuf buf = DotBuf{});
+// K-cycle visit of a level whose coarse level is one unknown (restriction by the
+// inner products om_r and, with rt_mode, om_v1; see k_post_direct).
+template <class T>
+void launch_post_direct(Rows R, const int *ci, const T *va, const T *minv, const T *r, const T *v1, KDots kd,
+                        DotRef om_r, DotRef om_v1, const double *ainv, T *xout, T *rt_out, int *flag, int G,
+                        bool rt_mode, hipStream_t s);
 // rt = rc - (alpha1/rho1) v1
-void launch_inner_residual(int n, const double *rc, const double *v1, KDots kd, double *rt, int *flag, hipStream_t s);
+template <class T>
+void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, hipStream_t s);
 // post-smoothing with the coarse correction folded in (mode 0: e = edirect;
 // 1: e = (alpha1/rho1) c1; 2: e = a1 c1 + a2 c2; 3: e = ainv * edirect, a dense
 // coarsest solve of size nc <= kInlineCoarse done in the kernel); returns
 // (out, wdot) if wdot
-DotRef launch_post_smooth(Rows R, const int *ci, const double *va, const double *minv, const double *r,
-                          const int *agg_pos, const int *cagg, int mode, const double *edirect, const double *c1, const double *c2,
-                          KDots kd, double *xout, const double *wdot, DotBuf buf, int *flag, int G, hipStream_t s,
-                          const double *ainv = nullptr, int nc = 0);
-void launch_dense_gemv(int n, const double *a, const double *x, double *y, hipStream_t s);
+template <class T>
+DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, const T *r, const int *agg_pos,
+                          const int *cagg, int mode, const T *edirect, const T *c1, const T *c2, KDots kd, T *xout,
+                          const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv = nullptr,
+                          int nc = 0);
+// y = A x with A dense row-major FP64
+template <class T>
+void launch_dense_gemv(int n, const double *a, const T *x, T *y, hipStream_t s);
+// r32 = r / sqrt(*rr) (FP32); z = sqrt(*rr) z32 with the partials of (z, q)
+void launch_to_inner(int n, const double *r, const double *rr, float *r32, hipStream_t s);
+DotRef launch_from_inner(int n, const float *z32, const double *rr, double *z, const double *q, DotBuf buf,
+                         hipStream_t s);
+void launch_to_float(int64_t n, const double *src, float *dst, hipStream_t s);
 // alpha = pr/pq; x += alpha p; r -= alpha q; returns (r, r)
 DotRef launch_fcg_update(int n, DotRef pq, DotRef pr, double *x, double *r, const double *p, const double *q,
                          DotBuf buf, int *flag, hipStream_t s);

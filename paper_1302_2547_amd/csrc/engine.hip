@@ -16,6 +16,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "amg.h"
@@ -199,6 +200,14 @@ struct Pool {
     }
 };
 
+// K-cycle values and work vectors of one level in storage type T (FP64, or FP32 in
+// the mixed-precision mode; the FP64 set aliases the level's own arrays).
+template <class T>
+struct KArrays {
+    const T *va = nullptr, *minv = nullptr, *wv = nullptr;
+    T *rc = nullptr, *rt = nullptr, *c1 = nullptr, *c2 = nullptr, *v1 = nullptr;
+};
+
 struct Level {
     int n = 0, nnz = 0, passes = 0;
     // natural numbering (setup result)
@@ -216,8 +225,27 @@ struct Level {
     Rows A{}, S{};  // rows of A and super-rows of P^T A, each with its hub-row chunks
     // work vectors and dot sites when this level is the coarse level of a visit
     double *rc = nullptr, *rt = nullptr, *c1 = nullptr, *c2 = nullptr, *v1 = nullptr;
-    DotBuf d_c1{}, d_c2{};  // (c1, A c1), (c1, rc) and (c2, A c2), (c2, v1), (c2, rt)
+    DotBuf d_c1{}, d_c2{};  // (c1, A c1), (c1, rc) [, (om, A c1)] and (c2, A c2), (c2, v1), (c2, rt)
+    // Level whose coarse level is a single unknown: the restriction is the row
+    // vector om^T, applied as inner products written by the producers of rc / v1.
+    double *omega = nullptr;
+    DotBuf d_om{};
+    DotRef om_rc{}, om_v1{};
+    KArrays<double> k64{};
+    KArrays<float> k32{};
+    template <class T>
+    const KArrays<T> &karr() const;
 };
+template <>
+inline const KArrays<double> &Level::karr<double>() const
+{
+    return k64;
+}
+template <>
+inline const KArrays<float> &Level::karr<float>() const
+{
+    return k32;
+}
 
 }  // namespace
 }  // namespace amg
@@ -241,6 +269,8 @@ struct amg_hierarchy {
     DotBuf d_pq{}, d_rr{}, d_zq{}, d_res{};
     DotRef dr_pq{}, dr_pr{}, dr_rr{}, dr_zq{};
     double *scal = nullptr;  // device scalars read by the host: rr, bb, rr0
+    bool mixed = false;       // FP32 K-cycle inside the FP64 outer iteration
+    float *r32 = nullptr, *z32 = nullptr;
     KDots kd0{};             // dots of the finest visit's coarse correction (for timing)
     int *flag = nullptr;     // bit 0: Krylov breakdown
     hipGraphExec_t g_kcycle = nullptr, g_first = nullptr, g_iter = nullptr;
@@ -344,11 +374,13 @@ struct amg_hierarchy {
     void build(const amg_csr &A);
     void finalize_layout();
     // the inner residual rt = rcf - (alpha1/rho1) v1 of a parent's first step
+    template <class T>
     struct RtSource {
-        const double *rcf, *v1;
+        const T *rcf, *v1;
         KDots kd;
     };
-    DotRef kcycle(int k, const double *r, double *x, const double *wdot, const RtSource *rts);
+    template <class T>
+    DotRef kcycle(int k, const T *r, T *x, const T *wdot, const RtSource<T> *rts);
     void run_kcycle();
     void run_first();
     void run_iter();
@@ -509,6 +541,7 @@ void amg_hierarchy::build(const amg_csr &A)
         if (err) throw Error(AMG_ERR_BREAKDOWN, "coarsest matrix is not positive definite");
     }
     AMG_TRACE_MSG("coarsest inverse done; solve layout");
+    mixed = opt.precision == AMG_PREC_FP32_INNER && levels() >= 2;
     finalize_layout();
     AMG_TRACE_MSG("solve layout done");
     AMG_HIP(hipEventRecord(ev1, stream));
@@ -578,6 +611,54 @@ void amg_hierarchy::finalize_layout()
             F.d_c2 = dot_buf();
         }
     }
+    // single coarse unknown below level L-1 (L >= 2): om_j = sum over the entries
+    // e of column j of w_e, summed in entry order on the host (small level)
+    if (L >= 2 && lev[L].n == 1 && lev[L - 1].nnz <= (1 << 24)) {
+        Level &F = lev[L - 1];
+        std::vector<int> rp(F.n + 1), ci(F.nnz);
+        std::vector<double> va(F.nnz), mv(F.n), om(F.n, 0.0);
+        to_host(rp.data(), F.rp, F.n + 1);
+        to_host(ci.data(), F.ci, F.nnz);
+        to_host(va.data(), F.va, F.nnz);
+        to_host(mv.data(), F.minv, F.n);
+        for (int q = 0; q < F.n; q++)
+            for (int e = rp[q]; e < rp[q + 1]; e++) {
+                const int t = ci[e];
+                om[t] += (t == q ? 1.0 : 0.0) - va[e] * mv[t];
+            }
+        F.omega = pool.alloc<double>(F.n);
+        AMG_HIP(hipMemcpyAsync(F.omega, om.data(), sizeof(double) * F.n, hipMemcpyHostToDevice, stream));
+        F.d_om = dot_buf();
+        AMG_TRACE_MSG("level %d: single coarse unknown below, restriction by inner products", L - 1);
+    }
+    for (int l = 0; l <= L; l++) {
+        Level &F = lev[l];
+        F.k64 = KArrays<double>{F.va, F.minv, F.wv, F.rc, F.rt, F.c1, F.c2, F.v1};
+    }
+    if (mixed) {  // FP32 copies of the K-cycle values and FP32 work vectors
+        auto to_float = [&](const double *src, size_t count) -> const float * {
+            if (!src) return nullptr;
+            float *dst = pool.alloc<float>(count);
+            launch_to_float((int64_t)count, src, dst, stream);
+            return dst;
+        };
+        for (int l = 0; l <= L; l++) {
+            Level &F = lev[l];
+            KArrays<float> &K = F.k32;
+            K.va = to_float(F.va, F.nnz);
+            K.minv = to_float(F.minv, F.n);
+            K.wv = to_float(F.wv, F.nnz);
+            if (l >= 1) {
+                K.rc = pool.alloc<float>(F.n);
+                K.rt = pool.alloc<float>(F.n);
+                K.c1 = pool.alloc<float>(F.n);
+                K.c2 = pool.alloc<float>(F.n);
+                K.v1 = pool.alloc<float>(F.n);
+            }
+        }
+        r32 = pool.alloc<float>(lev[0].n);
+        z32 = pool.alloc<float>(lev[0].n);
+    }
     const int n = lev[0].n;
     b = pool.alloc<double>(n);
     x = pool.alloc<double>(n);
@@ -603,49 +684,68 @@ void amg_hierarchy::finalize_layout()
 // coarse correction (exact on the coarsest level, else two flexible-CG steps
 // preconditioned by K_{k+1}), prolongation + post-smoothing.  When wdot is given
 // the returned reference holds (x, wdot).
-DotRef amg_hierarchy::kcycle(int k, const double *rr, double *xx, const double *wdot, const RtSource *rts)
+template <class T>
+DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtSource<T> *rts)
 {
     using namespace amg;
     const int L = levels() - 1;
     Level &F = lev[k];
-    if (k == L) {  // single-level hierarchy: the exact solve is the preconditioner
-        launch_dense_gemv(F.n, ainv, rr, xx, stream);
-        return wdot ? launch_dot(F.n, xx, wdot, d_zq, stream) : DotRef{nullptr, 0};
+    const KArrays<T> &FK = F.karr<T>();
+    if (k == L) {  // single-level hierarchy (FP64 only): the exact solve is the preconditioner
+        launch_dense_gemv<T>(F.n, ainv, rr, xx, stream);
+        if constexpr (std::is_same<T, double>::value) {
+            if (wdot) return launch_dot(F.n, xx, wdot, d_zq, stream);
+        }
+        return DotRef{nullptr, 0};
+    }
+    if (F.omega) {  // the coarse level is one unknown: restriction by inner products
+        // (rts: rr = rt is formed from the parent's first inner step and stored)
+        if (rts) {
+            launch_post_direct<T>(F.A, F.ci, FK.va, FK.minv, rts->rcf, rts->v1, rts->kd, F.om_rc, F.om_v1, ainv, xx,
+                                  const_cast<T *>(rr), flag, F.G, true, stream);
+        } else {
+            launch_post_direct<T>(F.A, F.ci, FK.va, FK.minv, rr, nullptr, KDots{}, F.om_rc, DotRef{}, ainv, xx,
+                                  nullptr, flag, F.G, false, stream);
+        }
+        return DotRef{nullptr, 0};
     }
     Level &C = lev[k + 1];
+    const KArrays<T> &CK = C.karr<T>();
     if (rts) {  // rr = rt is formed here from the parent's first inner step
-        launch_restrict_rt(F.S, F.n, F.ci, F.wv, rts->rcf, rts->v1, rts->kd, const_cast<double *>(rr), C.rc, flag,
-                           F.Gs, stream);
+        C.om_rc = launch_restrict_rt<T>(F.S, F.n, F.ci, FK.wv, rts->rcf, rts->v1, rts->kd, const_cast<T *>(rr), CK.rc,
+                                        flag, F.Gs, stream, C.omega, C.d_om);
     } else {
-        launch_restrict(F.S, F.ci, F.wv, rr, C.rc, F.Gs, stream);
+        C.om_rc = launch_restrict<T>(F.S, F.ci, FK.wv, rr, CK.rc, F.Gs, stream, C.omega, C.d_om);
     }
     KDots kd{};
     int mode;
-    const double *edirect = nullptr;
+    const T *edirect = nullptr;
     if (k + 1 == L) {
         if (C.n <= kInlineCoarse) {
             mode = 3;
-            edirect = C.rc;
+            edirect = CK.rc;
         } else {
-            launch_dense_gemv(C.n, ainv, C.rc, C.c1, stream);
+            launch_dense_gemv<T>(C.n, ainv, CK.rc, CK.c1, stream);
             mode = 0;
-            edirect = C.c1;
+            edirect = CK.c1;
         }
     } else {
-        kcycle(k + 1, C.rc, C.c1, nullptr, nullptr);
-        const DotSet s1 = launch_spmv_dots(C.A, C.ci, C.va, C.c1, C.v1, C.rc, nullptr, C.G, C.d_c1, stream);
+        kcycle<T>(k + 1, CK.rc, CK.c1, nullptr, nullptr);
+        const DotSet s1 =
+            launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c1, CK.v1, CK.rc, nullptr, C.G, C.d_c1, stream, C.omega);
         kd.rho1 = s1.d[0];
         kd.alpha1 = s1.d[1];
+        if (C.omega) C.om_v1 = s1.d[2];
         mode = 1;
         if (opt.kcycle_inner == 2) {
-            if (C.n < kSmallLevel) {  // fold the inner residual into the next restriction
-                const RtSource src{C.rc, C.v1, kd};
-                kcycle(k + 1, C.rt, C.c2, nullptr, &src);
+            if (C.n < kSmallLevel || C.omega) {  // fold the inner residual into the next restriction
+                const RtSource<T> src{CK.rc, CK.v1, kd};
+                kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, &src);
             } else {
-                launch_inner_residual(C.n, C.rc, C.v1, kd, C.rt, flag, stream);
-                kcycle(k + 1, C.rt, C.c2, nullptr, nullptr);
+                launch_inner_residual<T>(C.n, CK.rc, CK.v1, kd, CK.rt, flag, stream);
+                kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, nullptr);
             }
-            const DotSet s2 = launch_spmv_dots(C.A, C.ci, C.va, C.c2, nullptr, C.v1, C.rt, C.G, C.d_c2, stream);
+            const DotSet s2 = launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c2, nullptr, CK.v1, CK.rt, C.G, C.d_c2, stream);
             kd.beta = s2.d[0];
             kd.gamma = s2.d[1];
             kd.alpha2 = s2.d[2];
@@ -653,8 +753,8 @@ DotRef amg_hierarchy::kcycle(int k, const double *rr, double *xx, const double *
         }
     }
     if (k == 0) kd0 = kd;
-    return launch_post_smooth(F.A, F.ci, F.va, F.minv, rr, F.agg_pos, F.cagg, mode, edirect, C.c1, C.c2, kd, xx, wdot,
-                              k == 0 ? d_zq : DotBuf{}, flag, F.G, stream, ainv, C.n);
+    return launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rr, F.agg_pos, F.cagg, mode, edirect, CK.c1, CK.c2, kd, xx,
+                                 wdot, k == 0 ? d_zq : DotBuf{}, flag, F.G, stream, ainv, C.n);
 }
 
 // One outer iteration is split in three replayable pieces:
@@ -663,8 +763,17 @@ DotRef amg_hierarchy::kcycle(int k, const double *rr, double *xx, const double *
 //   iter  : p = z + beta p; then as in first
 void amg_hierarchy::run_kcycle()
 {
-    if (g_kcycle) AMG_HIP(hipGraphLaunch(g_kcycle, stream));
-    else dr_zq = kcycle(0, r, z, q, nullptr);
+    using namespace amg;
+    if (g_kcycle) {
+        AMG_HIP(hipGraphLaunch(g_kcycle, stream));
+    } else if (mixed) {  // scal[0] holds (r, r)
+        const int n = lev[0].n;
+        launch_to_inner(n, r, scal, r32, stream);
+        kcycle<float>(0, r32, z32, nullptr, nullptr);
+        dr_zq = launch_from_inner(n, z32, scal, z, q, d_zq, stream);
+    } else {
+        dr_zq = kcycle<double>(0, r, z, q, nullptr);
+    }
 }
 
 void amg_hierarchy::run_first()
@@ -676,7 +785,7 @@ void amg_hierarchy::run_first()
     }
     Level &F = lev[0];
     AMG_HIP(hipMemcpyAsync(p, z, sizeof(double) * F.n, hipMemcpyDeviceToDevice, stream));
-    const DotSet s1 = launch_spmv_dots(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream);
+    const DotSet s1 = launch_spmv_dots<double>(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream);
     dr_pq = s1.d[0];
     dr_pr = s1.d[1];
     dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream);
@@ -692,7 +801,7 @@ void amg_hierarchy::run_iter()
     }
     Level &F = lev[0];
     launch_fcg_direction(F.n, dr_pq, dr_zq, z, p, flag, stream);
-    const DotSet s1 = launch_spmv_dots(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream);
+    const DotSet s1 = launch_spmv_dots<double>(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream);
     dr_pq = s1.d[0];
     dr_pr = s1.d[1];
     dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream);
@@ -751,6 +860,7 @@ amg_status amg_hierarchy::solve(const double *b_user, double *x_user, double tol
         const DotSet s0 = launch_residual(F.A, F.ci, F.va, b, x, r, F.G, d_res, stream);
         launch_reduce(s0.d[0], scal + 1, stream);
         launch_reduce(s0.d[1], scal + 2, stream);
+        if (mixed) launch_reduce(s0.d[1], scal, stream);  // the K-cycle scales r by sqrt(scal[0])
         AMG_HIP(hipMemcpyAsync(host, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
         sync();
     };
@@ -859,7 +969,7 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy 
         opt.max_coarsest < 1)
         return AMG_ERR_INVALID_ARGUMENT;
     if (opt.kcycle_inner != 1 && opt.kcycle_inner != 2) return AMG_ERR_UNSUPPORTED;
-    if (opt.precision != AMG_PREC_FP64) return AMG_ERR_UNSUPPORTED;
+    if (opt.precision != AMG_PREC_FP64 && opt.precision != AMG_PREC_FP32_INNER) return AMG_ERR_UNSUPPORTED;
     amg_hierarchy *h = new (std::nothrow) amg_hierarchy();
     if (!h) return AMG_ERR_OUT_OF_MEMORY;
     h->opt = opt;
@@ -959,6 +1069,10 @@ amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z)
         h->capture_graphs();
         AMG_HIP(hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
         amg::launch_gather(F.n, r, F.perm, h->r, h->stream);
+        if (h->mixed) {  // the mixed K-cycle reads (r, r) from scal[0]
+            const DotRef rr = amg::launch_dot(F.n, h->r, h->r, h->d_res, h->stream);
+            amg::launch_reduce(rr, h->scal, h->stream);
+        }
         h->run_kcycle();
         amg::launch_scatter(F.n, h->z, F.perm, z, h->stream);
         AMG_HIP(hipMemcpyAsync(h->host_i, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -975,8 +1089,14 @@ amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, dou
         const Level &F = h->lev[0], &C = h->lev[1];
         const int mode = h->opt.kcycle_inner == 1 ? 1 : 2;
         auto launch = [&]() {
-            amg::launch_post_smooth(F.A, F.ci, F.va, F.minv, h->r, F.agg_pos, F.cagg, mode, nullptr, C.c1, C.c2, h->kd0, h->z,
-                                    nullptr, DotBuf{}, h->flag, F.G, h->stream);
+            if (h->mixed) {
+                amg::launch_post_smooth<float>(F.A, F.ci, F.k32.va, F.k32.minv, h->r32, F.agg_pos, F.cagg, mode,
+                                               nullptr, C.k32.c1, C.k32.c2, h->kd0, h->z32, nullptr, DotBuf{}, h->flag,
+                                               F.G, h->stream);
+            } else {
+                amg::launch_post_smooth<double>(F.A, F.ci, F.va, F.minv, h->r, F.agg_pos, F.cagg, mode, nullptr, C.c1,
+                                                C.c2, h->kd0, h->z, nullptr, DotBuf{}, h->flag, F.G, h->stream);
+            }
         };
         launch();
         AMG_HIP(hipEventRecord(h->ev0, h->stream));
@@ -986,9 +1106,11 @@ amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, dou
         float ms = 0.f;
         AMG_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
         *avg_us = 1000.0 * ms / reps;
-        // per entry: column, value (+ coarse column on small levels); per row:
-        // row pointer, minv, r, coarse index, output; coarse c1, c2 once each
-        if (bytes) *bytes = (F.cagg ? 16.0 : 12.0) * F.nnz + 4.0 * (F.n + 1) + 32.0 * F.n + 16.0 * C.n;
+        // per entry: column, value (+ coarse column on small levels); row pointers;
+        // per row: minv, r, output (values) and the coarse index; c1, c2 once each
+        const double w = h->mixed ? 4.0 : 8.0;
+        if (bytes) *bytes = (4.0 + w + (F.cagg ? 4.0 : 0.0)) * F.nnz + 4.0 * (F.n + 1) + (3.0 * w + 4.0) * F.n +
+                            2.0 * w * C.n;
         return AMG_OK;
     });
 }

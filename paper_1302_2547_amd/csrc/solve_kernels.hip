@@ -321,42 +321,47 @@ __global__ void __launch_bounds__(kBlock) k_spmv(Rows R, const int *__restrict__
         [&](int row, double s, int, const NoRow &) { y[row] = s; });
 }
 
-// y = A x (y may be NULL); dots (x, Ax) and, for each non-NULL w_j, (x, w_j).
-template <int G, int ND, bool LAT>
+// y = A x (y may be NULL); dots (x, Ax) and, for each non-NULL w_j, (x, w_j);
+// OMY adds (om, A x) as the last product.
+template <class T, int G, int ND, bool LAT, bool OMY>
 __global__ void __launch_bounds__(kBlock) k_spmv_dots(Rows R, const int *__restrict__ ci,
-                                                      const double *__restrict__ va, const double *__restrict__ x,
-                                                      double *__restrict__ y, const double *__restrict__ w1,
-                                                      const double *__restrict__ w2, double *__restrict__ part)
+                                                      const T *__restrict__ va, const T *__restrict__ x,
+                                                      T *__restrict__ y, const T *__restrict__ w1,
+                                                      const T *__restrict__ w2, const double *__restrict__ om,
+                                                      double *__restrict__ part)
 {
-    double d[ND] = {};
+    constexpr int NT = ND + (OMY ? 1 : 0);
+    double d[NT] = {};
     const int nb = gridDim.x;
     struct Pre {
-        double xr, w1r, w2r;
+        double xr, w1r, w2r, omr;
     };
     visit_rows<G, LAT>(
         R, AMG_NO_PROLOGUE,
         [&](int row) {
-            Pre v{x[row], 0.0, 0.0};
-            if (ND > 1) v.w1r = w1[row];
-            if (ND > 2) v.w2r = w2[row];
+            Pre v{(double)x[row], 0.0, 0.0, 0.0};
+            if (ND > 1) v.w1r = (double)w1[row];
+            if (ND > 2) v.w2r = (double)w2[row];
+            if (OMY) v.omr = om[row];
             return v;
         },
-        AMG_SAME, [&](int p) { return va[p] * x[ci[p]]; },
+        AMG_SAME, [&](int p) { return (double)va[p] * (double)x[ci[p]]; },
         [&](int row, double s, int k, const Pre &v) {
-            if (y) y[row] = s;
-            double t[ND];
+            if (y) y[row] = (T)s;
+            double t[NT];
             t[0] = v.xr * s;
-            if (ND > 1) t[1] = v.xr * v.w1r;
-            if (ND > 2) t[2] = v.xr * v.w2r;
+            if (ND > 1) t[1 % NT] = v.xr * v.w1r;
+            if (ND > 2) t[2 % NT] = v.xr * v.w2r;
+            if (OMY) t[NT - 1] = v.omr * s;
             if (k < 0) {
 #pragma unroll
-                for (int j = 0; j < ND; j++) d[j] += t[j];
+                for (int j = 0; j < NT; j++) d[j] += t[j];
             } else {
 #pragma unroll
-                for (int j = 0; j < ND; j++) part[j * kPartStride + nb + k] = t[j];
+                for (int j = 0; j < NT; j++) part[j * kPartStride + nb + k] = t[j];
             }
         });
-    store_partials<ND>(d, part);
+    store_partials<NT>(d, part);
 }
 
 // r = b - A x; partials of (b, b) and (r, r)
@@ -417,14 +422,27 @@ __global__ void __launch_bounds__(kReduceThreads) k_reduce_partials(int nd, cons
 // Pre-smoothing from zero fused with residual and restriction.  With x = M^-1 r,
 // rc_Q = sum_{q in G_Q} (r - A x)_q = sum_{e in super-row Q} w_e r_{col(e)} where
 // w = P^T (I - A M^-1) is stored per entry (w_e = [diagonal] - a_e minv_col).
-template <int G, bool LAT>
+// OM adds partials of (om, rc) (the restriction to a single coarse unknown of
+// the next level down, see k_post_direct).
+template <class T, int G, bool LAT, bool OM>
 __global__ void __launch_bounds__(kBlock) k_restrict(Rows S, const int *__restrict__ ci,
-                                                     const double *__restrict__ wv, const double *__restrict__ r,
-                                                     double *__restrict__ rc)
+                                                     const T *__restrict__ wv, const T *__restrict__ r,
+                                                     T *__restrict__ rc, const double *__restrict__ om,
+                                                     double *__restrict__ part)
 {
+    double d[1] = {0.0};
+    const int nb = gridDim.x;
     visit_rows<G, LAT>(
-        S, AMG_NO_PROLOGUE, AMG_NO_PRE, AMG_SAME, [&](int p) { return wv[p] * r[ci[p]]; },
-        [&](int Q, double s, int, const NoRow &) { rc[Q] = s; });
+        S, AMG_NO_PROLOGUE, [&](int Q) { return OM ? om[Q] : 0.0; }, AMG_SAME,
+        [&](int p) { return (double)wv[p] * (double)r[ci[p]]; },
+        [&](int Q, double s, int k, double w) {
+            rc[Q] = (T)s;
+            if (OM) {
+                if (k < 0) d[0] += w * s;
+                else part[nb + k] = w * s;
+            }
+        });
+    if (OM) store_partials<1>(d, part);
 }
 
 // K-cycle coefficients.  rho1 = (c1, A c1), alpha1 = (c1, rc), beta = (c2, A c2),
@@ -480,19 +498,22 @@ __device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd)
 // Restriction of the inner residual of the parent's first flexible-CG step:
 // rt = rcf - (alpha1/rho1) v1 is formed on the fly (and stored for the later
 // kernels of the visit), rc = W rt.
-template <int G>
+template <class T, int G, bool OM>
 __global__ void __launch_bounds__(kBlock) k_restrict_rt(Rows S, int nf, const int *__restrict__ ci,
-                                                        const double *__restrict__ wv,
-                                                        const double *__restrict__ rcf,
-                                                        const double *__restrict__ v1, KDots kd,
-                                                        double *__restrict__ rt, double *__restrict__ rc,
-                                                        int *__restrict__ flag)
+                                                        const T *__restrict__ wv,
+                                                        const T *__restrict__ rcf,
+                                                        const T *__restrict__ v1, KDots kd,
+                                                        T *__restrict__ rt, T *__restrict__ rc,
+                                                        int *__restrict__ flag, const double *__restrict__ om,
+                                                        double *__restrict__ part)
 {
+    double d[1] = {0.0};
+    const int nb = gridDim.x;
     const int gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
     double rq = 0.0, vq = 0.0;  // this thread's first element of rt, loaded before the coefficients
     if (gt < nf) {
-        rq = rcf[gt];
-        vq = v1[gt];
+        rq = (double)rcf[gt];
+        vq = (double)v1[gt];
     }
     double a = 0.0;
     visit_rows<G, true>(
@@ -501,25 +522,34 @@ __global__ void __launch_bounds__(kBlock) k_restrict_rt(Rows S, int nf, const in
             const KCoef c = kcycle_coefficients(1, kd);
             if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
             a = c.a1;
-            if (gt < nf) rt[gt] = rq - a * vq;
-            for (int q = gt + gs; q < nf; q += gs) rt[q] = rcf[q] - a * v1[q];
+            if (gt < nf) rt[gt] = (T)(rq - a * vq);
+            for (int q = gt + gs; q < nf; q += gs) rt[q] = (T)((double)rcf[q] - a * (double)v1[q]);
         },
-        AMG_NO_PRE, AMG_SAME,
+        [&](int Q) { return OM ? om[Q] : 0.0; }, AMG_SAME,
         [&](int p) {
             const int t = ci[p];
-            return wv[p] * (rcf[t] - a * v1[t]);
+            return (double)wv[p] * ((double)rcf[t] - a * (double)v1[t]);
         },
-        [&](int Q, double s, int, const NoRow &) { rc[Q] = s; });
+        [&](int Q, double s, int k, double w) {
+            rc[Q] = (T)s;
+            if (OM) {
+                if (k < 0) d[0] += w * s;
+                else part[nb + k] = w * s;
+            }
+        });
+    if (OM) store_partials<1>(d, part);
 }
 
 // rt = rc - (alpha1/rho1) v1
-__global__ void __launch_bounds__(kBlock) k_inner_residual(int n, const double *__restrict__ rc,
-                                                           const double *__restrict__ v1, KDots kd,
-                                                           double *__restrict__ rt, int *__restrict__ flag)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_inner_residual(int n, const T *__restrict__ rc,
+                                                           const T *__restrict__ v1, KDots kd,
+                                                           T *__restrict__ rt, int *__restrict__ flag)
 {
     const KCoef c = kcycle_coefficients<false>(1, kd);  // large levels only
     if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) rt[i] = rc[i] - c.a1 * v1[i];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        rt[i] = (T)((double)rc[i] - c.a1 * (double)v1[i]);
 }
 
 // Prolongation + post-smoothing: x = M^-1 r + P e (the pre-smoothed iterate plus
@@ -529,27 +559,27 @@ __global__ void __launch_bounds__(kBlock) k_inner_residual(int n, const double *
 // out = x + M^-1 (r - A x).  mode 0: e = edirect; mode 1: e = a1 c1;
 // mode 2: e = a1 c1 + a2 c2; mode 3: e = ainv edirect (small dense coarsest level).
 // DOT adds partials of (out, wdot).
-template <int G, int MODE, bool DOT, bool CAGG>
+template <class T, int G, int MODE, bool DOT, bool CAGG>
 __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__restrict__ ci,
-                                                        const double *__restrict__ va,
-                                                        const double *__restrict__ minv,
-                                                        const double *__restrict__ r,
+                                                        const T *__restrict__ va,
+                                                        const T *__restrict__ minv,
+                                                        const T *__restrict__ r,
                                                         const int *__restrict__ agg_pos,
                                                         const int *__restrict__ cagg,
-                                                        const double *__restrict__ edirect,
-                                                        const double *__restrict__ c1,
-                                                        const double *__restrict__ c2, KDots kd,
-                                                        double *__restrict__ xout, const double *__restrict__ wdot,
+                                                        const T *__restrict__ edirect,
+                                                        const T *__restrict__ c1,
+                                                        const T *__restrict__ c2, KDots kd,
+                                                        T *__restrict__ xout, const T *__restrict__ wdot,
                                                         double *__restrict__ part, int *__restrict__ flag,
                                                         const double *__restrict__ ainv, int nc)
 {
     double a1 = 0.0, a2 = 0.0;
     __shared__ double e_sh[MODE == 3 ? kInlineCoarse : 1];
     auto corr = [&](int J) -> double {
-        if (MODE == 0) return edirect[J];
+        if (MODE == 0) return (double)edirect[J];
         if (MODE == 3) return e_sh[J];
-        if (MODE == 1) return a1 * c1[J];
-        return a1 * c1[J] + a2 * c2[J];
+        if (MODE == 1) return a1 * (double)c1[J];
+        return a1 * (double)c1[J] + a2 * (double)c2[J];
     };
     struct Pre {
         double mr, rr, wd;
@@ -571,7 +601,7 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
                 // wavefront w forms rows w, w + 4, ...; lane j holds column j
                 constexpr int kRows = kInlineCoarse / (kBlock / kWave);
                 const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-                const double ej = lane < nc ? edirect[lane] : 0.0;
+                const double ej = lane < nc ? (double)edirect[lane] : 0.0;
                 double aij[kRows];
 #pragma unroll
                 for (int u = 0; u < kRows; u++) {
@@ -589,16 +619,16 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
                 __syncthreads();
             }
         },
-        [&](int row) { return Pre{minv[row], r[row], DOT ? wdot[row] : 0.0, agg_pos[row]}; },
+        [&](int row) { return Pre{(double)minv[row], (double)r[row], DOT ? (double)wdot[row] : 0.0, agg_pos[row]}; },
         [&](const Pre &v) { return Late{v.mr, v.rr, v.wd, corr(v.J)}; },
         [&](int p) {
             const int t = ci[p];
-            return va[p] * (minv[t] * r[t] + corr(CAGG ? cagg[p] : agg_pos[t]));
+            return (double)va[p] * ((double)minv[t] * (double)r[t] + corr(CAGG ? cagg[p] : agg_pos[t]));
         },
         [&](int row, double s, int k, const Late &v) {
             const double x = v.mr * v.rr + v.cj;
             const double o = x + v.mr * (v.rr - s);
-            xout[row] = o;
+            xout[row] = (T)o;
             if (DOT) {
                 if (k < 0) dsum[0] += o * v.wd;
                 else part[nb + k] = o * v.wd;
@@ -607,19 +637,108 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
     if (DOT) store_partials<1>(dsum, part);
 }
 
+// Post-smoothing on a level whose coarse level is a single unknown.  P is then
+// the all-ones column and the restriction W = P^T (I - A M^-1) is the row vector
+// om^T, om_j = 1 - minv_j sum_i a_ij, so rc = (om, r) is an inner product whose
+// partials the producers of r wrote.  e = rc / a_c, x = M^-1 r + e and
+// out = x + M^-1 (r - A x).  RT (the second inner step of the parent):
+// r = rcf - (alpha1/rho1) v1 is formed on the fly and stored, and
+// rc = (om, rcf) - (alpha1/rho1) (om, v1).
+template <class T, int G, bool RT>
+__global__ void __launch_bounds__(kBlock) k_post_direct(Rows R, const int *__restrict__ ci,
+                                                        const T *__restrict__ va,
+                                                        const T *__restrict__ minv,
+                                                        const T *__restrict__ r, const T *__restrict__ v1,
+                                                        KDots kd, DotRef om_r, DotRef om_v1,
+                                                        const double *__restrict__ ainv, T *__restrict__ xout,
+                                                        T *__restrict__ rt_out, int *__restrict__ flag)
+{
+    double a = 0.0, e = 0.0;
+    struct Pre {
+        double mr, rr, vr;
+    };
+    struct Late {
+        double mr, rr;
+    };
+    visit_rows<G, true>(
+        R,
+        [&]() {
+            const double ac_inv = ainv[0];
+            if (RT) {
+                const DotRef refs[4] = {kd.rho1, kd.alpha1, om_r, om_v1};
+                double v[4];
+                dot_values<4>(refs, v);
+                const bool bad = !(v[0] > 0.0);
+                if (bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
+                a = bad ? 0.0 : v[1] / v[0];
+                e = ac_inv * (v[2] - a * v[3]);
+            } else {
+                double v[1];
+                dot_values<1>(&om_r, v);
+                e = ac_inv * v[0];
+            }
+        },
+        [&](int row) { return Pre{(double)minv[row], (double)r[row], RT ? (double)v1[row] : 0.0}; },
+        [&](const Pre &v) { return Late{v.mr, RT ? v.rr - a * v.vr : v.rr}; },
+        [&](int p) {
+            const int t = ci[p];
+            const double rt = RT ? (double)r[t] - a * (double)v1[t] : (double)r[t];
+            return (double)va[p] * ((double)minv[t] * rt + e);
+        },
+        [&](int row, double s, int, const Late &v) {
+            const double x = v.mr * v.rr + e;
+            xout[row] = (T)(x + v.mr * (v.rr - s));
+            if (RT) rt_out[row] = (T)v.rr;
+        });
+}
+
 // y = A x for a dense row-major n x n matrix: one wavefront per row.
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_dense_gemv(int n, const double *__restrict__ a,
-                                                       const double *__restrict__ x, double *__restrict__ y)
+                                                       const T *__restrict__ x, T *__restrict__ y)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int nw = gridDim.x * (kBlock / kWave);
     for (int i = (blockIdx.x * kBlock + threadIdx.x) / kWave; i < n; i += nw) {
         double s = 0.0;
         const double *row = a + (size_t)i * n;
-        for (int j = lane; j < n; j += kWave) s += row[j] * x[j];
+        for (int j = lane; j < n; j += kWave) s += row[j] * (double)x[j];
         s = wave_sum(s);
-        if (lane == 0) y[i] = s;
+        if (lane == 0) y[i] = (T)s;
     }
+}
+
+// Mixed precision: the K-cycle takes r / ||r|| in FP32 (it is positively
+// homogeneous, so scaling the argument scales the result) and z = ||r|| z32
+// comes back in FP64 with the partials of (z, q).  rr is (r, r) on the device.
+__global__ void __launch_bounds__(kBlock) k_to_inner(int n, const double *__restrict__ r,
+                                                     const double *__restrict__ rr, float *__restrict__ r32)
+{
+    const double nr = sqrt(*rr);
+    const double inv = nr > 0.0 ? 1.0 / nr : 1.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) r32[i] = (float)(r[i] * inv);
+}
+
+__global__ void __launch_bounds__(kBlock) k_from_inner(int n, const float *__restrict__ z32,
+                                                       const double *__restrict__ rr, double *__restrict__ z,
+                                                       const double *__restrict__ q, double *__restrict__ part)
+{
+    const double nr = sqrt(*rr);
+    const double sc = nr > 0.0 ? nr : 1.0;
+    double d[1] = {0.0};
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double zi = sc * (double)z32[i];
+        z[i] = zi;
+        d[0] += zi * q[i];
+    }
+    store_partials<1>(d, part);
+}
+
+template <class S, class D>
+__global__ void __launch_bounds__(kBlock) k_convert(int64_t n, const S *__restrict__ src, D *__restrict__ dst)
+{
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        dst[i] = (D)src[i];
 }
 
 // ------------------------------------------------------------------ outer flexible CG
@@ -761,39 +880,49 @@ void launch_spmv(Rows R, const int *ci, const double *va, const double *x, doubl
     AMG_HIP(hipGetLastError());
 }
 
-DotSet launch_spmv_dots(Rows R, const int *ci, const double *va, const double *x, double *y, const double *w1,
-                        const double *w2, int G, DotBuf buf, hipStream_t s)
+template <class T>
+DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, const T *w1, const T *w2, int G,
+                        DotBuf buf, hipStream_t s, const double *omy)
 {
     const int grid = rows_grid(R, G, kMaxDotBlocks);
     const int nd = w2 ? 3 : (w1 ? 2 : 1);
-#define AMG_SPMV_DOTS(ND, LAT) \
-    AMG_SWITCH_G(G, (k_spmv_dots<kG, ND, LAT><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, buf.part)))
+    if (omy && nd == 3) throw Error(4, "spmv_dots: at most three products");
+#define AMG_SPMV_DOTS(ND, LAT, OMY)                                                                        \
+    AMG_SWITCH_G(G, (k_spmv_dots<T, kG, ND, LAT, OMY><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, omy, \
+                                                                               buf.part)))
     const bool lat = R.n < kSmallLevel;
-    if (nd == 1) {
-        if (lat) {
-            AMG_SPMV_DOTS(1, true);
+    if (omy) {
+        if (nd == 1) {
+            AMG_SPMV_DOTS(1, true, true);
         } else {
-            AMG_SPMV_DOTS(1, false);
+            AMG_SPMV_DOTS(2, true, true);
+        }
+    } else if (nd == 1) {
+        if (lat) {
+            AMG_SPMV_DOTS(1, true, false);
+        } else {
+            AMG_SPMV_DOTS(1, false, false);
         }
     } else if (nd == 2) {
         if (lat) {
-            AMG_SPMV_DOTS(2, true);
+            AMG_SPMV_DOTS(2, true, false);
         } else {
-            AMG_SPMV_DOTS(2, false);
+            AMG_SPMV_DOTS(2, false, false);
         }
     } else {
         if (lat) {
-            AMG_SPMV_DOTS(3, true);
+            AMG_SPMV_DOTS(3, true, false);
         } else {
-            AMG_SPMV_DOTS(3, false);
+            AMG_SPMV_DOTS(3, false, false);
         }
     }
 #undef AMG_SPMV_DOTS
     AMG_HIP(hipGetLastError());
+    const int nt = nd + (omy ? 1 : 0);
     const int count = grid + R.nlong;
-    reduce_if_large(nd, buf.part, count, buf.final_out, s);
+    reduce_if_large(nt, buf.part, count, buf.final_out, s);
     DotSet out{};
-    for (int d = 0; d < nd; d++) out.d[d] = finished(buf.part, count, buf.final_out, d);
+    for (int d = 0; d < nt; d++) out.d[d] = finished(buf.part, count, buf.final_out, d);
     return out;
 }
 
@@ -816,41 +945,50 @@ void launch_reduce(const DotRef &ref, double *out, hipStream_t s)
     AMG_HIP(hipGetLastError());
 }
 
-void launch_restrict(Rows S, const int *ci, const double *wv, const double *r, double *rc, int G, hipStream_t s)
+template <class T>
+DotRef launch_restrict(Rows S, const int *ci, const T *wv, const T *r, T *rc, int G, hipStream_t s, const double *om,
+                       DotBuf buf)
 {
-    const int grid = rows_grid(S, G, 1 << 20);
-    if (S.n < kSmallLevel) {
-        AMG_SWITCH_G(G, (k_restrict<kG, true><<<grid, kBlock, 0, s>>>(S, ci, wv, r, rc)));
+    const int grid = rows_grid(S, G, om ? kMaxDotBlocks : (1 << 20));
+    if (om) {
+        AMG_SWITCH_G(G, (k_restrict<T, kG, true, true><<<grid, kBlock, 0, s>>>(S, ci, wv, r, rc, om, buf.part)));
+    } else if (S.n < kSmallLevel) {
+        AMG_SWITCH_G(G, (k_restrict<T, kG, true, false><<<grid, kBlock, 0, s>>>(S, ci, wv, r, rc, om, buf.part)));
     } else {
-        AMG_SWITCH_G(G, (k_restrict<kG, false><<<grid, kBlock, 0, s>>>(S, ci, wv, r, rc)));
+        AMG_SWITCH_G(G, (k_restrict<T, kG, false, false><<<grid, kBlock, 0, s>>>(S, ci, wv, r, rc, om, buf.part)));
     }
     AMG_HIP(hipGetLastError());
+    if (!om) return DotRef{nullptr, 0};
+    const int count = grid + S.nlong;
+    reduce_if_large(1, buf.part, count, buf.final_out, s);
+    return finished(buf.part, count, buf.final_out, 0);
 }
 
-void launch_inner_residual(int n, const double *rc, const double *v1, KDots kd, double *rt, int *flag, hipStream_t s)
+template <class T>
+void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, hipStream_t s)
 {
-    k_inner_residual<<<grid_for(n, 4096), kBlock, 0, s>>>(n, rc, v1, kd, rt, flag);
+    k_inner_residual<T><<<grid_for(n, 4096), kBlock, 0, s>>>(n, rc, v1, kd, rt, flag);
     AMG_HIP(hipGetLastError());
 }
 
-DotRef launch_post_smooth(Rows R, const int *ci, const double *va, const double *minv, const double *r,
-                          const int *agg_pos, const int *cagg, int mode, const double *edirect, const double *c1, const double *c2,
-                          KDots kd, double *xout, const double *wdot, DotBuf buf, int *flag, int G, hipStream_t s,
-                          const double *ainv, int nc)
+template <class T>
+DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, const T *r, const int *agg_pos,
+                          const int *cagg, int mode, const T *edirect, const T *c1, const T *c2, KDots kd, T *xout,
+                          const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv, int nc)
 {
     const bool dot = wdot != nullptr;
     const int grid = rows_grid(R, G, dot ? kMaxDotBlocks : (1 << 20));
-#define AMG_POST(M, D)                                                                                        \
-    do {                                                                                                      \
-        if (cagg) {                                                                                           \
-            AMG_SWITCH_G(G, (k_post_smooth<kG, M, D, true><<<grid, kBlock, 0, s>>>(                           \
-                                R, ci, va, minv, r, agg_pos, cagg, edirect, c1, c2, kd, xout, wdot, buf.part, flag, \
-                                ainv, nc)));                                                                  \
-        } else {                                                                                              \
-            AMG_SWITCH_G(G, (k_post_smooth<kG, M, D, false><<<grid, kBlock, 0, s>>>(                          \
-                                R, ci, va, minv, r, agg_pos, cagg, edirect, c1, c2, kd, xout, wdot, buf.part, flag, \
-                                ainv, nc)));                                                                  \
-        }                                                                                                     \
+#define AMG_POST(M, D)                                                                                         \
+    do {                                                                                                       \
+        if (cagg) {                                                                                            \
+            AMG_SWITCH_G(G, (k_post_smooth<T, kG, M, D, true><<<grid, kBlock, 0, s>>>(                         \
+                                R, ci, va, minv, r, agg_pos, cagg, edirect, c1, c2, kd, xout, wdot, buf.part, flag,  \
+                                ainv, nc)));                                                                   \
+        } else {                                                                                               \
+            AMG_SWITCH_G(G, (k_post_smooth<T, kG, M, D, false><<<grid, kBlock, 0, s>>>(                        \
+                                R, ci, va, minv, r, agg_pos, cagg, edirect, c1, c2, kd, xout, wdot, buf.part, flag,  \
+                                ainv, nc)));                                                                   \
+        }                                                                                                      \
     } while (0)
     switch (mode) {
     case 0: if (dot) { AMG_POST(0, true); } else { AMG_POST(0, false); } break;
@@ -869,19 +1007,87 @@ DotRef launch_post_smooth(Rows R, const int *ci, const double *va, const double 
     return finished(buf.part, count, buf.final_out, 0);
 }
 
-void launch_restrict_rt(Rows S, int nf, const int *ci, const double *wv, const double *rcf, const double *v1,
-                        KDots kd, double *rt, double *rc, int *flag, int G, hipStream_t s)
+template <class T>
+DotRef launch_restrict_rt(Rows S, int nf, const int *ci, const T *wv, const T *rcf, const T *v1, KDots kd, T *rt,
+                          T *rc, int *flag, int G, hipStream_t s, const double *om, DotBuf buf)
 {
-    const int grid = rows_grid(S, G, 1 << 20);
-    AMG_SWITCH_G(G, (k_restrict_rt<kG><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, rcf, v1, kd, rt, rc, flag)));
+    const int grid = rows_grid(S, G, om ? kMaxDotBlocks : (1 << 20));
+    if (om) {
+        AMG_SWITCH_G(G, (k_restrict_rt<T, kG, true><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, rcf, v1, kd, rt, rc, flag,
+                                                                             om, buf.part)));
+    } else {
+        AMG_SWITCH_G(G, (k_restrict_rt<T, kG, false><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, rcf, v1, kd, rt, rc, flag,
+                                                                              om, buf.part)));
+    }
+    AMG_HIP(hipGetLastError());
+    if (!om) return DotRef{nullptr, 0};
+    const int count = grid + S.nlong;
+    reduce_if_large(1, buf.part, count, buf.final_out, s);
+    return finished(buf.part, count, buf.final_out, 0);
+}
+
+template <class T>
+void launch_post_direct(Rows R, const int *ci, const T *va, const T *minv, const T *r, const T *v1, KDots kd,
+                        DotRef om_r, DotRef om_v1, const double *ainv, T *xout, T *rt_out, int *flag, int G,
+                        bool rt_mode, hipStream_t s)
+{
+    const int grid = rows_grid(R, G, 1 << 20);
+    if (rt_mode) {
+        AMG_SWITCH_G(G, (k_post_direct<T, kG, true><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, v1, kd, om_r, om_v1,
+                                                                             ainv, xout, rt_out, flag)));
+    } else {
+        AMG_SWITCH_G(G, (k_post_direct<T, kG, false><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, v1, kd, om_r, om_v1,
+                                                                              ainv, xout, rt_out, flag)));
+    }
     AMG_HIP(hipGetLastError());
 }
 
-void launch_dense_gemv(int n, const double *a, const double *x, double *y, hipStream_t s)
+template <class T>
+void launch_dense_gemv(int n, const double *a, const T *x, T *y, hipStream_t s)
 {
-    k_dense_gemv<<<grid_for((int64_t)n * kWave), kBlock, 0, s>>>(n, a, x, y);
+    k_dense_gemv<T><<<grid_for((int64_t)n * kWave), kBlock, 0, s>>>(n, a, x, y);
     AMG_HIP(hipGetLastError());
 }
+
+void launch_to_inner(int n, const double *r, const double *rr, float *r32, hipStream_t s)
+{
+    k_to_inner<<<grid_for(n, 8192), kBlock, 0, s>>>(n, r, rr, r32);
+    AMG_HIP(hipGetLastError());
+}
+
+DotRef launch_from_inner(int n, const float *z32, const double *rr, double *z, const double *q, DotBuf buf,
+                         hipStream_t s)
+{
+    const int grid = grid_for(n, kMaxDotBlocks);
+    k_from_inner<<<grid, kBlock, 0, s>>>(n, z32, rr, z, q, buf.part);
+    AMG_HIP(hipGetLastError());
+    reduce_if_large(1, buf.part, grid, buf.final_out, s);
+    return finished(buf.part, grid, buf.final_out, 0);
+}
+
+void launch_to_float(int64_t n, const double *src, float *dst, hipStream_t s)
+{
+    k_convert<double, float><<<grid_for(n, 1 << 16), kBlock, 0, s>>>(n, src, dst);
+    AMG_HIP(hipGetLastError());
+}
+
+#define AMG_INSTANTIATE(T)                                                                                           \
+    template DotSet launch_spmv_dots<T>(Rows, const int *, const T *, const T *, T *, const T *, const T *, int,     \
+                                        DotBuf, hipStream_t, const double *);                                       \
+    template DotRef launch_restrict<T>(Rows, const int *, const T *, const T *, T *, int, hipStream_t,               \
+                                       const double *, DotBuf);                                                     \
+    template void launch_inner_residual<T>(int, const T *, const T *, KDots, T *, int *, hipStream_t);              \
+    template DotRef launch_post_smooth<T>(Rows, const int *, const T *, const T *, const T *, const int *,          \
+                                          const int *, int, const T *, const T *, const T *, KDots, T *, const T *, \
+                                          DotBuf, int *, int, hipStream_t, const double *, int);                    \
+    template DotRef launch_restrict_rt<T>(Rows, int, const int *, const T *, const T *, const T *, KDots, T *, T *, \
+                                          int *, int, hipStream_t, const double *, DotBuf);                         \
+    template void launch_post_direct<T>(Rows, const int *, const T *, const T *, const T *, const T *, KDots,       \
+                                        DotRef, DotRef, const double *, T *, T *, int *, int, bool, hipStream_t);   \
+    template void launch_dense_gemv<T>(int, const double *, const T *, T *, hipStream_t);
+AMG_INSTANTIATE(double)
+AMG_INSTANTIATE(float)
+#undef AMG_INSTANTIATE
 
 DotRef launch_fcg_update(int n, DotRef pq, DotRef pr, double *x, double *r, const double *p, const double *q,
                          DotBuf buf, int *flag, hipStream_t s)

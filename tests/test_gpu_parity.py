@@ -237,3 +237,25 @@ def test_option_variants_solve(amg, opt):
     r = b - oracle.spmv(rp, ci, va, x.cpu().numpy())
     assert st == amg.AMG_OK and np.linalg.norm(r) / np.linalg.norm(b) <= 1e-9
     assert abs(info.iterations - it_o) <= 2
+
+
+@pytest.mark.parametrize("case", ["grid3d_24_jitter", "grid2d_64"])
+def test_single_coarse_unknown(amg, case):
+    """coarsest_size=1 ends these hierarchies in one unknown, so the visit of the
+    level above it restricts by inner products (no restriction kernel)."""
+    rp, ci, va = CASES[case]()
+    n = len(rp) - 1
+    h, ref = setup_both(amg, rp, ci, va, coarsest_size=1)
+    assert_same_hierarchy(h, ref)
+    assert ref.level(ref.num_levels - 1).n == 1 and ref.num_levels >= 3
+    xv = inputs.rhs(n, 13)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.kcycle(dev(xv), z)
+    zo = ref.kcycle(xv)
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-10 * np.abs(zo).max())
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, info = h.solve(dev(xv), x, tol=1e-10)
+    xo, st_o, it_o, rel_o, _ = ref.solve(xv, tol=1e-10)
+    r = xv - oracle.spmv(rp, ci, va, x.cpu().numpy())
+    assert st == amg.AMG_OK and np.linalg.norm(r) / np.linalg.norm(xv) <= 1e-10
+    assert abs(info.iterations - it_o) <= 1
