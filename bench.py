@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=128, help="grid side (128 = the headline workload)")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--jitter", type=float, default=0.1, help="edge weights 1 + jitter U[-1,1] (0: unit weights)")
+    ap.add_argument("--precision", choices=["fp64", "fp32_inner"], default="fp64",
+                    help="fp32_inner: FP32-storage K-cycle inside the FP64 outer flexible CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--smoother-reps", type=int, default=50)
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "post_smooth_128cubed_traffic.json"))
@@ -67,7 +70,7 @@ def traffic_probe(args):
         dst.copy_(src)
     torch.cuda.synchronize()
     N = args.grid
-    rp, ci, va = inputs.grid_laplacian((N, N, N), jitter=0.1, seed=2)
+    rp, ci, va = inputs.grid_laplacian((N, N, N), jitter=args.jitter, seed=2)
     b = inputs.rhs(len(rp) - 1, 1)
     t = lambda a: torch.from_numpy(a).to(dev)
     h = amg.Hierarchy(t(rp), t(ci), t(va))
@@ -138,8 +141,9 @@ def main():
     dev = torch.device("cuda:0")
     N = args.grid
     t0 = time.perf_counter()
-    rp, ci, va = inputs.grid_laplacian((N, N, N), jitter=0.1, seed=2)
+    rp, ci, va = inputs.grid_laplacian((N, N, N), jitter=args.jitter, seed=2)
     n, nnz = len(rp) - 1, len(ci)
+    prec = amg.AMG_PREC_FP32_INNER if args.precision == "fp32_inner" else amg.AMG_PREC_FP64
     b = inputs.rhs(n, 1)
     gen_s = time.perf_counter() - t0
     d_rp, d_ci, d_va = (torch.from_numpy(a).to(dev) for a in (rp, ci, va))
@@ -149,7 +153,7 @@ def main():
 
     def step():
         x.zero_()
-        h = amg.Hierarchy(d_rp, d_ci, d_va)
+        h = amg.Hierarchy(d_rp, d_ci, d_va, precision=prec)
         st, info = h.solve(d_b, x, tol=args.tol)
         levels = h.num_levels
         sizes = [h.level_sizes(l) for l in range(levels)]
@@ -180,7 +184,7 @@ def main():
     assert max(rels) <= args.tol, rels
 
     # dominant kernel, timed live on the library's stream
-    h = amg.Hierarchy(d_rp, d_ci, d_va)
+    h = amg.Hierarchy(d_rp, d_ci, d_va, precision=prec)
     h.solve(d_b, x, tol=args.tol)
     avg_us, alg_bytes = h.time_smoother(args.smoother_reps)
     h.close()
@@ -189,9 +193,11 @@ def main():
     if os.path.exists(args.traffic_file):
         with open(args.traffic_file) as f:
             tr = json.load(f)
-        if tr.get("grid") == N and tr.get("source") == source_digest():
+        if tr.get("grid") == N and tr.get("source") == source_digest() and args.precision == "fp64":
             traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": "k_post_smooth (finest level)", "achieved": round(achieved, 1),
+    kname = "k_post_smooth (finest level, FP32 storage)" if args.precision == "fp32_inner" else \
+        "k_post_smooth (finest level)"
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "avg_us": round(avg_us, 2), "alg_bytes_per_launch": alg_bytes}
 
@@ -212,10 +218,14 @@ def main():
     out = {
         "metric": METRIC, "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"3D 7-point Laplacian {N}^3 (n={n}), weights 1+0.1U[-1,1] seed 2, Dirichlet, "
-                               f"FP64 CSR, rhs U[-1,1] seed 1, x0=0, tol {args.tol:g}; UA-AMG K-cycle (nu=2) "
-                               f"+ flexible CG, l1-Jacobi 1+1, coarsest <= 64",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32-storage K-cycle, f64 outer",
+        "data": "synthetic",
+        "config": {"workload": f"3D 7-point Laplacian {N}^3 (n={n}), "
+                               + (f"weights 1+{args.jitter:g}U[-1,1] seed 2" if args.jitter else "unit weights")
+                               + f", Dirichlet, FP64 CSR, rhs U[-1,1] seed 1, x0=0, tol {args.tol:g}; UA-AMG K-cycle "
+                               f"(nu=2) + flexible CG, l1-Jacobi 1+1, coarsest <= 64"
+                               + ("" if args.precision == "fp64" else "; K-cycle values and vectors in FP32"),
+                   "precision": args.precision,
                    "n": n, "nnz": nnz, "levels": levels, "level_sizes": [s[0] for s in sizes],
                    "passes": [s[2] for s in sizes], "parallelism": "single GPU"},
         "setup_ms": round(statistics.median(setups), 3), "solve_ms": round(statistics.median(solves), 3),

@@ -70,6 +70,8 @@ typedef struct {
                                 /* 0: launch its kernels one by one (same results)          */
     size_t mem_budget;          /* device bytes the hierarchy may hold; 0 = no limit        */
     void *stream;               /* hipStream_t, or NULL                                      */
+    int32_t max_rhs;            /* right-hand sides one amg_solve_batch may take (def. 1);   */
+                                /* work vectors are sized n_l * max_rhs on every level       */
 } amg_options;
 
 typedef struct {
@@ -97,6 +99,18 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt, amg_hierarchy **o
  * initial guess on entry and the solution on return (written on AMG_OK and
  * AMG_ERR_NOT_CONVERGED).  info (may be NULL) is filled on those two statuses. */
 amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, amg_solve_info *info);
+
+/* Solves A X = B for nrhs right-hand sides at once (1 <= nrhs <= opt.max_rhs): every
+ * kernel of the K-cycle and of the outer iteration serves all columns in one
+ * launch (grid dimension y = column).  B and X are column-major device arrays, column
+ * c at B + c * ldb and X + c * ldx (ldb, ldx >= n); X holds the initial guesses on
+ * entry.  Each column is iterated until its own recursive and true relative
+ * residuals are <= tol (columns that converge early keep iterating with the others;
+ * a zero right-hand side gives X = 0).  info (may be NULL) receives nrhs records,
+ * written on AMG_OK and AMG_ERR_NOT_CONVERGED; iterations is the iteration at which
+ * each column was confirmed.  One column gives the same result as amg_solve. */
+amg_status amg_solve_batch(amg_hierarchy *h, int32_t nrhs, const double *B, int32_t ldb, double *X, int32_t ldx,
+                           double tol, amg_solve_info *info);
 
 /* Releases every resource of h.  NULL is accepted.  Device blocks are kept in a
  * process-wide cache (per device and size class) for later hierarchies, because

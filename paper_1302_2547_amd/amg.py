@@ -37,7 +37,8 @@ class amg_options(ctypes.Structure):
     _fields_ = [("coarsest_size", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("stall_ratio", ctypes.c_double),
                 ("max_aggregate", ctypes.c_int32), ("seed", ctypes.c_uint64), ("kcycle_inner", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("max_coarsest", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
+                ("use_graph", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p),
+                ("max_rhs", ctypes.c_int32)]
 
 
 class amg_solve_info(ctypes.Structure):
@@ -55,6 +56,8 @@ _sig = {
     "amg_default_options": (None, [ctypes.POINTER(amg_options)]),
     "amg_setup": (ctypes.c_int, [ctypes.POINTER(amg_csr), ctypes.POINTER(amg_options), ctypes.POINTER(_P)]),
     "amg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(amg_solve_info)]),
+    "amg_solve_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.POINTER(amg_solve_info)]),
     "amg_free": (None, [_P]),
     "amg_release_cached_memory": (None, []),
     "amg_num_levels": (ctypes.c_int, [_P, _I32P]),
@@ -156,6 +159,18 @@ class Hierarchy:
         if raise_on_error and st not in (AMG_OK,):
             raise AmgError(st, "amg_solve")
         return st, info
+
+    def solve_batch(self, B, X, tol: float = 1e-8, raise_on_error: bool = True):
+        """B, X: (nrhs, n) contiguous float64 device tensors (row k = right-hand side k,
+        i.e. column-major n x nrhs with leading dimension n)."""
+        if B.dim() != 2 or B.shape != X.shape or B.shape[1] != self.n:
+            raise ValueError("B and X must both be (nrhs, n)")
+        k = B.shape[0]
+        infos = (amg_solve_info * k)()
+        st = amg_solve_batch(self._h, k, _ptr(B), self.n, _ptr(X), self.n, tol, infos)
+        if raise_on_error and st not in (AMG_OK,):
+            raise AmgError(st, "amg_solve_batch")
+        return st, list(infos)
 
     def spmv(self, level: int, x, y):
         self._check(amg_spmv(self._h, level, _ptr(x), _ptr(y)), "amg_spmv")

@@ -38,6 +38,10 @@ constexpr int kMaxLong = 2048;     // hub rows per operator (the threshold is ra
 constexpr int kSmallLevel = 100000;  // levels below this are latency-bound
 constexpr int kInlineCoarse = 64;    // coarsest levels up to this size are solved inside the post-smoother
 constexpr int kPartStride = kMaxDotBlocks + kMaxLong;
+// One right-hand side's block of a dot site: 3 partial sets, then 4 reduced values.
+// Column c of a batched solve (blockIdx.y = c) finds its block at c * kDotCol.
+constexpr int kDotCol = 3 * kPartStride + 4;
+constexpr int kScalCol = 8;  // device scalars per right-hand side
 
 struct Chunk {
     int row, beg, end, k;
@@ -63,7 +67,8 @@ struct DotRef {
 struct DotSet {
     DotRef d[3];
 };
-// Storage of one dot-product site: partials (3 * kPartStride) and 3 reduced values.
+// Storage of one dot-product site, per right-hand side: partials (3 * kPartStride)
+// and up to 4 reduced values (final_out = part + 3 * kPartStride).
 struct DotBuf {
     double *part;
     double *final_out;
@@ -134,61 +139,71 @@ int lanes_for(double avg_row_len, int n);
 void launch_spmv(Rows R, const int *ci, const double *va, const double *x, double *y, int G, hipStream_t s);
 // The K-cycle launchers take the storage type T of values and vectors (double, or
 // float in the mixed-precision mode); arithmetic and inner products are FP64.
+// ncol > 1 runs a batch of right-hand sides in one launch (gridDim.y = column):
+// each level's vectors are stored column after column (leading dimension = the
+// level's size) and every dot site holds one kDotCol block per column.
 //
 // y = A x (y may be NULL); d[0] = (x, A x), d[1] = (x, w1) if w1, d[2] = (x, w2) if w2
 // (omy, non-NULL only with at most two other products, adds (omy, A x) last.)
 template <class T>
 DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, const T *w1, const T *w2, int G,
-                        DotBuf buf, hipStream_t s, const double *omy = nullptr);
+                        DotBuf buf, hipStream_t s, const double *omy = nullptr, int ncol = 1);
 // r = b - A x; d[0] = (b, b), d[1] = (r, r)
 DotSet launch_residual(Rows R, const int *ci, const double *va, const double *b, const double *x, double *r, int G,
-                       DotBuf buf, hipStream_t s);
-// *out = value of ref (one block)
-void launch_reduce(const DotRef &ref, double *out, hipStream_t s);
-// rc = W r over the super-rows S, W = P^T (I - A M^-1) stored per entry
+                       DotBuf buf, hipStream_t s, int ncol = 1);
+// out[c * out_stride] = value of ref for column c (one block per column)
+void launch_reduce(const DotRef &ref, double *out, hipStream_t s, int ncol = 1, int out_stride = kScalCol);
+// rc = W r over the super-rows S (nf fine rows), W = P^T (I - A M^-1) stored per entry.
 // With om, also the partials of (om, rc) into buf (returned; else a null reference).
 template <class T>
-DotRef launch_restrict(Rows S, const int *ci, const T *wv, const T *r, T *rc, int G, hipStream_t s,
-                       const double *om = nullptr, DotBuf buf = DotBuf{});
+DotRef launch_restrict(Rows S, int nf, const int *ci, const T *wv, const T *r, T *rc, int G, hipStream_t s,
+                       const double *om = nullptr, DotBuf buf = DotBuf{}, int ncol = 1);
 // rc = W r with r = rt formed on the fly as rt = rcf - (alpha1/rho1) v1 (the
 // inner residual of the parent's first flexible-CG step), rt also stored
 template <class T>
 DotRef launch_restrict_rt(Rows S, int nf, const int *ci, const T *wv, const T *rcf, const T *v1, KDots kd, T *rt,
-                          T *rc, int *flag, int G, hipStream_t s, const double *om = nullptr, DotBuf buf = DotBuf{});
+                          T *rc, int *flag, int G, hipStream_t s, const double *om = nullptr, DotBuf buf = DotBuf{},
+                          int ncol = 1);
 // K-cycle visit of a level whose coarse level is one unknown (restriction by the
 // inner products om_r and, with rt_mode, om_v1; see k_post_direct).
 template <class T>
 void launch_post_direct(Rows R, const int *ci, const T *va, const T *minv, const T *r, const T *v1, KDots kd,
                         DotRef om_r, DotRef om_v1, const double *ainv, T *xout, T *rt_out, int *flag, int G,
-                        bool rt_mode, hipStream_t s);
+                        bool rt_mode, hipStream_t s, int ncol = 1);
 // rt = rc - (alpha1/rho1) v1
 template <class T>
-void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, hipStream_t s);
+void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, hipStream_t s, int ncol = 1);
 // post-smoothing with the coarse correction folded in (mode 0: e = edirect;
 // 1: e = (alpha1/rho1) c1; 2: e = a1 c1 + a2 c2; 3: e = ainv * edirect, a dense
 // coarsest solve of size nc <= kInlineCoarse done in the kernel); returns
-// (out, wdot) if wdot
+// (out, wdot) if wdot.  nc is the coarse level's size (the leading dimension of
+// edirect, c1, c2).
 template <class T>
 DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, const T *r, const int *agg_pos,
                           const int *cagg, int mode, const T *edirect, const T *c1, const T *c2, KDots kd, T *xout,
-                          const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv = nullptr,
-                          int nc = 0);
+                          const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv, int nc,
+                          int ncol = 1);
 // y = A x with A dense row-major FP64
 template <class T>
-void launch_dense_gemv(int n, const double *a, const T *x, T *y, hipStream_t s);
-// r32 = r / sqrt(*rr) (FP32); z = sqrt(*rr) z32 with the partials of (z, q)
-void launch_to_inner(int n, const double *r, const double *rr, float *r32, hipStream_t s);
+void launch_dense_gemv(int n, const double *a, const T *x, T *y, hipStream_t s, int ncol = 1);
+// r32 = r / sqrt(rr[c * kScalCol]) (FP32); z = sqrt(rr[c * kScalCol]) z32 with the
+// partials of (z, q)
+void launch_to_inner(int n, const double *r, const double *rr, float *r32, hipStream_t s, int ncol = 1);
 DotRef launch_from_inner(int n, const float *z32, const double *rr, double *z, const double *q, DotBuf buf,
-                         hipStream_t s);
+                         hipStream_t s, int ncol = 1);
 void launch_to_float(int64_t n, const double *src, float *dst, hipStream_t s);
 // alpha = pr/pq; x += alpha p; r -= alpha q; returns (r, r)
 DotRef launch_fcg_update(int n, DotRef pq, DotRef pr, double *x, double *r, const double *p, const double *q,
-                         DotBuf buf, int *flag, hipStream_t s);
+                         DotBuf buf, int *flag, hipStream_t s, int ncol = 1);
 // beta = -zq/pq; p = z + beta p
-void launch_fcg_direction(int n, DotRef pq, DotRef zq, const double *z, double *p, int *flag, hipStream_t s);
-DotRef launch_dot(int n, const double *a, const double *b, DotBuf buf, hipStream_t s);
-void launch_gather(int n, const double *src, const int *idx, double *dst, hipStream_t s);   // dst[i] = src[idx[i]]
-void launch_scatter(int n, const double *src, const int *idx, double *dst, hipStream_t s);  // dst[idx[i]] = src[i]
+void launch_fcg_direction(int n, DotRef pq, DotRef zq, const double *z, double *p, int *flag, hipStream_t s,
+                          int ncol = 1);
+DotRef launch_dot(int n, const double *a, const double *b, DotBuf buf, hipStream_t s, int ncol = 1);
+// dst[i] = src[idx[i]] / dst[idx[i]] = src[i]; ld <= 0 means n
+void launch_gather(int n, const double *src, const int *idx, double *dst, hipStream_t s, int ncol = 1,
+                   int ld_src = 0, int ld_dst = 0);
+void launch_scatter(int n, const double *src, const int *idx, double *dst, hipStream_t s, int ncol = 1,
+                    int ld_src = 0, int ld_dst = 0);
 // cagg[p] = agg_pos[ci[p]]: coarse unknown of every entry's column
 void launch_entry_coarse_column(int nnz, const int *ci, const int *agg_pos, int *cagg, hipStream_t s);
 void launch_restriction_weights(int n, const int *rp, const int *ci, const double *va, const double *minv, double *wv,

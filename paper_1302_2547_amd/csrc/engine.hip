@@ -273,8 +273,10 @@ struct amg_hierarchy {
     float *r32 = nullptr, *z32 = nullptr;
     KDots kd0{};             // dots of the finest visit's coarse correction (for timing)
     int *flag = nullptr;     // bit 0: Krylov breakdown
-    hipGraphExec_t g_kcycle = nullptr, g_first = nullptr, g_iter = nullptr;
-    bool graphs_tried = false;
+    struct Graphs {
+        hipGraphExec_t k = nullptr, first = nullptr, iter = nullptr;
+    };
+    std::map<int, Graphs> graphs;  // per batch width (an entry without graphs: launch eagerly)
     static constexpr int kMaxGraphDepth = 12;
     double *host = nullptr;  // pinned: readbacks
     int *host_i = nullptr;
@@ -285,8 +287,9 @@ struct amg_hierarchy {
     {
         AMG_TRACE_MSG("free: start");
         if (stream) (void)hipStreamSynchronize(stream);
-        for (hipGraphExec_t g : {g_kcycle, g_first, g_iter})
-            if (g) (void)hipGraphExecDestroy(g);
+        for (auto &kv : graphs)
+            for (hipGraphExec_t g : {kv.second.k, kv.second.first, kv.second.iter})
+                if (g) (void)hipGraphExecDestroy(g);
         AMG_TRACE_MSG("free: graphs destroyed");
         pool.release_all();
         AMG_TRACE_MSG("free: device memory released");
@@ -318,7 +321,9 @@ struct amg_hierarchy {
 
     DotBuf dot_buf()
     {
-        return DotBuf{pool.alloc<double>(3 * (size_t)amg::kPartStride), pool.alloc<double>(4)};
+        // one kDotCol block per right-hand side: partials, then the reduced values
+        double *base = pool.alloc<double>((size_t)amg::kDotCol * (size_t)opt.max_rhs);
+        return DotBuf{base, base + 3 * (size_t)amg::kPartStride};
     }
 
     // Rows descriptor of a CSR-like operator: rows longer than lim = 8 G entries
@@ -380,12 +385,13 @@ struct amg_hierarchy {
         KDots kd;
     };
     template <class T>
-    DotRef kcycle(int k, const T *r, T *x, const T *wdot, const RtSource<T> *rts);
-    void run_kcycle();
-    void run_first();
-    void run_iter();
-    void capture_graphs();
-    amg_status solve(const double *b_user, double *x_user, double tol, amg_solve_info *info);
+    DotRef kcycle(int k, const T *r, T *x, const T *wdot, const RtSource<T> *rts, int ncol);
+    void run_kcycle(int ncol);
+    void run_first(int ncol);
+    void run_iter(int ncol);
+    void capture_graphs(int ncol);
+    amg_status solve(int ncol, const double *b_user, int ldb, double *x_user, int ldx, double tol,
+                     amg_solve_info *info);
 };
 
 void amg_hierarchy::build(const amg_csr &A)
@@ -393,8 +399,9 @@ void amg_hierarchy::build(const amg_csr &A)
     using namespace amg;
     AMG_HIP(hipEventCreate(&ev0));
     AMG_HIP(hipEventCreate(&ev1));
-    AMG_HIP(hipHostMalloc((void **)&host, 64 * sizeof(double), hipHostMallocDefault));
-    host_i = reinterpret_cast<int *>(host + 32);
+    const size_t nscal = (size_t)amg::kScalCol * (size_t)opt.max_rhs;  // per-column device scalars
+    AMG_HIP(hipHostMalloc((void **)&host, (nscal + 64) * sizeof(double), hipHostMallocDefault));
+    host_i = reinterpret_cast<int *>(host + nscal + 32);
     AMG_HIP(hipEventRecord(ev0, stream));
 
     const int n0 = A.n, nnz0 = A.nnz;
@@ -557,6 +564,7 @@ void amg_hierarchy::finalize_layout()
 {
     using namespace amg;
     const int L = levels() - 1;
+    const size_t nr = (size_t)opt.max_rhs;  // columns of every work vector
     int *tmp = pool.alloc<int>(lev[0].n + 1);
     int *scan_tmp = pool.alloc<int>(scan_tmp_ints((int64_t)lev[0].nnz + 1));
     lev[L].perm = pool.alloc<int>(lev[L].n);
@@ -602,11 +610,11 @@ void amg_hierarchy::finalize_layout()
             }
         }
         if (l >= 1) {
-            F.rc = pool.alloc<double>(F.n);
-            F.rt = pool.alloc<double>(F.n);
-            F.c1 = pool.alloc<double>(F.n);
-            F.c2 = pool.alloc<double>(F.n);
-            F.v1 = pool.alloc<double>(F.n);
+            F.rc = pool.alloc<double>((size_t)F.n * nr);
+            F.rt = pool.alloc<double>((size_t)F.n * nr);
+            F.c1 = pool.alloc<double>((size_t)F.n * nr);
+            F.c2 = pool.alloc<double>((size_t)F.n * nr);
+            F.v1 = pool.alloc<double>((size_t)F.n * nr);
             F.d_c1 = dot_buf();
             F.d_c2 = dot_buf();
         }
@@ -649,30 +657,30 @@ void amg_hierarchy::finalize_layout()
             K.minv = to_float(F.minv, F.n);
             K.wv = to_float(F.wv, F.nnz);
             if (l >= 1) {
-                K.rc = pool.alloc<float>(F.n);
-                K.rt = pool.alloc<float>(F.n);
-                K.c1 = pool.alloc<float>(F.n);
-                K.c2 = pool.alloc<float>(F.n);
-                K.v1 = pool.alloc<float>(F.n);
+                K.rc = pool.alloc<float>((size_t)F.n * nr);
+                K.rt = pool.alloc<float>((size_t)F.n * nr);
+                K.c1 = pool.alloc<float>((size_t)F.n * nr);
+                K.c2 = pool.alloc<float>((size_t)F.n * nr);
+                K.v1 = pool.alloc<float>((size_t)F.n * nr);
             }
         }
-        r32 = pool.alloc<float>(lev[0].n);
-        z32 = pool.alloc<float>(lev[0].n);
+        r32 = pool.alloc<float>((size_t)lev[0].n * nr);
+        z32 = pool.alloc<float>((size_t)lev[0].n * nr);
     }
     const int n = lev[0].n;
-    b = pool.alloc<double>(n);
-    x = pool.alloc<double>(n);
-    r = pool.alloc<double>(n);
-    z = pool.alloc<double>(n);
-    p = pool.alloc<double>(n);
-    q = pool.alloc<double>(n);
-    AMG_HIP(hipMemsetAsync(q, 0, sizeof(double) * n, stream));
-    AMG_HIP(hipMemsetAsync(p, 0, sizeof(double) * n, stream));
+    b = pool.alloc<double>((size_t)n * nr);
+    x = pool.alloc<double>((size_t)n * nr);
+    r = pool.alloc<double>((size_t)n * nr);
+    z = pool.alloc<double>((size_t)n * nr);
+    p = pool.alloc<double>((size_t)n * nr);
+    q = pool.alloc<double>((size_t)n * nr);
+    AMG_HIP(hipMemsetAsync(q, 0, sizeof(double) * n * nr, stream));
+    AMG_HIP(hipMemsetAsync(p, 0, sizeof(double) * n * nr, stream));
     d_pq = dot_buf();
     d_rr = dot_buf();
     d_zq = dot_buf();
     d_res = dot_buf();
-    scal = pool.alloc<double>(8);
+    scal = pool.alloc<double>((size_t)amg::kScalCol * nr);
     flag = pool.alloc<int>(1);
     AMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
     sync();
@@ -685,16 +693,16 @@ void amg_hierarchy::finalize_layout()
 // preconditioned by K_{k+1}), prolongation + post-smoothing.  When wdot is given
 // the returned reference holds (x, wdot).
 template <class T>
-DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtSource<T> *rts)
+DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtSource<T> *rts, int ncol)
 {
     using namespace amg;
     const int L = levels() - 1;
     Level &F = lev[k];
     const KArrays<T> &FK = F.karr<T>();
     if (k == L) {  // single-level hierarchy (FP64 only): the exact solve is the preconditioner
-        launch_dense_gemv<T>(F.n, ainv, rr, xx, stream);
+        launch_dense_gemv<T>(F.n, ainv, rr, xx, stream, ncol);
         if constexpr (std::is_same<T, double>::value) {
-            if (wdot) return launch_dot(F.n, xx, wdot, d_zq, stream);
+            if (wdot) return launch_dot(F.n, xx, wdot, d_zq, stream, ncol);
         }
         return DotRef{nullptr, 0};
     }
@@ -702,10 +710,10 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
         // (rts: rr = rt is formed from the parent's first inner step and stored)
         if (rts) {
             launch_post_direct<T>(F.A, F.ci, FK.va, FK.minv, rts->rcf, rts->v1, rts->kd, F.om_rc, F.om_v1, ainv, xx,
-                                  const_cast<T *>(rr), flag, F.G, true, stream);
+                                  const_cast<T *>(rr), flag, F.G, true, stream, ncol);
         } else {
             launch_post_direct<T>(F.A, F.ci, FK.va, FK.minv, rr, nullptr, KDots{}, F.om_rc, DotRef{}, ainv, xx,
-                                  nullptr, flag, F.G, false, stream);
+                                  nullptr, flag, F.G, false, stream, ncol);
         }
         return DotRef{nullptr, 0};
     }
@@ -713,9 +721,9 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
     const KArrays<T> &CK = C.karr<T>();
     if (rts) {  // rr = rt is formed here from the parent's first inner step
         C.om_rc = launch_restrict_rt<T>(F.S, F.n, F.ci, FK.wv, rts->rcf, rts->v1, rts->kd, const_cast<T *>(rr), CK.rc,
-                                        flag, F.Gs, stream, C.omega, C.d_om);
+                                        flag, F.Gs, stream, C.omega, C.d_om, ncol);
     } else {
-        C.om_rc = launch_restrict<T>(F.S, F.ci, FK.wv, rr, CK.rc, F.Gs, stream, C.omega, C.d_om);
+        C.om_rc = launch_restrict<T>(F.S, F.n, F.ci, FK.wv, rr, CK.rc, F.Gs, stream, C.omega, C.d_om, ncol);
     }
     KDots kd{};
     int mode;
@@ -725,14 +733,14 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
             mode = 3;
             edirect = CK.rc;
         } else {
-            launch_dense_gemv<T>(C.n, ainv, CK.rc, CK.c1, stream);
+            launch_dense_gemv<T>(C.n, ainv, CK.rc, CK.c1, stream, ncol);
             mode = 0;
             edirect = CK.c1;
         }
     } else {
-        kcycle<T>(k + 1, CK.rc, CK.c1, nullptr, nullptr);
+        kcycle<T>(k + 1, CK.rc, CK.c1, nullptr, nullptr, ncol);
         const DotSet s1 =
-            launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c1, CK.v1, CK.rc, nullptr, C.G, C.d_c1, stream, C.omega);
+            launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c1, CK.v1, CK.rc, nullptr, C.G, C.d_c1, stream, C.omega, ncol);
         kd.rho1 = s1.d[0];
         kd.alpha1 = s1.d[1];
         if (C.omega) C.om_v1 = s1.d[2];
@@ -740,12 +748,13 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
         if (opt.kcycle_inner == 2) {
             if (C.n < kSmallLevel || C.omega) {  // fold the inner residual into the next restriction
                 const RtSource<T> src{CK.rc, CK.v1, kd};
-                kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, &src);
+                kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, &src, ncol);
             } else {
-                launch_inner_residual<T>(C.n, CK.rc, CK.v1, kd, CK.rt, flag, stream);
-                kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, nullptr);
+                launch_inner_residual<T>(C.n, CK.rc, CK.v1, kd, CK.rt, flag, stream, ncol);
+                kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, nullptr, ncol);
             }
-            const DotSet s2 = launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c2, nullptr, CK.v1, CK.rt, C.G, C.d_c2, stream);
+            const DotSet s2 =
+                launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c2, nullptr, CK.v1, CK.rt, C.G, C.d_c2, stream, nullptr, ncol);
             kd.beta = s2.d[0];
             kd.gamma = s2.d[1];
             kd.alpha2 = s2.d[2];
@@ -754,68 +763,72 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
     }
     if (k == 0) kd0 = kd;
     return launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rr, F.agg_pos, F.cagg, mode, edirect, CK.c1, CK.c2, kd, xx,
-                                 wdot, k == 0 ? d_zq : DotBuf{}, flag, F.G, stream, ainv, C.n);
+                                 wdot, k == 0 ? d_zq : DotBuf{}, flag, F.G, stream, ainv, C.n, ncol);
 }
 
 // One outer iteration is split in three replayable pieces:
 //   K     : z = B r, with (z, A p) for the direction update
 //   first : p = z; q = A p, (p, q), (p, r); x += alpha p, r -= alpha q; (r, r)
 //   iter  : p = z + beta p; then as in first
-void amg_hierarchy::run_kcycle()
+void amg_hierarchy::run_kcycle(int ncol)
 {
     using namespace amg;
-    if (g_kcycle) {
-        AMG_HIP(hipGraphLaunch(g_kcycle, stream));
-    } else if (mixed) {  // scal[0] holds (r, r)
+    const auto g = graphs.find(ncol);
+    if (g != graphs.end() && g->second.k) {
+        AMG_HIP(hipGraphLaunch(g->second.k, stream));
+    } else if (mixed) {  // scal[c * kScalCol] holds (r, r) of column c
         const int n = lev[0].n;
-        launch_to_inner(n, r, scal, r32, stream);
-        kcycle<float>(0, r32, z32, nullptr, nullptr);
-        dr_zq = launch_from_inner(n, z32, scal, z, q, d_zq, stream);
+        launch_to_inner(n, r, scal, r32, stream, ncol);
+        kcycle<float>(0, r32, z32, nullptr, nullptr, ncol);
+        dr_zq = launch_from_inner(n, z32, scal, z, q, d_zq, stream, ncol);
     } else {
-        dr_zq = kcycle<double>(0, r, z, q, nullptr);
+        dr_zq = kcycle<double>(0, r, z, q, nullptr, ncol);
     }
 }
 
-void amg_hierarchy::run_first()
+void amg_hierarchy::run_first(int ncol)
 {
     using namespace amg;
-    if (g_first) {
-        AMG_HIP(hipGraphLaunch(g_first, stream));
+    const auto g = graphs.find(ncol);
+    if (g != graphs.end() && g->second.first) {
+        AMG_HIP(hipGraphLaunch(g->second.first, stream));
         return;
     }
     Level &F = lev[0];
-    AMG_HIP(hipMemcpyAsync(p, z, sizeof(double) * F.n, hipMemcpyDeviceToDevice, stream));
-    const DotSet s1 = launch_spmv_dots<double>(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream);
+    AMG_HIP(hipMemcpyAsync(p, z, sizeof(double) * F.n * (size_t)ncol, hipMemcpyDeviceToDevice, stream));
+    const DotSet s1 = launch_spmv_dots<double>(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream, nullptr, ncol);
     dr_pq = s1.d[0];
     dr_pr = s1.d[1];
-    dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream);
-    launch_reduce(dr_rr, scal, stream);
+    dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream, ncol);
+    launch_reduce(dr_rr, scal, stream, ncol);
 }
 
-void amg_hierarchy::run_iter()
+void amg_hierarchy::run_iter(int ncol)
 {
     using namespace amg;
-    if (g_iter) {
-        AMG_HIP(hipGraphLaunch(g_iter, stream));
+    const auto g = graphs.find(ncol);
+    if (g != graphs.end() && g->second.iter) {
+        AMG_HIP(hipGraphLaunch(g->second.iter, stream));
         return;
     }
     Level &F = lev[0];
-    launch_fcg_direction(F.n, dr_pq, dr_zq, z, p, flag, stream);
-    const DotSet s1 = launch_spmv_dots<double>(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream);
+    launch_fcg_direction(F.n, dr_pq, dr_zq, z, p, flag, stream, ncol);
+    const DotSet s1 = launch_spmv_dots<double>(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream, nullptr, ncol);
     dr_pq = s1.d[0];
     dr_pr = s1.d[1];
-    dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream);
-    launch_reduce(dr_rr, scal, stream);
+    dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream, ncol);
+    launch_reduce(dr_rr, scal, stream, ncol);
 }
 
-// Records the three pieces once per hierarchy; every launch argument (buffers,
-// partial-set sizes) is fixed by the level sizes, so the graphs stay valid.
-void amg_hierarchy::capture_graphs()
+// Records the three pieces once per hierarchy and batch width; every launch
+// argument (buffers, partial-set sizes) is fixed by the level sizes, so the graphs
+// stay valid.
+void amg_hierarchy::capture_graphs(int ncol)
 {
     // The K-cycle visits level k 2^k times, so its graph has about 6 (2^L - 1)
     // nodes; deep hierarchies (small aggregates) are launched eagerly instead.
-    if (!opt.use_graph || graphs_tried) return;
-    graphs_tried = true;
+    if (!opt.use_graph || graphs.count(ncol)) return;
+    Graphs &G = graphs[ncol];
     const int L = levels() - 1;
     if (L > kMaxGraphDepth) return;
     auto capture = [&](auto &&body, hipGraphExec_t *out) {
@@ -834,73 +847,99 @@ void amg_hierarchy::capture_graphs()
         AMG_HIP(e);
     };
     hipGraphExec_t gk = nullptr, gf = nullptr, gi = nullptr;
-    AMG_TRACE_MSG("capturing K-cycle graph");
-    capture([&] { run_kcycle(); }, &gk);
+    AMG_TRACE_MSG("capturing K-cycle graph (%d right-hand sides)", ncol);
+    capture([&] { run_kcycle(ncol); }, &gk);
     AMG_TRACE_MSG("capturing outer-iteration graphs");
-    capture([&] { run_first(); }, &gf);
-    capture([&] { run_iter(); }, &gi);
+    capture([&] { run_first(ncol); }, &gf);
+    capture([&] { run_iter(ncol); }, &gi);
     AMG_TRACE_MSG("graphs ready");
-    g_kcycle = gk;
-    g_first = gf;
-    g_iter = gi;
+    G.k = gk;
+    G.first = gf;
+    G.iter = gi;
 }
 
-amg_status amg_hierarchy::solve(const double *b_user, double *x_user, double tol, amg_solve_info *info)
+// Outer flexible CG over ncol right-hand sides at once (column c of b_user at
+// b_user + c * ldb).  Each column stops being counted when its recursive and its
+// true relative residual are <= tol; it keeps iterating with the others (a zero
+// residual gives a zero correction), and any confirmation restarts every column
+// from its true residual.
+amg_status amg_hierarchy::solve(int ncol, const double *b_user, int ldb, double *x_user, int ldx, double tol,
+                                amg_solve_info *info)
 {
     using namespace amg;
     Level &F = lev[0];
     const int n = F.n;
-    AMG_TRACE_MSG("solve: start");
+    AMG_TRACE_MSG("solve: start (%d right-hand sides)", ncol);
     AMG_HIP(hipEventRecord(ev0, stream));
-    capture_graphs();
+    capture_graphs(ncol);
     AMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
-    launch_gather(n, b_user, F.perm, b, stream);
-    launch_gather(n, x_user, F.perm, x, stream);
-    auto true_residual = [&]() {  // r = b - A x; scal[1] = (b, b), scal[2] = (r, r)
-        const DotSet s0 = launch_residual(F.A, F.ci, F.va, b, x, r, F.G, d_res, stream);
-        launch_reduce(s0.d[0], scal + 1, stream);
-        launch_reduce(s0.d[1], scal + 2, stream);
-        if (mixed) launch_reduce(s0.d[1], scal, stream);  // the K-cycle scales r by sqrt(scal[0])
-        AMG_HIP(hipMemcpyAsync(host, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    launch_gather(n, b_user, F.perm, b, stream, ncol, ldb, n);
+    launch_gather(n, x_user, F.perm, x, stream, ncol, ldx, n);
+    auto true_residual = [&]() {  // r = b - A x; per column (b, b), (r, r) at scal[c * kScalCol + 1, + 2]
+        const DotSet s0 = launch_residual(F.A, F.ci, F.va, b, x, r, F.G, d_res, stream, ncol);
+        launch_reduce(s0.d[0], scal + 1, stream, ncol);
+        launch_reduce(s0.d[1], scal + 2, stream, ncol);
+        if (mixed) launch_reduce(s0.d[1], scal, stream, ncol);  // the K-cycle scales r by sqrt(scal[0])
+        AMG_HIP(hipMemcpyAsync(host, scal, sizeof(double) * kScalCol * ncol, hipMemcpyDeviceToHost, stream));
         sync();
     };
+    std::vector<double> bnorm(ncol), rel(ncol);
+    std::vector<int> iters(ncol, 0);
+    std::vector<char> done(ncol, 0), claim(ncol, 0);
     true_residual();
-    const double bb = host[1];
-    if (!std::isfinite(bb) || !std::isfinite(host[2])) return AMG_ERR_INVALID_ARGUMENT;
-    double rel = bb > 0.0 ? std::sqrt(host[2] / bb) : 0.0;
+    for (int c = 0; c < ncol; c++) {
+        const double bb = host[c * kScalCol + 1], rr = host[c * kScalCol + 2];
+        if (!std::isfinite(bb) || !std::isfinite(rr)) return AMG_ERR_INVALID_ARGUMENT;
+        bnorm[c] = std::sqrt(bb);
+        rel[c] = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+        done[c] = bb == 0.0 || rel[c] <= tol;
+    }
+    auto all_done = [&]() {
+        for (int c = 0; c < ncol; c++)
+            if (!done[c]) return false;
+        return true;
+    };
     int it = 0;
     amg_status st = AMG_ERR_NOT_CONVERGED;
-    if (bb == 0.0) {
-        AMG_HIP(hipMemsetAsync(x_user, 0, sizeof(double) * n, stream));
-        st = AMG_OK;
-    } else {
-        const double bnorm = std::sqrt(bb);
-        bool restart = true;
-        if (rel <= tol) st = AMG_OK;
-        while (st != AMG_OK && it < opt.max_iters) {
-            run_kcycle();  // z = B r
-            if (restart) run_first();
-            else run_iter();
-            restart = false;
-            AMG_HIP(hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, stream));
-            AMG_HIP(hipMemcpyAsync(host_i, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
-            sync();
-            it++;
-            if (host_i[0]) {
-                st = AMG_ERR_BREAKDOWN;
-                break;
-            }
-            rel = std::sqrt(host[0]) / bnorm;
-            if (rel <= tol) {  // confirm with the true residual; restart from it if they disagree
-                true_residual();
-                rel = std::sqrt(host[2]) / bnorm;
-                if (rel <= tol) st = AMG_OK;
-                else restart = true;
-            }
+    bool restart = true;
+    while (!all_done() && it < opt.max_iters) {
+        run_kcycle(ncol);  // z = B r
+        if (restart) run_first(ncol);
+        else run_iter(ncol);
+        restart = false;
+        AMG_HIP(hipMemcpyAsync(host, scal, sizeof(double) * kScalCol * ncol, hipMemcpyDeviceToHost, stream));
+        AMG_HIP(hipMemcpyAsync(host_i, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+        sync();
+        it++;
+        if (host_i[0]) {
+            st = AMG_ERR_BREAKDOWN;
+            break;
         }
-        launch_scatter(n, x, F.perm, x_user, stream);
-        true_residual();  // the reported residual is always the true one
-        rel = std::sqrt(host[2] / host[1]);
+        bool any = false;
+        for (int c = 0; c < ncol; c++) {
+            claim[c] = !done[c] && std::sqrt(host[c * kScalCol]) / bnorm[c] <= tol;
+            any = any || claim[c];
+        }
+        if (any) {  // confirm with the true residual, then restart every column from it
+            true_residual();
+            for (int c = 0; c < ncol; c++) {
+                if (claim[c] && std::sqrt(host[c * kScalCol + 2]) / bnorm[c] <= tol) {
+                    done[c] = 1;
+                    iters[c] = it;
+                }
+            }
+            restart = true;
+        }
+    }
+    if (st != AMG_ERR_BREAKDOWN) st = all_done() ? AMG_OK : AMG_ERR_NOT_CONVERGED;
+    launch_scatter(n, x, F.perm, x_user, stream, ncol, n, ldx);
+    for (int c = 0; c < ncol; c++)  // b = 0 has the solution 0
+        if (bnorm[c] == 0.0) AMG_HIP(hipMemsetAsync(x_user + (size_t)c * ldx, 0, sizeof(double) * n, stream));
+    true_residual();  // the reported residual is always the true one
+    for (int c = 0; c < ncol; c++) {
+        const double bb = host[c * kScalCol + 1];
+        rel[c] = bb > 0.0 ? std::sqrt(host[c * kScalCol + 2] / bb) : 0.0;
+        if (!done[c]) iters[c] = it;
     }
     AMG_HIP(hipEventRecord(ev1, stream));
     sync();
@@ -908,10 +947,12 @@ amg_status amg_hierarchy::solve(const double *b_user, double *x_user, double tol
     float ms = 0.f;
     AMG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     if (info) {
-        info->iterations = it;
-        info->rel_residual = rel;
-        info->setup_ms = setup_ms;
-        info->solve_ms = ms;
+        for (int c = 0; c < ncol; c++) {
+            info[c].iterations = iters[c];
+            info[c].rel_residual = rel[c];
+            info[c].setup_ms = setup_ms;
+            info[c].solve_ms = ms;
+        }
     }
     return st;
 }
@@ -954,6 +995,7 @@ void amg_default_options(amg_options *opt)
     opt->use_graph = 1;
     opt->mem_budget = 0;
     opt->stream = nullptr;
+    opt->max_rhs = 1;
 }
 
 amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy **out)
@@ -966,7 +1008,7 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy 
     else amg_default_options(&opt);
     if (opt.coarsest_size < 1 || opt.max_levels < 1 || opt.max_levels > 64 || !(opt.stall_ratio > 0.0) ||
         !(opt.stall_ratio <= 1.0) || opt.max_aggregate < 0 || opt.max_aggregate == 1 || opt.max_iters < 0 ||
-        opt.max_coarsest < 1)
+        opt.max_coarsest < 1 || opt.max_rhs < 1 || opt.max_rhs > 1024)
         return AMG_ERR_INVALID_ARGUMENT;
     if (opt.kcycle_inner != 1 && opt.kcycle_inner != 2) return AMG_ERR_UNSUPPORTED;
     if (opt.precision != AMG_PREC_FP64 && opt.precision != AMG_PREC_FP32_INNER) return AMG_ERR_UNSUPPORTED;
@@ -997,7 +1039,16 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy 
 amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, amg_solve_info *info)
 {
     if (!h || !b || !x || !(tol > 0.0) || !std::isfinite(tol)) return AMG_ERR_INVALID_ARGUMENT;
-    return guarded([&]() { return h->solve(b, x, tol, info); });
+    return guarded([&]() { return h->solve(1, b, h->lev[0].n, x, h->lev[0].n, tol, info); });
+}
+
+amg_status amg_solve_batch(amg_hierarchy *h, int32_t nrhs, const double *B, int32_t ldb, double *X, int32_t ldx,
+                           double tol, amg_solve_info *info)
+{
+    if (!h || !B || !X || !(tol > 0.0) || !std::isfinite(tol)) return AMG_ERR_INVALID_ARGUMENT;
+    const int n = h->lev[0].n;
+    if (nrhs < 1 || nrhs > h->opt.max_rhs || ldb < n || ldx < n) return AMG_ERR_INVALID_ARGUMENT;
+    return guarded([&]() { return h->solve(nrhs, B, ldb, X, ldx, tol, info); });
 }
 
 void amg_free(amg_hierarchy *h) { delete h; }
@@ -1066,14 +1117,14 @@ amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z)
     if (!h || !r || !z) return AMG_ERR_INVALID_ARGUMENT;
     return guarded([&]() {
         const Level &F = h->lev[0];
-        h->capture_graphs();
+        h->capture_graphs(1);
         AMG_HIP(hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
         amg::launch_gather(F.n, r, F.perm, h->r, h->stream);
         if (h->mixed) {  // the mixed K-cycle reads (r, r) from scal[0]
             const DotRef rr = amg::launch_dot(F.n, h->r, h->r, h->d_res, h->stream);
             amg::launch_reduce(rr, h->scal, h->stream);
         }
-        h->run_kcycle();
+        h->run_kcycle(1);
         amg::launch_scatter(F.n, h->z, F.perm, z, h->stream);
         AMG_HIP(hipMemcpyAsync(h->host_i, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         h->sync();
@@ -1092,10 +1143,11 @@ amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, dou
             if (h->mixed) {
                 amg::launch_post_smooth<float>(F.A, F.ci, F.k32.va, F.k32.minv, h->r32, F.agg_pos, F.cagg, mode,
                                                nullptr, C.k32.c1, C.k32.c2, h->kd0, h->z32, nullptr, DotBuf{}, h->flag,
-                                               F.G, h->stream);
+                                               F.G, h->stream, h->ainv, C.n);
             } else {
                 amg::launch_post_smooth<double>(F.A, F.ci, F.va, F.minv, h->r, F.agg_pos, F.cagg, mode, nullptr, C.c1,
-                                                C.c2, h->kd0, h->z, nullptr, DotBuf{}, h->flag, F.G, h->stream);
+                                                C.c2, h->kd0, h->z, nullptr, DotBuf{}, h->flag, F.G, h->stream,
+                                                h->ainv, C.n);
             }
         };
         launch();

@@ -45,6 +45,19 @@ __device__ inline double group_sum(double v)
     return v;
 }
 
+// Batched launches: right-hand side c = blockIdx.y; a level's vectors (n rows)
+// are stored column after column, and every dot site keeps one kDotCol block per
+// column.  Unbatched launches have gridDim.y = 1 and change nothing.
+template <class P>
+__device__ inline P *colv(P *v, int ld)
+{
+    return v ? v + (size_t)blockIdx.y * (size_t)ld : v;
+}
+__device__ inline double *colp(double *part)
+{
+    return part ? part + (size_t)blockIdx.y * kDotCol : part;
+}
+
 // Sum over the block; every thread receives the same value (fixed order).
 __device__ inline double block_sum(double v)
 {
@@ -93,12 +106,13 @@ __device__ inline void block_sums(double (&v)[N])
 template <int N, bool PREFETCH = true>
 __device__ inline void dot_values(const DotRef *refs, double (&out)[N])
 {
+    const size_t col = (size_t)blockIdx.y * kDotCol;  // this right-hand side's dot block
     bool all_final = true;
 #pragma unroll
     for (int d = 0; d < N; d++) all_final = all_final && refs[d].count == 1;
     if (all_final) {  // one load each, no reduction
 #pragma unroll
-        for (int d = 0; d < N; d++) out[d] = refs[d].part[0];
+        for (int d = 0; d < N; d++) out[d] = refs[d].part[col];
         return;
     }
     if (!PREFETCH) {
@@ -106,7 +120,7 @@ __device__ inline void dot_values(const DotRef *refs, double (&out)[N])
 #pragma unroll
         for (int d = 0; d < N; d++) {
             double t = 0.0;
-            for (int b = lane; b < refs[d].count; b += kWave) t += refs[d].part[b];
+            for (int b = lane; b < refs[d].count; b += kWave) t += refs[d].part[col + b];
             out[d] = wave_sum(t);
         }
         return;
@@ -119,7 +133,7 @@ __device__ inline void dot_values(const DotRef *refs, double (&out)[N])
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int b = t + u * kBlock;
-            v[d][u] = refs[d].part[b < last ? b : last];
+            v[d][u] = refs[d].part[col + (b < last ? b : last)];
         }
     }
 #pragma unroll
@@ -128,7 +142,7 @@ __device__ inline void dot_values(const DotRef *refs, double (&out)[N])
         double a = 0.0;
 #pragma unroll
         for (int u = 0; u < 4; u++) a += t + u * kBlock < count ? v[d][u] : 0.0;
-        for (int b = t + 4 * kBlock; b < count; b += kBlock) a += refs[d].part[b];  // beyond kBlock * 4
+        for (int b = t + 4 * kBlock; b < count; b += kBlock) a += refs[d].part[col + b];  // beyond kBlock * 4
         out[d] = a;
     }
     block_sums<N>(out);
@@ -331,6 +345,11 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dots(Rows R, const int *__restr
                                                       double *__restrict__ part)
 {
     constexpr int NT = ND + (OMY ? 1 : 0);
+    x = colv(x, R.n);
+    y = colv(y, R.n);
+    w1 = colv(w1, R.n);
+    w2 = colv(w2, R.n);
+    part = colp(part);
     double d[NT] = {};
     const int nb = gridDim.x;
     struct Pre {
@@ -371,6 +390,10 @@ __global__ void __launch_bounds__(kBlock) k_residual(Rows R, const int *__restri
                                                      const double *__restrict__ x, double *__restrict__ r,
                                                      double *__restrict__ part)
 {
+    b = colv(b, R.n);
+    x = colv(x, R.n);
+    r = colv(r, R.n);
+    part = colp(part);
     double d[2] = {0.0, 0.0};
     const int nb = gridDim.x;
     visit_rows<G, false>(
@@ -392,8 +415,11 @@ __global__ void __launch_bounds__(kBlock) k_residual(Rows R, const int *__restri
 // One block of 1024 threads reduces large partial sets (fixed order).
 constexpr int kReduceThreads = 1024;
 __global__ void __launch_bounds__(kReduceThreads) k_reduce_partials(int nd, const double *__restrict__ part,
-                                                                    int count, double *__restrict__ out)
+                                                                    int count, double *__restrict__ out,
+                                                                    int out_stride)
 {
+    part += (size_t)blockIdx.y * kDotCol;
+    out += (size_t)blockIdx.y * out_stride;
     __shared__ double sh[kReduceThreads / kWave];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     for (int d = 0; d < nd; d++) {
@@ -425,11 +451,14 @@ __global__ void __launch_bounds__(kReduceThreads) k_reduce_partials(int nd, cons
 // OM adds partials of (om, rc) (the restriction to a single coarse unknown of
 // the next level down, see k_post_direct).
 template <class T, int G, bool LAT, bool OM>
-__global__ void __launch_bounds__(kBlock) k_restrict(Rows S, const int *__restrict__ ci,
+__global__ void __launch_bounds__(kBlock) k_restrict(Rows S, int nf, const int *__restrict__ ci,
                                                      const T *__restrict__ wv, const T *__restrict__ r,
                                                      T *__restrict__ rc, const double *__restrict__ om,
                                                      double *__restrict__ part)
 {
+    r = colv(r, nf);
+    rc = colv(rc, S.n);
+    part = colp(part);
     double d[1] = {0.0};
     const int nb = gridDim.x;
     visit_rows<G, LAT>(
@@ -477,8 +506,11 @@ __device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd)
         rho1 = v[0];
         alpha1 = v[1];
     }
+    // A zero coarse residual (rc = 0: a converged or empty right-hand side of a
+    // batch) gives c1 = 0, rho1 = alpha1 = 0 and a zero correction, not a breakdown;
+    // likewise rt = 0 in the second step.
     if (!(rho1 > 0.0)) {
-        c.bad = true;
+        c.bad = !(rho1 == 0.0 && alpha1 == 0.0);
         return c;
     }
     const double q1 = alpha1 / rho1;
@@ -487,6 +519,7 @@ __device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd)
     const double g1 = gamma / rho1;
     const double rho2 = beta - gamma * g1;
     if (!(rho2 > 0.0)) {
+        if (beta == 0.0 && alpha2 == 0.0) return c;  // c2 = 0: only the first step counts
         c.bad = true;
         return c;
     }
@@ -507,6 +540,11 @@ __global__ void __launch_bounds__(kBlock) k_restrict_rt(Rows S, int nf, const in
                                                         int *__restrict__ flag, const double *__restrict__ om,
                                                         double *__restrict__ part)
 {
+    rcf = colv(rcf, nf);
+    v1 = colv(v1, nf);
+    rt = colv(rt, nf);
+    rc = colv(rc, S.n);
+    part = colp(part);
     double d[1] = {0.0};
     const int nb = gridDim.x;
     const int gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
@@ -546,6 +584,9 @@ __global__ void __launch_bounds__(kBlock) k_inner_residual(int n, const T *__res
                                                            const T *__restrict__ v1, KDots kd,
                                                            T *__restrict__ rt, int *__restrict__ flag)
 {
+    rc = colv(rc, n);
+    v1 = colv(v1, n);
+    rt = colv(rt, n);
     const KCoef c = kcycle_coefficients<false>(1, kd);  // large levels only
     if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
@@ -573,6 +614,13 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
                                                         double *__restrict__ part, int *__restrict__ flag,
                                                         const double *__restrict__ ainv, int nc)
 {
+    r = colv(r, R.n);
+    xout = colv(xout, R.n);
+    wdot = colv(wdot, R.n);
+    edirect = colv(edirect, nc);
+    c1 = colv(c1, nc);
+    c2 = colv(c2, nc);
+    part = colp(part);
     double a1 = 0.0, a2 = 0.0;
     __shared__ double e_sh[MODE == 3 ? kInlineCoarse : 1];
     auto corr = [&](int J) -> double {
@@ -653,6 +701,10 @@ __global__ void __launch_bounds__(kBlock) k_post_direct(Rows R, const int *__res
                                                         const double *__restrict__ ainv, T *__restrict__ xout,
                                                         T *__restrict__ rt_out, int *__restrict__ flag)
 {
+    r = colv(r, R.n);
+    v1 = colv(v1, R.n);
+    xout = colv(xout, R.n);
+    rt_out = colv(rt_out, R.n);
     double a = 0.0, e = 0.0;
     struct Pre {
         double mr, rr, vr;
@@ -668,9 +720,10 @@ __global__ void __launch_bounds__(kBlock) k_post_direct(Rows R, const int *__res
                 const DotRef refs[4] = {kd.rho1, kd.alpha1, om_r, om_v1};
                 double v[4];
                 dot_values<4>(refs, v);
-                const bool bad = !(v[0] > 0.0);
+                const bool zero = v[0] == 0.0 && v[1] == 0.0;
+                const bool bad = !(v[0] > 0.0) && !zero;
                 if (bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
-                a = bad ? 0.0 : v[1] / v[0];
+                a = (bad || zero) ? 0.0 : v[1] / v[0];
                 e = ac_inv * (v[2] - a * v[3]);
             } else {
                 double v[1];
@@ -697,6 +750,8 @@ template <class T>
 __global__ void __launch_bounds__(kBlock) k_dense_gemv(int n, const double *__restrict__ a,
                                                        const T *__restrict__ x, T *__restrict__ y)
 {
+    x = colv(x, n);
+    y = colv(y, n);
     const int lane = threadIdx.x & (kWave - 1);
     const int nw = gridDim.x * (kBlock / kWave);
     for (int i = (blockIdx.x * kBlock + threadIdx.x) / kWave; i < n; i += nw) {
@@ -714,7 +769,9 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemv(int n, const double *__re
 __global__ void __launch_bounds__(kBlock) k_to_inner(int n, const double *__restrict__ r,
                                                      const double *__restrict__ rr, float *__restrict__ r32)
 {
-    const double nr = sqrt(*rr);
+    r = colv(r, n);
+    r32 = colv(r32, n);
+    const double nr = sqrt(rr[(size_t)blockIdx.y * kScalCol]);
     const double inv = nr > 0.0 ? 1.0 / nr : 1.0;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) r32[i] = (float)(r[i] * inv);
 }
@@ -723,7 +780,11 @@ __global__ void __launch_bounds__(kBlock) k_from_inner(int n, const float *__res
                                                        const double *__restrict__ rr, double *__restrict__ z,
                                                        const double *__restrict__ q, double *__restrict__ part)
 {
-    const double nr = sqrt(*rr);
+    z32 = colv(z32, n);
+    z = colv(z, n);
+    q = colv(q, n);
+    part = colp(part);
+    const double nr = sqrt(rr[(size_t)blockIdx.y * kScalCol]);
     const double sc = nr > 0.0 ? nr : 1.0;
     double d[1] = {0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
@@ -749,9 +810,15 @@ __global__ void __launch_bounds__(kBlock) k_fcg_update(int n, DotRef pq, DotRef 
                                                        const double *__restrict__ q, double *__restrict__ part,
                                                        int *__restrict__ flag)
 {
+    x = colv(x, n);
+    r = colv(r, n);
+    p = colv(p, n);
+    q = colv(q, n);
+    part = colp(part);
     const double vpq = dot_value(pq), vpr = dot_value(pr);
-    const bool bad = !(vpq > 0.0);
-    const double alpha = bad ? 0.0 : vpr / vpq;
+    const bool zero = vpq == 0.0 && vpr == 0.0;  // p = 0: a converged or empty right-hand side
+    const bool bad = !(vpq > 0.0) && !zero;
+    const double alpha = (bad || zero) ? 0.0 : vpr / vpq;
     if (bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
     double d[1] = {0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
@@ -767,9 +834,12 @@ __global__ void __launch_bounds__(kBlock) k_fcg_update(int n, DotRef pq, DotRef 
 __global__ void __launch_bounds__(kBlock) k_fcg_direction(int n, DotRef pq, DotRef zq, const double *__restrict__ z,
                                                           double *__restrict__ p, int *__restrict__ flag)
 {
+    z = colv(z, n);
+    p = colv(p, n);
     const double vpq = dot_value(pq), vzq = dot_value(zq);
-    const bool bad = !(vpq > 0.0);
-    const double beta = bad ? 0.0 : -vzq / vpq;
+    const bool zero = vpq == 0.0 && vzq == 0.0;
+    const bool bad = !(vpq > 0.0) && !zero;
+    const double beta = (bad || zero) ? 0.0 : -vzq / vpq;
     if (bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i] + beta * p[i];
 }
@@ -777,20 +847,27 @@ __global__ void __launch_bounds__(kBlock) k_fcg_direction(int n, DotRef pq, DotR
 __global__ void __launch_bounds__(kBlock) k_dot(int n, const double *__restrict__ a, const double *__restrict__ b,
                                                 double *__restrict__ part)
 {
+    a = colv(a, n);
+    b = colv(b, n);
+    part = colp(part);
     double d[1] = {0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) d[0] += a[i] * b[i];
     store_partials<1>(d, part);
 }
 
-__global__ void __launch_bounds__(kBlock) k_gather(int n, const double *__restrict__ src, const int *__restrict__ idx,
-                                                   double *__restrict__ dst)
+__global__ void __launch_bounds__(kBlock) k_gather(int n, const double *__restrict__ src, int ld_src,
+                                                   const int *__restrict__ idx, double *__restrict__ dst, int ld_dst)
 {
+    src = colv(src, ld_src);
+    dst = colv(dst, ld_dst);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[idx[i]];
 }
 
-__global__ void __launch_bounds__(kBlock) k_scatter(int n, const double *__restrict__ src, const int *__restrict__ idx,
-                                                    double *__restrict__ dst)
+__global__ void __launch_bounds__(kBlock) k_scatter(int n, const double *__restrict__ src, int ld_src,
+                                                    const int *__restrict__ idx, double *__restrict__ dst, int ld_dst)
 {
+    src = colv(src, ld_src);
+    dst = colv(dst, ld_dst);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[idx[i]] = src[i];
 }
 
@@ -830,10 +907,10 @@ inline int rows_grid(const Rows &R, int G, int cap)
 // every consumer block.
 constexpr int kConsumerReduceMax = 1024;
 
-void reduce_if_large(int nd, double *part, int count, double *final_out, hipStream_t s)
+void reduce_if_large(int nd, double *part, int count, double *final_out, hipStream_t s, int ncol)
 {
     if (count > kConsumerReduceMax && final_out) {
-        k_reduce_partials<<<1, kReduceThreads, 0, s>>>(nd, part, count, final_out);
+        k_reduce_partials<<<dim3(1, ncol), kReduceThreads, 0, s>>>(nd, part, count, final_out, kDotCol);
         AMG_HIP(hipGetLastError());
     }
 }
@@ -882,9 +959,9 @@ void launch_spmv(Rows R, const int *ci, const double *va, const double *x, doubl
 
 template <class T>
 DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, const T *w1, const T *w2, int G,
-                        DotBuf buf, hipStream_t s, const double *omy)
+                        DotBuf buf, hipStream_t s, const double *omy, int ncol)
 {
-    const int grid = rows_grid(R, G, kMaxDotBlocks);
+    const dim3 grid(rows_grid(R, G, kMaxDotBlocks), ncol);
     const int nd = w2 ? 3 : (w1 ? 2 : 1);
     if (omy && nd == 3) throw Error(4, "spmv_dots: at most three products");
 #define AMG_SPMV_DOTS(ND, LAT, OMY)                                                                        \
@@ -919,65 +996,66 @@ DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, co
 #undef AMG_SPMV_DOTS
     AMG_HIP(hipGetLastError());
     const int nt = nd + (omy ? 1 : 0);
-    const int count = grid + R.nlong;
-    reduce_if_large(nt, buf.part, count, buf.final_out, s);
+    const int count = (int)grid.x + R.nlong;
+    reduce_if_large(nt, buf.part, count, buf.final_out, s, ncol);
     DotSet out{};
     for (int d = 0; d < nt; d++) out.d[d] = finished(buf.part, count, buf.final_out, d);
     return out;
 }
 
 DotSet launch_residual(Rows R, const int *ci, const double *va, const double *b, const double *x, double *r, int G,
-                       DotBuf buf, hipStream_t s)
+                       DotBuf buf, hipStream_t s, int ncol)
 {
-    const int grid = rows_grid(R, G, kMaxDotBlocks);
+    const dim3 grid(rows_grid(R, G, kMaxDotBlocks), ncol);
     AMG_SWITCH_G(G, (k_residual<kG><<<grid, kBlock, 0, s>>>(R, ci, va, b, x, r, buf.part)));
     AMG_HIP(hipGetLastError());
-    const int count = grid + R.nlong;
-    reduce_if_large(2, buf.part, count, buf.final_out, s);
+    const int count = (int)grid.x + R.nlong;
+    reduce_if_large(2, buf.part, count, buf.final_out, s, ncol);
     DotSet out{};
     for (int d = 0; d < 2; d++) out.d[d] = finished(buf.part, count, buf.final_out, d);
     return out;
 }
 
-void launch_reduce(const DotRef &ref, double *out, hipStream_t s)
+void launch_reduce(const DotRef &ref, double *out, hipStream_t s, int ncol, int out_stride)
 {
-    k_reduce_partials<<<1, kReduceThreads, 0, s>>>(1, ref.part, ref.count, out);
+    k_reduce_partials<<<dim3(1, ncol), kReduceThreads, 0, s>>>(1, ref.part, ref.count, out, out_stride);
     AMG_HIP(hipGetLastError());
 }
 
 template <class T>
-DotRef launch_restrict(Rows S, const int *ci, const T *wv, const T *r, T *rc, int G, hipStream_t s, const double *om,
-                       DotBuf buf)
+DotRef launch_restrict(Rows S, int nf, const int *ci, const T *wv, const T *r, T *rc, int G, hipStream_t s,
+                       const double *om, DotBuf buf, int ncol)
 {
-    const int grid = rows_grid(S, G, om ? kMaxDotBlocks : (1 << 20));
+    const dim3 grid(rows_grid(S, G, om ? kMaxDotBlocks : (1 << 20)), ncol);
     if (om) {
-        AMG_SWITCH_G(G, (k_restrict<T, kG, true, true><<<grid, kBlock, 0, s>>>(S, ci, wv, r, rc, om, buf.part)));
+        AMG_SWITCH_G(G, (k_restrict<T, kG, true, true><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part)));
     } else if (S.n < kSmallLevel) {
-        AMG_SWITCH_G(G, (k_restrict<T, kG, true, false><<<grid, kBlock, 0, s>>>(S, ci, wv, r, rc, om, buf.part)));
+        AMG_SWITCH_G(G, (k_restrict<T, kG, true, false><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part)));
     } else {
-        AMG_SWITCH_G(G, (k_restrict<T, kG, false, false><<<grid, kBlock, 0, s>>>(S, ci, wv, r, rc, om, buf.part)));
+        AMG_SWITCH_G(G, (k_restrict<T, kG, false, false><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part)));
     }
     AMG_HIP(hipGetLastError());
     if (!om) return DotRef{nullptr, 0};
-    const int count = grid + S.nlong;
-    reduce_if_large(1, buf.part, count, buf.final_out, s);
+    const int count = (int)grid.x + S.nlong;
+    reduce_if_large(1, buf.part, count, buf.final_out, s, ncol);
     return finished(buf.part, count, buf.final_out, 0);
 }
 
 template <class T>
-void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, hipStream_t s)
+void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, hipStream_t s, int ncol)
 {
-    k_inner_residual<T><<<grid_for(n, 4096), kBlock, 0, s>>>(n, rc, v1, kd, rt, flag);
+    k_inner_residual<T><<<dim3(grid_for(n, 4096), ncol), kBlock, 0, s>>>(n, rc, v1, kd, rt, flag);
     AMG_HIP(hipGetLastError());
 }
 
 template <class T>
 DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, const T *r, const int *agg_pos,
                           const int *cagg, int mode, const T *edirect, const T *c1, const T *c2, KDots kd, T *xout,
-                          const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv, int nc)
+                          const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv, int nc,
+                          int ncol)
 {
     const bool dot = wdot != nullptr;
-    const int grid = rows_grid(R, G, dot ? kMaxDotBlocks : (1 << 20));
+    const dim3 grid(rows_grid(R, G, dot ? kMaxDotBlocks : (1 << 20)), ncol);
 #define AMG_POST(M, D)                                                                                         \
     do {                                                                                                       \
         if (cagg) {                                                                                            \
@@ -1002,16 +1080,16 @@ DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, con
 #undef AMG_POST
     AMG_HIP(hipGetLastError());
     if (!dot) return DotRef{nullptr, 0};
-    const int count = grid + R.nlong;
-    reduce_if_large(1, buf.part, count, buf.final_out, s);
+    const int count = (int)grid.x + R.nlong;
+    reduce_if_large(1, buf.part, count, buf.final_out, s, ncol);
     return finished(buf.part, count, buf.final_out, 0);
 }
 
 template <class T>
 DotRef launch_restrict_rt(Rows S, int nf, const int *ci, const T *wv, const T *rcf, const T *v1, KDots kd, T *rt,
-                          T *rc, int *flag, int G, hipStream_t s, const double *om, DotBuf buf)
+                          T *rc, int *flag, int G, hipStream_t s, const double *om, DotBuf buf, int ncol)
 {
-    const int grid = rows_grid(S, G, om ? kMaxDotBlocks : (1 << 20));
+    const dim3 grid(rows_grid(S, G, om ? kMaxDotBlocks : (1 << 20)), ncol);
     if (om) {
         AMG_SWITCH_G(G, (k_restrict_rt<T, kG, true><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, rcf, v1, kd, rt, rc, flag,
                                                                              om, buf.part)));
@@ -1021,17 +1099,17 @@ DotRef launch_restrict_rt(Rows S, int nf, const int *ci, const T *wv, const T *r
     }
     AMG_HIP(hipGetLastError());
     if (!om) return DotRef{nullptr, 0};
-    const int count = grid + S.nlong;
-    reduce_if_large(1, buf.part, count, buf.final_out, s);
+    const int count = (int)grid.x + S.nlong;
+    reduce_if_large(1, buf.part, count, buf.final_out, s, ncol);
     return finished(buf.part, count, buf.final_out, 0);
 }
 
 template <class T>
 void launch_post_direct(Rows R, const int *ci, const T *va, const T *minv, const T *r, const T *v1, KDots kd,
                         DotRef om_r, DotRef om_v1, const double *ainv, T *xout, T *rt_out, int *flag, int G,
-                        bool rt_mode, hipStream_t s)
+                        bool rt_mode, hipStream_t s, int ncol)
 {
-    const int grid = rows_grid(R, G, 1 << 20);
+    const dim3 grid(rows_grid(R, G, 1 << 20), ncol);
     if (rt_mode) {
         AMG_SWITCH_G(G, (k_post_direct<T, kG, true><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, v1, kd, om_r, om_v1,
                                                                              ainv, xout, rt_out, flag)));
@@ -1043,25 +1121,25 @@ void launch_post_direct(Rows R, const int *ci, const T *va, const T *minv, const
 }
 
 template <class T>
-void launch_dense_gemv(int n, const double *a, const T *x, T *y, hipStream_t s)
+void launch_dense_gemv(int n, const double *a, const T *x, T *y, hipStream_t s, int ncol)
 {
-    k_dense_gemv<T><<<grid_for((int64_t)n * kWave), kBlock, 0, s>>>(n, a, x, y);
+    k_dense_gemv<T><<<dim3(grid_for((int64_t)n * kWave), ncol), kBlock, 0, s>>>(n, a, x, y);
     AMG_HIP(hipGetLastError());
 }
 
-void launch_to_inner(int n, const double *r, const double *rr, float *r32, hipStream_t s)
+void launch_to_inner(int n, const double *r, const double *rr, float *r32, hipStream_t s, int ncol)
 {
-    k_to_inner<<<grid_for(n, 8192), kBlock, 0, s>>>(n, r, rr, r32);
+    k_to_inner<<<dim3(grid_for(n, 8192), ncol), kBlock, 0, s>>>(n, r, rr, r32);
     AMG_HIP(hipGetLastError());
 }
 
 DotRef launch_from_inner(int n, const float *z32, const double *rr, double *z, const double *q, DotBuf buf,
-                         hipStream_t s)
+                         hipStream_t s, int ncol)
 {
     const int grid = grid_for(n, kMaxDotBlocks);
-    k_from_inner<<<grid, kBlock, 0, s>>>(n, z32, rr, z, q, buf.part);
+    k_from_inner<<<dim3(grid, ncol), kBlock, 0, s>>>(n, z32, rr, z, q, buf.part);
     AMG_HIP(hipGetLastError());
-    reduce_if_large(1, buf.part, grid, buf.final_out, s);
+    reduce_if_large(1, buf.part, grid, buf.final_out, s, ncol);
     return finished(buf.part, grid, buf.final_out, 0);
 }
 
@@ -1073,56 +1151,61 @@ void launch_to_float(int64_t n, const double *src, float *dst, hipStream_t s)
 
 #define AMG_INSTANTIATE(T)                                                                                           \
     template DotSet launch_spmv_dots<T>(Rows, const int *, const T *, const T *, T *, const T *, const T *, int,     \
-                                        DotBuf, hipStream_t, const double *);                                       \
-    template DotRef launch_restrict<T>(Rows, const int *, const T *, const T *, T *, int, hipStream_t,               \
-                                       const double *, DotBuf);                                                     \
-    template void launch_inner_residual<T>(int, const T *, const T *, KDots, T *, int *, hipStream_t);              \
+                                        DotBuf, hipStream_t, const double *, int);                                  \
+    template DotRef launch_restrict<T>(Rows, int, const int *, const T *, const T *, T *, int, hipStream_t,          \
+                                       const double *, DotBuf, int);                                                \
+    template void launch_inner_residual<T>(int, const T *, const T *, KDots, T *, int *, hipStream_t, int);         \
     template DotRef launch_post_smooth<T>(Rows, const int *, const T *, const T *, const T *, const int *,          \
                                           const int *, int, const T *, const T *, const T *, KDots, T *, const T *, \
-                                          DotBuf, int *, int, hipStream_t, const double *, int);                    \
+                                          DotBuf, int *, int, hipStream_t, const double *, int, int);               \
     template DotRef launch_restrict_rt<T>(Rows, int, const int *, const T *, const T *, const T *, KDots, T *, T *, \
-                                          int *, int, hipStream_t, const double *, DotBuf);                         \
+                                          int *, int, hipStream_t, const double *, DotBuf, int);                    \
     template void launch_post_direct<T>(Rows, const int *, const T *, const T *, const T *, const T *, KDots,       \
-                                        DotRef, DotRef, const double *, T *, T *, int *, int, bool, hipStream_t);   \
-    template void launch_dense_gemv<T>(int, const double *, const T *, T *, hipStream_t);
+                                        DotRef, DotRef, const double *, T *, T *, int *, int, bool, hipStream_t,    \
+                                        int);                                                                       \
+    template void launch_dense_gemv<T>(int, const double *, const T *, T *, hipStream_t, int);
 AMG_INSTANTIATE(double)
 AMG_INSTANTIATE(float)
 #undef AMG_INSTANTIATE
 
 DotRef launch_fcg_update(int n, DotRef pq, DotRef pr, double *x, double *r, const double *p, const double *q,
-                         DotBuf buf, int *flag, hipStream_t s)
+                         DotBuf buf, int *flag, hipStream_t s, int ncol)
 {
     const int grid = grid_for(n, kMaxDotBlocks);
-    k_fcg_update<<<grid, kBlock, 0, s>>>(n, pq, pr, x, r, p, q, buf.part, flag);
+    k_fcg_update<<<dim3(grid, ncol), kBlock, 0, s>>>(n, pq, pr, x, r, p, q, buf.part, flag);
     AMG_HIP(hipGetLastError());
-    reduce_if_large(1, buf.part, grid, buf.final_out, s);
+    reduce_if_large(1, buf.part, grid, buf.final_out, s, ncol);
     return finished(buf.part, grid, buf.final_out, 0);
 }
 
-void launch_fcg_direction(int n, DotRef pq, DotRef zq, const double *z, double *p, int *flag, hipStream_t s)
+void launch_fcg_direction(int n, DotRef pq, DotRef zq, const double *z, double *p, int *flag, hipStream_t s, int ncol)
 {
-    k_fcg_direction<<<grid_for(n, 4096), kBlock, 0, s>>>(n, pq, zq, z, p, flag);
+    k_fcg_direction<<<dim3(grid_for(n, 4096), ncol), kBlock, 0, s>>>(n, pq, zq, z, p, flag);
     AMG_HIP(hipGetLastError());
 }
 
-DotRef launch_dot(int n, const double *a, const double *b, DotBuf buf, hipStream_t s)
+DotRef launch_dot(int n, const double *a, const double *b, DotBuf buf, hipStream_t s, int ncol)
 {
     const int grid = grid_for(n, kMaxDotBlocks);
-    k_dot<<<grid, kBlock, 0, s>>>(n, a, b, buf.part);
+    k_dot<<<dim3(grid, ncol), kBlock, 0, s>>>(n, a, b, buf.part);
     AMG_HIP(hipGetLastError());
-    reduce_if_large(1, buf.part, grid, buf.final_out, s);
+    reduce_if_large(1, buf.part, grid, buf.final_out, s, ncol);
     return finished(buf.part, grid, buf.final_out, 0);
 }
 
-void launch_gather(int n, const double *src, const int *idx, double *dst, hipStream_t s)
+void launch_gather(int n, const double *src, const int *idx, double *dst, hipStream_t s, int ncol, int ld_src,
+                   int ld_dst)
 {
-    k_gather<<<grid_for(n, 4096), kBlock, 0, s>>>(n, src, idx, dst);
+    k_gather<<<dim3(grid_for(n, 4096), ncol), kBlock, 0, s>>>(n, src, ld_src > 0 ? ld_src : n, idx, dst,
+                                                              ld_dst > 0 ? ld_dst : n);
     AMG_HIP(hipGetLastError());
 }
 
-void launch_scatter(int n, const double *src, const int *idx, double *dst, hipStream_t s)
+void launch_scatter(int n, const double *src, const int *idx, double *dst, hipStream_t s, int ncol, int ld_src,
+                    int ld_dst)
 {
-    k_scatter<<<grid_for(n, 4096), kBlock, 0, s>>>(n, src, idx, dst);
+    k_scatter<<<dim3(grid_for(n, 4096), ncol), kBlock, 0, s>>>(n, src, ld_src > 0 ? ld_src : n, idx, dst,
+                                                               ld_dst > 0 ? ld_dst : n);
     AMG_HIP(hipGetLastError());
 }
 

@@ -1,0 +1,111 @@
+"""Batched right-hand sides: one hierarchy, nrhs columns per launch (C ABI
+amg_solve_batch), against the FP64 oracle solving each column on its own."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1302_2547_amd import inputs  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def amg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1302_2547_amd import amg as mod
+    return mod
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+CASES = {
+    "grid3d_24_jitter": lambda: inputs.grid_laplacian((24, 24, 24), jitter=0.1, seed=2),
+    "grid2d_64_single_coarse": lambda: inputs.grid_laplacian((64, 64)),
+    "rgg_20k": lambda: inputs.rgg_laplacian(20000, seed=3, weight_range=(0.5, 1.5)),
+}
+OPTS = {"grid2d_64_single_coarse": {"coarsest_size": 1}}
+
+
+def rhs_block(n, k, zero_col=None):
+    B = np.stack([inputs.rhs(n, 100 + c) for c in range(k)])
+    if zero_col is not None:
+        B[zero_col] = 0.0
+    return B
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_columns_reach_tolerance(amg, case, precision):
+    rp, ci, va = CASES[case]()
+    n, k, tol = len(rp) - 1, 8, 1e-8
+    opt = OPTS.get(case, {})
+    print(f"[batch] {case} n={n} k={k} precision={precision}", flush=True)
+    h = amg.Hierarchy(dev(rp), dev(ci), dev(va), max_rhs=k, precision=precision, **opt)
+    ref = oracle.Hierarchy(rp, ci, va, **opt)
+    B = rhs_block(n, k, zero_col=5)
+    X = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+    st, infos = h.solve_batch(dev(B), X)
+    assert st == amg.AMG_OK
+    Xg = X.cpu().numpy()
+    for c in range(k):
+        if c == 5:
+            assert np.all(Xg[c] == 0.0) and infos[c].iterations == 0
+            continue
+        rel = np.linalg.norm(B[c] - oracle.spmv(rp, ci, va, Xg[c])) / np.linalg.norm(B[c])
+        xo, _, it_o, _, _ = ref.solve(B[c], tol=tol)
+        err = np.abs(Xg[c] - xo).max() / np.abs(xo).max()
+        print(f"[batch] col {c}: iters {infos[c].iterations} (oracle {it_o}) rel {rel:.2e} "
+              f"reported {infos[c].rel_residual:.2e} error vs oracle {err:.2e}")
+        assert rel <= tol and abs(rel - infos[c].rel_residual) <= 1e-12
+        assert infos[c].iterations <= it_o + 3
+        assert err <= 1e3 * tol
+    h.close()
+
+
+def test_batch_of_one_equals_single_solve(amg):
+    rp, ci, va = CASES["grid3d_24_jitter"]()
+    n = len(rp) - 1
+    h = amg.Hierarchy(dev(rp), dev(ci), dev(va), max_rhs=4)
+    b = inputs.rhs(n, 7)
+    x1 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st1, info1 = h.solve(dev(b), x1, tol=1e-9)
+    X = torch.zeros((1, n), dtype=torch.float64, device="cuda")
+    st2, infos = h.solve_batch(dev(b[None, :]), X, tol=1e-9)
+    assert st1 == st2 == amg.AMG_OK and info1.iterations == infos[0].iterations
+    np.testing.assert_array_equal(X[0].cpu().numpy(), x1.cpu().numpy())
+    h.close()
+
+
+def test_batch_graph_replay_matches_eager(amg):
+    rp, ci, va = CASES["grid3d_24_jitter"]()
+    n, k = len(rp) - 1, 4
+    B = dev(rhs_block(n, k))
+    out = []
+    for use_graph in (1, 0):
+        h = amg.Hierarchy(dev(rp), dev(ci), dev(va), max_rhs=k, use_graph=use_graph)
+        for _ in range(2):
+            X = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+            st, infos = h.solve_batch(B, X, tol=1e-9)
+            assert st == amg.AMG_OK
+            out.append((X.cpu().numpy(), [i.iterations for i in infos]))
+        h.close()
+    for X, its in out[1:]:
+        np.testing.assert_array_equal(X, out[0][0])
+        assert its == out[0][1]
+
+
+def test_batch_rejects_too_many_columns(amg):
+    rp, ci, va = inputs.grid_laplacian((16, 16))
+    n = len(rp) - 1
+    h = amg.Hierarchy(dev(rp), dev(ci), dev(va), max_rhs=2)
+    B = torch.ones((3, n), dtype=torch.float64, device="cuda")
+    X = torch.zeros_like(B)
+    with pytest.raises(amg.AmgError) as e:
+        h.solve_batch(B, X)
+    assert e.value.status == amg.AMG_ERR_INVALID_ARGUMENT
+    h.close()
