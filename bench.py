@@ -31,7 +31,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["grid", "rgg"], default="grid",
+                    help="grid: 3D 7-point Laplacian (the headline); rgg: 2D random geometric graph Laplacian")
     ap.add_argument("--grid", type=int, default=128, help="grid side (128 = the headline workload)")
+    ap.add_argument("--points", type=int, default=4_000_000, help="rgg: number of points")
+    ap.add_argument("--rhs", type=int, default=1, help="right-hand sides solved together (amg_solve_batch)")
+    ap.add_argument("--compare-sequential", action="store_true",
+                    help="with --rhs > 1: also time the same right-hand sides solved one at a time")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--jitter", type=float, default=0.1, help="edge weights 1 + jitter U[-1,1] (0: unit weights)")
     ap.add_argument("--precision", choices=["fp64", "fp32_inner"], default="fp64",
@@ -140,8 +146,12 @@ def main():
 
     dev = torch.device("cuda:0")
     N = args.grid
+    K = args.rhs
     t0 = time.perf_counter()
-    rp, ci, va = inputs.grid_laplacian((N, N, N), jitter=args.jitter, seed=2)
+    if args.workload == "grid":
+        rp, ci, va = inputs.grid_laplacian((N, N, N), jitter=args.jitter, seed=2)
+    else:
+        rp, ci, va = inputs.rgg_laplacian(args.points, seed=4, weight_range=(0.5, 1.5))
     n, nnz = len(rp) - 1, len(ci)
     prec = amg.AMG_PREC_FP32_INNER if args.precision == "fp32_inner" else amg.AMG_PREC_FP64
     b = inputs.rhs(n, 1)
@@ -149,16 +159,32 @@ def main():
     d_rp, d_ci, d_va = (torch.from_numpy(a).to(dev) for a in (rp, ci, va))
     d_b = torch.from_numpy(b).to(dev)
     x = torch.zeros(n, dtype=torch.float64, device=dev)
+    if K > 1:  # right-hand side k: U[-1,1] from seed 500 + k
+        d_B = torch.from_numpy(np.stack([inputs.rhs(n, 500 + k) for k in range(K)])).to(dev)
+        d_X = torch.zeros((K, n), dtype=torch.float64, device=dev)
     print(f"[bench] generated n={n} nnz={nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
+    class Info:  # one step's totals (a batch reports its slowest column)
+        pass
+
     def step():
-        x.zero_()
-        h = amg.Hierarchy(d_rp, d_ci, d_va, precision=prec)
-        st, info = h.solve(d_b, x, tol=args.tol)
+        h = amg.Hierarchy(d_rp, d_ci, d_va, precision=prec, max_rhs=K)
+        out = Info()
+        if K == 1:
+            x.zero_()
+            st, info = h.solve(d_b, x, tol=args.tol)
+            out.setup_ms, out.solve_ms = info.setup_ms, info.solve_ms
+            out.iterations, out.rel_residual = info.iterations, info.rel_residual
+        else:
+            d_X.zero_()
+            st, infos = h.solve_batch(d_B, d_X, tol=args.tol)
+            out.setup_ms, out.solve_ms = infos[0].setup_ms, infos[0].solve_ms
+            out.iterations = max(i.iterations for i in infos)
+            out.rel_residual = max(i.rel_residual for i in infos)
         levels = h.num_levels
         sizes = [h.level_sizes(l) for l in range(levels)]
         h.close()
-        return info, levels, sizes
+        return out, levels, sizes
 
     for w in range(args.warmup):
         info, levels, sizes = step()
@@ -183,6 +209,21 @@ def main():
     total_s = time.perf_counter() - t_all
     assert max(rels) <= args.tol, rels
 
+    sequential = None
+    if K > 1 and args.compare_sequential:  # the same right-hand sides one at a time, one hierarchy
+        h = amg.Hierarchy(d_rp, d_ci, d_va, precision=prec)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        seq_solve_ms = 0.0
+        for k in range(K):
+            xk = torch.zeros(n, dtype=torch.float64, device=dev)
+            st, info = h.solve(d_B[k], xk, tol=args.tol)
+            seq_solve_ms += info.solve_ms
+        torch.cuda.synchronize()
+        sequential = {"solve_ms_total": round(seq_solve_ms, 3),
+                      "wall_ms_total": round((time.perf_counter() - ts) * 1e3, 3)}
+        h.close()
+
     # dominant kernel, timed live on the library's stream
     h = amg.Hierarchy(d_rp, d_ci, d_va, precision=prec)
     h.solve(d_b, x, tol=args.tol)
@@ -193,7 +234,8 @@ def main():
     if os.path.exists(args.traffic_file):
         with open(args.traffic_file) as f:
             tr = json.load(f)
-        if tr.get("grid") == N and tr.get("source") == source_digest() and args.precision == "fp64":
+        if tr.get("grid") == N and tr.get("source") == source_digest() and args.precision == "fp64" and \
+                args.workload == "grid":
             traffic = tr.get("bytes_per_launch")
     kname = "k_post_smooth (finest level, FP32 storage)" if args.precision == "fp32_inner" else \
         "k_post_smooth (finest level)"
@@ -202,7 +244,7 @@ def main():
                 "traffic": traffic, "avg_us": round(avg_us, 2), "alg_bytes_per_launch": alg_bytes}
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "grid" and K == 1:
         import oracle
         tc = time.perf_counter()
         ref = oracle.Hierarchy(rp, ci, va)
@@ -215,17 +257,24 @@ def main():
                "host_cpus": os.cpu_count()}
 
     ms = statistics.median(walls)
+    if args.workload == "grid":
+        problem = (f"3D 7-point Laplacian {N}^3 (n={n}), "
+                   + (f"weights 1+{args.jitter:g}U[-1,1] seed 2" if args.jitter else "unit weights")
+                   + ", Dirichlet")
+    else:
+        problem = (f"2D random geometric graph Laplacian, {n} points U[0,1)^2 seed 4, mean degree 8, "
+                   f"weights U[0.5,1.5], shift 1e-6")
+    rhs_text = "rhs U[-1,1] seed 1" if K == 1 else f"{K} right-hand sides U[-1,1] seeds 500..{499 + K} in one batch"
+    workload = (problem + f", FP64 CSR, {rhs_text}, x0=0, tol {args.tol:g}; UA-AMG K-cycle (nu=2) + flexible CG, "
+                "l1-Jacobi 1+1, coarsest <= 64" + ("" if args.precision == "fp64" else "; K-cycle values and vectors "
+                                                   "in FP32"))
     out = {
         "metric": METRIC, "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32-storage K-cycle, f64 outer",
         "data": "synthetic",
-        "config": {"workload": f"3D 7-point Laplacian {N}^3 (n={n}), "
-                               + (f"weights 1+{args.jitter:g}U[-1,1] seed 2" if args.jitter else "unit weights")
-                               + f", Dirichlet, FP64 CSR, rhs U[-1,1] seed 1, x0=0, tol {args.tol:g}; UA-AMG K-cycle "
-                               f"(nu=2) + flexible CG, l1-Jacobi 1+1, coarsest <= 64"
-                               + ("" if args.precision == "fp64" else "; K-cycle values and vectors in FP32"),
-                   "precision": args.precision,
+        "config": {"workload": workload,
+                   "precision": args.precision, "rhs": K,
                    "n": n, "nnz": nnz, "levels": levels, "level_sizes": [s[0] for s in sizes],
                    "passes": [s[2] for s in sizes], "parallelism": "single GPU"},
         "setup_ms": round(statistics.median(setups), 3), "solve_ms": round(statistics.median(solves), 3),
@@ -233,6 +282,11 @@ def main():
         "timed_region_s": round(total_s, 3),
         "roofline": roofline, "cpu_baseline": cpu,
     }
+    if K > 1:
+        out["rhs_per_s"] = round(K / (ms * 1e-3), 2)
+        out["solve_ms_per_rhs"] = round(statistics.median(solves) / K, 3)
+        if sequential:
+            out["sequential_same_rhs"] = sequential
     print(json.dumps(out), flush=True)
 
 

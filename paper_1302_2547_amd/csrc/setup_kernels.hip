@@ -22,6 +22,8 @@
 // form A_c run in a fixed order.
 #include "amg_internal.h"
 
+#include <algorithm>
+
 namespace amg {
 namespace {
 
@@ -891,6 +893,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_from_csr(int n, const int *__r
 // inv = L^-T L^-1 column by column (forward then backward substitution).
 constexpr int kCholThreads = 1024;
 
+constexpr int kSmallDense = 256;  // coarsest levels up to this size: one block factors them
 __global__ void __launch_bounds__(kCholThreads) k_cholesky_inverse(int n, double *a, double *inv, int *err)
 {
     __shared__ double piv;
@@ -936,6 +939,44 @@ __global__ void __launch_bounds__(kCholThreads) k_cholesky_inverse(int n, double
             for (int k = i + 1; k < n; k++) s -= a[(size_t)k * n + i] * inv[(size_t)k * n + j];
             inv[(size_t)i * n + j] = s / a[(size_t)i * n + i];
         }
+    }
+}
+
+// Larger coarsest levels: Gauss-Jordan inversion in place, one launch per pivot
+// (no pivoting: every pivot is a Schur complement of an SPD matrix, hence > 0).
+// Step k reads row k and column k as step k-1 left them from rk / ck and writes
+// row and column k+1 of its result to rn / cn for the next step.
+__global__ void __launch_bounds__(kBlock) k_gauss_jordan_step(int n, int k, double *__restrict__ a,
+                                                              const double *__restrict__ rk,
+                                                              const double *__restrict__ ck, double *__restrict__ rn,
+                                                              double *__restrict__ cn, int *__restrict__ err)
+{
+    const double p = rk[k];
+    if (!(p > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *err = 1;
+        return;
+    }
+    const double ip = 1.0 / p;
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < nn; t += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(t / n), j = (int)(t % n);
+        double v;
+        if (i == k && j == k) v = ip;
+        else if (i == k) v = rk[j] * ip;
+        else if (j == k) v = -ck[i] * ip;
+        else v = a[t] - ck[i] * (rk[j] * ip);
+        a[t] = v;
+        if (i == k + 1) rn[j] = v;
+        if (j == k + 1) cn[i] = v;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_row_col(int n, const double *__restrict__ a, double *__restrict__ r0,
+                                                    double *__restrict__ c0)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        r0[i] = a[i];
+        c0[i] = a[(size_t)i * n];
     }
 }
 
@@ -1190,7 +1231,21 @@ void launch_dense_from_csr(int n, const int *rp, const int *ci, const double *va
 
 void launch_cholesky_inverse(int n, double *a, double *inv, int *err, hipStream_t s)
 {
-    k_cholesky_inverse<<<1, kCholThreads, 0, s>>>(n, a, inv, err);
+    if (n <= kSmallDense) {
+        k_cholesky_inverse<<<1, kCholThreads, 0, s>>>(n, a, inv, err);
+        AMG_HIP(hipGetLastError());
+        return;
+    }
+    // inv <- a, then Gauss-Jordan in place; the row / column buffers follow a.
+    const size_t nn = (size_t)n * n;
+    AMG_HIP(hipMemcpyAsync(inv, a, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    double *buf = a;  // a (n^2 >= 4n) is free now: two row/column pairs
+    double *r[2] = {buf, buf + 2 * (size_t)n}, *c[2] = {buf + n, buf + 3 * (size_t)n};
+    k_row_col<<<grid_for(n), kBlock, 0, s>>>(n, inv, r[0], c[0]);
+    const int grid = (int)std::min<int64_t>(((int64_t)nn + 4 * kBlock - 1) / (4 * kBlock), 1 << 16);
+    for (int k = 0; k < n; k++)
+        k_gauss_jordan_step<<<grid, kBlock, 0, s>>>(n, k, inv, r[k & 1], c[k & 1], r[(k + 1) & 1], c[(k + 1) & 1],
+                                                     err);
     AMG_HIP(hipGetLastError());
 }
 

@@ -746,20 +746,32 @@ __global__ void __launch_bounds__(kBlock) k_post_direct(Rows R, const int *__res
 }
 
 // y = A x for a dense row-major n x n matrix: one wavefront per row.
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_dense_gemv(int n, const double *__restrict__ a,
+// Y = A X for a dense row-major n x n A and CB right-hand sides per block (column
+// c0 + c of X at x + (c0 + c) n): one wavefront per row, lanes across the row, so
+// A is read once for CB columns.
+template <class T, int CB>
+__global__ void __launch_bounds__(kBlock) k_dense_gemm(int n, int ncol, const double *__restrict__ a,
                                                        const T *__restrict__ x, T *__restrict__ y)
 {
-    x = colv(x, n);
-    y = colv(y, n);
+    const int c0 = blockIdx.y * CB;
     const int lane = threadIdx.x & (kWave - 1);
     const int nw = gridDim.x * (kBlock / kWave);
     for (int i = (blockIdx.x * kBlock + threadIdx.x) / kWave; i < n; i += nw) {
-        double s = 0.0;
+        double s[CB];
+#pragma unroll
+        for (int c = 0; c < CB; c++) s[c] = 0.0;
         const double *row = a + (size_t)i * n;
-        for (int j = lane; j < n; j += kWave) s += row[j] * (double)x[j];
-        s = wave_sum(s);
-        if (lane == 0) y[i] = (T)s;
+        for (int j = lane; j < n; j += kWave) {
+            const double aij = row[j];
+#pragma unroll
+            for (int c = 0; c < CB; c++)
+                if (c0 + c < ncol) s[c] += aij * (double)x[(size_t)(c0 + c) * n + j];
+        }
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+            const double t = wave_sum(s[c]);
+            if (lane == 0 && c0 + c < ncol) y[(size_t)(c0 + c) * n + i] = (T)t;
+        }
     }
 }
 
@@ -1123,7 +1135,9 @@ void launch_post_direct(Rows R, const int *ci, const T *va, const T *minv, const
 template <class T>
 void launch_dense_gemv(int n, const double *a, const T *x, T *y, hipStream_t s, int ncol)
 {
-    k_dense_gemv<T><<<dim3(grid_for((int64_t)n * kWave), ncol), kBlock, 0, s>>>(n, a, x, y);
+    // one right-hand side per block row: measured faster than several per block
+    // (more waves in flight; the inverse is re-read from L2/MALL)
+    k_dense_gemm<T, 1><<<dim3(grid_for((int64_t)n * kWave), ncol), kBlock, 0, s>>>(n, ncol, a, x, y);
     AMG_HIP(hipGetLastError());
 }
 

@@ -259,3 +259,23 @@ def test_single_coarse_unknown(amg, case):
     r = xv - oracle.spmv(rp, ci, va, x.cpu().numpy())
     assert st == amg.AMG_OK and np.linalg.norm(r) / np.linalg.norm(xv) <= 1e-10
     assert abs(info.iterations - it_o) <= 1
+
+
+def test_large_coarsest_gauss_jordan(amg):
+    """coarsest_size=500 stops the 77x50 grid at 345 unknowns: a coarsest level
+    above 256 is inverted by the multi-launch Gauss-Jordan path."""
+    rp, ci, va = CASES["grid2d_77x50_jitter"]()
+    n = len(rp) - 1
+    h, ref = setup_both(amg, rp, ci, va, coarsest_size=500)
+    assert_same_hierarchy(h, ref)
+    nl = ref.level(ref.num_levels - 1).n
+    assert 256 < nl <= 500, nl
+    xv = inputs.rhs(n, 19)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.kcycle(dev(xv), z)
+    zo = ref.kcycle(xv)
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-10 * np.abs(zo).max())
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, info = h.solve(dev(xv), x, tol=1e-10)
+    r = xv - oracle.spmv(rp, ci, va, x.cpu().numpy())
+    assert st == amg.AMG_OK and np.linalg.norm(r) / np.linalg.norm(xv) <= 1e-10
