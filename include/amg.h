@@ -112,6 +112,22 @@ amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, a
 amg_status amg_solve_batch(amg_hierarchy *h, int32_t nrhs, const double *B, int32_t ldb, double *X, int32_t ldx,
                            double tol, amg_solve_info *info);
 
+/* ---- Synthetic workload (the benchmarks' inputs, built in device memory) ----
+ * The (2d+1)-point finite-difference Laplacian on the interior of a d-dimensional
+ * grid (d = 1, 2, 3; dims[a] >= 1 interior nodes along axis a; unknowns numbered x
+ * fastest), Dirichlet boundary, edge weights 1 + jitter (2u - 1) with u drawn by
+ * SplitMix64 from `seed` (the model problem of Sec. 2).  Bit-identical to the host
+ * generator of the Python package.  row_ptr (n + 1), col_idx and values
+ * (amg_grid_laplacian_nnz entries) are device arrays owned by the caller; the call
+ * is ordered on `stream` (hipStream_t or NULL) and returns when the arrays are
+ * written.  amg_grid_laplacian_nnz returns -1 for invalid dimensions. */
+int64_t amg_grid_laplacian_nnz(int32_t dim, const int32_t *dims);
+amg_status amg_grid_laplacian(int32_t dim, const int32_t *dims, double jitter, uint64_t seed, int32_t *row_ptr,
+                              int32_t *col_idx, double *values, void *stream);
+/* out[i] = 2 u_i - 1 with u_i the i-th SplitMix64 uniform of `seed` (device array of n,
+ * ordered on `stream`, asynchronous). */
+amg_status amg_uniform_rhs(int64_t n, uint64_t seed, double *out, void *stream);
+
 /* Releases every resource of h.  NULL is accepted.  Device blocks are kept in a
  * process-wide cache (per device and size class) for later hierarchies, because
  * returning memory to the driver synchronises the device; see
@@ -122,6 +138,10 @@ void amg_free(amg_hierarchy *h);
  * hierarchies are not affected.  An allocation that the driver refuses does this
  * by itself before it fails.  Call it with no solve in flight on any stream. */
 void amg_release_cached_memory(void);
+
+/* Device bytes the hierarchy holds (matrices, layouts, work vectors, inner-product
+ * sites) -- the figure a caller admitting work by memory footprint accounts. */
+amg_status amg_memory_bytes(const amg_hierarchy *h, size_t *bytes);
 
 /* Number of levels (finest = 0, coarsest = levels - 1). */
 amg_status amg_num_levels(const amg_hierarchy *h, int32_t *levels);

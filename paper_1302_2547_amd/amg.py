@@ -59,8 +59,12 @@ _sig = {
     "amg_solve_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
                                        ctypes.POINTER(amg_solve_info)]),
     "amg_free": (None, [_P]),
+    "amg_grid_laplacian_nnz": (ctypes.c_int64, [ctypes.c_int32, _I32P]),
+    "amg_grid_laplacian": (ctypes.c_int, [ctypes.c_int32, _I32P, ctypes.c_double, ctypes.c_uint64, _P, _P, _P, _P]),
+    "amg_uniform_rhs": (ctypes.c_int, [ctypes.c_int64, ctypes.c_uint64, _P, _P]),
     "amg_release_cached_memory": (None, []),
     "amg_num_levels": (ctypes.c_int, [_P, _I32P]),
+    "amg_memory_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "amg_level_sizes": (ctypes.c_int, [_P, ctypes.c_int32, _I32P, _I32P, _I32P]),
     "amg_export_level": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "amg_spmv": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
@@ -74,6 +78,37 @@ for _name, (_res, _args) in _sig.items():
     _f.restype = _res
     _f.argtypes = _args
     globals()[_name] = _f
+
+
+def device_grid_laplacian(dims, jitter: float = 0.0, seed: int = 0, stream: int | None = None):
+    """The grid Laplacian of ``inputs.grid_laplacian(dims, jitter, seed)`` built on
+    the current device (bit-identical); returns (row_ptr, col, val) tensors."""
+    import torch
+    d = len(dims)
+    arr = (ctypes.c_int32 * 3)(*[int(v) for v in dims], *([1] * (3 - d)))
+    nnz = amg_grid_laplacian_nnz(d, arr)
+    if nnz < 0:
+        raise ValueError(f"invalid grid {dims}")
+    n = 1
+    for v in dims:
+        n *= int(v)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    ci = torch.empty(nnz, dtype=torch.int32, device=dev)
+    va = torch.empty(nnz, dtype=torch.float64, device=dev)
+    st = amg_grid_laplacian(d, arr, float(jitter), seed & (2**64 - 1), rp.data_ptr(), ci.data_ptr(), va.data_ptr(),
+                            stream or 0)
+    if st != AMG_OK:
+        raise AmgError(st, "amg_grid_laplacian")
+    return rp, ci, va
+
+
+def device_rhs(out, seed: int, stream: int | None = None):
+    """out[i] = ``inputs.rhs(n, seed)[i]``, written on the device (asynchronous)."""
+    st = amg_uniform_rhs(out.numel(), seed & (2**64 - 1), _ptr(out), stream or 0)
+    if st != AMG_OK:
+        raise AmgError(st, "amg_uniform_rhs")
+    return out
 
 
 class AmgError(RuntimeError):
@@ -130,6 +165,12 @@ class Hierarchy:
         if st != AMG_OK:
             raise AmgError(st, "amg_setup")
         self.n = n
+
+    @property
+    def memory_bytes(self) -> int:
+        v = ctypes.c_size_t()
+        self._check(amg_memory_bytes(self._h, ctypes.byref(v)), "amg_memory_bytes")
+        return v.value
 
     @property
     def num_levels(self) -> int:

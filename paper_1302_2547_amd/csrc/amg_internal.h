@@ -209,4 +209,13 @@ void launch_entry_coarse_column(int nnz, const int *ci, const int *agg_pos, int 
 void launch_restriction_weights(int n, const int *rp, const int *ci, const double *va, const double *minv, double *wv,
                                 hipStream_t s);
 
+// ---------------------------------------------------------------- generate.hip
+// Synthetic grid Laplacians and right-hand sides on the device (bit-identical to
+// the host generator): rp must hold n + 1 ints, ci / va grid_nnz entries, scan_tmp
+// scan_tmp_ints(n) ints.
+int64_t grid_nnz(int d, const int *dims);
+void launch_grid_laplacian(int d, const int *dims, double jitter, uint64_t seed, int *rp, int *ci, double *va,
+                           int *scan_tmp, hipStream_t s);
+void launch_uniform_rhs(int64_t n, uint64_t seed, double *out, hipStream_t s);
+
 }  // namespace amg

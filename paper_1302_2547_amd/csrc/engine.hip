@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -961,6 +962,21 @@ amg_status amg_hierarchy::solve(int ncol, const double *b_user, int ldb, double 
 
 namespace {
 
+// The ABI takes device arrays.  Memory the GPU cannot address (pageable host
+// memory) is rejected here, with AMG_ERR_INVALID_ARGUMENT, instead of faulting
+// inside a kernel; device, managed and pinned host memory pass.
+bool device_array(const void *p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged ||
+           (a.type == hipMemoryTypeHost && a.devicePointer != nullptr);
+}
+
 template <class F>
 amg_status guarded(F &&f)
 {
@@ -1003,6 +1019,8 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy 
     if (!out) return AMG_ERR_INVALID_ARGUMENT;
     *out = nullptr;
     if (!A || !A->row_ptr || !A->col_idx || !A->values || A->n < 1 || A->nnz < A->n) return AMG_ERR_INVALID_ARGUMENT;
+    if (!device_array(A->row_ptr) || !device_array(A->col_idx) || !device_array(A->values))
+        return AMG_ERR_INVALID_ARGUMENT;
     amg_options opt;
     if (opt_in) opt = *opt_in;
     else amg_default_options(&opt);
@@ -1039,6 +1057,7 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy 
 amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, amg_solve_info *info)
 {
     if (!h || !b || !x || !(tol > 0.0) || !std::isfinite(tol)) return AMG_ERR_INVALID_ARGUMENT;
+    if (!device_array(b) || !device_array(x)) return AMG_ERR_INVALID_ARGUMENT;
     return guarded([&]() { return h->solve(1, b, h->lev[0].n, x, h->lev[0].n, tol, info); });
 }
 
@@ -1048,10 +1067,60 @@ amg_status amg_solve_batch(amg_hierarchy *h, int32_t nrhs, const double *B, int3
     if (!h || !B || !X || !(tol > 0.0) || !std::isfinite(tol)) return AMG_ERR_INVALID_ARGUMENT;
     const int n = h->lev[0].n;
     if (nrhs < 1 || nrhs > h->opt.max_rhs || ldb < n || ldx < n) return AMG_ERR_INVALID_ARGUMENT;
+    if (!device_array(B) || !device_array(X)) return AMG_ERR_INVALID_ARGUMENT;
     return guarded([&]() { return h->solve(nrhs, B, ldb, X, ldx, tol, info); });
 }
 
 void amg_free(amg_hierarchy *h) { delete h; }
+
+int64_t amg_grid_laplacian_nnz(int32_t dim, const int32_t *dims)
+{
+    if (!dims || dim < 1 || dim > 3) return -1;
+    int64_t n = 1;
+    for (int a = 0; a < dim; a++) {
+        if (dims[a] < 1) return -1;
+        n *= dims[a];
+    }
+    if (n > INT32_MAX - 1) return -1;
+    const int64_t nnz = amg::grid_nnz(dim, dims);
+    return nnz > INT32_MAX ? -1 : nnz;
+}
+
+amg_status amg_grid_laplacian(int32_t dim, const int32_t *dims, double jitter, uint64_t seed, int32_t *row_ptr,
+                              int32_t *col_idx, double *values, void *stream)
+{
+    if (amg_grid_laplacian_nnz(dim, dims) < 0 || !std::isfinite(jitter) || !(jitter >= 0.0 && jitter < 1.0) ||
+        !device_array(row_ptr) || !device_array(col_idx) || !device_array(values))
+        return AMG_ERR_INVALID_ARGUMENT;
+    return guarded([&]() {
+        int64_t n = 1;
+        for (int a = 0; a < dim; a++) n *= dims[a];
+        const hipStream_t s = (hipStream_t)stream;
+        const size_t cls = amg::BlockCache::size_class(sizeof(int) * amg::scan_tmp_ints(n));
+        void *tmp = amg::BlockCache::get().take(cls);
+        if (!tmp) return AMG_ERR_OUT_OF_MEMORY;
+        int dev = 0;
+        AMG_HIP(hipGetDevice(&dev));
+        try {
+            amg::launch_grid_laplacian(dim, dims, jitter, seed, row_ptr, col_idx, values, static_cast<int *>(tmp), s);
+            AMG_HIP(hipStreamSynchronize(s));
+        } catch (...) {
+            amg::BlockCache::get().give(tmp, cls, dev);
+            throw;
+        }
+        amg::BlockCache::get().give(tmp, cls, dev);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_uniform_rhs(int64_t n, uint64_t seed, double *out, void *stream)
+{
+    if (n < 1 || !device_array(out)) return AMG_ERR_INVALID_ARGUMENT;
+    return guarded([&]() {
+        amg::launch_uniform_rhs(n, seed, out, (hipStream_t)stream);
+        return AMG_OK;
+    });
+}
 
 void amg_release_cached_memory(void)
 {
@@ -1059,6 +1128,13 @@ void amg_release_cached_memory(void)
         amg::BlockCache::get().release_all();
     } catch (...) {
     }
+}
+
+amg_status amg_memory_bytes(const amg_hierarchy *h, size_t *bytes)
+{
+    if (!h || !bytes) return AMG_ERR_INVALID_ARGUMENT;
+    *bytes = h->pool.used;
+    return AMG_OK;
 }
 
 amg_status amg_num_levels(const amg_hierarchy *h, int32_t *levels)
@@ -1099,6 +1175,7 @@ amg_status amg_export_level(const amg_hierarchy *h_c, int32_t level, int32_t *ag
 amg_status amg_spmv(amg_hierarchy *h, int32_t level, const double *x, double *y)
 {
     if (!h || !x || !y || level < 0 || level >= h->levels()) return AMG_ERR_INVALID_ARGUMENT;
+    if (!device_array(x) || !device_array(y)) return AMG_ERR_INVALID_ARGUMENT;
     return guarded([&]() {
         const Level &L = h->lev[level];
         // natural numbering, no hub-row table: one wavefront per row
@@ -1115,6 +1192,7 @@ amg_status amg_spmv(amg_hierarchy *h, int32_t level, const double *x, double *y)
 amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z)
 {
     if (!h || !r || !z) return AMG_ERR_INVALID_ARGUMENT;
+    if (!device_array(r) || !device_array(z)) return AMG_ERR_INVALID_ARGUMENT;
     return guarded([&]() {
         const Level &F = h->lev[0];
         h->capture_graphs(1);

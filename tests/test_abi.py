@@ -54,6 +54,23 @@ def test_host_only_paths(lib):
     assert amg.amg_num_levels(None, ctypes.byref(n)) == amg.AMG_ERR_INVALID_ARGUMENT
 
 
+def test_host_arrays_are_rejected(lib):
+    """Entry points that take device arrays refuse pageable host memory (an error
+    status, never a kernel writing through a host address)."""
+    import numpy as np
+    from paper_1302_2547_amd import amg
+    host = np.zeros(64, np.float64)
+    hi = np.zeros(65, np.int32)
+    assert amg.amg_uniform_rhs(64, 1, host.ctypes.data, None) == amg.AMG_ERR_INVALID_ARGUMENT
+    dims = (ctypes.c_int32 * 3)(4, 4, 1)
+    assert amg.amg_grid_laplacian(2, dims, 0.1, 1, hi.ctypes.data, hi.ctypes.data, host.ctypes.data,
+                                  None) == amg.AMG_ERR_INVALID_ARGUMENT
+    csr = amg.amg_csr(8, 8, hi.ctypes.data, hi.ctypes.data, host.ctypes.data)
+    out = ctypes.c_void_p()
+    assert amg.amg_setup(ctypes.byref(csr), None, ctypes.byref(out)) == amg.AMG_ERR_INVALID_ARGUMENT
+    assert amg.amg_grid_laplacian_nnz(2, dims) == 16 + 2 * 2 * 4 * 3
+
+
 def test_options_struct_matches_header():
     from paper_1302_2547_amd import amg
     text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)

@@ -1,0 +1,100 @@
+"""Serving: device-built inputs equal the host generator, and every served
+result is the same alone and in the mix (bit for bit), within the tolerance, and
+close to the FP64 oracle's solution."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1302_2547_amd import inputs  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def amg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1302_2547_amd import amg as mod
+    return mod
+
+
+@pytest.mark.parametrize("dims,jitter,seed", [((7,), 0.0, 0), ((9, 5), 0.1, 3), ((6, 5, 4), 0.1, 11),
+                                              ((30, 30, 30), 0.1, 2), ((64, 64), 0.3, 5)])
+def test_device_generator_is_the_host_one(amg, dims, jitter, seed):
+    rp, ci, va = amg.device_grid_laplacian(dims, jitter, seed)
+    hrp, hci, hva = inputs.grid_laplacian(dims, jitter=jitter, seed=seed)
+    np.testing.assert_array_equal(rp.cpu().numpy(), hrp)
+    np.testing.assert_array_equal(ci.cpu().numpy(), hci)
+    np.testing.assert_array_equal(va.cpu().numpy(), hva)
+    out = torch.empty(rp.numel() - 1, dtype=torch.float64, device="cuda")
+    amg.device_rhs(out, 1234)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), inputs.rhs(rp.numel() - 1, 1234))
+
+
+def test_host_memory_is_refused_not_written(amg):
+    with pytest.raises(ValueError):
+        amg.device_rhs(torch.empty(100, dtype=torch.float64), 1)  # a CPU tensor
+    host = np.zeros(100)
+    assert amg.amg_uniform_rhs(100, 1, host.ctypes.data, None) == amg.AMG_ERR_INVALID_ARGUMENT
+    rp, ci, va = amg.device_grid_laplacian((10, 10))
+    h = amg.Hierarchy(rp, ci, va, max_rhs=2)
+    X = torch.zeros((1, 100), dtype=torch.float64, device="cuda")
+    assert amg.amg_solve_batch(h._h, 1, host.ctypes.data, 100, X.data_ptr(), 100, 1e-8,
+                               None) == amg.AMG_ERR_INVALID_ARGUMENT
+    assert amg.amg_solve(h._h, host.ctypes.data, X.data_ptr(), 1e-8, None) == amg.AMG_ERR_INVALID_ARGUMENT
+    h.close()
+
+
+def small_stream(count=20):
+    from paper_1302_2547_amd import serve
+    return serve.make_requests(count=count, rate=1000.0, seed=7, n_range_2d=(500, 20000), n_range_3d=(500, 30000))
+
+
+def test_served_results_same_alone_and_in_mix(amg):
+    from paper_1302_2547_amd import serve
+    reqs = small_stream()
+    alone = serve.Server(slots=1, keep_solutions=True)
+    r1, s1 = alone.run(reqs, realtime=False)
+    alone.close()
+    mix = serve.Server(slots=4, keep_solutions=True)
+    r2, s2 = mix.run(reqs, realtime=False)
+    mix.close()
+    print(f"[serve] alone {s1}\n[serve] mix {s2}")
+    assert s1["failed"] == 0 and s2["failed"] == 0 and s2["reused"] > 0
+    for rid in r1:
+        a, b = r1[rid], r2[rid]
+        assert a.status == b.status == amg.AMG_OK
+        assert max(a.rel_residuals) <= 1e-8 and max(b.rel_residuals) <= 1e-8
+        assert a.iterations == b.iterations
+        np.testing.assert_array_equal(a.solution, b.solution)
+
+
+def test_served_solutions_match_oracle(amg):
+    from paper_1302_2547_amd import serve
+    reqs = small_stream(6)
+    srv = serve.Server(slots=3, keep_solutions=True, precision=amg.AMG_PREC_FP64)
+    res, _ = srv.run(reqs, realtime=False)
+    srv.close()
+    for q in reqs:
+        rp, ci, va = inputs.grid_laplacian(q.dims, jitter=0.1, seed=q.jitter_seed)
+        ref = oracle.Hierarchy(rp, ci, va)
+        for j, s in enumerate(q.rhs_seeds):
+            b = inputs.rhs(q.n, s)
+            xo, _, _, _, _ = ref.solve(b, tol=1e-8)
+            x = res[q.rid].solution[j]
+            rel = np.linalg.norm(b - oracle.spmv(rp, ci, va, x)) / np.linalg.norm(b)
+            assert rel <= 1e-8
+            assert np.abs(x - xo).max() <= 1e-5 * np.abs(xo).max()
+        ref.close()
+
+
+def test_tiny_budget_still_serves_everything(amg):
+    from paper_1302_2547_amd import serve
+    reqs = small_stream(8)
+    srv = serve.Server(slots=4, budget=1 << 20)  # 1 MiB: one request at a time, nothing stays resident
+    res, stats = srv.run(reqs, realtime=False)
+    srv.close()
+    assert stats["failed"] == 0 and len(res) == len(reqs)
