@@ -149,11 +149,13 @@ def serve_bench(args):
     srv = serve.Server(slots=args.slots, precision=prec, tol=args.tol)
     print(f"[bench] serving {len(reqs)} requests over {reqs[-1].t_arrival:.1f} s of arrivals, "
           f"{args.slots} slots, budget {srv.budget / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+    by_rid = {q.rid: q for q in reqs}
+
     def progress(done, total, r):
-        if done % 50 == 0 or done == total:
-            print(f"[bench] served {done}/{total}: last latency {r.latency_ms:.0f} ms "
-                  f"(queue {r.queue_ms:.0f}, setup {r.setup_ms:.1f}, solve {r.solve_ms:.1f})",
-                  file=sys.stderr, flush=True)
+        q = by_rid[r.rid]
+        print(f"[bench] served {done}/{total}: request {r.rid} {q.dims} x{len(q.rhs_seeds)} latency "
+              f"{r.latency_ms:.0f} ms (queue {r.queue_ms:.0f}, setup {r.setup_ms:.1f}, solve {r.solve_ms:.1f}, "
+              f"iterations {max(r.iterations)}, status {r.status})", file=sys.stderr, flush=True)
 
     res, st = srv.run(reqs, realtime=True, progress=progress)
     srv.close()

@@ -30,8 +30,8 @@ void hip_check(hipError_t e, const char *what);
 // Rows of a CSR-like operator: row r has entries ptr[r] .. ptr[r+1].  Rows with
 // more than lim entries ("hub" rows) are cut into chunks of at most kChunk
 // entries, each served by one block; long_first[k] .. long_first[k+1] are the
-// chunks of hub row k.  chunk_sum / arrive are device workspaces (arrive is zero
-// between launches).
+// chunks of hub row k.  chunk_sum / arrive are device workspaces, one set of
+// nchunks / nlong per right-hand side of a batch (arrive is zero between launches).
 constexpr int kChunk = 1024;
 constexpr int kLongBlocks = 1024;  // blocks that serve chunks
 constexpr int kMaxLong = 2048;     // hub rows per operator (the threshold is raised beyond)

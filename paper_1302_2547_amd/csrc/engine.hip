@@ -365,12 +365,12 @@ struct amg_hierarchy {
         R.nchunks = (int)chunks.size();
         amg::Chunk *dchunks = pool.alloc<amg::Chunk>(chunks.size());
         int *dfirst = pool.alloc<int>(first.size());
-        R.chunk_sum = pool.alloc<double>(chunks.size());
-        R.arrive = pool.alloc<unsigned>(R.nlong);
+        R.chunk_sum = pool.alloc<double>(chunks.size() * (size_t)opt.max_rhs);  // per right-hand side
+        R.arrive = pool.alloc<unsigned>((size_t)R.nlong * opt.max_rhs);
         AMG_HIP(hipMemcpyAsync(dchunks, chunks.data(), sizeof(amg::Chunk) * chunks.size(), hipMemcpyHostToDevice,
                                stream));
         AMG_HIP(hipMemcpyAsync(dfirst, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, stream));
-        AMG_HIP(hipMemsetAsync(R.arrive, 0, sizeof(unsigned) * R.nlong, stream));
+        AMG_HIP(hipMemsetAsync(R.arrive, 0, sizeof(unsigned) * R.nlong * opt.max_rhs, stream));
         sync();
         R.chunks = dchunks;
         R.long_first = dfirst;

@@ -200,20 +200,23 @@ __device__ inline void finish_chunk(const Rows &R, int c, const Chunk &ch, doubl
     // write-back: the store's completion is awaited (vector memory counter) before
     // the count is raised, and the last arrival reads the sums only after its
     // count returned.  Nothing else is read afterwards, so no acquire either.
+    // every right-hand side of a batched launch (blockIdx.y) has its own sums and counters
+    double *chunk_sum = R.chunk_sum + (size_t)blockIdx.y * R.nchunks;
+    unsigned *arrive = R.arrive + (size_t)blockIdx.y * R.nlong;
     unsigned prev = 0;
     if (lane == 0) {
-        __hip_atomic_store(&R.chunk_sum[c], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&chunk_sum[c], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        prev = __hip_atomic_fetch_add(&R.arrive[ch.k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        prev = __hip_atomic_fetch_add(&arrive[ch.k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     prev = __shfl(prev, 0, kWave);
     if (prev != (unsigned)(m - 1)) return;  // not the last chunk of this row
     double t = 0.0;
     for (int j = lane; j < m; j += kWave)
-        t += __hip_atomic_load(&R.chunk_sum[first + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t += __hip_atomic_load(&chunk_sum[first + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     t = wave_sum(t);
     if (lane == 0) {
-        __hip_atomic_store(&R.arrive[ch.k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&arrive[ch.k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         done(ch.row, t, ch.k);
     }
 }

@@ -6,7 +6,8 @@ on the device from its seed) and 1..8 right-hand sides.  The server:
 * replays arrivals at their timestamps (a Poisson stream);
 * admits a request when a slot is free and its HBM footprint fits the budget:
   requests that arrive while others run are admitted as slots and memory free up,
-  and their kernels run concurrently on the slots' HIP streams;
+  and their kernels run concurrently (each slot builds inputs on its own HIP
+  stream; each hierarchy solves on a stream of its own);
 * keeps hierarchies resident (least recently used evicted first when memory is
   needed), so a request for a resident problem skips the setup;
 * solves each request's right-hand sides together (``amg_solve_batch``);
@@ -154,15 +155,20 @@ class Server:
                 self.lock.wait()
 
     def _release(self, req: Request, h, reserved: int, new: bool):
+        """Return a request's reservation; keep its hierarchy resident (h may be None
+        when the setup failed)."""
         with self.lock:
             self.inflight_bytes -= reserved
-            nb = h.memory_bytes
-            if new:
-                self.resident[req.key] = [h, nb, False]
-                self.resident_bytes += nb
-            else:
-                self.resident[req.key][2] = False
-            self.resident.move_to_end(req.key)
+            if h is not None:
+                if new and req.key in self.resident:  # built twice concurrently: keep the first
+                    h.close()
+                elif new:
+                    nb = h.memory_bytes
+                    self.resident[req.key] = [h, nb, False]
+                    self.resident_bytes += nb
+                else:
+                    self.resident[req.key][2] = False
+                self.resident.move_to_end(req.key)
             self._evict(0)
             self.lock.notify_all()
 
@@ -173,22 +179,29 @@ class Server:
         t_admit = time.perf_counter()
         new = h is None
         sp = stream.cuda_stream
-        with torch.cuda.stream(stream):
-            if new:
-                rp, ci, va = amg.device_grid_laplacian(req.dims, 0.1, req.jitter_seed, stream=sp)
-                h = amg.Hierarchy(rp, ci, va, precision=self.precision, max_rhs=self.max_rhs, stream=sp)
-                del rp, ci, va
-            k = len(req.rhs_seeds)
-            B = torch.empty((k, req.n), dtype=torch.float64, device="cuda")
-            for j, s in enumerate(req.rhs_seeds):
-                amg.device_rhs(B[j], s, stream=sp)
-            X = torch.zeros_like(B)
-            stream.synchronize()  # a resident hierarchy may run on another slot's stream
-            st, infos = h.solve_batch(B, X, tol=self.tol, raise_on_error=False)
-            sol = X.cpu().numpy() if self.keep else None
-            del B, X
+        st, infos, sol = -1, [], None
+        try:
+            with torch.cuda.stream(stream):
+                if new:
+                    rp, ci, va = amg.device_grid_laplacian(req.dims, 0.1, req.jitter_seed, stream=sp)
+                    # the hierarchy gets a stream of its own (the library's): a resident
+                    # hierarchy is later used from other slots, and work of another slot
+                    # on this slot's stream would mix with, or break, a graph this slot
+                    # is capturing
+                    h = amg.Hierarchy(rp, ci, va, precision=self.precision, max_rhs=self.max_rhs)
+                    del rp, ci, va
+                k = len(req.rhs_seeds)
+                B = torch.empty((k, req.n), dtype=torch.float64, device="cuda")
+                for j, s in enumerate(req.rhs_seeds):
+                    amg.device_rhs(B[j], s, stream=sp)
+                X = torch.zeros_like(B)
+                stream.synchronize()  # the hierarchy's stream does not wait for this one
+                st, infos = h.solve_batch(B, X, tol=self.tol, raise_on_error=False)
+                sol = X.cpu().numpy() if self.keep else None
+                del B, X
+        finally:
+            self._release(req, h, reserved, new)
         t_done = time.perf_counter()
-        self._release(req, h, reserved, new)
         return Result(req.rid, st, 1e3 * (t_done - (t0 + req.t_arrival)), 1e3 * (t_admit - t_start),
                       infos[0].setup_ms if new else 0.0, infos[0].solve_ms, not new,
                       [i.iterations for i in infos], [i.rel_residual for i in infos], sol)
@@ -219,8 +232,9 @@ class Server:
                         done = len(results)
                     if progress:
                         progress(done, len(requests), res)
-                except Exception as e:  # noqa: BLE001 - reported by run()
+                except Exception as e:  # noqa: BLE001 - reported at once and by run()
                     errors.append((req.rid, repr(e)))
+                    print(f"[serve] request {req.rid} {req.dims} x{len(req.rhs_seeds)} failed: {e!r}", flush=True)
 
         threads = [threading.Thread(target=worker, daemon=True) for _ in range(self.slots)]
         for t in threads:

@@ -109,3 +109,27 @@ def test_batch_rejects_too_many_columns(amg):
         h.solve_batch(B, X)
     assert e.value.status == amg.AMG_ERR_INVALID_ARGUMENT
     h.close()
+
+
+def test_batch_with_multi_chunk_hub_rows(amg):
+    """A row of 6000 entries is cut into several chunks whose sums meet in a
+    device workspace: every right-hand side of a batch needs its own (fewer
+    columns than max_rhs, as a server sends)."""
+    from test_gpu_parity import hub_graph
+    rp, ci, va = hub_graph()
+    n, k, tol = len(rp) - 1, 3, 1e-9
+    for precision in (0, 1):
+        h = amg.Hierarchy(dev(rp), dev(ci), dev(va), max_rhs=8, coarsest_size=16, precision=precision)
+        ref = oracle.Hierarchy(rp, ci, va, coarsest_size=16)
+        B = rhs_block(n, k)
+        X = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+        st, infos = h.solve_batch(dev(B), X, tol=tol)
+        assert st == amg.AMG_OK
+        Xg = X.cpu().numpy()
+        for c in range(k):
+            rel = np.linalg.norm(B[c] - oracle.spmv(rp, ci, va, Xg[c])) / np.linalg.norm(B[c])
+            xo, _, it_o, _, _ = ref.solve(B[c], tol=tol)
+            print(f"[batch] hub precision={precision} col {c}: iters {infos[c].iterations} (oracle {it_o}) rel {rel:.2e}")
+            assert rel <= tol and infos[c].iterations <= it_o + 3
+        h.close()
+        ref.close()
