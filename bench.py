@@ -174,6 +174,7 @@ def serve_bench(args):
                                f"device; tol {args.tol:g}; admission by HBM footprint, {args.slots} slots",
                    "precision": args.precision, "slots": args.slots, "parallelism": "single GPU"},
         "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2), "max_ms": round(st["max_ms"], 2),
+        "service_p50_ms": round(st["service_p50_ms"], 2), "service_p99_ms": round(st["service_p99_ms"], 2),
         "requests_per_s": round(st["requests_per_s"], 2), "wall_s": round(st["wall_s"], 2),
         "solves": st["solves"], "reused": st["reused"], "failed": st["failed"],
         "median_setup_ms": med(setup), "median_solve_ms": med(solve), "median_queue_ms": med(queue),

@@ -76,10 +76,12 @@ uint64_t splitmix64(uint64_t seed, uint64_t k)
 }
 
 // Process-wide cache of device blocks.  hipFree synchronises the device and is
-// slow, so blocks a hierarchy releases are kept, per device and size class, for
-// the next allocation of the same class.  An allocation that the driver refuses
-// returns the cached blocks first and tries again; amg_release_cached_memory()
-// returns them on request.
+// slow, so blocks a hierarchy releases are kept, per device, for later
+// allocations: a request takes the smallest cached block of at least its size
+// class and at most 1.5 times it.  The cache holds at most an eighth of the
+// device's memory (blocks beyond that go back to the driver); an allocation that
+// the driver refuses returns the cached blocks first and tries again;
+// amg_release_cached_memory() returns them on request.
 class BlockCache {
 public:
     static BlockCache &get()
@@ -94,17 +96,19 @@ public:
         const size_t q = bytes <= (1u << 20) ? 256 : (bytes <= (64u << 20) ? (64u << 10) : (2u << 20));
         return (bytes + q - 1) / q * q;
     }
-    void *take(size_t cls)
+    // A block of at least cls bytes; *got receives its size (return it with give).
+    void *take(size_t cls, size_t *got)
     {
         int dev = 0;
         AMG_HIP(hipGetDevice(&dev));
         {
             std::lock_guard<std::mutex> lk(mu_);
-            auto it = free_.find(Key{dev, cls});
-            if (it != free_.end()) {
+            auto it = free_.lower_bound(Key{dev, cls});
+            if (it != free_.end() && it->first.dev == dev && it->first.cls <= cls + cls / 2) {
                 void *p = it->second;
+                *got = it->first.cls;
+                cached_ -= it->first.cls;
                 free_.erase(it);
-                cached_ -= cls;
                 return p;
             }
         }
@@ -119,13 +123,24 @@ public:
                 return nullptr;
             }
         }
+        *got = cls;
         return p;
     }
     void give(void *p, size_t cls, int dev)
     {
-        std::lock_guard<std::mutex> lk(mu_);
-        free_.emplace(Key{dev, cls}, p);
-        cached_ += cls;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (cached_ + cls <= cap(dev)) {
+                free_.emplace(Key{dev, cls}, p);
+                cached_ += cls;
+                return;
+            }
+        }
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(dev);
+        (void)hipFree(p);
+        (void)hipSetDevice(cur);
     }
     void release_all()
     {
@@ -150,13 +165,30 @@ private:
         size_t cls;
         bool operator<(const Key &o) const { return dev != o.dev ? dev < o.dev : cls < o.cls; }
     };
+    // an eighth of the device's memory (caller holds mu_)
+    size_t cap(int dev)
+    {
+        if (cap_ == 0) {
+            size_t free_b = 0, total = 0;
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(dev);
+            if (hipMemGetInfo(&free_b, &total) != hipSuccess) {
+                (void)hipGetLastError();
+                total = size_t(16) << 30;
+            }
+            (void)hipSetDevice(cur);
+            cap_ = total / 8;
+        }
+        return cap_;
+    }
     std::mutex mu_;
     std::multimap<Key, void *> free_;
-    size_t cached_ = 0;
+    size_t cached_ = 0, cap_ = 0;
 };
 
 // Device allocations of one hierarchy, with an optional byte budget (counted in
-// requested bytes).  Blocks go back to the process-wide cache, not the driver.
+// requested bytes).  Blocks go back to the process-wide cache.
 struct Pool {
     struct Block {
         void *p;
@@ -171,12 +203,12 @@ struct Pool {
     {
         const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
         if (budget && used + bytes > budget) throw Error(AMG_ERR_OUT_OF_MEMORY, "mem_budget exceeded");
-        const size_t cls = BlockCache::size_class(bytes);
-        void *p = BlockCache::get().take(cls);
+        size_t got = 0;
+        void *p = BlockCache::get().take(BlockCache::size_class(bytes), &got);
         if (!p) throw Error(AMG_ERR_OUT_OF_MEMORY, "hipMalloc");
         int dev = 0;
         AMG_HIP(hipGetDevice(&dev));
-        blocks.push_back(Block{p, bytes, cls, dev});
+        blocks.push_back(Block{p, bytes, got, dev});
         used += bytes;
         peak = std::max(peak, used);
         return static_cast<T *>(p);
@@ -1096,8 +1128,9 @@ amg_status amg_grid_laplacian(int32_t dim, const int32_t *dims, double jitter, u
         int64_t n = 1;
         for (int a = 0; a < dim; a++) n *= dims[a];
         const hipStream_t s = (hipStream_t)stream;
-        const size_t cls = amg::BlockCache::size_class(sizeof(int) * amg::scan_tmp_ints(n));
-        void *tmp = amg::BlockCache::get().take(cls);
+        size_t cls = 0;
+        void *tmp = amg::BlockCache::get().take(amg::BlockCache::size_class(sizeof(int) * amg::scan_tmp_ints(n)),
+                                                &cls);
         if (!tmp) return AMG_ERR_OUT_OF_MEMORY;
         int dev = 0;
         AMG_HIP(hipGetDevice(&dev));

@@ -49,8 +49,9 @@ class Request:
 class Result:
     rid: int
     status: int
-    latency_ms: float
-    queue_ms: float
+    latency_ms: float  # arrival to completion
+    service_ms: float  # taken by a slot to completion
+    queue_ms: float    # waiting for memory / a busy hierarchy after being taken
     setup_ms: float
     solve_ms: float
     reused: bool
@@ -133,6 +134,25 @@ class Server:
             self.resident_bytes -= nb
             h.close()
 
+    def _ensure_free(self, need: int):
+        """The budget is an account; the device also holds cached blocks (the
+        library's and torch's).  When the memory actually free is short of `need`
+        plus a margin, drop idle resident hierarchies and both caches (the cache
+        releases synchronise the device: done only under pressure).  Caller holds
+        self.lock."""
+        torch = self.torch
+        margin = 1 << 30
+        if torch.cuda.mem_get_info()[0] >= need + margin:
+            return
+        for key in list(self.resident):
+            h, nb, in_use = self.resident[key]
+            if not in_use:
+                del self.resident[key]
+                self.resident_bytes -= nb
+                h.close()
+        amg.amg_release_cached_memory()
+        torch.cuda.empty_cache()
+
     def _admit(self, req: Request):
         """Block until req fits; returns (hierarchy or None, reserved bytes)."""
         with self.lock:
@@ -144,6 +164,7 @@ class Server:
                 need = self.vector_bytes(req) + (0 if entry else self.hierarchy_estimate(req, self.max_rhs))
                 if self.resident_bytes + self.inflight_bytes + need > self.budget:
                     self._evict(need)
+                self._ensure_free(need)
                 if self.resident_bytes + self.inflight_bytes + need <= self.budget or \
                         (self.inflight_bytes == 0 and not any(e[2] for e in self.resident.values())):
                     self.inflight_bytes += need
@@ -202,7 +223,8 @@ class Server:
         finally:
             self._release(req, h, reserved, new)
         t_done = time.perf_counter()
-        return Result(req.rid, st, 1e3 * (t_done - (t0 + req.t_arrival)), 1e3 * (t_admit - t_start),
+        return Result(req.rid, st, 1e3 * (t_done - (t0 + req.t_arrival)), 1e3 * (t_done - t_start),
+                      1e3 * (t_admit - t_start),
                       infos[0].setup_ms if new else 0.0, infos[0].solve_ms, not new,
                       [i.iterations for i in infos], [i.rel_residual for i in infos], sol)
 
@@ -256,10 +278,12 @@ class Server:
         if errors:
             raise RuntimeError(f"{len(errors)} requests failed, first: {errors[0]}")
         lat = sorted(r.latency_ms for r in results.values())
-        pct = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
+        svc = sorted(r.service_ms for r in results.values())
+        pct = lambda q, v=lat: v[min(len(v) - 1, int(math.ceil(q * len(v))) - 1)]
         solves = sum(len(r.iterations) for r in results.values())
         stats = {"requests": len(results), "solves": solves, "wall_s": wall, "solves_per_s": solves / wall,
                  "requests_per_s": len(results) / wall, "p50_ms": pct(0.50), "p99_ms": pct(0.99),
+                 "service_p50_ms": pct(0.50, svc), "service_p99_ms": pct(0.99, svc),
                  "max_ms": lat[-1], "reused": sum(r.reused for r in results.values()),
                  "failed": sum(r.status != amg.AMG_OK for r in results.values())}
         return results, stats
