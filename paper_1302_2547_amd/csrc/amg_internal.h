@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include <stdexcept>
+#include <vector>
 
 namespace amg {
 
@@ -170,6 +171,43 @@ template <class T>
 void launch_post_direct(Rows R, const int *ci, const T *va, const T *minv, const T *r, const T *v1, KDots kd,
                         DotRef om_r, DotRef om_v1, const double *ainv, T *xout, T *rt_out, int *flag, int G,
                         bool rt_mode, hipStream_t s, int ncol = 1);
+// A small level whose coarse level is one unknown, laid out for a whole coarse
+// correction (two flexible-CG steps, Sec. 4.4) in one block of kTailThreads
+// threads per right-hand side.  Thread t owns rows t + u kTailThreads
+// (u < kTailRows); the entries of an owned ordinary row (at most kTailWidth) sit
+// in that thread's slots u kTailWidth .. u kTailWidth + kTailWidth - 1 in CSR
+// order, padded with zero values; the entries of at most kTailLong long rows
+// (the hub of the single aggregate has every row of the level as a neighbour)
+// fill the slots from kTailRows kTailWidth on: entry j of long row m sits in slot
+// kTailRows kTailWidth + long_slot[m] + j / kTailThreads of thread
+// j % kTailThreads.  ci[s kTailThreads + t] is slot s of thread t (the values are
+// a separate array of the same shape, per storage type); padding slots hold
+// column 0 and value 0.
+constexpr int kTailThreads = 1024;
+constexpr int kTailRows = 5;
+constexpr int kTailWidth = 2;
+constexpr int kTailLong = 2;
+constexpr int kTailLongSlots = 6;
+constexpr int kTailSlots = kTailRows * kTailWidth + kTailLongSlots;
+struct TailLayout {
+    int n;
+    int nlong;
+    int long_row[kTailLong];       // -1 when unused
+    int long_slot[kTailLong + 1];  // long row m: slots long_slot[m] .. long_slot[m+1] (after the row slots)
+    const uint16_t *ci;  // column indices (n <= kTailRows kTailThreads < 2^16)
+};
+// Builds the layout of a CSR level on the host; false when the level does not fit.
+bool build_tail_layout(int n, const int *rp, const int *ci, const double *va, std::vector<uint16_t> &tci,
+                       std::vector<double> &tva, TailLayout &L);
+// Both flexible-CG steps of a K-cycle visit of such a level from its restricted
+// residual rc: c1 = K(rc), v1 = A c1, rt = rc - (alpha1/rho1) v1, c2 = K(rt), where K
+// is the two-grid visit of k_post_direct (pre-smoothing, restriction by om,
+// coarse solve, prolongation, post-smoothing).  Writes c1 and c2 and the five
+// products as reduced values: d1[0] = rho1 = (c1, A c1), d1[1] = alpha1 = (c1, rc),
+// d2[0] = beta = (c2, A c2), d2[1] = gamma = (c2, v1), d2[2] = alpha2 = (c2, rt).
+template <class T>
+void launch_tail_visit(const TailLayout &L, const T *va, const T *minv, const double *om, const double *ainv,
+                       const T *rc, T *c1, T *c2, double *d1, double *d2, int *flag, hipStream_t s, int ncol = 1);
 // rt = rc - (alpha1/rho1) v1
 template <class T>
 void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, hipStream_t s, int ncol = 1);

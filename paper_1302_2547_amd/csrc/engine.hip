@@ -264,6 +264,10 @@ struct Level {
     double *omega = nullptr;
     DotBuf d_om{};
     DotRef om_rc{}, om_v1{};
+    // ... and small enough for the one-block coarse correction (tail.n = 0: not laid out)
+    TailLayout tail{};
+    double *tail_va = nullptr;
+    float *tail_va32 = nullptr;
     KArrays<double> k64{};
     KArrays<float> k32{};
     template <class T>
@@ -339,6 +343,13 @@ struct amg_hierarchy {
     void to_host(T *dst, const T *src, size_t count)
     {
         AMG_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, stream));
+        sync();
+    }
+    // copy of pageable host memory: complete before the source may go
+    template <class T>
+    void to_dev(T *dst, const T *src, size_t count)
+    {
+        AMG_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, stream));
         sync();
     }
     int read_int(const int *dev)
@@ -668,9 +679,26 @@ void amg_hierarchy::finalize_layout()
                 om[t] += (t == q ? 1.0 : 0.0) - va[e] * mv[t];
             }
         F.omega = pool.alloc<double>(F.n);
-        AMG_HIP(hipMemcpyAsync(F.omega, om.data(), sizeof(double) * F.n, hipMemcpyHostToDevice, stream));
+        to_dev(F.omega, om.data(), F.n);
         F.d_om = dot_buf();
         AMG_TRACE_MSG("level %d: single coarse unknown below, restriction by inner products", L - 1);
+        std::vector<uint16_t> tci;
+        std::vector<double> tva;
+        TailLayout tl{};
+        if (opt.kcycle_inner == 2 && build_tail_layout(F.n, rp.data(), ci.data(), va.data(), tci, tva, tl)) {
+            uint16_t *dci = pool.alloc<uint16_t>(tci.size());
+            to_dev(dci, tci.data(), tci.size());
+            F.tail_va = pool.alloc<double>(tva.size());
+            to_dev(F.tail_va, tva.data(), tva.size());
+            if (mixed) {
+                const std::vector<float> t32(tva.begin(), tva.end());
+                F.tail_va32 = pool.alloc<float>(t32.size());
+                to_dev(F.tail_va32, t32.data(), t32.size());
+            }
+            tl.ci = dci;
+            F.tail = tl;
+            AMG_TRACE_MSG("level %d: one-block coarse correction (%d long rows)", L - 1, tl.nlong);
+        }
     }
     for (int l = 0; l <= L; l++) {
         Level &F = lev[l];
@@ -752,16 +780,28 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
     }
     Level &C = lev[k + 1];
     const KArrays<T> &CK = C.karr<T>();
+    // C small with a single unknown below: the whole coarse correction in one block,
+    // which forms (om, rc) itself
+    const bool tail = C.tail.n > 0;
+    const double *om = tail ? nullptr : C.omega;
     if (rts) {  // rr = rt is formed here from the parent's first inner step
         C.om_rc = launch_restrict_rt<T>(F.S, F.n, F.ci, FK.wv, rts->rcf, rts->v1, rts->kd, const_cast<T *>(rr), CK.rc,
-                                        flag, F.Gs, stream, C.omega, C.d_om, ncol);
+                                        flag, F.Gs, stream, om, C.d_om, ncol);
     } else {
-        C.om_rc = launch_restrict<T>(F.S, F.n, F.ci, FK.wv, rr, CK.rc, F.Gs, stream, C.omega, C.d_om, ncol);
+        C.om_rc = launch_restrict<T>(F.S, F.n, F.ci, FK.wv, rr, CK.rc, F.Gs, stream, om, C.d_om, ncol);
     }
     KDots kd{};
     int mode;
     const T *edirect = nullptr;
-    if (k + 1 == L) {
+    if (tail) {
+        const T *tva;
+        if constexpr (std::is_same<T, double>::value) tva = C.tail_va;
+        else tva = C.tail_va32;
+        double *d1 = C.d_c1.final_out, *d2 = C.d_c2.final_out;
+        launch_tail_visit<T>(C.tail, tva, CK.minv, C.omega, ainv, CK.rc, CK.c1, CK.c2, d1, d2, flag, stream, ncol);
+        kd = KDots{DotRef{d1, 1}, DotRef{d1 + 1, 1}, DotRef{d2, 1}, DotRef{d2 + 1, 1}, DotRef{d2 + 2, 1}};
+        mode = 2;
+    } else if (k + 1 == L) {
         if (C.n <= kInlineCoarse) {
             mode = 3;
             edirect = CK.rc;

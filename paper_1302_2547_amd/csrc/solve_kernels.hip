@@ -30,18 +30,53 @@ inline int grid_for(int64_t threads, int cap = 1 << 20)
     return (int)b;
 }
 
-__device__ inline double wave_sum(double v)
+// Cross-lane moves inside rows of 16 lanes (DPP, no LDS traffic): exchange with
+// lane ^ 1 and lane ^ 2 inside a quad, mirror inside 8 lanes, mirror inside 16.
+constexpr int kDppQuadXor1 = 0xB1, kDppQuadXor2 = 0x4E, kDppRowHalfMirror = 0x141, kDppRowMirror = 0x140;
+template <int CTRL>
+__device__ inline double dpp_f64(double v)
 {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// Sum over each row of 16 lanes, received by every lane of the row: each step adds
+// the partner's partial sum, and both partners form the same sum (fixed order).
+// The lanes of the row must be active.
+__device__ inline double row16_sum(double v)
+{
+    v += dpp_f64<kDppQuadXor1>(v);
+    v += dpp_f64<kDppQuadXor2>(v);
+    v += dpp_f64<kDppRowHalfMirror>(v);
+    v += dpp_f64<kDppRowMirror>(v);
     return v;
 }
+// v of one lane, as a wavefront-uniform value
+__device__ inline double lane_value(double v, int lane)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+// Sum over the wavefront, the same value in every lane (fixed order).  All lanes
+// must be active.
+__device__ inline double wave_sum(double v)
+{
+    v = row16_sum(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
 
+// Sum over each aligned group of G lanes, received by every lane of the group
+// (fixed order).  The moves stay inside the group, so lanes of other groups may
+// be inactive.
 template <int G>
 __device__ inline double group_sum(double v)
 {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    if (G >= 2) v += dpp_f64<kDppQuadXor1>(v);
+    if (G >= 4) v += dpp_f64<kDppQuadXor2>(v);
+    if (G >= 8) v += dpp_f64<kDppRowHalfMirror>(v);
+    if (G >= 16) v += dpp_f64<kDppRowMirror>(v);
+    if (G >= 32) v += __shfl_xor(v, 16, kWave);
+    if (G >= 64) v += __shfl_xor(v, 32, kWave);
     return v;
 }
 
@@ -748,7 +783,209 @@ __global__ void __launch_bounds__(kBlock) k_post_direct(Rows R, const int *__res
         });
 }
 
-// y = A x for a dense row-major n x n matrix: one wavefront per row.
+// ------------------------------------------------------------------ small single-aggregate level
+
+// Sum over a block of kTailThreads threads (16 wavefronts); every thread
+// receives the sums.
+template <int N>
+__device__ inline void tail_sums(double (&v)[N])
+{
+    static_assert(kTailThreads / kWave == 16, "one wavefront sum per lane of a row of 16");
+    __shared__ double sh[N][kTailThreads / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int d = 0; d < N; d++) {
+        const double t = wave_sum(v[d]);
+        if (lane == 0) sh[d][wid] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < N; d++) v[d] = lane_value(row16_sum(sh[d][lane & 15]), 0);
+    __syncthreads();
+}
+
+// The whole coarse correction of a K-cycle visit whose coarse level C is small
+// and has a single unknown below it: both flexible-CG steps (Sec. 4.4) on C, each
+// preconditioned by the two-grid visit of k_post_direct, in one block per
+// right-hand side.  C's entries stay in registers for the four products with A,
+// the vector being multiplied is shared through LDS (as are rc and M^-1 of the
+// owned rows), and every inner product is a block sum, so the correction takes
+// one launch instead of four.  Vectors that the separate kernels store in T are
+// rounded to T here at the same points (c1, A c1, rt, c2).
+template <class T>
+__global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const T *__restrict__ va,
+                                                             const T *__restrict__ minv,
+                                                             const double *__restrict__ om,
+                                                             const double *__restrict__ ainv,
+                                                             const T *__restrict__ rc, T *__restrict__ c1,
+                                                             T *__restrict__ c2, double *__restrict__ d1,
+                                                             double *__restrict__ d2, int *__restrict__ flag)
+{
+    constexpr int R = kTailRows, W = kTailWidth, S = kTailSlots, NL = kTailLong;
+    __shared__ double xs[R * kTailThreads];  // the vector being multiplied
+    __shared__ double rs[R * kTailThreads];  // rc (first step), then rt (second step)
+    __shared__ double ms[R * kTailThreads];  // M^-1
+    const int n = L.n, t = threadIdx.x;
+    rc = colv(rc, n);
+    c1 = colv(c1, n);
+    c2 = colv(c2, n);
+    d1 = colp(d1);
+    d2 = colp(d2);
+    int ci[S];
+    double a[S];
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        ci[s] = L.ci[s * kTailThreads + t];
+        a[s] = (double)va[s * kTailThreads + t];
+    }
+    // first row index of this wavefront's lanes (row slots of u are all padding
+    // for the whole wavefront when u * kTailThreads + wbase >= n)
+    const int wbase = __builtin_amdgcn_readfirstlane(t & ~(kWave - 1));
+    double o[R];
+    double q[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < R; u++) {
+        const int i = t + u * kTailThreads;
+        double rv = 0.0, mv = 0.0;
+        o[u] = 0.0;
+        if (i < n) {
+            rv = (double)rc[i];
+            mv = (double)minv[i];
+            o[u] = om[i];
+        }
+        rs[i] = rv;
+        ms[i] = mv;
+        q[0] += o[u] * rv;
+    }
+    const double acinv = ainv[0];
+    // y = (A xs) at the owned rows; the sums of long rows are block sums (whose
+    // barriers also end every thread's reads of xs)
+    auto apply = [&](double (&y)[R]) {
+        double p[S];
+#pragma unroll
+        for (int u = 0; u < R; u++) {
+            if (u * kTailThreads + wbase < n) {
+#pragma unroll
+                for (int k = 0; k < W; k++) p[u * W + k] = a[u * W + k] * xs[ci[u * W + k]];
+            } else {
+#pragma unroll
+                for (int k = 0; k < W; k++) p[u * W + k] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int s = R * W; s < S; s++) p[s] = a[s] * xs[ci[s]];
+#pragma unroll
+        for (int u = 0; u < R; u++) {
+            double acc = p[u * W];
+#pragma unroll
+            for (int k = 1; k < W; k++) acc += p[u * W + k];
+            y[u] = acc;
+        }
+        double l[NL];
+#pragma unroll
+        for (int m = 0; m < NL; m++) {
+            l[m] = 0.0;
+            if (m < L.nlong) {
+#pragma unroll
+                for (int s = R * W; s < S; s++) {
+                    const int j = s - R * W;
+                    l[m] += (j >= L.long_slot[m] && j < L.long_slot[m + 1]) ? p[s] : 0.0;
+                }
+            }
+        }
+        tail_sums<NL>(l);
+#pragma unroll
+        for (int u = 0; u < R; u++) {
+#pragma unroll
+            for (int m = 0; m < NL; m++)
+                if (t + u * kTailThreads == L.long_row[m]) y[u] = l[m];
+        }
+    };
+    // first step: c1 = K(rc) with e = (om, rc) / a_c
+    double om_r[1] = {q[0]};
+    tail_sums<1>(om_r);
+    const double e1 = acinv * om_r[0];
+    double x[R], y[R], c[R];
+#pragma unroll
+    for (int u = 0; u < R; u++) {
+        const int i = t + u * kTailThreads;
+        x[u] = ms[i] * rs[i] + e1;
+        xs[i] = x[u];
+    }
+    __syncthreads();
+    apply(y);
+#pragma unroll
+    for (int u = 0; u < R; u++) {
+        const int i = t + u * kTailThreads;
+        const T cv = (T)(x[u] + ms[i] * (rs[i] - y[u]));
+        c[u] = (double)cv;
+        if (i < n) c1[i] = cv;
+        xs[i] = c[u];
+    }
+    __syncthreads();
+    apply(y);  // A c1
+    double v[R];
+    q[0] = q[1] = q[2] = 0.0;
+#pragma unroll
+    for (int u = 0; u < R; u++) {
+        const int i = t + u * kTailThreads;
+        v[u] = (double)(T)y[u];
+        if (i < n) {
+            q[0] += c[u] * y[u];
+            q[1] += c[u] * rs[i];
+            q[2] += o[u] * y[u];
+        }
+    }
+    tail_sums<3>(q);
+    const double rho1 = q[0], alpha1 = q[1];
+    // a zero coarse residual gives c1 = 0 and no correction; a non-positive rho1
+    // otherwise means A is not SPD
+    const bool zero = rho1 == 0.0 && alpha1 == 0.0;
+    const bool bad = !(rho1 > 0.0) && !zero;
+    if (bad && t == 0) atomicOr(flag, 1);
+    const double al = (bad || zero) ? 0.0 : alpha1 / rho1;
+    // second step: rt = rc - (alpha1/rho1) v1, c2 = K(rt) with e = (om, rt) / a_c
+    const double e2 = acinv * (om_r[0] - al * q[2]);
+#pragma unroll
+    for (int u = 0; u < R; u++) {
+        const int i = t + u * kTailThreads;
+        const double rr = rs[i] - al * v[u];
+        x[u] = ms[i] * rr + e2;
+        rs[i] = rr;
+        xs[i] = x[u];
+    }
+    __syncthreads();
+    apply(y);  // A x
+#pragma unroll
+    for (int u = 0; u < R; u++) {
+        const int i = t + u * kTailThreads;
+        const T cv = (T)(x[u] + ms[i] * (rs[i] - y[u]));
+        c[u] = (double)cv;
+        if (i < n) c2[i] = cv;
+        xs[i] = c[u];
+    }
+    __syncthreads();
+    apply(y);  // A c2
+    q[0] = q[1] = q[2] = 0.0;
+#pragma unroll
+    for (int u = 0; u < R; u++) {
+        const int i = t + u * kTailThreads;
+        if (i < n) {
+            q[0] += c[u] * y[u];
+            q[1] += c[u] * v[u];
+            q[2] += c[u] * (double)(T)rs[i];
+        }
+    }
+    tail_sums<3>(q);
+    if (t == 0) {
+        d1[0] = rho1;
+        d1[1] = alpha1;
+        d2[0] = q[0];
+        d2[1] = q[1];
+        d2[2] = q[2];
+    }
+}
+
 // Y = A X for a dense row-major n x n A and CB right-hand sides per block (column
 // c0 + c of X at x + (c0 + c) n): one wavefront per row, lanes across the row, so
 // A is read once for CB columns.
@@ -1136,6 +1373,52 @@ void launch_post_direct(Rows R, const int *ci, const T *va, const T *minv, const
 }
 
 template <class T>
+void launch_tail_visit(const TailLayout &L, const T *va, const T *minv, const double *om, const double *ainv,
+                       const T *rc, T *c1, T *c2, double *d1, double *d2, int *flag, hipStream_t s, int ncol)
+{
+    k_tail_visit<T><<<dim3(1, ncol), kTailThreads, 0, s>>>(L, va, minv, om, ainv, rc, c1, c2, d1, d2, flag);
+    AMG_HIP(hipGetLastError());
+}
+
+bool build_tail_layout(int n, const int *rp, const int *ci, const double *va, std::vector<uint16_t> &tci,
+                       std::vector<double> &tva, TailLayout &L)
+{
+    if (n < 1 || n > kTailRows * kTailThreads) return false;
+    L = TailLayout{};
+    L.n = n;
+    for (int m = 0; m < kTailLong; m++) L.long_row[m] = -1;
+    tci.assign((size_t)kTailSlots * kTailThreads, 0);  // padding: column 0, value 0
+    tva.assign((size_t)kTailSlots * kTailThreads, 0.0);
+    constexpr int first_long = kTailRows * kTailWidth;
+    int nlong = 0, used = 0;
+    for (int i = 0; i < n; i++) {
+        const int b = rp[i], len = rp[i + 1] - b;
+        if (len <= kTailWidth) {
+            const int t = i % kTailThreads, u = i / kTailThreads;
+            for (int k = 0; k < len; k++) {
+                const size_t at = (size_t)(u * kTailWidth + k) * kTailThreads + t;
+                tci[at] = (uint16_t)ci[b + k];
+                tva[at] = va[b + k];
+            }
+            continue;
+        }
+        const int slots = (len + kTailThreads - 1) / kTailThreads;
+        if (nlong == kTailLong || used + slots > kTailLongSlots) return false;
+        for (int j = 0; j < len; j++) {
+            const size_t at = (size_t)(first_long + used + j / kTailThreads) * kTailThreads + j % kTailThreads;
+            tci[at] = (uint16_t)ci[b + j];
+            tva[at] = va[b + j];
+        }
+        L.long_row[nlong] = i;
+        used += slots;
+        L.long_slot[++nlong] = used;
+    }
+    for (int m = nlong; m < kTailLong; m++) L.long_slot[m + 1] = used;  // empty ranges
+    L.nlong = nlong;
+    return true;
+}
+
+template <class T>
 void launch_dense_gemv(int n, const double *a, const T *x, T *y, hipStream_t s, int ncol)
 {
     // one right-hand side per block row: measured faster than several per block
@@ -1180,7 +1463,9 @@ void launch_to_float(int64_t n, const double *src, float *dst, hipStream_t s)
     template void launch_post_direct<T>(Rows, const int *, const T *, const T *, const T *, const T *, KDots,       \
                                         DotRef, DotRef, const double *, T *, T *, int *, int, bool, hipStream_t,    \
                                         int);                                                                       \
-    template void launch_dense_gemv<T>(int, const double *, const T *, T *, hipStream_t, int);
+    template void launch_dense_gemv<T>(int, const double *, const T *, T *, hipStream_t, int);                     \
+    template void launch_tail_visit<T>(const TailLayout &, const T *, const T *, const double *, const double *,    \
+                                       const T *, T *, T *, double *, double *, int *, hipStream_t, int);
 AMG_INSTANTIATE(double)
 AMG_INSTANTIATE(float)
 #undef AMG_INSTANTIATE

@@ -52,6 +52,30 @@ def test_grid_128cubed_jitter(amg):
     run_case(amg, rp, ci, va, inputs.rhs(len(rp) - 1, 1))
 
 
+def test_grid_128cubed_kcycle(amg):
+    """One K-cycle application at 128^3, element by element.  Its level 7 (4128
+    unknowns: a hub row of 4128 entries, every other row the diagonal and the hub)
+    has a single unknown below it, so the coarse corrections of level 6 run in the
+    one-block kernel: four rows per thread and more, a hub row over five slots."""
+    rp, ci, va = inputs.grid_laplacian((128, 128, 128), jitter=0.1, seed=2)
+    n = len(rp) - 1
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    ref = oracle.Hierarchy(rp, ci, va)
+    L = ref.num_levels - 1
+    assert ref.level(L).n == 1 and ref.level(L - 1).n > 4096
+    r = inputs.rhs(n, 29)
+    zo = ref.kcycle(r)
+    for precision, bound in ((amg.AMG_PREC_FP64, 1e-10), (amg.AMG_PREC_FP32_INNER, 2e-5)):
+        print(f"[fullsize] 128^3 K-cycle precision={precision}", flush=True)
+        h = amg.Hierarchy(d(rp), d(ci), d(va), precision=precision)
+        z = torch.empty(n, dtype=torch.float64, device="cuda")
+        h.kcycle(d(r), z)
+        err = np.abs(z.cpu().numpy() - zo).max() / np.abs(zo).max()
+        print(f"[fullsize] max error {err:.2e}", flush=True)
+        assert err <= bound
+        h.close()
+
+
 def test_rgg_1m(amg):
     rp, ci, va = inputs.rgg_laplacian(1_000_000, mean_degree=8.0, seed=3)
     run_case(amg, rp, ci, va, inputs.rhs(len(rp) - 1, 1))
