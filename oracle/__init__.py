@@ -36,7 +36,10 @@ def build(force: bool = False) -> str:
 class _Options(ctypes.Structure):
     _fields_ = [("coarsest_size", ctypes.c_int), ("max_levels", ctypes.c_int),
                 ("stall_ratio", ctypes.c_double), ("max_aggregate", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("kcycle_inner", ctypes.c_int)]
+                ("seed", ctypes.c_uint64), ("kcycle_inner", ctypes.c_int),
+                ("smoother", ctypes.c_int), ("jacobi_weight", ctypes.c_double)]
+
+SMOOTHERS = {"l1": 0, "jacobi": 1}
 
 
 _lib = None
@@ -67,6 +70,8 @@ def _load():
                                         ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]
     lib.orc_l1_inverse_diagonal.argtypes = [c_int, _I, _I, _D, _D]
     lib.orc_l1_inverse_diagonal.restype = None
+    lib.orc_jacobi_inverse_diagonal.argtypes = [c_int, _I, _I, _D, c_double, _D]
+    lib.orc_jacobi_inverse_diagonal.restype = None
     lib.orc_default_options.argtypes = [ctypes.POINTER(_Options)]
     lib.orc_default_options.restype = None
     lib.orc_setup.argtypes = [c_int, c_int, _I, _I, _D, ctypes.POINTER(_Options), ctypes.POINTER(c_void_p)]
@@ -175,6 +180,13 @@ def l1_inverse_diagonal(rp, ci, va):
     return out
 
 
+def jacobi_inverse_diagonal(rp, ci, va, omega):
+    rp, ci, va = _csr(rp, ci, va)
+    out = np.empty(len(rp) - 1)
+    _load().orc_jacobi_inverse_diagonal(len(rp) - 1, rp, ci, va, float(omega), out)
+    return out
+
+
 # --- hierarchy and solve -------------------------------------------------------------------
 
 @dataclass
@@ -193,13 +205,14 @@ class Hierarchy:
     """Oracle hierarchy (Alg. 1 setup); owns C memory, freed on close()/del."""
 
     def __init__(self, rp, ci, va, coarsest_size=64, max_levels=40, stall_ratio=0.9, max_aggregate=0,
-                 seed=0x5EED5EED, kcycle_inner=2):
+                 seed=0x5EED5EED, kcycle_inner=2, smoother="l1", jacobi_weight=2.0 / 3.0):
         lib = _load()
         rp, ci, va = _csr(rp, ci, va)
         opt = _Options()
         lib.orc_default_options(ctypes.byref(opt))
         opt.coarsest_size, opt.max_levels, opt.stall_ratio = coarsest_size, max_levels, stall_ratio
         opt.max_aggregate, opt.seed, opt.kcycle_inner = max_aggregate, seed & (2**64 - 1), kcycle_inner
+        opt.smoother, opt.jacobi_weight = SMOOTHERS[smoother], jacobi_weight
         self._h = ctypes.c_void_p()
         st = lib.orc_setup(len(rp) - 1, len(ci), rp, ci, va, ctypes.byref(opt), ctypes.byref(self._h))
         if st:

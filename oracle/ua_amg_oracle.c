@@ -17,7 +17,8 @@
  *       vertex within graph distance 1 or 2, (B) forms an aggregate around each.
  *   Sec. 5.1: aggregate k is the one whose coarse vertex is the k-th smallest index.
  *   Alg. 1: the setup loop over levels.
- *   Sec. 4.1: l1-Jacobi smoother M_ii = a_ii + sum_{j!=i} |a_ij|.
+ *   Sec. 4.1: l1-Jacobi smoother M_ii = a_ii + sum_{j!=i} |a_ij|, or the damped
+ *       Jacobi smoother M^-1 = omega D^-1 (option).
  *   Sec. 4.2: prolongation (Pv)_i = v[agg[i]], restriction (P^T v)_I = sum_{agg[j]=I} v_j.
  *   Sec. 4.3-4.4: K-cycle (nonlinear AMLI cycle: nu flexible-CG steps on every
  *       coarse level, preconditioned recursively) as the preconditioner of an
@@ -43,6 +44,8 @@
  *   - Every structural entry of A_c is kept (no dropping).
  *   - The coarsest level is solved with a dense Cholesky factorisation.
  *   - One pre- and one post-smoothing l1-Jacobi sweep; the pre-sweep starts from 0.
+ *     The damping factor of the damped Jacobi variant is not given; it is a
+ *     parameter (default 2/3).
  *   - The outer iteration stops when ||b - A x||_2 <= tol ||b||_2 for the true
  *     residual (checked when the recursive residual first says so).
  */
@@ -329,6 +332,17 @@ void orc_l1_inverse_diagonal(int n, const int *rp, const int *ci, const double *
     }
 }
 
+/* Sec. 4.1: damped Jacobi, x <- x + omega D^-1 (b - A x), i.e. minv_i = omega / a_ii. */
+void orc_jacobi_inverse_diagonal(int n, const int *rp, const int *ci, const double *va, double omega, double *minv)
+{
+    for (int i = 0; i < n; i++) {
+        double diag = 0.0;
+        for (int p = rp[i]; p < rp[i + 1]; p++)
+            if (ci[p] == i) diag += va[p];
+        minv[i] = omega / diag;
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Hierarchy.                                                                 */
 /* ------------------------------------------------------------------------- */
@@ -360,6 +374,8 @@ typedef struct {
     int max_aggregate;    /* t, 0 = unlimited */
     uint64_t seed;
     int kcycle_inner;     /* nu */
+    int smoother;         /* 0: l1-Jacobi, 1: damped Jacobi */
+    double jacobi_weight; /* omega of the damped Jacobi smoother */
 } orc_options;
 
 static void free_level(orc_level *L, int own_matrix)
@@ -444,6 +460,8 @@ void orc_default_options(orc_options *o)
     o->max_aggregate = 0;
     o->seed = 0x5EED5EEDULL;
     o->kcycle_inner = 2;
+    o->smoother = 0;
+    o->jacobi_weight = 2.0 / 3.0;
 }
 
 /* Alg. 1, setup phase.  Copies the input matrix. */
@@ -453,7 +471,8 @@ int orc_setup(int n, int nnz, const int *rp, const int *ci, const double *va,
     double t0 = now_ms();
     *out = NULL;
     if (!opt || opt->max_levels < 1 || opt->max_levels > ORC_MAX_LEVELS || opt->kcycle_inner < 1 ||
-        opt->coarsest_size < 1 || opt->max_aggregate < 0 || opt->max_aggregate == 1)
+        opt->coarsest_size < 1 || opt->max_aggregate < 0 || opt->max_aggregate == 1 || opt->smoother < 0 ||
+        opt->smoother > 1 || !(opt->jacobi_weight > 0.0) || !isfinite(opt->jacobi_weight))
         return ORC_ERR_ARG;
     int st = orc_check_csr(n, nnz, rp, ci, va);
     if (st) return st;
@@ -505,7 +524,10 @@ int orc_setup(int n, int nnz, const int *rp, const int *ci, const double *va,
         orc_level *Lk = &h->lev[k];
         Lk->minv = (double *)malloc(sizeof(double) * (size_t)Lk->n);
         if (!Lk->minv || alloc_work(Lk)) { orc_free(h); return ORC_ERR_NOMEM; }
-        orc_l1_inverse_diagonal(Lk->n, Lk->rp, Lk->ci, Lk->va, Lk->minv);
+        if (opt->smoother == 1)
+            orc_jacobi_inverse_diagonal(Lk->n, Lk->rp, Lk->ci, Lk->va, opt->jacobi_weight, Lk->minv);
+        else
+            orc_l1_inverse_diagonal(Lk->n, Lk->rp, Lk->ci, Lk->va, Lk->minv);
     }
     orc_level *Lc = &h->lev[h->nlev - 1];
     st = dense_cholesky(Lc->n, Lc->rp, Lc->ci, Lc->va, &h->chol);

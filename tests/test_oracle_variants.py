@@ -1,0 +1,94 @@
+"""Pins of the oracle's damped Jacobi smoother (Sec. 4.1), CPU only.
+
+Independent references: the closed-form spectrum of damped Jacobi on the 1D
+Laplacian, the two-grid operator written as a matrix product with the smoother
+taken from the dense matrix's diagonal, and dense direct solves.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1302_2547_amd import inputs
+
+
+def dense(rp, ci, va):
+    return inputs.csr_to_dense(rp, ci, va)
+
+
+def laplacian_1d(n):
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        for j, v in ((i - 1, -1.0), (i, 2.0), (i + 1, -1.0)):
+            if 0 <= j < n:
+                rows.append(i); cols.append(j); vals.append(v)
+    rp = np.searchsorted(rows, np.arange(n + 1)).astype(np.int32)
+    return rp, np.array(cols, np.int32), np.array(vals)
+
+
+@pytest.mark.parametrize("omega", [2.0 / 3.0, 1.0, 0.5])
+def test_damped_jacobi_spectrum_closed_form(omega):
+    """I - omega D^-1 A on tridiag(-1, 2, -1) has eigenvalues
+    1 - omega (1 - cos(k pi / (n + 1))), k = 1..n."""
+    n = 30
+    rp, ci, va = laplacian_1d(n)
+    minv = oracle.jacobi_inverse_diagonal(rp, ci, va, omega)
+    ev = np.sort(np.linalg.eigvals(np.eye(n) - np.diag(minv) @ dense(rp, ci, va)).real)
+    k = np.arange(1, n + 1)
+    expect = np.sort(1.0 - omega * (1.0 - np.cos(k * np.pi / (n + 1))))
+    np.testing.assert_allclose(ev, expect, atol=1e-12)
+
+
+def test_hierarchy_levels_carry_the_chosen_smoother():
+    rp, ci, va = inputs.grid_laplacian((14, 13), jitter=0.2, seed=4)
+    hl = oracle.Hierarchy(rp, ci, va, coarsest_size=10)
+    hj = oracle.Hierarchy(rp, ci, va, coarsest_size=10, smoother="jacobi", jacobi_weight=0.7)
+    assert hl.num_levels == hj.num_levels >= 3
+    for l in range(hj.num_levels):
+        a, b = hl.level(l), hj.level(l)
+        np.testing.assert_array_equal(a.agg, b.agg)   # the smoother does not change the hierarchy
+        np.testing.assert_array_equal(a.val, b.val)
+        d = dense(b.row_ptr, b.col, b.val).diagonal()
+        np.testing.assert_allclose(b.minv * d, 0.7, rtol=1e-15)
+
+
+@pytest.mark.parametrize("omega", [2.0 / 3.0, 0.9])
+def test_two_level_kcycle_with_damped_jacobi(omega):
+    rp, ci, va = inputs.grid_laplacian((12, 12), jitter=0.2, seed=5)
+    h = oracle.Hierarchy(rp, ci, va, coarsest_size=100, smoother="jacobi", jacobi_weight=omega)
+    assert h.num_levels == 2
+    l0, l1 = h.level(0), h.level(1)
+    a = dense(rp, ci, va)
+    n = l0.n
+    p = np.zeros((n, l1.n))
+    p[np.arange(n), l0.agg] = 1.0
+    m = np.diag(omega / a.diagonal())
+    ac_inv = np.linalg.inv(p.T @ a @ p)
+    x2 = m + p @ ac_inv @ p.T @ (np.eye(n) - a @ m)
+    expect = x2 + m @ (np.eye(n) - a @ x2)
+    got = np.column_stack([h.kcycle(e) for e in np.eye(n)])
+    np.testing.assert_allclose(got, expect, rtol=0, atol=1e-12 * np.abs(expect).max())
+    np.testing.assert_allclose(got, got.T, atol=1e-12 * np.abs(got).max())
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_damped_jacobi_solve_reaches_direct_solution(case):
+    if case == 0:
+        rp, ci, va = inputs.grid_laplacian((20, 20), jitter=0.1, seed=1)
+    elif case == 1:
+        rp, ci, va = inputs.grid_laplacian((8, 7, 6), jitter=0.1, seed=1)
+    else:
+        rp, ci, va = inputs.random_graph_laplacian(120, p=0.08, seed=2, integer_weights=False, shift=1e-3)
+    a = dense(rp, ci, va)
+    b = inputs.rhs(a.shape[0], 20 + case)
+    h = oracle.Hierarchy(rp, ci, va, coarsest_size=10, smoother="jacobi")
+    x, st, it, rel, _ = h.solve(b, tol=1e-12, max_iters=300)
+    assert st == oracle.OK
+    x_ref = np.linalg.solve(a, b)
+    np.testing.assert_allclose(x, x_ref, rtol=0, atol=1e-9 * np.abs(x_ref).max())
+
+
+def test_invalid_jacobi_weight_is_rejected():
+    rp, ci, va = inputs.grid_laplacian((6, 6))
+    for w in (0.0, -1.0, float("nan")):
+        with pytest.raises(RuntimeError):
+            oracle.Hierarchy(rp, ci, va, smoother="jacobi", jacobi_weight=w)
