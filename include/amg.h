@@ -43,6 +43,11 @@ typedef enum {
     AMG_PREC_FP32_INNER = 1  /* K-cycle in binary32 inside the binary64 outer iteration */
 } amg_precision;
 
+typedef enum {
+    AMG_SMOOTHER_L1 = 0,     /* l1-Jacobi, M_ii = a_ii + sum_{j != i} |a_ij| (Sec. 4.1)  */
+    AMG_SMOOTHER_JACOBI = 1  /* damped Jacobi, M^-1 = omega D^-1 (Sec. 4.1)            */
+} amg_smoother;
+
 /* Opaque hierarchy: owns copies of every level and all its device memory. */
 typedef struct amg_hierarchy amg_hierarchy;
 
@@ -72,6 +77,8 @@ typedef struct {
     void *stream;               /* hipStream_t, or NULL                                      */
     int32_t max_rhs;            /* right-hand sides one amg_solve_batch may take (def. 1);   */
                                 /* work vectors are sized n_l * max_rhs on every level       */
+    int32_t smoother;           /* amg_smoother of every level (default AMG_SMOOTHER_L1)     */
+    double jacobi_weight;       /* omega of AMG_SMOOTHER_JACOBI, finite and > 0 (def. 2/3)  */
 } amg_options;
 
 typedef struct {

@@ -26,6 +26,8 @@ AMG_ERR_BREAKDOWN = 6
 AMG_ERR_UNSUPPORTED = 7
 AMG_PREC_FP64 = 0
 AMG_PREC_FP32_INNER = 1
+AMG_SMOOTHER_L1 = 0
+AMG_SMOOTHER_JACOBI = 1
 
 
 class amg_csr(ctypes.Structure):
@@ -38,7 +40,7 @@ class amg_options(ctypes.Structure):
                 ("max_aggregate", ctypes.c_int32), ("seed", ctypes.c_uint64), ("kcycle_inner", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("max_coarsest", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p),
-                ("max_rhs", ctypes.c_int32)]
+                ("max_rhs", ctypes.c_int32), ("smoother", ctypes.c_int32), ("jacobi_weight", ctypes.c_double)]
 
 
 class amg_solve_info(ctypes.Structure):

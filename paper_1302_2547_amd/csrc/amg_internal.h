@@ -87,7 +87,9 @@ void scan_exclusive(const int *in, int *out, int64_t n, int *total_dev, int *tmp
 
 // ---------------------------------------------------------------- setup_kernels.hip
 void launch_validate_csr(int n, int nnz, const int *rp, const int *ci, const double *va, int *err, hipStream_t s);
-void launch_l1_inverse_diagonal(int n, const int *rp, const int *ci, const double *va, double *minv, hipStream_t s);
+// the smoother's inverse diagonal: l1-Jacobi for weight <= 0, else damped Jacobi weight / a_ii
+void launch_inverse_diagonal(int n, const int *rp, const int *ci, const double *va, double weight, double *minv,
+                             hipStream_t s);
 void launch_priorities(int n, const int *rp, uint32_t s_l, uint64_t *key, int *owner, hipStream_t s);
 // one pass of Alg. 2; rows longer than lim (listed in hubs) are served by whole blocks
 void launch_mis_pass(int n, const int *rp, const int *ci, uint64_t *key, uint64_t *m1, int *owner, int cap, int G,
@@ -113,7 +115,7 @@ void launch_coarse_big_rows(int nbig, const int *big_rows, const int64_t *scratc
                             const int *members, const int *tptr, int *tcol, double *tval, int *cnt,
                             hipStream_t s);
 void launch_coarse_compact(int nc, const int *tptr, const int *tcol, const double *tval, const int *crp, int *cci,
-                           double *cva, double *cminv, hipStream_t s);
+                           double *cva, double weight, double *cminv, hipStream_t s);
 void launch_dense_from_csr(int n, const int *rp, const int *ci, const double *va, double *dense, hipStream_t s);
 void launch_cholesky_inverse(int n, double *a, double *inv, int *err, hipStream_t s);
 // solve-layout permutation

@@ -337,6 +337,8 @@ struct amg_hierarchy {
     }
 
     int levels() const { return (int)lev.size(); }
+    // weight of the damped Jacobi smoother, 0 for l1-Jacobi
+    double smoother_weight() const { return opt.smoother == AMG_SMOOTHER_JACOBI ? opt.jacobi_weight : 0.0; }
     void sync() { AMG_HIP(hipStreamSynchronize(stream)); }
 
     template <class T>
@@ -484,7 +486,8 @@ void amg_hierarchy::build(const amg_csr &A)
     AMG_HIP(hipMemsetAsync(ibuf, 0, 16 * sizeof(int), stream));
     launch_validate_csr(n0, nnz0, lev[0].rp_nat, lev[0].ci_nat, lev[0].va_nat, ibuf, stream);
     if (read_int(ibuf) != 0) throw Error(AMG_ERR_INVALID_MATRIX, "invalid CSR");
-    launch_l1_inverse_diagonal(n0, lev[0].rp_nat, lev[0].ci_nat, lev[0].va_nat, lev[0].minv_nat, stream);
+    launch_inverse_diagonal(n0, lev[0].rp_nat, lev[0].ci_nat, lev[0].va_nat, smoother_weight(), lev[0].minv_nat,
+                            stream);
 
     const int acc_cap = coarse_acc_capacity();
     // Alg. 1: coarsen while n_l > n_0 and fewer than L levels exist
@@ -566,7 +569,8 @@ void amg_hierarchy::build(const amg_csr &A)
         C.ci_nat = pool.alloc<int>(C.nnz);
         C.va_nat = pool.alloc<double>(C.nnz);
         C.minv_nat = pool.alloc<double>(nc);
-        launch_coarse_compact(nc, tptr, tcol, tval, C.rp_nat, C.ci_nat, C.va_nat, C.minv_nat, stream);
+        launch_coarse_compact(nc, tptr, tcol, tval, C.rp_nat, C.ci_nat, C.va_nat, smoother_weight(), C.minv_nat,
+                              stream);
         lev.push_back(C);
         l++;
     }
@@ -1084,6 +1088,8 @@ void amg_default_options(amg_options *opt)
     opt->mem_budget = 0;
     opt->stream = nullptr;
     opt->max_rhs = 1;
+    opt->smoother = AMG_SMOOTHER_L1;
+    opt->jacobi_weight = 2.0 / 3.0;
 }
 
 amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy **out)
@@ -1098,8 +1104,10 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy 
     else amg_default_options(&opt);
     if (opt.coarsest_size < 1 || opt.max_levels < 1 || opt.max_levels > 64 || !(opt.stall_ratio > 0.0) ||
         !(opt.stall_ratio <= 1.0) || opt.max_aggregate < 0 || opt.max_aggregate == 1 || opt.max_iters < 0 ||
-        opt.max_coarsest < 1 || opt.max_rhs < 1 || opt.max_rhs > 1024)
+        opt.max_coarsest < 1 || opt.max_rhs < 1 || opt.max_rhs > 1024 || !(opt.jacobi_weight > 0.0) ||
+        !std::isfinite(opt.jacobi_weight))
         return AMG_ERR_INVALID_ARGUMENT;
+    if (opt.smoother != AMG_SMOOTHER_L1 && opt.smoother != AMG_SMOOTHER_JACOBI) return AMG_ERR_UNSUPPORTED;
     if (opt.kcycle_inner != 1 && opt.kcycle_inner != 2) return AMG_ERR_UNSUPPORTED;
     if (opt.precision != AMG_PREC_FP64 && opt.precision != AMG_PREC_FP32_INNER) return AMG_ERR_UNSUPPORTED;
     amg_hierarchy *h = new (std::nothrow) amg_hierarchy();

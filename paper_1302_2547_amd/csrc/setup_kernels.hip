@@ -8,7 +8,7 @@
 //                                     LDS bitonic sort + ordered segmented sums),
 //                                     k_coarse_big_rows (one block per row beyond
 //                                     LDS capacity, LDS-tiled bitonic sort)
-//   l1-Jacobi diagonal (Sec. 4.1)     k_l1_inverse_diagonal / k_coarse_compact
+//   smoother diagonal (Sec. 4.1)      k_inverse_diagonal / k_coarse_compact
 //   coarsest level                    dense Cholesky and explicit inverse
 //   solve layout                      nested aggregate order for every level
 //
@@ -128,11 +128,18 @@ __global__ void __launch_bounds__(kBlock) k_validate_csr(int n, int nnz, const i
     if (!diag) atomicOr(err, 32);
 }
 
-// minv_i = 1 / (a_ii + sum_{j != i} |a_ij|), the row summed in column order.
-__global__ void __launch_bounds__(kBlock) k_l1_inverse_diagonal(int n, const int *__restrict__ rp,
-                                                                const int *__restrict__ ci,
-                                                                const double *__restrict__ va,
-                                                                double *__restrict__ minv)
+// The smoother's inverse diagonal (Sec. 4.1): with weight <= 0 the l1-Jacobi
+// minv_i = 1 / (a_ii + sum_{j != i} |a_ij|) (the row summed in column order),
+// else the damped Jacobi minv_i = weight / a_ii.
+__device__ inline double smoother_inverse(double diag, double off, double weight)
+{
+    return weight > 0.0 ? weight / diag : 1.0 / (diag + off);
+}
+
+__global__ void __launch_bounds__(kBlock) k_inverse_diagonal(int n, const int *__restrict__ rp,
+                                                             const int *__restrict__ ci,
+                                                             const double *__restrict__ va, double weight,
+                                                             double *__restrict__ minv)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -141,7 +148,7 @@ __global__ void __launch_bounds__(kBlock) k_l1_inverse_diagonal(int n, const int
         if (ci[p] == i) diag += va[p];
         else off += fabs(va[p]);
     }
-    minv[i] = 1.0 / (diag + off);
+    minv[i] = smoother_inverse(diag, off, weight);
 }
 
 // ------------------------------------------------------------------ eq. (3.2)
@@ -857,7 +864,8 @@ __global__ void __launch_bounds__(kBlock) k_coarse_compact(int nc, const int *__
                                                            const int *__restrict__ tcol,
                                                            const double *__restrict__ tval,
                                                            const int *__restrict__ crp, int *__restrict__ cci,
-                                                           double *__restrict__ cva, double *__restrict__ cminv)
+                                                           double *__restrict__ cva, double weight,
+                                                           double *__restrict__ cminv)
 {
     const int sub = threadIdx.x % G;
     const int ngroups = gridDim.x * (kBlock / G);
@@ -874,7 +882,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_compact(int nc, const int *__
         }
         diag = group_dsum<G>(diag);
         off = group_dsum<G>(off);
-        if (sub == 0) cminv[I] = 1.0 / (diag + off);
+        if (sub == 0) cminv[I] = smoother_inverse(diag, off, weight);
     }
 }
 
@@ -1121,9 +1129,10 @@ void launch_validate_csr(int n, int nnz, const int *rp, const int *ci, const dou
     AMG_HIP(hipGetLastError());
 }
 
-void launch_l1_inverse_diagonal(int n, const int *rp, const int *ci, const double *va, double *minv, hipStream_t s)
+void launch_inverse_diagonal(int n, const int *rp, const int *ci, const double *va, double weight, double *minv,
+                             hipStream_t s)
 {
-    k_l1_inverse_diagonal<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, va, minv);
+    k_inverse_diagonal<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, va, weight, minv);
     AMG_HIP(hipGetLastError());
 }
 
@@ -1216,10 +1225,10 @@ void launch_coarse_big_rows_acc(int nbig, const int *big_rows, int nc, const int
 }
 
 void launch_coarse_compact(int nc, const int *tptr, const int *tcol, const double *tval, const int *crp, int *cci,
-                           double *cva, double *cminv, hipStream_t s)
+                           double *cva, double weight, double *cminv, hipStream_t s)
 {
     const int G = wide(nc) ? kWave : 1;
-    AMG_LAUNCH_G(G, k_coarse_compact, grid_for((int64_t)nc * G), s, nc, tptr, tcol, tval, crp, cci, cva, cminv);
+    AMG_LAUNCH_G(G, k_coarse_compact, grid_for((int64_t)nc * G), s, nc, tptr, tcol, tval, crp, cci, cva, weight, cminv);
     AMG_HIP(hipGetLastError());
 }
 

@@ -279,3 +279,40 @@ def test_large_coarsest_gauss_jordan(amg):
     st, info = h.solve(dev(xv), x, tol=1e-10)
     r = xv - oracle.spmv(rp, ci, va, x.cpu().numpy())
     assert st == amg.AMG_OK and np.linalg.norm(r) / np.linalg.norm(xv) <= 1e-10
+
+
+@pytest.mark.parametrize("case,opt", [("grid3d_24_jitter", {}), ("grid3d_24_jitter", {"coarsest_size": 1}),
+                                      ("grid2d_64", {"coarsest_size": 1}), ("rgg_20k", {})])
+def test_damped_jacobi_matches_oracle(amg, case, opt):
+    """Damped Jacobi smoother (Sec. 4.1, weight 0.7): same hierarchy values, the
+    K-cycle element by element and the solve against the oracle."""
+    rp, ci, va = CASES[case]()
+    n = len(rp) - 1
+    w = 0.7
+    print(f"[parity] damped Jacobi {case} {opt}", flush=True)
+    h = amg.Hierarchy(dev(rp), dev(ci), dev(va), smoother=amg.AMG_SMOOTHER_JACOBI, jacobi_weight=w, **opt)
+    ref = oracle.Hierarchy(rp, ci, va, smoother="jacobi", jacobi_weight=w, **opt)
+    assert_same_hierarchy(h, ref)
+    xv = inputs.rhs(n, 31)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.kcycle(dev(xv), z)
+    zo = ref.kcycle(xv)
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-10 * np.abs(zo).max())
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, info = h.solve(dev(xv), x, tol=1e-10)
+    _, st_o, it_o, _, _ = ref.solve(xv, tol=1e-10)
+    r = xv - oracle.spmv(rp, ci, va, x.cpu().numpy())
+    assert st == amg.AMG_OK and np.linalg.norm(r) / np.linalg.norm(xv) <= 1e-10
+    assert abs(info.iterations - it_o) <= 1
+    h.close()
+
+
+def test_smoother_options_are_validated(amg):
+    rp, ci, va = CASES["grid2d_64"]()
+    for w in (0.0, -0.5, float("nan"), float("inf")):
+        with pytest.raises(amg.AmgError) as e:
+            amg.Hierarchy(dev(rp), dev(ci), dev(va), smoother=amg.AMG_SMOOTHER_JACOBI, jacobi_weight=w)
+        assert e.value.status == amg.AMG_ERR_INVALID_ARGUMENT
+    with pytest.raises(amg.AmgError) as e:
+        amg.Hierarchy(dev(rp), dev(ci), dev(va), smoother=5)
+    assert e.value.status == amg.AMG_ERR_UNSUPPORTED
