@@ -60,15 +60,18 @@ def parse():
 
 
 COPY_BYTES = 1 << 28  # 256 MiB read + 256 MiB written by the reference copy
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1302_2547_amd", "csrc", "solve_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1302_2547_amd", "csrc", f) for f in ("solve_kernels.hip", "engine.hip")]
 
 
 def source_digest():
-    """Digest of the source that holds the post-smoother: counters taken from an
-    older build of it no longer describe the kernel that runs."""
+    """Digest of the sources that hold the post-smoother and the finest level's
+    layout: counters taken from an older build no longer describe the kernel that runs."""
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_probe(args):

@@ -254,6 +254,7 @@ struct Level {
     int *perm = nullptr, *pos = nullptr;                        // position -> natural, natural -> position
     int *agg_pos = nullptr, *seg_ptr = nullptr, *srp = nullptr;  // all but the coarsest level
     int *cagg = nullptr;                                         // coarse unknown of each entry's column
+    int *sci = nullptr;  // columns of the super-rows of P^T A (the same array as ci unless level 0 is natural)
     int G = 2, Gs = 2;
     Rows A{}, S{};  // rows of A and super-rows of P^T A, each with its hub-row chunks
     // work vectors and dot sites when this level is the coarse level of a visit
@@ -306,6 +307,9 @@ struct amg_hierarchy {
     DotBuf d_pq{}, d_rr{}, d_zq{}, d_res{};
     DotRef dr_pq{}, dr_pr{}, dr_rr{}, dr_zq{};
     double *scal = nullptr;  // device scalars read by the host: rr, bb, rr0
+    // position -> caller's index of the finest level's solve layout (NULL: the
+    // finest level keeps the caller's numbering)
+    const int *uperm = nullptr;
     bool mixed = false;       // FP32 K-cycle inside the FP64 outer iteration
     float *r32 = nullptr, *z32 = nullptr;
     KDots kd0{};             // dots of the finest visit's coarse correction (for timing)
@@ -630,6 +634,8 @@ void amg_hierarchy::finalize_layout()
         F.agg_pos = pool.alloc<int>(F.n);
         launch_agg_positions(F.n, F.perm, F.agg_nat, C.pos, F.agg_pos, stream);
     }
+    uperm = lev[0].perm;
+    std::vector<void *> drained;
     for (int l = 0; l <= L; l++) {
         Level &F = lev[l];
         launch_permuted_row_lengths(F.n, F.rp_nat, F.perm, tmp, stream);
@@ -641,7 +647,8 @@ void amg_hierarchy::finalize_layout()
         launch_permute_rows(F.n, F.rp_nat, F.ci_nat, F.va_nat, F.minv_nat, F.perm, F.pos, F.rp, F.ci, F.va, F.minv,
                             stream);
         F.G = lanes_for((double)F.nnz / F.n, F.n);
-        F.A = make_rows(F.n, F.rp, F.G, tmp, scan_tmp);
+        const bool natural = l == 0 && L >= 1;  // see below
+        F.A = make_rows(F.n, natural ? F.rp_nat : F.rp, F.G, tmp, scan_tmp);
         AMG_TRACE_MSG("layout level %d: G=%d hub rows=%d chunks=%d", l, F.G, F.A.nlong, F.A.nchunks);
         if (l < L) {
             const int nc = lev[l + 1].n;
@@ -652,6 +659,27 @@ void amg_hierarchy::finalize_layout()
             AMG_TRACE_MSG("layout level %d: super-rows Gs=%d hub rows=%d chunks=%d", l, F.Gs, F.S.nlong, F.S.nchunks);
             F.wv = pool.alloc<double>(F.nnz);
             launch_restriction_weights(F.n, F.rp, F.ci, F.va, F.minv, F.wv, stream);
+            F.sci = F.ci;
+            if (natural) {
+                // The finest level keeps the caller's numbering for A (the stencil's
+                // neighbours stay in nearby cache lines; the nested order scatters them
+                // and the finest sweeps fetched ~3x their bytes).  Only the restriction
+                // needs the aggregate-grouped super-rows: their entries keep the nested
+                // order built above, with the columns mapped back to natural indices.
+                int *sci = pool.alloc<int>(F.nnz);
+                launch_gather_int(F.nnz, F.perm, F.ci, sci, stream);  // sci[e] = perm[ci[e]]
+                launch_gather_int(F.n, lev[1].pos, F.agg_nat, F.agg_pos, stream);  // natural row -> coarse position
+                // released once the stream has drained (another hierarchy's stream
+                // may receive the blocks from the shared cache)
+                drained.insert(drained.end(), {F.rp, F.ci, F.va, F.minv});
+                F.sci = sci;
+                F.rp = F.rp_nat;
+                F.ci = F.ci_nat;
+                F.va = F.va_nat;
+                F.minv = F.minv_nat;
+                uperm = nullptr;
+                AMG_TRACE_MSG("layout level 0: natural numbering, hub rows=%d", F.A.nlong);
+            }
             if (F.n < kSmallLevel) {
                 F.cagg = pool.alloc<int>(F.nnz);
                 launch_entry_coarse_column(F.nnz, F.ci, F.agg_pos, F.cagg, stream);
@@ -751,6 +779,7 @@ void amg_hierarchy::finalize_layout()
     sync();
     pool.release(tmp);
     pool.release(scan_tmp);
+    for (void *p : drained) pool.release(p);
 }
 
 // x = K_k(r) on level k (solve layout): pre-smoothing from zero + restriction,
@@ -789,10 +818,10 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
     const bool tail = C.tail.n > 0;
     const double *om = tail ? nullptr : C.omega;
     if (rts) {  // rr = rt is formed here from the parent's first inner step
-        C.om_rc = launch_restrict_rt<T>(F.S, F.n, F.ci, FK.wv, rts->rcf, rts->v1, rts->kd, const_cast<T *>(rr), CK.rc,
-                                        flag, F.Gs, stream, om, C.d_om, ncol);
+        C.om_rc = launch_restrict_rt<T>(F.S, F.n, F.sci, FK.wv, rts->rcf, rts->v1, rts->kd, const_cast<T *>(rr),
+                                        CK.rc, flag, F.Gs, stream, om, C.d_om, ncol);
     } else {
-        C.om_rc = launch_restrict<T>(F.S, F.n, F.ci, FK.wv, rr, CK.rc, F.Gs, stream, om, C.d_om, ncol);
+        C.om_rc = launch_restrict<T>(F.S, F.n, F.sci, FK.wv, rr, CK.rc, F.Gs, stream, om, C.d_om, ncol);
     }
     KDots kd{};
     int mode;
@@ -950,8 +979,8 @@ amg_status amg_hierarchy::solve(int ncol, const double *b_user, int ldb, double 
     AMG_HIP(hipEventRecord(ev0, stream));
     capture_graphs(ncol);
     AMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
-    launch_gather(n, b_user, F.perm, b, stream, ncol, ldb, n);
-    launch_gather(n, x_user, F.perm, x, stream, ncol, ldx, n);
+    launch_gather(n, b_user, uperm, b, stream, ncol, ldb, n);
+    launch_gather(n, x_user, uperm, x, stream, ncol, ldx, n);
     auto true_residual = [&]() {  // r = b - A x; per column (b, b), (r, r) at scal[c * kScalCol + 1, + 2]
         const DotSet s0 = launch_residual(F.A, F.ci, F.va, b, x, r, F.G, d_res, stream, ncol);
         launch_reduce(s0.d[0], scal + 1, stream, ncol);
@@ -1009,7 +1038,7 @@ amg_status amg_hierarchy::solve(int ncol, const double *b_user, int ldb, double 
         }
     }
     if (st != AMG_ERR_BREAKDOWN) st = all_done() ? AMG_OK : AMG_ERR_NOT_CONVERGED;
-    launch_scatter(n, x, F.perm, x_user, stream, ncol, n, ldx);
+    launch_scatter(n, x, uperm, x_user, stream, ncol, n, ldx);
     for (int c = 0; c < ncol; c++)  // b = 0 has the solution 0
         if (bnorm[c] == 0.0) AMG_HIP(hipMemsetAsync(x_user + (size_t)c * ldx, 0, sizeof(double) * n, stream));
     true_residual();  // the reported residual is always the true one
@@ -1278,13 +1307,13 @@ amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z)
         const Level &F = h->lev[0];
         h->capture_graphs(1);
         AMG_HIP(hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
-        amg::launch_gather(F.n, r, F.perm, h->r, h->stream);
+        amg::launch_gather(F.n, r, h->uperm, h->r, h->stream);
         if (h->mixed) {  // the mixed K-cycle reads (r, r) from scal[0]
             const DotRef rr = amg::launch_dot(F.n, h->r, h->r, h->d_res, h->stream);
             amg::launch_reduce(rr, h->scal, h->stream);
         }
         h->run_kcycle(1);
-        amg::launch_scatter(F.n, h->z, F.perm, z, h->stream);
+        amg::launch_scatter(F.n, h->z, h->uperm, z, h->stream);
         AMG_HIP(hipMemcpyAsync(h->host_i, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         h->sync();
         return h->host_i[0] ? AMG_ERR_BREAKDOWN : AMG_OK;

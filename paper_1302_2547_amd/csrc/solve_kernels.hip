@@ -1112,7 +1112,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(int n, const double *__restri
 {
     src = colv(src, ld_src);
     dst = colv(dst, ld_dst);
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[idx[i]];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[idx ? idx[i] : i];
 }
 
 __global__ void __launch_bounds__(kBlock) k_scatter(int n, const double *__restrict__ src, int ld_src,
@@ -1120,7 +1120,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int n, const double *__restr
 {
     src = colv(src, ld_src);
     dst = colv(dst, ld_dst);
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[idx[i]] = src[i];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[idx ? idx[i] : i] = src[i];
 }
 
 // w_e = [col(e) is the row's diagonal] - a_e minv_col(e) for every entry (solve
