@@ -223,9 +223,20 @@ DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, con
                           const int *cagg, int mode, const T *edirect, const T *c1, const T *c2, KDots kd, T *xout,
                           const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv, int nc,
                           int ncol = 1);
-// y = A x with A dense row-major FP64
+// Exact solve on a coarsest level of n unknowns: rows with no off-diagonal entry (and
+// no entry in their column) are decoupled, x_i = r_i / a_ii (dinv[k] = 1 / a_ii for
+// row didx[k], k < nd); the other m rows idx[0..m) (ascending; NULL: all rows, m = n)
+// are coupled only among themselves and use the dense row-major m x m inverse ainv of
+// their block.
+struct CoarseSolve {
+    int n, m, nd;
+    const int *idx;
+    const double *ainv;
+    const int *didx;
+    const double *dinv;
+};
 template <class T>
-void launch_dense_gemv(int n, const double *a, const T *x, T *y, hipStream_t s, int ncol = 1);
+void launch_coarse_solve(const CoarseSolve &cs, const T *x, T *y, hipStream_t s, int ncol = 1);
 // r32 = r / sqrt(rr[c * kScalCol]) (FP32); z = sqrt(rr[c * kScalCol]) z32 with the
 // partials of (z, q)
 void launch_to_inner(int n, const double *r, const double *rr, float *r32, hipStream_t s, int ncol = 1);

@@ -301,7 +301,8 @@ struct amg_hierarchy {
     bool own_stream = false;
     amg::Pool pool;
     std::vector<Level> lev;
-    double *ainv = nullptr;  // dense inverse of the coarsest matrix
+    double *ainv = nullptr;  // dense inverse of the coarsest matrix (of its coupled block when split)
+    amg::CoarseSolve coarse{};  // the coarsest level's exact solve
     // outer iteration vectors (finest level, solve layout)
     double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     DotBuf d_pq{}, d_rr{}, d_zq{}, d_res{};
@@ -583,21 +584,91 @@ void amg_hierarchy::build(const amg_csr &A)
                                                   big_rows, scan_tmp})
         pool.release(ptr);
 
-    // coarsest level: dense Cholesky factorisation and explicit inverse
+    // coarsest level: exact solve.  Unknowns with no off-diagonal entry in their row
+    // or column (isolated vertices, which also stall the coarsening of random graphs)
+    // are a division each; the dense Cholesky factorisation and explicit inverse are
+    // formed for the block of the others only (102 of 2,223 unknowns on the 4M-point
+    // random graph).  Levels of at most kInlineCoarse unknowns keep the whole inverse
+    // (the post-smoother applies it inline).
     Level &Lc = lev.back();
     AMG_TRACE_MSG("coarsest level %d: n=%d", levels() - 1, Lc.n);
-    if (Lc.n > opt.max_coarsest) throw Error(AMG_ERR_UNSUPPORTED, "coarsest level larger than max_coarsest");
     {
-        const size_t nn = (size_t)Lc.n * Lc.n;
-        double *dense = pool.alloc<double>(nn);
-        ainv = pool.alloc<double>(nn);
-        AMG_HIP(hipMemsetAsync(dense, 0, nn * sizeof(double), stream));
-        AMG_HIP(hipMemsetAsync(ibuf, 0, sizeof(int), stream));
-        launch_dense_from_csr(Lc.n, Lc.rp_nat, Lc.ci_nat, Lc.va_nat, dense, stream);
-        launch_cholesky_inverse(Lc.n, dense, ainv, ibuf, stream);
-        const int err = read_int(ibuf);
-        pool.release(dense);
-        if (err) throw Error(AMG_ERR_BREAKDOWN, "coarsest matrix is not positive definite");
+        const int n = Lc.n;
+        std::vector<int> crp(n + 1), cci, idx, didx;
+        std::vector<double> cva, dinv;
+        int m = n;
+        if (n > kInlineCoarse) {
+            std::vector<int> rp(n + 1), ci(Lc.nnz), cnt(n, 0), pos(n, -1);
+            std::vector<double> va(Lc.nnz);
+            to_host(rp.data(), Lc.rp_nat, n + 1);
+            to_host(ci.data(), Lc.ci_nat, Lc.nnz);
+            to_host(va.data(), Lc.va_nat, Lc.nnz);
+            for (int e = 0; e < Lc.nnz; e++) cnt[ci[e]]++;
+            for (int i = 0; i < n; i++) {
+                if (rp[i + 1] - rp[i] == 1 && ci[rp[i]] == i && cnt[i] == 1) {
+                    if (!(va[rp[i]] > 0.0)) throw Error(AMG_ERR_BREAKDOWN, "coarsest matrix is not positive definite");
+                    didx.push_back(i);
+                    dinv.push_back(1.0 / va[rp[i]]);
+                } else {
+                    pos[i] = (int)idx.size();
+                    idx.push_back(i);
+                }
+            }
+            m = (int)idx.size();
+            if (!didx.empty()) {  // the coupled block in CSR, columns renumbered
+                crp.assign(m + 1, 0);
+                for (int k = 0; k < m; k++) {
+                    const int i = idx[k];
+                    for (int e = rp[i]; e < rp[i + 1]; e++) {
+                        cci.push_back(pos[ci[e]]);
+                        cva.push_back(va[e]);
+                    }
+                    crp[k + 1] = (int)cci.size();
+                }
+            }
+        }
+        if (m > opt.max_coarsest) throw Error(AMG_ERR_UNSUPPORTED, "coarsest level larger than max_coarsest");
+        coarse = CoarseSolve{n, m, (int)didx.size(), nullptr, nullptr, nullptr, nullptr};
+        if (!didx.empty()) {
+            int *d_didx = pool.alloc<int>(didx.size());
+            double *d_dinv = pool.alloc<double>(dinv.size());
+            to_dev(d_didx, didx.data(), didx.size());
+            to_dev(d_dinv, dinv.data(), dinv.size());
+            coarse.didx = d_didx;
+            coarse.dinv = d_dinv;
+        }
+        if (m > 0) {
+            const size_t nn = (size_t)m * m;
+            double *dense = pool.alloc<double>(nn);
+            ainv = pool.alloc<double>(nn);
+            AMG_HIP(hipMemsetAsync(dense, 0, nn * sizeof(double), stream));
+            AMG_HIP(hipMemsetAsync(ibuf, 0, sizeof(int), stream));
+            int *b_rp = nullptr, *b_ci = nullptr;
+            double *b_va = nullptr;
+            if (m == n) {
+                launch_dense_from_csr(n, Lc.rp_nat, Lc.ci_nat, Lc.va_nat, dense, stream);
+            } else {
+                int *d_idx = pool.alloc<int>(m);
+                to_dev(d_idx, idx.data(), m);
+                coarse.idx = d_idx;
+                b_rp = pool.alloc<int>(m + 1);
+                b_ci = pool.alloc<int>(cci.size());
+                b_va = pool.alloc<double>(cva.size());
+                to_dev(b_rp, crp.data(), m + 1);
+                to_dev(b_ci, cci.data(), cci.size());
+                to_dev(b_va, cva.data(), cva.size());
+                launch_dense_from_csr(m, b_rp, b_ci, b_va, dense, stream);
+            }
+            launch_cholesky_inverse(m, dense, ainv, ibuf, stream);
+            const int err = read_int(ibuf);
+            pool.release(dense);
+            pool.release(b_rp);
+            pool.release(b_ci);
+            pool.release(b_va);
+            if (err) throw Error(AMG_ERR_BREAKDOWN, "coarsest matrix is not positive definite");
+            coarse.ainv = ainv;
+        }
+        AMG_TRACE_MSG("coarsest solve: %d coupled unknowns, %d decoupled", m, (int)didx.size());
     }
     AMG_TRACE_MSG("coarsest inverse done; solve layout");
     mixed = opt.precision == AMG_PREC_FP32_INNER && levels() >= 2;
@@ -794,7 +865,7 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
     Level &F = lev[k];
     const KArrays<T> &FK = F.karr<T>();
     if (k == L) {  // single-level hierarchy (FP64 only): the exact solve is the preconditioner
-        launch_dense_gemv<T>(F.n, ainv, rr, xx, stream, ncol);
+        launch_coarse_solve<T>(coarse, rr, xx, stream, ncol);
         if constexpr (std::is_same<T, double>::value) {
             if (wdot) return launch_dot(F.n, xx, wdot, d_zq, stream, ncol);
         }
@@ -839,7 +910,7 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
             mode = 3;
             edirect = CK.rc;
         } else {
-            launch_dense_gemv<T>(C.n, ainv, CK.rc, CK.c1, stream, ncol);
+            launch_coarse_solve<T>(coarse, CK.rc, CK.c1, stream, ncol);
             mode = 0;
             edirect = CK.c1;
         }

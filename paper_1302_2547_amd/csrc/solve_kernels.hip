@@ -19,6 +19,8 @@
 // leave the device, so the K-cycle has no host round trip.
 #include "amg_internal.h"
 
+#include <algorithm>
+
 namespace amg {
 namespace {
 
@@ -986,31 +988,46 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const
     }
 }
 
-// Y = A X for a dense row-major n x n A and CB right-hand sides per block (column
-// c0 + c of X at x + (c0 + c) n): one wavefront per row, lanes across the row, so
-// A is read once for CB columns.
+// Y = A_c^-1 X on the coarsest level for CB right-hand sides per block (see
+// CoarseSolve): the block stages the coupled entries of its columns in LDS, then
+// one wavefront per coupled row (lanes across the row) reads the row of the inverse
+// once for all CB columns; decoupled rows are a division each.
 template <class T, int CB>
-__global__ void __launch_bounds__(kBlock) k_dense_gemm(int n, int ncol, const double *__restrict__ a,
-                                                       const T *__restrict__ x, T *__restrict__ y)
+__global__ void __launch_bounds__(kBlock) k_coarse_solve(CoarseSolve cs, int ncol, const T *__restrict__ x,
+                                                         T *__restrict__ y)
 {
+    extern __shared__ double xs[];  // CB x m
+    const int n = cs.n, m = cs.m;
     const int c0 = blockIdx.y * CB;
+    const int nc = ncol - c0 < CB ? ncol - c0 : CB;
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < cs.nd * nc; e += gridDim.x * kBlock) {
+        const int c = e / cs.nd, k = e - c * cs.nd;
+        const size_t at = (size_t)(c0 + c) * n + cs.didx[k];
+        y[at] = (T)((double)x[at] * cs.dinv[k]);
+    }
+    if (m == 0) return;
+    for (int e = threadIdx.x; e < CB * m; e += kBlock) {
+        const int c = e / m, j = e - c * m;
+        xs[e] = c < nc ? (double)x[(size_t)(c0 + c) * n + (cs.idx ? cs.idx[j] : j)] : 0.0;
+    }
+    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     const int nw = gridDim.x * (kBlock / kWave);
-    for (int i = (blockIdx.x * kBlock + threadIdx.x) / kWave; i < n; i += nw) {
-        double s[CB];
+    for (int i = (blockIdx.x * kBlock + threadIdx.x) / kWave; i < m; i += nw) {
+        const double *row = cs.ainv + (size_t)i * m;
+        double acc[CB];
 #pragma unroll
-        for (int c = 0; c < CB; c++) s[c] = 0.0;
-        const double *row = a + (size_t)i * n;
-        for (int j = lane; j < n; j += kWave) {
-            const double aij = row[j];
+        for (int c = 0; c < CB; c++) acc[c] = 0.0;
+        for (int j = lane; j < m; j += kWave) {
+            const double a = row[j];
 #pragma unroll
-            for (int c = 0; c < CB; c++)
-                if (c0 + c < ncol) s[c] += aij * (double)x[(size_t)(c0 + c) * n + j];
+            for (int c = 0; c < CB; c++) acc[c] += a * xs[c * m + j];
         }
+        const int dst = cs.idx ? cs.idx[i] : i;
 #pragma unroll
         for (int c = 0; c < CB; c++) {
-            const double t = wave_sum(s[c]);
-            if (lane == 0 && c0 + c < ncol) y[(size_t)(c0 + c) * n + i] = (T)t;
+            const double t = wave_sum(acc[c]);
+            if (lane == 0 && c < nc) y[(size_t)(c0 + c) * n + dst] = (T)t;
         }
     }
 }
@@ -1419,11 +1436,23 @@ bool build_tail_layout(int n, const int *rp, const int *ci, const double *va, st
 }
 
 template <class T>
-void launch_dense_gemv(int n, const double *a, const T *x, T *y, hipStream_t s, int ncol)
+void launch_coarse_solve(const CoarseSolve &cs, const T *x, T *y, hipStream_t s, int ncol)
 {
-    // one right-hand side per block row: measured faster than several per block
-    // (more waves in flight; the inverse is re-read from L2/MALL)
-    k_dense_gemm<T, 1><<<dim3(grid_for((int64_t)n * kWave), ncol), kBlock, 0, s>>>(n, ncol, a, x, y);
+    // columns per block: the staged columns take at most 64 KiB of LDS
+    int cb = 1;
+    while (cb < 16 && cb < ncol && (size_t)(2 * cb) * cs.m * sizeof(double) <= 65536) cb *= 2;
+    const int rows_blocks = cs.m > 0 ? (cs.m + kBlock / kWave - 1) / (kBlock / kWave) : 1;
+    const int dec_blocks = (cs.nd * cb + kBlock - 1) / kBlock;
+    const int gx = std::max(1, std::min(1024, std::max(rows_blocks, dec_blocks)));
+    const dim3 grid(gx, (ncol + cb - 1) / cb);
+    const size_t lds = (size_t)cb * cs.m * sizeof(double);
+    switch (cb) {
+    case 1: k_coarse_solve<T, 1><<<grid, kBlock, lds, s>>>(cs, ncol, x, y); break;
+    case 2: k_coarse_solve<T, 2><<<grid, kBlock, lds, s>>>(cs, ncol, x, y); break;
+    case 4: k_coarse_solve<T, 4><<<grid, kBlock, lds, s>>>(cs, ncol, x, y); break;
+    case 8: k_coarse_solve<T, 8><<<grid, kBlock, lds, s>>>(cs, ncol, x, y); break;
+    default: k_coarse_solve<T, 16><<<grid, kBlock, lds, s>>>(cs, ncol, x, y); break;
+    }
     AMG_HIP(hipGetLastError());
 }
 
@@ -1463,7 +1492,7 @@ void launch_to_float(int64_t n, const double *src, float *dst, hipStream_t s)
     template void launch_post_direct<T>(Rows, const int *, const T *, const T *, const T *, const T *, KDots,       \
                                         DotRef, DotRef, const double *, T *, T *, int *, int, bool, hipStream_t,    \
                                         int);                                                                       \
-    template void launch_dense_gemv<T>(int, const double *, const T *, T *, hipStream_t, int);                     \
+    template void launch_coarse_solve<T>(const CoarseSolve &, const T *, T *, hipStream_t, int);                   \
     template void launch_tail_visit<T>(const TailLayout &, const T *, const T *, const double *, const double *,    \
                                        const T *, T *, T *, double *, double *, int *, hipStream_t, int);
 AMG_INSTANTIATE(double)

@@ -316,3 +316,56 @@ def test_smoother_options_are_validated(amg):
     with pytest.raises(amg.AmgError) as e:
         amg.Hierarchy(dev(rp), dev(ci), dev(va), smoother=5)
     assert e.value.status == amg.AMG_ERR_UNSUPPORTED
+
+
+def grid_plus_isolated(side=24, isolated=300, seed=9):
+    """A jittered side x side grid Laplacian and `isolated` vertices with only a
+    diagonal entry (1 + u), numbered in a seeded random order: the isolated vertices
+    never coarsen, so the hierarchy stalls with a coarsest level that holds all of
+    them and a few coupled unknowns."""
+    rp, ci, va = inputs.grid_laplacian((side, side), jitter=0.2, seed=seed)
+    n0 = len(rp) - 1
+    n = n0 + isolated
+    dense_rows = [list(zip(ci[rp[i]:rp[i + 1]], va[rp[i]:rp[i + 1]])) for i in range(n0)]
+    u = inputs.uniform(seed, np.arange(isolated))
+    dense_rows += [[(n0 + k, 1.0 + u[k])] for k in range(isolated)]
+    perm = np.argsort(inputs.uniform(seed + 1, np.arange(n)))  # new index -> old index
+    inv = np.empty(n, np.int64)
+    inv[perm] = np.arange(n)
+    rows = [sorted((int(inv[j]), v) for j, v in dense_rows[perm[i]]) for i in range(n)]
+    rp2 = np.zeros(n + 1, np.int32)
+    rp2[1:] = np.cumsum([len(r) for r in rows])
+    ci2 = np.array([j for r in rows for j, _ in r], np.int32)
+    va2 = np.array([v for r in rows for _, v in r])
+    return rp2, ci2, va2
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_inner"])
+def test_coarsest_with_decoupled_unknowns(amg, precision):
+    """The coarsest level (beyond the inline size) holds isolated vertices, solved by
+    division, and coupled unknowns, solved through the inverse of their block: the
+    K-cycle matches the oracle's (dense Cholesky of the whole coarsest matrix) and
+    batched solves reach the tolerance."""
+    rp, ci, va = grid_plus_isolated()
+    n = len(rp) - 1
+    prec = amg.AMG_PREC_FP64 if precision == "fp64" else amg.AMG_PREC_FP32_INNER
+    h = amg.Hierarchy(dev(rp), dev(ci), dev(va), precision=prec, max_rhs=3)
+    ref = oracle.Hierarchy(rp, ci, va)
+    assert_same_hierarchy(h, ref)
+    c = ref.level(ref.num_levels - 1)
+    lens = np.diff(c.row_ptr)
+    assert c.n > 64 and (lens == 1).sum() >= 290 and (lens > 1).sum() > 0
+    xv = inputs.rhs(n, 41)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.kcycle(dev(xv), z)
+    zo = ref.kcycle(xv)
+    bound = 1e-10 if precision == "fp64" else 2e-5
+    assert np.abs(z.cpu().numpy() - zo).max() <= bound * np.abs(zo).max()
+    B = torch.from_numpy(np.stack([inputs.rhs(n, 50 + k) for k in range(3)])).cuda()
+    X = torch.zeros_like(B)
+    st, infos = h.solve_batch(B, X, tol=1e-9)
+    assert st == amg.AMG_OK
+    for k in range(3):
+        r = B[k].cpu().numpy() - oracle.spmv(rp, ci, va, X[k].cpu().numpy())
+        assert np.linalg.norm(r) / np.linalg.norm(B[k].cpu().numpy()) <= 1e-9
+    h.close()
