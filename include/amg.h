@@ -79,6 +79,10 @@ typedef struct {
                                 /* work vectors are sized n_l * max_rhs on every level       */
     int32_t smoother;           /* amg_smoother of every level (default AMG_SMOOTHER_L1)     */
     double jacobi_weight;       /* omega of AMG_SMOOTHER_JACOBI, finite and > 0 (def. 2/3)  */
+    int32_t autotune;           /* 1: at the first solve, time the candidate lanes per row   */
+                                /* of levels >= 100k rows and keep the fastest (cached per  */
+                                /* level shape and right-hand-side count; default);         */
+                                /* 0: lanes from the mean row length                        */
 } amg_options;
 
 typedef struct {

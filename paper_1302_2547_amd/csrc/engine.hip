@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <new>
 #include <type_traits>
@@ -441,6 +442,11 @@ struct amg_hierarchy {
     void run_first(int ncol);
     void run_iter(int ncol);
     void capture_graphs(int ncol);
+    // lanes per row of the bandwidth-bound levels, by measurement (once per hierarchy)
+    bool tuned = false;
+    void autotune(int ncol);
+    template <class T>
+    void autotune_level(int l, int ncol);
     amg_status solve(int ncol, const double *b_user, int ldb, double *x_user, int ldx, double tol,
                      amg_solve_info *info);
 };
@@ -1000,6 +1006,115 @@ void amg_hierarchy::run_iter(int ncol)
 // Records the three pieces once per hierarchy and batch width; every launch
 // argument (buffers, partial-set sizes) is fixed by the level sizes, so the graphs
 // stay valid.
+// ---------------------------------------------------------------- lane-count autotuner
+// On levels of at least kSmallLevel rows (bandwidth-bound) the lanes per row of A (G,
+// used by the SpMVs and smoothers) and of the super-rows (Gs, used by the restriction)
+// are chosen by measurement: each candidate launch of the post-smoother and of the
+// restriction is timed with HIP events on the hierarchy's stream (one warm-up launch,
+// then kTuneReps), and the fastest wins.  The rows table does not depend on the choice
+// (rows beyond its hub threshold are served by chunks whatever G is).  Choices are cached
+// for the process by (level rows, entries, right-hand sides, storage type, operator), so
+// later hierarchies of the same shape skip the measurement.
+namespace {
+constexpr int kTuneReps = 3;
+struct TuneCache {
+    std::mutex mu;
+    std::map<std::tuple<int, int, int, int, int>, int> best;
+    static TuneCache &get()
+    {
+        static TuneCache c;
+        return c;
+    }
+};
+}  // namespace
+
+template <class T>
+void amg_hierarchy::autotune_level(int l, int ncol)
+{
+    using namespace amg;
+    Level &F = lev[l], &C = lev[l + 1];
+    const KArrays<T> &FK = F.karr<T>();
+    const KArrays<T> &CK = C.karr<T>();
+    // vectors of this level: the work vectors of a coarse level, the outer ones on level 0
+    const T *rv;
+    T *out;
+    if (l == 0) {
+        if constexpr (std::is_same<T, float>::value) {
+            rv = r32;
+            out = z32;
+        } else {
+            rv = r;
+            out = z;
+        }
+    } else {
+        rv = FK.rt;
+        out = FK.v1;
+    }
+    struct Events {  // the solve's own events time the solve
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    AMG_HIP(hipEventCreate(&ev.a));
+    AMG_HIP(hipEventCreate(&ev.b));
+    auto timed = [&](auto &&launch) {
+        launch();
+        AMG_HIP(hipEventRecord(ev.a, stream));
+        for (int k = 0; k < kTuneReps; k++) launch();
+        AMG_HIP(hipEventRecord(ev.b, stream));
+        AMG_HIP(hipEventSynchronize(ev.b));
+        float ms = 0.f;
+        AMG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+        return ms;
+    };
+    auto pick = [&](int kind, double avg_len, int current, auto &&launch_with) {
+        const auto key = std::make_tuple(F.n, F.nnz, ncol, (int)sizeof(T), kind);
+        {
+            TuneCache &c = TuneCache::get();
+            std::lock_guard<std::mutex> lk(c.mu);
+            const auto it = c.best.find(key);
+            if (it != c.best.end()) return it->second;
+        }
+        int best = current;
+        float best_ms = 0.f;
+        for (int g = 2; g <= 32; g *= 2) {
+            if (g > 2 * avg_len + 2 && g != current) continue;  // most lanes would idle
+            const float ms = timed([&] { launch_with(g); });
+            if (best_ms == 0.f || ms < best_ms) {
+                best_ms = ms;
+                best = g;
+            }
+        }
+        TuneCache &c = TuneCache::get();
+        std::lock_guard<std::mutex> lk(c.mu);
+        c.best[key] = best;
+        return best;
+    };
+    // post-smoother with a directly given correction (no inner products read or written)
+    F.G = pick(0, (double)F.nnz / F.n, F.G, [&](int g) {
+        launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rv, F.agg_pos, F.cagg, 0, CK.c1, nullptr, nullptr, KDots{},
+                              out, nullptr, DotBuf{}, flag, g, stream, ainv, C.n, ncol);
+    });
+    F.Gs = pick(1, (double)F.nnz / C.n, F.Gs, [&](int g) {
+        launch_restrict<T>(F.S, F.n, F.sci, FK.wv, rv, CK.rc, g, stream, nullptr, DotBuf{}, ncol);
+    });
+    AMG_TRACE_MSG("autotune level %d (%d right-hand sides): G=%d Gs=%d", l, ncol, F.G, F.Gs);
+}
+
+void amg_hierarchy::autotune(int ncol)
+{
+    if (tuned || !opt.autotune) return;
+    tuned = true;
+    for (int l = 0; l + 1 < levels(); l++) {
+        if (lev[l].n < amg::kSmallLevel || lev[l].omega) continue;
+        if (mixed) autotune_level<float>(l, ncol);
+        else autotune_level<double>(l, ncol);
+    }
+}
+
 void amg_hierarchy::capture_graphs(int ncol)
 {
     // The K-cycle visits level k 2^k times, so its graph has about 6 (2^L - 1)
@@ -1048,6 +1163,7 @@ amg_status amg_hierarchy::solve(int ncol, const double *b_user, int ldb, double 
     const int n = F.n;
     AMG_TRACE_MSG("solve: start (%d right-hand sides)", ncol);
     AMG_HIP(hipEventRecord(ev0, stream));
+    autotune(ncol);
     capture_graphs(ncol);
     AMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
     launch_gather(n, b_user, uperm, b, stream, ncol, ldb, n);
@@ -1190,6 +1306,7 @@ void amg_default_options(amg_options *opt)
     opt->max_rhs = 1;
     opt->smoother = AMG_SMOOTHER_L1;
     opt->jacobi_weight = 2.0 / 3.0;
+    opt->autotune = 1;
 }
 
 amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy **out)
@@ -1376,6 +1493,7 @@ amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z)
     if (!device_array(r) || !device_array(z)) return AMG_ERR_INVALID_ARGUMENT;
     return guarded([&]() {
         const Level &F = h->lev[0];
+        h->autotune(1);
         h->capture_graphs(1);
         AMG_HIP(hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
         amg::launch_gather(F.n, r, h->uperm, h->r, h->stream);

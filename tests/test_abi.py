@@ -41,7 +41,7 @@ def test_host_only_paths(lib):
     o = amg.default_options()
     assert o.coarsest_size == 64 and o.max_levels == 40 and o.kcycle_inner == 2
     assert abs(o.stall_ratio - 0.9) < 1e-15 and o.max_iters == 200 and o.precision == amg.AMG_PREC_FP64
-    assert o.smoother == amg.AMG_SMOOTHER_L1 and o.jacobi_weight == 2.0 / 3.0
+    assert o.smoother == amg.AMG_SMOOTHER_L1 and o.jacobi_weight == 2.0 / 3.0 and o.autotune == 1
     assert amg.amg_status_string(amg.AMG_ERR_BREAKDOWN) == b"AMG_ERR_BREAKDOWN"
     # argument errors are reported before any device work
     out = ctypes.c_void_p(123)

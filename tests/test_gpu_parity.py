@@ -369,3 +369,25 @@ def test_coarsest_with_decoupled_unknowns(amg, precision):
         r = B[k].cpu().numpy() - oracle.spmv(rp, ci, va, X[k].cpu().numpy())
         assert np.linalg.norm(r) / np.linalg.norm(B[k].cpu().numpy()) <= 1e-9
     h.close()
+
+
+def test_autotuned_lanes_are_cached_and_converge(amg):
+    """Levels of at least 100k rows take their lanes per row from a timing of the
+    candidates at the first solve.  A second hierarchy of the same shape reuses the
+    cached choice, so its solution is bitwise the first one's; with autotune = 0 the
+    solve reaches the same tolerance."""
+    rp, ci, va = inputs.grid_laplacian((80, 80, 80), jitter=0.1, seed=3)
+    n = len(rp) - 1
+    b = inputs.rhs(n, 5)
+    sols = []
+    for tune in (1, 1, 0):
+        print(f"[parity] autotune={tune}", flush=True)
+        h = amg.Hierarchy(dev(rp), dev(ci), dev(va), autotune=tune)
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        st, info = h.solve(dev(b), x, tol=1e-9)
+        xs = x.cpu().numpy()
+        r = b - oracle.spmv(rp, ci, va, xs)
+        assert st == amg.AMG_OK and np.linalg.norm(r) / np.linalg.norm(b) <= 1e-9
+        sols.append(xs)
+        h.close()
+    np.testing.assert_array_equal(sols[0], sols[1])
