@@ -176,10 +176,11 @@ amg_status amg_spmv(amg_hierarchy *h, int32_t level, const double *x, double *y)
  * (Sec. 4.3), device vectors of length n in the natural numbering. */
 amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z);
 
-/* Average device time in microseconds of the finest-level post-smoothing kernel
- * (the fused prolongation + l1-Jacobi sweep, the solve's dominant kernel),
- * measured with events over `reps` back-to-back launches on the hierarchy's
- * stream; *bytes receives its algorithmic DRAM traffic per launch. */
+/* Average device time in microseconds of the finest level's post-smoothing step
+ * (prolongation of the coarse correction + one smoothing sweep, Sec. 4.2-4.3;
+ * two launches on levels of at least 100k rows, one fused launch below),
+ * measured with events over `reps` back-to-back steps on the hierarchy's stream;
+ * *bytes receives the step's algorithmic DRAM traffic. */
 amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, double *bytes);
 
 /* Human-readable name of a status code (static storage). */

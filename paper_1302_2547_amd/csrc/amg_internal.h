@@ -217,12 +217,13 @@ void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int
 // 1: e = (alpha1/rho1) c1; 2: e = a1 c1 + a2 c2; 3: e = ainv * edirect, a dense
 // coarsest solve of size nc <= kInlineCoarse done in the kernel); returns
 // (out, wdot) if wdot.  nc is the coarse level's size (the leading dimension of
-// edirect, c1, c2).
+// edirect, c1, c2).  xtmp (FP64, n per right-hand side, or NULL): on levels of at
+// least kSmallLevel rows the step is then split in two launches through it.
 template <class T>
 DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, const T *r, const int *agg_pos,
                           const int *cagg, int mode, const T *edirect, const T *c1, const T *c2, KDots kd, T *xout,
                           const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv, int nc,
-                          int ncol = 1);
+                          int ncol = 1, double *xtmp = nullptr);
 // Exact solve on a coarsest level of n unknowns: rows with no off-diagonal entry (and
 // no entry in their column) are decoupled, x_i = r_i / a_ii (dinv[k] = 1 / a_ii for
 // row didx[k], k < nd); the other m rows idx[0..m) (ascending; NULL: all rows, m = n)

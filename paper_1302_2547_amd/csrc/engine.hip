@@ -256,6 +256,7 @@ struct Level {
     int *agg_pos = nullptr, *seg_ptr = nullptr, *srp = nullptr;  // all but the coarsest level
     int *cagg = nullptr;                                         // coarse unknown of each entry's column
     int *sci = nullptr;  // columns of the super-rows of P^T A (the same array as ci unless level 0 is natural)
+    double *xs = nullptr;  // FP64 iterate of the split post-smoothing (levels >= kSmallLevel rows), n per column
     int G = 2, Gs = 2;
     Rows A{}, S{};  // rows of A and super-rows of P^T A, each with its hub-row chunks
     // work vectors and dot sites when this level is the coarse level of a visit
@@ -757,6 +758,7 @@ void amg_hierarchy::finalize_layout()
                 uperm = nullptr;
                 AMG_TRACE_MSG("layout level 0: natural numbering, hub rows=%d", F.A.nlong);
             }
+            if (F.n >= kSmallLevel) F.xs = pool.alloc<double>((size_t)F.n * nr);
             if (F.n < kSmallLevel) {
                 F.cagg = pool.alloc<int>(F.nnz);
                 launch_entry_coarse_column(F.nnz, F.ci, F.agg_pos, F.cagg, stream);
@@ -946,7 +948,7 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
     }
     if (k == 0) kd0 = kd;
     return launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rr, F.agg_pos, F.cagg, mode, edirect, CK.c1, CK.c2, kd, xx,
-                                 wdot, k == 0 ? d_zq : DotBuf{}, flag, F.G, stream, ainv, C.n, ncol);
+                                 wdot, k == 0 ? d_zq : DotBuf{}, flag, F.G, stream, ainv, C.n, ncol, F.xs);
 }
 
 // One outer iteration is split in three replayable pieces:
@@ -1096,7 +1098,7 @@ void amg_hierarchy::autotune_level(int l, int ncol)
     // post-smoother with a directly given correction (no inner products read or written)
     F.G = pick(0, (double)F.nnz / F.n, F.G, [&](int g) {
         launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rv, F.agg_pos, F.cagg, 0, CK.c1, nullptr, nullptr, KDots{},
-                              out, nullptr, DotBuf{}, flag, g, stream, ainv, C.n, ncol);
+                              out, nullptr, DotBuf{}, flag, g, stream, ainv, C.n, ncol, F.xs);
     });
     F.Gs = pick(1, (double)F.nnz / C.n, F.Gs, [&](int g) {
         launch_restrict<T>(F.S, F.n, F.sci, FK.wv, rv, CK.rc, g, stream, nullptr, DotBuf{}, ncol);
@@ -1520,11 +1522,11 @@ amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, dou
             if (h->mixed) {
                 amg::launch_post_smooth<float>(F.A, F.ci, F.k32.va, F.k32.minv, h->r32, F.agg_pos, F.cagg, mode,
                                                nullptr, C.k32.c1, C.k32.c2, h->kd0, h->z32, nullptr, DotBuf{}, h->flag,
-                                               F.G, h->stream, h->ainv, C.n);
+                                               F.G, h->stream, h->ainv, C.n, 1, F.xs);
             } else {
                 amg::launch_post_smooth<double>(F.A, F.ci, F.va, F.minv, h->r, F.agg_pos, F.cagg, mode, nullptr, C.c1,
                                                 C.c2, h->kd0, h->z, nullptr, DotBuf{}, h->flag, F.G, h->stream,
-                                                h->ainv, C.n);
+                                                h->ainv, C.n, 1, F.xs);
             }
         };
         launch();

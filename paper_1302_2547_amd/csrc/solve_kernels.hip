@@ -725,6 +725,70 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
     if (DOT) store_partials<1>(dsum, part);
 }
 
+// Large levels split the same step in two launches, so that each entry gathers one
+// value instead of five (the fused form recomputes x_t = M^-1 r_t + (P e)_t for every
+// entry that references column t, which at 128^3 and above is bound by the gathers):
+//   k_smooth_start:  x = M^-1 r + P e, one row per thread, stored in FP64;
+//   k_smooth_finish: out = x + M^-1 (r - A x), with the partials of (out, wdot).
+template <class T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_smooth_start(int n, const T *__restrict__ minv,
+                                                         const T *__restrict__ r,
+                                                         const int *__restrict__ agg_pos,
+                                                         const T *__restrict__ edirect,
+                                                         const T *__restrict__ c1,
+                                                         const T *__restrict__ c2, KDots kd,
+                                                         double *__restrict__ x, int *__restrict__ flag, int nc)
+{
+    r = colv(r, n);
+    x = colv(x, n);
+    edirect = colv(edirect, nc);
+    c1 = colv(c1, nc);
+    c2 = colv(c2, nc);
+    const KCoef c = kcycle_coefficients<false>(MODE, kd);
+    if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int J = agg_pos[i];
+        double e;
+        if (MODE == 0) e = (double)edirect[J];
+        else if (MODE == 1) e = c.a1 * (double)c1[J];
+        else e = c.a1 * (double)c1[J] + c.a2 * (double)c2[J];
+        x[i] = (double)minv[i] * (double)r[i] + e;
+    }
+}
+
+template <class T, int G, bool DOT>
+__global__ void __launch_bounds__(kBlock) k_smooth_finish(Rows R, const int *__restrict__ ci,
+                                                          const T *__restrict__ va,
+                                                          const T *__restrict__ minv,
+                                                          const T *__restrict__ r,
+                                                          const double *__restrict__ x, T *__restrict__ xout,
+                                                          const T *__restrict__ wdot, double *__restrict__ part)
+{
+    r = colv(r, R.n);
+    x = colv(x, R.n);
+    xout = colv(xout, R.n);
+    wdot = colv(wdot, R.n);
+    part = colp(part);
+    struct Pre {
+        double mr, rr, xr, wd;
+    };
+    double dsum[1] = {0.0};
+    const int nb = gridDim.x;
+    visit_rows<G, false>(
+        R, AMG_NO_PROLOGUE,
+        [&](int row) { return Pre{(double)minv[row], (double)r[row], x[row], DOT ? (double)wdot[row] : 0.0}; },
+        AMG_SAME, [&](int p) { return (double)va[p] * x[ci[p]]; },
+        [&](int row, double s, int k, const Pre &v) {
+            const double o = v.xr + v.mr * (v.rr - s);
+            xout[row] = (T)o;
+            if (DOT) {
+                if (k < 0) dsum[0] += o * v.wd;
+                else part[nb + k] = o * v.wd;
+            }
+        });
+    if (DOT) store_partials<1>(dsum, part);
+}
+
 // Post-smoothing on a level whose coarse level is a single unknown.  P is then
 // the all-ones column and the restriction W = P^T (I - A M^-1) is the row vector
 // om^T, om_j = 1 - minv_j sum_i a_ij, so rc = (om, r) is an inner product whose
@@ -1321,10 +1385,33 @@ template <class T>
 DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, const T *r, const int *agg_pos,
                           const int *cagg, int mode, const T *edirect, const T *c1, const T *c2, KDots kd, T *xout,
                           const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv, int nc,
-                          int ncol)
+                          int ncol, double *xtmp)
 {
     const bool dot = wdot != nullptr;
     const dim3 grid(rows_grid(R, G, dot ? kMaxDotBlocks : (1 << 20)), ncol);
+    if (xtmp && !cagg && R.n >= kSmallLevel && mode >= 0 && mode <= 2) {  // two launches, see k_smooth_start
+        const dim3 g1(grid_for(R.n, 1 << 16), ncol);
+#define AMG_START(M) k_smooth_start<T, M><<<g1, kBlock, 0, s>>>(R.n, minv, r, agg_pos, edirect, c1, c2, kd, xtmp, flag, nc)
+        switch (mode) {
+        case 0: AMG_START(0); break;
+        case 1: AMG_START(1); break;
+        default: AMG_START(2); break;
+        }
+#undef AMG_START
+        AMG_HIP(hipGetLastError());
+        if (dot) {
+            AMG_SWITCH_G(G, (k_smooth_finish<T, kG, true><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, xtmp, xout, wdot,
+                                                                                buf.part)));
+        } else {
+            AMG_SWITCH_G(G, (k_smooth_finish<T, kG, false><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, xtmp, xout, wdot,
+                                                                                 buf.part)));
+        }
+        AMG_HIP(hipGetLastError());
+        if (!dot) return DotRef{nullptr, 0};
+        const int count = (int)grid.x + R.nlong;
+        reduce_if_large(1, buf.part, count, buf.final_out, s, ncol);
+        return finished(buf.part, count, buf.final_out, 0);
+    }
 #define AMG_POST(M, D)                                                                                         \
     do {                                                                                                       \
         if (cagg) {                                                                                            \
@@ -1486,7 +1573,7 @@ void launch_to_float(int64_t n, const double *src, float *dst, hipStream_t s)
     template void launch_inner_residual<T>(int, const T *, const T *, KDots, T *, int *, hipStream_t, int);         \
     template DotRef launch_post_smooth<T>(Rows, const int *, const T *, const T *, const T *, const int *,          \
                                           const int *, int, const T *, const T *, const T *, KDots, T *, const T *, \
-                                          DotBuf, int *, int, hipStream_t, const double *, int, int);               \
+                                          DotBuf, int *, int, hipStream_t, const double *, int, int, double *);     \
     template DotRef launch_restrict_rt<T>(Rows, int, const int *, const T *, const T *, const T *, KDots, T *, T *, \
                                           int *, int, hipStream_t, const double *, DotBuf, int);                    \
     template void launch_post_direct<T>(Rows, const int *, const T *, const T *, const T *, const T *, KDots,       \
