@@ -116,11 +116,12 @@ class Server:
         return 12 * nnz + 4 * req.n + 16 * req.n * len(req.rhs_seeds)
 
     # a hierarchy's bytes before it exists: measured figures of this library are
-    # about 110 bytes per unknown and 56 per stored entry with 8 right-hand sides
+    # about 110 bytes per unknown and 56 per stored entry with 8 right-hand sides,
+    # plus an FP64 iterate per right-hand side on the levels of at least 100k rows
     @staticmethod
     def hierarchy_estimate(req: Request, max_rhs: int) -> int:
         nnz = (2 * len(req.dims) + 1) * req.n
-        return 56 * nnz + (60 + 6 * max_rhs) * req.n + (64 << 20)
+        return 56 * nnz + (60 + 17 * max_rhs) * req.n + (64 << 20)
 
     def _evict(self, need: int):
         """Drop least recently used idle hierarchies until `need` more bytes fit."""
@@ -209,7 +210,9 @@ class Server:
                     # hierarchy is later used from other slots, and work of another slot
                     # on this slot's stream would mix with, or break, a graph this slot
                     # is capturing
-                    h = amg.Hierarchy(rp, ci, va, precision=self.precision, max_rhs=self.max_rhs)
+                    # no lane-count autotuning: most requests bring a new shape, and the
+                    # measurement would add to their latency
+                    h = amg.Hierarchy(rp, ci, va, precision=self.precision, max_rhs=self.max_rhs, autotune=0)
                     del rp, ci, va
                 k = len(req.rhs_seeds)
                 B = torch.empty((k, req.n), dtype=torch.float64, device="cuda")
