@@ -27,6 +27,9 @@ CASES = {
     "grid3d_24_jitter": lambda: inputs.grid_laplacian((24, 24, 24), jitter=0.1, seed=2),
     "grid2d_64_single_coarse": lambda: inputs.grid_laplacian((64, 64)),
     "rgg_20k": lambda: inputs.rgg_laplacian(20000, seed=3, weight_range=(0.5, 1.5)),
+    # 125k rows: the finest level takes the large-level path (split post-smoothing,
+    # lane counts timed for 8 columns)
+    "grid3d_50_jitter": lambda: inputs.grid_laplacian((50, 50, 50), jitter=0.1, seed=4),
 }
 OPTS = {"grid2d_64_single_coarse": {"coarsest_size": 1}}
 
