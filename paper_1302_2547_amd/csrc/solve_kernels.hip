@@ -897,6 +897,17 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const
     c2 = colv(c2, n);
     d1 = colp(d1);
     d2 = colp(d2);
+    // The owned rows' rc, M^-1 and om are loaded first (clamped indices, no
+    // branches) and the entries after them, so that the first block sum, which
+    // needs only the former, overlaps the arrival of the entries.
+    double o[R], rv[R], mv[R];
+#pragma unroll
+    for (int u = 0; u < R; u++) {
+        const int i = t + u * kTailThreads < n ? t + u * kTailThreads : n - 1;
+        rv[u] = (double)rc[i];
+        mv[u] = (double)minv[i];
+        o[u] = om[i];
+    }
     int ci[S];
     double a[S];
 #pragma unroll
@@ -907,21 +918,14 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const
     // first row index of this wavefront's lanes (row slots of u are all padding
     // for the whole wavefront when u * kTailThreads + wbase >= n)
     const int wbase = __builtin_amdgcn_readfirstlane(t & ~(kWave - 1));
-    double o[R];
     double q[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int u = 0; u < R; u++) {
         const int i = t + u * kTailThreads;
-        double rv = 0.0, mv = 0.0;
-        o[u] = 0.0;
-        if (i < n) {
-            rv = (double)rc[i];
-            mv = (double)minv[i];
-            o[u] = om[i];
-        }
-        rs[i] = rv;
-        ms[i] = mv;
-        q[0] += o[u] * rv;
+        if (i >= n) rv[u] = mv[u] = o[u] = 0.0;
+        rs[i] = rv[u];
+        ms[i] = mv[u];
+        q[0] += o[u] * rv[u];
     }
     const double acinv = ainv[0];
     // y = (A xs) at the owned rows; the sums of long rows are block sums (whose
