@@ -4,7 +4,9 @@
 // Device memory is owned by one pool per hierarchy; a failed setup releases
 // everything it allocated.  All work is ordered on one HIP stream; the host
 // waits on it only where it needs a value: the per-pass count of processed
-// vertices, level sizes, and the outer residual norm.
+// vertices, level sizes, the small levels it lays out itself (the coarsest
+// level's split solve, the level above a single coarse unknown), the lane-count
+// timings of the first solve, and the outer residual norm.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,9 +17,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
-#include <tuple>
 #include <mutex>
 #include <new>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 

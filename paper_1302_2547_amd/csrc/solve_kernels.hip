@@ -1,12 +1,14 @@
 // solve_kernels.hip -- gfx950 kernels of the solve phase (Sec. 4).
 //
-// All matrices are CSR in the nested aggregate order of their level, so the
+// Coarse matrices are CSR in the nested aggregate order of their level, so the
 // aggregate of coarse unknown Q is the contiguous range seg_ptr[Q] .. seg_ptr[Q+1]
 // of fine rows, and its rows' entries form the contiguous "super-row" srp[Q] ..
-// srp[Q+1] of P^T A.
+// srp[Q+1] of P^T A.  The finest level keeps the caller's numbering for A; its
+// super-rows are a separate copy of the entries grouped by aggregate.
 //
 // Row mapping.  A group of G lanes (G | 64) serves one ordinary row, G chosen per
-// level from the mean row length so the column/value streams stay coalesced.
+// level from the mean row length (or timed, on large levels) so the column/value
+// streams stay coalesced.
 // Coarse levels of 3D problems contain hub rows with thousands of entries; rows
 // longer than R.lim are cut into chunks of at most kChunk entries, one block per
 // chunk; the last chunk of a row to finish adds the chunk sums in chunk order and
