@@ -480,7 +480,7 @@ void amg_hierarchy::build(const amg_csr &A)
         AMG_HIP(hipMemcpyAsync(L0.va_nat, A.values, sizeof(double) * (size_t)nnz0, hipMemcpyDeviceToDevice, stream));
     }
     // setup scratch, sized by the finest level and released at the end of setup
-    int *ibuf = pool.alloc<int>(16);  // 0 err, 1 done, 2 big_count, 3 nc, 4 total, 5 nnz_c
+    int *ibuf = pool.alloc<int>(16);  // 0 err, 1 done, 2 big_count, 3 nc, 4 total, 5 nnz_c, 8.. pass counts
     uint64_t *key = pool.alloc<uint64_t>(n0);
     uint64_t *m1 = pool.alloc<uint64_t>(n0);
     int *owner = pool.alloc<int>(n0);
@@ -518,15 +518,28 @@ void amg_hierarchy::build(const amg_csr &A)
         launch_long_rows(n, lev[l].rp_nat, lim, tptr, nullptr, tptr + n, scan_tmp, stream);
         const int nhub = read_int(tptr + n);
         if (nhub > 0) launch_long_rows(n, lev[l].rp_nat, lim, tptr, big_rows, nullptr, scan_tmp, stream);
+        // Passes are launched kPassBatch at a time and the processed count after each
+        // is read back once per batch: a pass over a fully processed level changes
+        // nothing, so the passes past the last useful one are no-ops, and the count
+        // of useful passes is exact.
+        constexpr int kPassBatch = 4;
+        unsigned *after = reinterpret_cast<unsigned *>(ibuf + 8);
+        unsigned after_h[kPassBatch];
         int passes = 0;
         unsigned processed = 0;
         while (processed < (unsigned)n) {
-            launch_mis_pass(n, lev[l].rp_nat, lev[l].ci_nat, key, m1, owner, opt.max_aggregate, G, done, big_rows,
-                            nhub, lim, stream);
-            passes++;
-            const unsigned now = (unsigned)read_int(reinterpret_cast<int *>(done));
-            if (now <= processed || now > (unsigned)n) throw Error(AMG_ERR_DEVICE, "aggregation made no progress");
-            processed = now;
+            for (int b = 0; b < kPassBatch; b++) {
+                launch_mis_pass(n, lev[l].rp_nat, lev[l].ci_nat, key, m1, owner, opt.max_aggregate, G, done,
+                                big_rows, nhub, lim, stream);
+                AMG_HIP(hipMemcpyAsync(after + b, done, sizeof(unsigned), hipMemcpyDeviceToDevice, stream));
+            }
+            to_host(after_h, after, kPassBatch);
+            for (int b = 0; b < kPassBatch && processed < (unsigned)n; b++) {
+                passes++;
+                if (after_h[b] <= processed || after_h[b] > (unsigned)n)
+                    throw Error(AMG_ERR_DEVICE, "aggregation made no progress");
+                processed = after_h[b];
+            }
         }
         AMG_TRACE_MSG("level %d: %d aggregation passes", l, passes);
         // Sec. 5.1: aggregates numbered by increasing coarse-vertex index
