@@ -53,14 +53,30 @@ __device__ inline uint32_t fmix32(uint32_t h)
     return h;
 }
 
+// 64-bit value of another lane of the same row of 16 (DPP move of both halves):
+// exchange with lane ^ 1 or lane ^ 2 inside a quad, mirror inside 8 or 16 lanes.
+constexpr int kDppQuadXor1 = 0xB1, kDppQuadXor2 = 0x4E, kDppRowHalfMirror = 0x141, kDppRowMirror = 0x140;
+template <int CTRL>
+__device__ inline uint64_t dpp_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Maximum over each aligned group of G lanes, in every lane of the group.  Up to 16
+// lanes the partners are reached by DPP inside the group (lanes of other groups may
+// be inactive); wider groups add cross-row exchanges.
 template <int G>
 __device__ inline uint64_t group_max(uint64_t v)
 {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-        const uint64_t w = __shfl_xor(v, o, kWave);
-        v = w > v ? w : v;
-    }
+    uint64_t w;
+    if (G >= 2) { w = dpp_u64<kDppQuadXor1>(v); v = w > v ? w : v; }
+    if (G >= 4) { w = dpp_u64<kDppQuadXor2>(v); v = w > v ? w : v; }
+    if (G >= 8) { w = dpp_u64<kDppRowHalfMirror>(v); v = w > v ? w : v; }
+    if (G >= 16) { w = dpp_u64<kDppRowMirror>(v); v = w > v ? w : v; }
+    if (G >= 32) { w = __shfl_xor(v, 16, kWave); v = w > v ? w : v; }
+    if (G >= 64) { w = __shfl_xor(v, 32, kWave); v = w > v ? w : v; }
     return v;
 }
 
