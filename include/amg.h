@@ -161,6 +161,12 @@ amg_status amg_num_levels(const amg_hierarchy *h, int32_t *levels);
  * Alg. 2 that aggregated it (0 on the coarsest level).  NULL outputs are skipped. */
 amg_status amg_level_sizes(const amg_hierarchy *h, int32_t level, int32_t *n, int32_t *nnz, int32_t *passes);
 
+/* Slots (stored entries, padding included) of the sliced ELLPACK copy that the
+ * solve sweeps of level `level` read (slices of 64 rows stored column-major;
+ * kept on levels of at least 100k rows whose row lengths vary little), or 0 when
+ * the level is swept in CSR only. */
+amg_status amg_level_slots(const amg_hierarchy *h, int32_t level, int64_t *slots);
+
 /* Copies level `level` to host arrays in the natural (aggregation) numbering:
  * agg_host[n] = coarse index of each unknown (column of P, eq. (2.2); -1 on the
  * coarsest level), row_ptr_host[n+1], col_host[nnz], val_host[nnz].  Any output
@@ -177,10 +183,13 @@ amg_status amg_spmv(amg_hierarchy *h, int32_t level, const double *x, double *y)
 amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z);
 
 /* Average device time in microseconds of the finest level's post-smoothing step
- * (prolongation of the coarse correction + one smoothing sweep, Sec. 4.2-4.3;
- * two launches on levels of at least 100k rows, one fused launch below),
- * measured with events over `reps` back-to-back steps on the hierarchy's stream;
- * *bytes receives the step's algorithmic DRAM traffic. */
+ * as the solve runs it (prolongation of the coarse correction + one smoothing
+ * sweep, Sec. 4.2-4.3, with the inner product (z, A p) of the outer flexible CG
+ * in the FP64 mode; two launches on levels of at least 100k rows, one fused
+ * launch below), measured with events over `reps` back-to-back steps on the
+ * hierarchy's stream; *bytes receives the step's algorithmic DRAM traffic.
+ * AMG_ERR_UNSUPPORTED below 3 levels or before the first solve or K-cycle
+ * application (the step reads that K-cycle's inner products). */
 amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, double *bytes);
 
 /* Human-readable name of a status code (static storage). */

@@ -69,6 +69,7 @@ _sig = {
     "amg_num_levels": (ctypes.c_int, [_P, _I32P]),
     "amg_memory_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "amg_level_sizes": (ctypes.c_int, [_P, ctypes.c_int32, _I32P, _I32P, _I32P]),
+    "amg_level_slots": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "amg_export_level": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "amg_spmv": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     "amg_kcycle": (ctypes.c_int, [_P, _P, _P]),
@@ -186,6 +187,12 @@ class Hierarchy:
         self._check(amg_level_sizes(self._h, level, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(passes)),
                     "amg_level_sizes")
         return n.value, nnz.value, passes.value
+
+    def level_slots(self, level: int) -> int:
+        """Slots of the level's sliced ELLPACK copy (0: swept in CSR only)."""
+        v = ctypes.c_int64()
+        self._check(amg_level_slots(self._h, level, ctypes.byref(v)), "amg_level_slots")
+        return v.value
 
     def export_level(self, level: int) -> LevelExport:
         n, nnz, passes = self.level_sizes(level)

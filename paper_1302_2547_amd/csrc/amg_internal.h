@@ -60,6 +60,24 @@ struct Rows {
     unsigned *arrive;
 };
 
+// Sliced ELLPACK copy of a level's matrix, for the sweeps of levels of at least
+// kSmallLevel rows whose row lengths vary little (a 3D stencil: 4..7 entries).
+// Slice s holds rows kWave s .. kWave s + kWave - 1 stored column-major: entry k of
+// row i (slice s = i / kWave, lane t = i % kWave) is at ptr[s] + kWave k + t for
+// k < w_s = (ptr[s+1] - ptr[s]) / kWave, in the row's CSR order; a row shorter than
+// w_s (and every slot of the rows past n in the last slice) is padded with column
+// min(i, n - 1) and value 0.  Every slice has w_s >= 1.  One lane serves one row, so
+// the entry and value loads of a wavefront are contiguous.  tpb: tiles of kBlock rows
+// served by one block (the partial sums of a block's inner products are written once
+// per block, so fewer, longer blocks amortise that step).
+struct Sell {
+    int n = 0, nslices = 0, tpb = 1;
+    const int *ptr = nullptr;
+    const int *ci = nullptr;
+};
+constexpr double kSellMaxPadding = 1.25;  // padded / actual entries beyond which a level keeps CSR only
+constexpr int kSellMaxWidth = 64;         // widest slice accepted (entries per row)
+
 // A dot product as a set of partial sums (count 1: already reduced).
 struct DotRef {
     const double *part;
@@ -136,6 +154,12 @@ void launch_gather_int(int n, const int *src, const int *idx, int *dst, hipStrea
 void launch_long_rows(int n, const int *ptr, int lim, int *flags, int *list, int *count_dev, int *scan_tmp,
                       hipStream_t s);
 
+// Sliced ELLPACK build: width[s] = longest row of slice s (at least 1), for the
+// ceil(n / kWave) slices; then, with the entry offsets ptr (nslices + 1), the copy.
+void launch_sell_widths(int n, const int *rp, int *width, hipStream_t s);
+void launch_sell_fill(int n, int nslices, const int *rp, const int *ci, const double *va, const int *ptr, int *sci,
+                      double *sva, hipStream_t s);
+
 // ---------------------------------------------------------------- solve_kernels.hip
 int lanes_for(double avg_row_len, int n);
 // plain y = A x
@@ -148,9 +172,12 @@ void launch_spmv(Rows R, const int *ci, const double *va, const double *x, doubl
 //
 // y = A x (y may be NULL); d[0] = (x, A x), d[1] = (x, w1) if w1, d[2] = (x, w2) if w2
 // (omy, non-NULL only with at most two other products, adds (omy, A x) last.)
+// With sl (and its values sva), the rows are served from the sliced ELLPACK copy
+// (omy must then be NULL).
 template <class T>
 DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, const T *w1, const T *w2, int G,
-                        DotBuf buf, hipStream_t s, const double *omy = nullptr, int ncol = 1);
+                        DotBuf buf, hipStream_t s, const double *omy = nullptr, int ncol = 1,
+                        const Sell *sl = nullptr, const T *sva = nullptr);
 // r = b - A x; d[0] = (b, b), d[1] = (r, r)
 DotSet launch_residual(Rows R, const int *ci, const double *va, const double *b, const double *x, double *r, int G,
                        DotBuf buf, hipStream_t s, int ncol = 1);
@@ -161,6 +188,13 @@ void launch_reduce(const DotRef &ref, double *out, hipStream_t s, int ncol = 1, 
 template <class T>
 DotRef launch_restrict(Rows S, int nf, const int *ci, const T *wv, const T *r, T *rc, int G, hipStream_t s,
                        const double *om = nullptr, DotBuf buf = DotBuf{}, int ncol = 1);
+// rc = P^T (r - A M^-1 r) on a level with a sliced copy S (values sva): the
+// pre-smoothing residual t (FP64, n per right-hand side, scratch) row by row, then
+// the sums of t over the aggregates: rc[J] = sum of t[idx[p]] (t[p] when idx is
+// NULL) for positions p in seg[J] .. seg[J+1] of the level's nested order.
+template <class T>
+void launch_sell_restrict(const Sell &S, const T *sva, const T *minv, const T *r, double *t, int nc, const int *seg,
+                          const int *idx, T *rc, hipStream_t s, int ncol = 1);
 // rc = W r with r = rt formed on the fly as rt = rcf - (alpha1/rho1) v1 (the
 // inner residual of the parent's first flexible-CG step), rt also stored
 template <class T>
@@ -218,12 +252,13 @@ void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int
 // coarsest solve of size nc <= kInlineCoarse done in the kernel); returns
 // (out, wdot) if wdot.  nc is the coarse level's size (the leading dimension of
 // edirect, c1, c2).  xtmp (FP64, n per right-hand side, or NULL): on levels of at
-// least kSmallLevel rows the step is then split in two launches through it.
+// least kSmallLevel rows the step is then split in two launches through it, the
+// second served from the sliced ELLPACK copy sl (values sva) when given.
 template <class T>
 DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, const T *r, const int *agg_pos,
                           const int *cagg, int mode, const T *edirect, const T *c1, const T *c2, KDots kd, T *xout,
                           const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv, int nc,
-                          int ncol = 1, double *xtmp = nullptr);
+                          int ncol = 1, double *xtmp = nullptr, const Sell *sl = nullptr, const T *sva = nullptr);
 // Exact solve on a coarsest level of n unknowns: rows with no off-diagonal entry (and
 // no entry in their column) are decoupled, x_i = r_i / a_ii (dinv[k] = 1 / a_ii for
 // row didx[k], k < nd); the other m rows idx[0..m) (ascending; NULL: all rows, m = n)

@@ -242,6 +242,7 @@ template <class T>
 struct KArrays {
     const T *va = nullptr, *minv = nullptr, *wv = nullptr;
     T *rc = nullptr, *rt = nullptr, *c1 = nullptr, *c2 = nullptr, *v1 = nullptr;
+    const T *sva = nullptr;  // values of the sliced ELLPACK copy (NULL: none)
 };
 
 struct Level {
@@ -259,6 +260,10 @@ struct Level {
     int *cagg = nullptr;                                         // coarse unknown of each entry's column
     int *sci = nullptr;  // columns of the super-rows of P^T A (the same array as ci unless level 0 is natural)
     double *xs = nullptr;  // FP64 iterate of the split post-smoothing (levels >= kSmallLevel rows), n per column
+    Sell sell{};             // sliced ELLPACK copy of A for the large-level sweeps (ptr NULL: none)
+    double *sell_va = nullptr;
+    size_t sell_slots = 0;
+    const Sell *sl() const { return sell.ptr ? &sell : nullptr; }
     int G = 2, Gs = 2;
     Rows A{}, S{};  // rows of A and super-rows of P^T A, each with its hub-row chunks
     // work vectors and dot sites when this level is the coarse level of a visit
@@ -433,6 +438,7 @@ struct amg_hierarchy {
 
     void build(const amg_csr &A);
     void finalize_layout();
+    void build_sell();
     // the inner residual rt = rcf - (alpha1/rho1) v1 of a parent's first step
     template <class T>
     struct RtSource {
@@ -826,9 +832,10 @@ void amg_hierarchy::finalize_layout()
             AMG_TRACE_MSG("level %d: one-block coarse correction (%d long rows)", L - 1, tl.nlong);
         }
     }
+    build_sell();
     for (int l = 0; l <= L; l++) {
         Level &F = lev[l];
-        F.k64 = KArrays<double>{F.va, F.minv, F.wv, F.rc, F.rt, F.c1, F.c2, F.v1};
+        F.k64 = KArrays<double>{F.va, F.minv, F.wv, F.rc, F.rt, F.c1, F.c2, F.v1, F.sell_va};
     }
     if (mixed) {  // FP32 copies of the K-cycle values and FP32 work vectors
         auto to_float = [&](const double *src, size_t count) -> const float * {
@@ -843,6 +850,7 @@ void amg_hierarchy::finalize_layout()
             K.va = to_float(F.va, F.nnz);
             K.minv = to_float(F.minv, F.n);
             K.wv = to_float(F.wv, F.nnz);
+            K.sva = to_float(F.sell_va, F.sell_slots);
             if (l >= 1) {
                 K.rc = pool.alloc<float>((size_t)F.n * nr);
                 K.rt = pool.alloc<float>((size_t)F.n * nr);
@@ -874,6 +882,47 @@ void amg_hierarchy::finalize_layout()
     pool.release(tmp);
     pool.release(scan_tmp);
     for (void *p : drained) pool.release(p);
+}
+
+// Sliced ELLPACK copies of the levels of at least kSmallLevel rows (not the last
+// fine level of a single coarse unknown, whose visits take another path), kept
+// where the padding stays within kSellMaxPadding of the entries and no slice is
+// wider than kSellMaxWidth; other levels (irregular graphs) keep CSR only.
+void amg_hierarchy::build_sell()
+{
+    using namespace amg;
+    for (int l = 0; l + 1 < levels(); l++) {
+        Level &F = lev[l];
+        if (F.n < kSmallLevel || F.omega || F.n > (1 << 28)) continue;
+        const int ns = (F.n + kWave - 1) / kWave;
+        int *w = pool.alloc<int>(ns);
+        launch_sell_widths(F.n, F.rp, w, stream);
+        std::vector<int> hw(ns), ptr(ns + 1);
+        to_host(hw.data(), w, ns);
+        pool.release(w);
+        int64_t slots = 0;
+        int wmax = 0;
+        for (int k = 0; k < ns; k++) {
+            ptr[k] = (int)std::min<int64_t>(slots, INT32_MAX);
+            slots += (int64_t)hw[k] * kWave;
+            wmax = std::max(wmax, hw[k]);
+        }
+        ptr[ns] = (int)std::min<int64_t>(slots, INT32_MAX);
+        const size_t bytes = sizeof(int) * (ns + 1) + (sizeof(int) + sizeof(double)) * (size_t)slots;
+        const bool fits = !pool.budget || pool.used + bytes <= pool.budget;
+        if (wmax > kSellMaxWidth || slots > kSellMaxPadding * F.nnz || slots >= INT32_MAX || !fits) {
+            AMG_TRACE_MSG("level %d: CSR only (sliced copy %lld slots, widest %d)", l, (long long)slots, wmax);
+            continue;
+        }
+        int *dptr = pool.alloc<int>(ns + 1);
+        to_dev(dptr, ptr.data(), ns + 1);
+        int *sci = pool.alloc<int>((size_t)slots);
+        F.sell_va = pool.alloc<double>((size_t)slots);
+        launch_sell_fill(F.n, ns, F.rp, F.ci, F.va, dptr, sci, F.sell_va, stream);
+        F.sell = Sell{F.n, ns, 1, dptr, sci};
+        F.sell_slots = (size_t)slots;
+        AMG_TRACE_MSG("level %d: sliced copy, %lld slots for %d entries (widest %d)", l, (long long)slots, F.nnz, wmax);
+    }
 }
 
 // x = K_k(r) on level k (solve layout): pre-smoothing from zero + restriction,
@@ -914,6 +963,10 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
     if (rts) {  // rr = rt is formed here from the parent's first inner step
         C.om_rc = launch_restrict_rt<T>(F.S, F.n, F.sci, FK.wv, rts->rcf, rts->v1, rts->kd, const_cast<T *>(rr),
                                         CK.rc, flag, F.Gs, stream, om, C.d_om, ncol);
+    } else if (F.sell.ptr && !om) {  // sliced level: row sweep, then sums per aggregate
+        const int *idx = k == 0 && !uperm ? F.perm : nullptr;  // the finest level's rows are in natural order
+        launch_sell_restrict<T>(F.sell, FK.sva, FK.minv, rr, F.xs, C.n, F.seg_ptr, idx, CK.rc, stream, ncol);
+        C.om_rc = DotRef{nullptr, 0};
     } else {
         C.om_rc = launch_restrict<T>(F.S, F.n, F.sci, FK.wv, rr, CK.rc, F.Gs, stream, om, C.d_om, ncol);
     }
@@ -939,8 +992,8 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
         }
     } else {
         kcycle<T>(k + 1, CK.rc, CK.c1, nullptr, nullptr, ncol);
-        const DotSet s1 =
-            launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c1, CK.v1, CK.rc, nullptr, C.G, C.d_c1, stream, C.omega, ncol);
+        const DotSet s1 = launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c1, CK.v1, CK.rc, nullptr, C.G, C.d_c1, stream,
+                                              C.omega, ncol, C.sl(), CK.sva);
         kd.rho1 = s1.d[0];
         kd.alpha1 = s1.d[1];
         if (C.omega) C.om_v1 = s1.d[2];
@@ -953,8 +1006,8 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
                 launch_inner_residual<T>(C.n, CK.rc, CK.v1, kd, CK.rt, flag, stream, ncol);
                 kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, nullptr, ncol);
             }
-            const DotSet s2 =
-                launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c2, nullptr, CK.v1, CK.rt, C.G, C.d_c2, stream, nullptr, ncol);
+            const DotSet s2 = launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c2, nullptr, CK.v1, CK.rt, C.G, C.d_c2,
+                                                  stream, nullptr, ncol, C.sl(), CK.sva);
             kd.beta = s2.d[0];
             kd.gamma = s2.d[1];
             kd.alpha2 = s2.d[2];
@@ -963,7 +1016,8 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
     }
     if (k == 0) kd0 = kd;
     return launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rr, F.agg_pos, F.cagg, mode, edirect, CK.c1, CK.c2, kd, xx,
-                                 wdot, k == 0 ? d_zq : DotBuf{}, flag, F.G, stream, ainv, C.n, ncol, F.xs);
+                                 wdot, k == 0 ? d_zq : DotBuf{}, flag, F.G, stream, ainv, C.n, ncol, F.xs, F.sl(),
+                                 FK.sva);
 }
 
 // One outer iteration is split in three replayable pieces:
@@ -996,7 +1050,8 @@ void amg_hierarchy::run_first(int ncol)
     }
     Level &F = lev[0];
     AMG_HIP(hipMemcpyAsync(p, z, sizeof(double) * F.n * (size_t)ncol, hipMemcpyDeviceToDevice, stream));
-    const DotSet s1 = launch_spmv_dots<double>(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream, nullptr, ncol);
+    const DotSet s1 = launch_spmv_dots<double>(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream, nullptr, ncol,
+                                               F.sl(), F.k64.sva);
     dr_pq = s1.d[0];
     dr_pr = s1.d[1];
     dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream, ncol);
@@ -1013,7 +1068,8 @@ void amg_hierarchy::run_iter(int ncol)
     }
     Level &F = lev[0];
     launch_fcg_direction(F.n, dr_pq, dr_zq, z, p, flag, stream, ncol);
-    const DotSet s1 = launch_spmv_dots<double>(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream, nullptr, ncol);
+    const DotSet s1 = launch_spmv_dots<double>(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream, nullptr, ncol,
+                                               F.sl(), F.k64.sva);
     dr_pq = s1.d[0];
     dr_pr = s1.d[1];
     dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream, ncol);
@@ -1110,15 +1166,30 @@ void amg_hierarchy::autotune_level(int l, int ncol)
         c.best[key] = best;
         return best;
     };
-    // post-smoother with a directly given correction (no inner products read or written)
-    F.G = pick(0, (double)F.nnz / F.n, F.G, [&](int g) {
-        launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rv, F.agg_pos, F.cagg, 0, CK.c1, nullptr, nullptr, KDots{},
-                              out, nullptr, DotBuf{}, flag, g, stream, ainv, C.n, ncol, F.xs);
-    });
-    F.Gs = pick(1, (double)F.nnz / C.n, F.Gs, [&](int g) {
-        launch_restrict<T>(F.S, F.n, F.sci, FK.wv, rv, CK.rc, g, stream, nullptr, DotBuf{}, ncol);
-    });
-    AMG_TRACE_MSG("autotune level %d (%d right-hand sides): G=%d Gs=%d", l, ncol, F.G, F.Gs);
+    if (F.sell.ptr) {
+        // sliced copy: tiles per block of the post-smoother with its inner product
+        // (the partials go to a dot site the solve rewrites before reading)
+        Sell &S = F.sell;
+        const DotBuf scratch = l == 0 ? d_zq : F.d_c1;
+        S.tpb = pick(2, 8.0, S.tpb, [&](int g) {
+            S.tpb = g / 2;
+            launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rv, F.agg_pos, F.cagg, 0, CK.c1, nullptr, nullptr,
+                                  KDots{}, out, rv, scratch, flag, F.G, stream, ainv, C.n, ncol, F.xs, &S, FK.sva);
+        }) / 2;
+    } else {
+        // post-smoother with a directly given correction (no inner products read or written)
+        F.G = pick(0, (double)F.nnz / F.n, F.G, [&](int g) {
+            launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rv, F.agg_pos, F.cagg, 0, CK.c1, nullptr, nullptr,
+                                  KDots{}, out, nullptr, DotBuf{}, flag, g, stream, ainv, C.n, ncol, F.xs);
+        });
+    }
+    if (!F.sell.ptr) {  // (a sliced level restricts from its sliced copy)
+        F.Gs = pick(1, (double)F.nnz / C.n, F.Gs, [&](int g) {
+            launch_restrict<T>(F.S, F.n, F.sci, FK.wv, rv, CK.rc, g, stream, nullptr, DotBuf{}, ncol);
+        });
+    }
+    AMG_TRACE_MSG("autotune level %d (%d right-hand sides): G=%d Gs=%d tiles per block=%d", l, ncol, F.G, F.Gs,
+                  F.sell.tpb);
 }
 
 void amg_hierarchy::autotune(int ncol)
@@ -1469,6 +1540,13 @@ amg_status amg_level_sizes(const amg_hierarchy *h, int32_t level, int32_t *n, in
     return AMG_OK;
 }
 
+amg_status amg_level_slots(const amg_hierarchy *h, int32_t level, int64_t *slots)
+{
+    if (!h || !slots || level < 0 || level >= h->levels()) return AMG_ERR_INVALID_ARGUMENT;
+    *slots = (int64_t)h->lev[level].sell_slots;
+    return AMG_OK;
+}
+
 amg_status amg_export_level(const amg_hierarchy *h_c, int32_t level, int32_t *agg_host, int32_t *row_ptr_host,
                             int32_t *col_host, double *val_host)
 {
@@ -1530,18 +1608,19 @@ amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, dou
 {
     if (!h || reps < 1 || !avg_us) return AMG_ERR_INVALID_ARGUMENT;
     if (h->levels() < 3) return AMG_ERR_UNSUPPORTED;
+    if (!h->kd0.rho1.part) return AMG_ERR_UNSUPPORTED;  // the step reads the products of a K-cycle already run
     return guarded([&]() {
         const Level &F = h->lev[0], &C = h->lev[1];
         const int mode = h->opt.kcycle_inner == 1 ? 1 : 2;
-        auto launch = [&]() {
+        auto launch = [&]() {  // as in the solve: the FP64 step also forms (z, q)
             if (h->mixed) {
                 amg::launch_post_smooth<float>(F.A, F.ci, F.k32.va, F.k32.minv, h->r32, F.agg_pos, F.cagg, mode,
                                                nullptr, C.k32.c1, C.k32.c2, h->kd0, h->z32, nullptr, DotBuf{}, h->flag,
-                                               F.G, h->stream, h->ainv, C.n, 1, F.xs);
+                                               F.G, h->stream, h->ainv, C.n, 1, F.xs, F.sl(), F.k32.sva);
             } else {
                 amg::launch_post_smooth<double>(F.A, F.ci, F.va, F.minv, h->r, F.agg_pos, F.cagg, mode, nullptr, C.c1,
-                                                C.c2, h->kd0, h->z, nullptr, DotBuf{}, h->flag, F.G, h->stream,
-                                                h->ainv, C.n, 1, F.xs);
+                                                C.c2, h->kd0, h->z, h->q, h->d_zq, h->flag, F.G, h->stream, h->ainv,
+                                                C.n, 1, F.xs, F.sl(), F.k64.sva);
             }
         };
         launch();
@@ -1553,10 +1632,10 @@ amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, dou
         AMG_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
         *avg_us = 1000.0 * ms / reps;
         // per entry: column, value (+ coarse column on small levels); row pointers;
-        // per row: minv, r, output (values) and the coarse index; c1, c2 once each
+        // per row: minv, r, output (values), the coarse index and (FP64) q; c1, c2 once each
         const double w = h->mixed ? 4.0 : 8.0;
-        if (bytes) *bytes = (4.0 + w + (F.cagg ? 4.0 : 0.0)) * F.nnz + 4.0 * (F.n + 1) + (3.0 * w + 4.0) * F.n +
-                            2.0 * w * C.n;
+        if (bytes) *bytes = (4.0 + w + (F.cagg ? 4.0 : 0.0)) * F.nnz + 4.0 * (F.n + 1) +
+                            ((h->mixed ? 3.0 : 4.0) * w + 4.0) * F.n + 2.0 * w * C.n;
         return AMG_OK;
     });
 }

@@ -1110,6 +1110,36 @@ __global__ void __launch_bounds__(kBlock) k_long_compact(int n, const int *__res
 // Lanes per row/aggregate for the helper kernels: a wavefront on small levels.
 inline bool wide(int n) { return n < kSmallLevel; }
 
+// Sliced ELLPACK build (layout in amg_internal.h).  One wavefront per slice: the
+// width is the wavefront's largest row length, at least 1.
+__global__ void __launch_bounds__(kBlock) k_sell_widths(int n, const int *__restrict__ rp, int *__restrict__ width)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    int len = i < n ? rp[i + 1] - rp[i] : 0;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o));
+    if ((threadIdx.x & (kWave - 1)) == 0 && i < n) width[i / kWave] = max(len, 1);
+}
+
+// One thread per slot row (nslices * kWave threads): rows past n are padding rows.
+__global__ void __launch_bounds__(kBlock) k_sell_fill(int n, int nslices, const int *__restrict__ rp,
+                                                      const int *__restrict__ ci, const double *__restrict__ va,
+                                                      const int *__restrict__ ptr, int *__restrict__ sci,
+                                                      double *__restrict__ sva)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int s = i / kWave, t = i % kWave;
+    if (s >= nslices) return;
+    const int b = i < n ? rp[i] : 0, len = i < n ? rp[i + 1] - b : 0;
+    const int pad = i < n ? i : n - 1;
+    const int beg = ptr[s], w = (ptr[s + 1] - beg) / kWave;
+    for (int k = 0; k < w; k++) {
+        const int q = beg + k * kWave + t;
+        sci[q] = k < len ? ci[b + k] : pad;
+        sva[q] = k < len ? va[b + k] : 0.0;
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -1321,6 +1351,19 @@ void launch_agg_positions(int n, const int *perm_f, const int *agg_nat, const in
 void launch_gather_int(int n, const int *src, const int *idx, int *dst, hipStream_t s)
 {
     k_gather_int<<<grid_for(n), kBlock, 0, s>>>(n, src, idx, dst);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_sell_widths(int n, const int *rp, int *width, hipStream_t s)
+{
+    k_sell_widths<<<grid_for(n), kBlock, 0, s>>>(n, rp, width);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_sell_fill(int n, int nslices, const int *rp, const int *ci, const double *va, const int *ptr, int *sci,
+                      double *sva, hipStream_t s)
+{
+    k_sell_fill<<<grid_for((int64_t)nslices * kWave), kBlock, 0, s>>>(n, nslices, rp, ci, va, ptr, sci, sva);
     AMG_HIP(hipGetLastError());
 }
 

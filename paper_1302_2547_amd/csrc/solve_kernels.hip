@@ -791,6 +791,164 @@ __global__ void __launch_bounds__(kBlock) k_smooth_finish(Rows R, const int *__r
     if (DOT) store_partials<1>(dsum, part);
 }
 
+// ------------------------------------------------------------------ sliced ELLPACK sweeps
+// One lane per row and one slice per wavefront (tiles of kBlock rows start at
+// multiples of kWave), so a slice's width is uniform over the wavefront and the
+// entry and value loads of each slot are contiguous.  The first kSellUnroll slots
+// are loaded together (slots past the width re-read the first one with weight 0),
+// then their gathers; the sum runs in slot order, i.e. in the row's CSR order.
+constexpr int kSellUnroll = 8;
+
+// sum over the row's slots of a_ij * gx(j)
+template <class V, class GX>
+__device__ inline double sell_row(const int *__restrict__ sc, const V *__restrict__ sv, int beg, int w, int t,
+                                  GX gx)
+{
+    const int p0 = beg + t;
+    int c[kSellUnroll];
+    double v[kSellUnroll];
+#pragma unroll
+    for (int u = 0; u < kSellUnroll; u++) {
+        const int p = u < w ? p0 + u * kWave : p0;
+        c[u] = sc[p];
+        v[u] = u < w ? (double)sv[p] : 0.0;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < kSellUnroll; u++) s += v[u] * gx(c[u]);
+    for (int k = kSellUnroll; k < w; k++) {
+        const int p = p0 + k * kWave;
+        s += (double)sv[p] * gx(sc[p]);
+    }
+    return s;
+}
+
+// Row i of tile u of this block (blocks renumbered so that each XCD serves a
+// contiguous range of tiles); calls row_fn(i, slice offset, width, lane) for
+// every row < n.
+template <class RowFn>
+__device__ inline void sell_tiles(int n, int tpb, const int *__restrict__ sptr, RowFn row_fn)
+{
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int t = threadIdx.x & (kWave - 1);
+    for (int u = 0; u < tpb; u++) {
+        const int i = (b * tpb + u) * kBlock + (int)threadIdx.x;
+        if (i >= n) break;
+        const int s = __builtin_amdgcn_readfirstlane(i / kWave);
+        const int beg = sptr[s];
+        const int w = (sptr[s + 1] - beg) / kWave;
+        row_fn(i, beg, w, t);
+    }
+}
+
+// k_smooth_finish on the sliced copy: out = x + M^-1 (r - A x), with the partials of
+// (out, wdot) when DOT.
+template <class T, bool DOT>
+__global__ void __launch_bounds__(kBlock) k_sell_smooth_finish(int n, int tpb, const int *__restrict__ sptr,
+                                                               const int *__restrict__ sc, const T *__restrict__ sv,
+                                                               const T *__restrict__ minv, const T *__restrict__ r,
+                                                               const double *__restrict__ x, T *__restrict__ xout,
+                                                               const T *__restrict__ wdot, double *__restrict__ part)
+{
+    r = colv(r, n);
+    x = colv(x, n);
+    xout = colv(xout, n);
+    wdot = colv(wdot, n);
+    part = colp(part);
+    double d[1] = {0.0};
+    sell_tiles(n, tpb, sptr, [&](int i, int beg, int w, int t) {
+        const double mr = (double)minv[i], rr = (double)r[i], xr = x[i];
+        const double wd = DOT ? (double)wdot[i] : 0.0;
+        const double o = xr + mr * (rr - sell_row(sc, sv, beg, w, t, [&](int j) { return x[j]; }));
+        xout[i] = (T)o;
+        if (DOT) d[0] += o * wd;
+    });
+    if (DOT) store_partials<1>(d, part);
+}
+
+// k_spmv_dots on the sliced copy: y = A x (y may be NULL), partials of (x, A x),
+// (x, w1) if ND > 1, (x, w2) if ND > 2.
+template <class T, int ND>
+__global__ void __launch_bounds__(kBlock) k_sell_spmv_dots(int n, int tpb, const int *__restrict__ sptr,
+                                                           const int *__restrict__ sc, const T *__restrict__ sv,
+                                                           const T *__restrict__ x, T *__restrict__ y,
+                                                           const T *__restrict__ w1, const T *__restrict__ w2,
+                                                           double *__restrict__ part)
+{
+    x = colv(x, n);
+    y = colv(y, n);
+    w1 = colv(w1, n);
+    w2 = colv(w2, n);
+    part = colp(part);
+    double d[ND] = {};
+    sell_tiles(n, tpb, sptr, [&](int i, int beg, int w, int t) {
+        const double xr = (double)x[i];
+        const double w1r = ND > 1 ? (double)w1[i] : 0.0, w2r = ND > 2 ? (double)w2[i] : 0.0;
+        const double sum = sell_row(sc, sv, beg, w, t, [&](int j) { return (double)x[j]; });
+        if (y) y[i] = (T)sum;
+        d[0] += xr * sum;
+        if (ND > 1) d[1 % ND] += xr * w1r;
+        if (ND > 2) d[2 % ND] += xr * w2r;
+    });
+    store_partials<ND>(d, part);
+}
+
+// Restriction on a sliced level in two launches.  The pre-smoothing sweep from
+// zero gives M^-1 r, and its residual t = r - A M^-1 r is formed row by row
+// (t_i = r_i - sum_j a_ij minv_j r_j, FP64, stored in the level's FP64 scratch);
+// then rc = P^T t sums t over the members of each aggregate in their nested order
+// (Sec. 4.2: the restriction of piecewise-constant P adds the fine values of an
+// aggregate).
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_sell_presmooth_residual(int n, int tpb, const int *__restrict__ sptr,
+                                                                    const int *__restrict__ sc,
+                                                                    const T *__restrict__ sv,
+                                                                    const T *__restrict__ minv,
+                                                                    const T *__restrict__ r, double *__restrict__ t)
+{
+    r = colv(r, n);
+    t = colv(t, n);
+    sell_tiles(n, tpb, sptr, [&](int i, int beg, int w, int lane) {
+        const double ri = (double)r[i];
+        const double s = sell_row(sc, sv, beg, w, lane, [&](int j) { return (double)minv[j] * (double)r[j]; });
+        t[i] = ri - s;
+    });
+}
+
+// rc_J = sum of t over positions seg[J] .. seg[J+1] (fine row idx[p], or p when
+// idx is NULL) in position order, one thread per aggregate.  The first kSegUnroll
+// members' indices are loaded together (clamped to the last member), then their
+// values; members past the end add 0.
+constexpr int kSegUnroll = 8;
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_segment_sum(int nc, const int *__restrict__ seg,
+                                                        const int *__restrict__ idx, int nf,
+                                                        const double *__restrict__ t, T *__restrict__ rc)
+{
+    t = colv(t, nf);
+    rc = colv(rc, nc);
+    for (int J = blockIdx.x * kBlock + threadIdx.x; J < nc; J += gridDim.x * kBlock) {
+        const int b = seg[J], e = seg[J + 1];
+        double s = 0.0;
+        if (e > b) {
+            int q[kSegUnroll];
+#pragma unroll
+            for (int u = 0; u < kSegUnroll; u++) {
+                const int p = b + u < e ? b + u : e - 1;
+                q[u] = idx ? idx[p] : p;
+            }
+            double v[kSegUnroll];
+#pragma unroll
+            for (int u = 0; u < kSegUnroll; u++) v[u] = t[q[u]];
+#pragma unroll
+            for (int u = 0; u < kSegUnroll; u++) s += b + u < e ? v[u] : 0.0;
+            for (int p = b + kSegUnroll; p < e; p++) s += t[idx ? idx[p] : p];
+        }
+        rc[J] = (T)s;
+    }
+}
+
 // Post-smoothing on a level whose coarse level is a single unknown.  P is then
 // the all-ones column and the restriction W = P^T (I - A M^-1) is the row vector
 // om^T, om_j = 1 - minv_j sum_i a_ij, so rc = (om, r) is an inner product whose
@@ -1243,20 +1401,23 @@ inline int rows_grid(const Rows &R, int G, int cap)
 }
 
 // Partial sets larger than this are reduced by one extra block instead of by
-// every consumer block.
+// every consumer block.  The sliced sweeps pass a limit of 1: their consumers
+// (the outer-iteration updates, the next level's smoothers) are grids of
+// thousands of blocks, each of which would otherwise load the whole set.
 constexpr int kConsumerReduceMax = 1024;
 
-void reduce_if_large(int nd, double *part, int count, double *final_out, hipStream_t s, int ncol)
+void reduce_if_large(int nd, double *part, int count, double *final_out, hipStream_t s, int ncol,
+                     int limit = kConsumerReduceMax)
 {
-    if (count > kConsumerReduceMax && final_out) {
+    if (count > limit && final_out) {
         k_reduce_partials<<<dim3(1, ncol), kReduceThreads, 0, s>>>(nd, part, count, final_out, kDotCol);
         AMG_HIP(hipGetLastError());
     }
 }
 
-DotRef finished(double *part, int count, double *final_out, int d)
+DotRef finished(double *part, int count, double *final_out, int d, int limit = kConsumerReduceMax)
 {
-    if (count <= kConsumerReduceMax || final_out == nullptr) return DotRef{part + d * kPartStride, count};
+    if (count <= limit || final_out == nullptr) return DotRef{part + d * kPartStride, count};
     return DotRef{final_out + d, 1};
 }
 
@@ -1296,12 +1457,40 @@ void launch_spmv(Rows R, const int *ci, const double *va, const double *x, doubl
     AMG_HIP(hipGetLastError());
 }
 
+// Blocks of a sliced sweep: tpb tiles each, raised so that a dot site's partial
+// set (one per block) fits kMaxDotBlocks.
+inline int sell_grid(const Sell &S, bool dot, int *tpb)
+{
+    const int64_t tiles = ((int64_t)S.n + kBlock - 1) / kBlock;
+    int64_t t = S.tpb < 1 ? 1 : S.tpb;
+    if (dot && (tiles + t - 1) / t > kMaxDotBlocks) t = (tiles + kMaxDotBlocks - 1) / kMaxDotBlocks;
+    *tpb = (int)t;
+    return (int)((tiles + t - 1) / t);
+}
+
 template <class T>
 DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, const T *w1, const T *w2, int G,
-                        DotBuf buf, hipStream_t s, const double *omy, int ncol)
+                        DotBuf buf, hipStream_t s, const double *omy, int ncol, const Sell *sl, const T *sva)
 {
-    const dim3 grid(rows_grid(R, G, kMaxDotBlocks), ncol);
     const int nd = w2 ? 3 : (w1 ? 2 : 1);
+    if (sl) {
+        if (omy) throw Error(4, "spmv_dots: no (om, A x) on a sliced level");
+        int tpb = 1;
+        const dim3 grid(sell_grid(*sl, true, &tpb), ncol);
+#define AMG_SELL_DOTS(ND) \
+    k_sell_spmv_dots<T, ND><<<grid, kBlock, 0, s>>>(sl->n, tpb, sl->ptr, sl->ci, sva, x, y, w1, w2, buf.part)
+        if (nd == 1) AMG_SELL_DOTS(1);
+        else if (nd == 2) AMG_SELL_DOTS(2);
+        else AMG_SELL_DOTS(3);
+#undef AMG_SELL_DOTS
+        AMG_HIP(hipGetLastError());
+        const int count = (int)grid.x;
+        reduce_if_large(nd, buf.part, count, buf.final_out, s, ncol, 1);
+        DotSet out{};
+        for (int d = 0; d < nd; d++) out.d[d] = finished(buf.part, count, buf.final_out, d, 1);
+        return out;
+    }
+    const dim3 grid(rows_grid(R, G, kMaxDotBlocks), ncol);
     if (omy && nd == 3) throw Error(4, "spmv_dots: at most three products");
 #define AMG_SPMV_DOTS(ND, LAT, OMY)                                                                        \
     AMG_SWITCH_G(G, (k_spmv_dots<T, kG, ND, LAT, OMY><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, omy, \
@@ -1391,7 +1580,7 @@ template <class T>
 DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, const T *r, const int *agg_pos,
                           const int *cagg, int mode, const T *edirect, const T *c1, const T *c2, KDots kd, T *xout,
                           const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv, int nc,
-                          int ncol, double *xtmp)
+                          int ncol, double *xtmp, const Sell *sl, const T *sva)
 {
     const bool dot = wdot != nullptr;
     const dim3 grid(rows_grid(R, G, dot ? kMaxDotBlocks : (1 << 20)), ncol);
@@ -1405,6 +1594,21 @@ DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, con
         }
 #undef AMG_START
         AMG_HIP(hipGetLastError());
+        if (sl) {
+            int tpb = 1;
+            const dim3 gs(sell_grid(*sl, dot, &tpb), ncol);
+            if (dot) {
+                k_sell_smooth_finish<T, true><<<gs, kBlock, 0, s>>>(sl->n, tpb, sl->ptr, sl->ci, sva, minv, r, xtmp,
+                                                                    xout, wdot, buf.part);
+            } else {
+                k_sell_smooth_finish<T, false><<<gs, kBlock, 0, s>>>(sl->n, tpb, sl->ptr, sl->ci, sva, minv, r, xtmp,
+                                                                     xout, wdot, buf.part);
+            }
+            AMG_HIP(hipGetLastError());
+            if (!dot) return DotRef{nullptr, 0};
+            reduce_if_large(1, buf.part, (int)gs.x, buf.final_out, s, ncol, 1);
+            return finished(buf.part, (int)gs.x, buf.final_out, 0, 1);
+        }
         if (dot) {
             AMG_SWITCH_G(G, (k_smooth_finish<T, kG, true><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, xtmp, xout, wdot,
                                                                                 buf.part)));
@@ -1445,6 +1649,18 @@ DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, con
     const int count = (int)grid.x + R.nlong;
     reduce_if_large(1, buf.part, count, buf.final_out, s, ncol);
     return finished(buf.part, count, buf.final_out, 0);
+}
+
+template <class T>
+void launch_sell_restrict(const Sell &S, const T *sva, const T *minv, const T *r, double *t, int nc, const int *seg,
+                          const int *idx, T *rc, hipStream_t s, int ncol)
+{
+    int tpb = 1;
+    const dim3 grid(sell_grid(S, false, &tpb), ncol);
+    k_sell_presmooth_residual<T><<<grid, kBlock, 0, s>>>(S.n, tpb, S.ptr, S.ci, sva, minv, r, t);
+    AMG_HIP(hipGetLastError());
+    k_segment_sum<T><<<dim3(grid_for(nc), ncol), kBlock, 0, s>>>(nc, seg, idx, S.n, t, rc);
+    AMG_HIP(hipGetLastError());
 }
 
 template <class T>
@@ -1573,13 +1789,16 @@ void launch_to_float(int64_t n, const double *src, float *dst, hipStream_t s)
 
 #define AMG_INSTANTIATE(T)                                                                                           \
     template DotSet launch_spmv_dots<T>(Rows, const int *, const T *, const T *, T *, const T *, const T *, int,     \
-                                        DotBuf, hipStream_t, const double *, int);                                  \
+                                        DotBuf, hipStream_t, const double *, int, const Sell *, const T *);         \
     template DotRef launch_restrict<T>(Rows, int, const int *, const T *, const T *, T *, int, hipStream_t,          \
                                        const double *, DotBuf, int);                                                \
+    template void launch_sell_restrict<T>(const Sell &, const T *, const T *, const T *, double *, int, const int *, \
+                                          const int *, T *, hipStream_t, int);                                      \
     template void launch_inner_residual<T>(int, const T *, const T *, KDots, T *, int *, hipStream_t, int);         \
     template DotRef launch_post_smooth<T>(Rows, const int *, const T *, const T *, const T *, const int *,          \
                                           const int *, int, const T *, const T *, const T *, KDots, T *, const T *, \
-                                          DotBuf, int *, int, hipStream_t, const double *, int, int, double *);     \
+                                          DotBuf, int *, int, hipStream_t, const double *, int, int, double *,      \
+                                          const Sell *, const T *);                                                 \
     template DotRef launch_restrict_rt<T>(Rows, int, const int *, const T *, const T *, const T *, KDots, T *, T *, \
                                           int *, int, hipStream_t, const double *, DotBuf, int);                    \
     template void launch_post_direct<T>(Rows, const int *, const T *, const T *, const T *, const T *, KDots,       \

@@ -118,10 +118,11 @@ class Server:
     # a hierarchy's bytes before it exists: measured figures of this library are
     # about 110 bytes per unknown and 56 per stored entry with 8 right-hand sides,
     # plus an FP64 iterate per right-hand side on the levels of at least 100k rows
+    # and up to 16 bytes per entry for the sliced copies of those levels
     @staticmethod
     def hierarchy_estimate(req: Request, max_rhs: int) -> int:
         nnz = (2 * len(req.dims) + 1) * req.n
-        return 56 * nnz + (60 + 17 * max_rhs) * req.n + (64 << 20)
+        return 72 * nnz + (60 + 17 * max_rhs) * req.n + (64 << 20)
 
     def _evict(self, need: int):
         """Drop least recently used idle hierarchies until `need` more bytes fit."""

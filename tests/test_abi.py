@@ -53,6 +53,8 @@ def test_host_only_paths(lib):
     amg.amg_free(None)
     n = ctypes.c_int32()
     assert amg.amg_num_levels(None, ctypes.byref(n)) == amg.AMG_ERR_INVALID_ARGUMENT
+    slots = ctypes.c_int64()
+    assert amg.amg_level_slots(None, 0, ctypes.byref(slots)) == amg.AMG_ERR_INVALID_ARGUMENT
 
 
 def test_host_arrays_are_rejected(lib):
