@@ -439,3 +439,24 @@ def test_sliced_levels_match_oracle(amg, case):
         res = b - oracle.spmv(rp, ci, va, x.cpu().numpy())
         assert st == amg.AMG_OK and np.linalg.norm(res) / np.linalg.norm(b) <= 1e-8
         h.close()
+
+
+def test_time_smoother_needs_a_kcycle(amg):
+    """The timed post-smoothing step reads the inner products of a K-cycle, so it is
+    refused before the first solve; afterwards it reports the step's algorithmic
+    bytes (FP64: column + value per entry, row pointers, minv, r, z, q and the
+    coarse index per row, c1 and c2 per coarse row)."""
+    import ctypes
+    rp, ci, va = inputs.grid_laplacian((48, 48, 48), jitter=0.1, seed=2)
+    n, nnz = len(rp) - 1, len(ci)
+    h = amg.Hierarchy(dev(rp), dev(ci), dev(va))
+    us, by = ctypes.c_double(), ctypes.c_double()
+    assert amg.amg_time_smoother(h._h, 3, ctypes.byref(us), ctypes.byref(by)) == amg.AMG_ERR_UNSUPPORTED
+    b = inputs.rhs(n, 4)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    h.solve(dev(b), x, tol=1e-8)
+    avg_us, alg = h.time_smoother(3)
+    nc = h.level_sizes(1)[0]
+    assert h.level_slots(0) > 0 and avg_us > 0
+    assert alg == 12.0 * nnz + 4.0 * (n + 1) + 36.0 * n + 16.0 * nc
+    h.close()
