@@ -102,18 +102,15 @@ def traffic_from(args):
     ratio the same counters show for the reference copy of known size."""
     import sqlite3
 
-    def per_kernel(db, counter):
+    def per_kernel(db, counter):  # (kernel name, value) in dispatch order
         con = sqlite3.connect(db)
-        out = {}
-        for kname, cname, val in con.execute(
-                "select kernel_name, counter_name, value from counters_collection order by dispatch_id"):
-            if cname == counter:
-                out.setdefault(kname, []).append(val)
-        return out
+        return [(kname, val) for kname, cname, val in con.execute(
+            "select kernel_name, counter_name, value from counters_collection order by dispatch_id")
+            if cname == counter]
 
     fetch = per_kernel(args.traffic_from[0], "FETCH_SIZE")
     write = per_kernel(args.traffic_from[1], "WRITE_SIZE")
-    pick = lambda d, key: [v for k, vs in d.items() if key(k) for v in vs]
+    pick = lambda d, key: [v for k, v in d if key(k)]
 
     def reference(d):  # the 256 MiB copies: the largest copy dispatches of the probe
         vals = pick(d, lambda k: "copybuffer" in k.lower())
@@ -122,8 +119,9 @@ def traffic_from(args):
 
     copy_f, copy_w = reference(fetch), reference(write)
     # the finest post-smoothing step as amg_time_smoother launches it, the last five
-    # steps of the probe: on levels of at least 100k rows two kernels (start: the
-    # iterate, finish: the smoothing sweep), whose counters add up, else one
+    # steps of the probe (its last dispatches of these kernels): on levels of at least
+    # 100k rows two kernels (start: the iterate, finish: the smoothing sweep), whose
+    # counters add up, else one
     med = lambda v: sorted(v)[len(v) // 2]
 
     def step(d):
