@@ -109,9 +109,15 @@ void launch_validate_csr(int n, int nnz, const int *rp, const int *ci, const dou
 void launch_inverse_diagonal(int n, const int *rp, const int *ci, const double *va, double weight, double *minv,
                              hipStream_t s);
 void launch_priorities(int n, const int *rp, uint32_t s_l, uint64_t *key, int *owner, hipStream_t s);
-// one pass of Alg. 2; rows longer than lim (listed in hubs) are served by whole blocks
+// one pass of Alg. 2; rows longer than lim (listed in hubs) are served by whole blocks.
+// done_counter: kDoneSlots counters kDoneStride apart (block b adds the vertices it
+// processed to slot b % kDoneSlots, so that no single address takes every block's
+// atomic); launch_sum_slots writes their total to *out.
+constexpr int kDoneSlots = 256;
+constexpr int kDoneStride = 32;  // one 128-byte line per slot
 void launch_mis_pass(int n, const int *rp, const int *ci, uint64_t *key, uint64_t *m1, int *owner, int cap, int G,
                      unsigned *done_counter, const int *hubs, int nhub, int lim, hipStream_t s);
+void launch_sum_slots(const unsigned *slots, unsigned *out, hipStream_t s);
 void launch_centre_flags(int n, const int *owner, int *flag, hipStream_t s);
 void launch_assign_aggregates(int n, const int *owner, const int *cid, int *agg, int *centre_of, hipStream_t s);
 void launch_member_counts(int nc, const int *rp, const int *ci, const int *owner, const int *centre_of, int *size,

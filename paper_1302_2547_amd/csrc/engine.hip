@@ -486,7 +486,7 @@ void amg_hierarchy::build(const amg_csr &A)
         AMG_HIP(hipMemcpyAsync(L0.va_nat, A.values, sizeof(double) * (size_t)nnz0, hipMemcpyDeviceToDevice, stream));
     }
     // setup scratch, sized by the finest level and released at the end of setup
-    int *ibuf = pool.alloc<int>(16);  // 0 err, 1 done, 2 big_count, 3 nc, 4 total, 5 nnz_c, 8.. pass counts
+    int *ibuf = pool.alloc<int>(16);  // 0 err, 2 big_count, 3 nc, 4 total, 5 nnz_c, 8.. pass counts
     uint64_t *key = pool.alloc<uint64_t>(n0);
     uint64_t *m1 = pool.alloc<uint64_t>(n0);
     int *owner = pool.alloc<int>(n0);
@@ -500,7 +500,7 @@ void amg_hierarchy::build(const amg_csr &A)
     double *tval = pool.alloc<double>(nnz0);
     int *big_rows = pool.alloc<int>(n0);
     int *scan_tmp = pool.alloc<int>(scan_tmp_ints((int64_t)nnz0 + 1));
-    unsigned *done = reinterpret_cast<unsigned *>(ibuf + 1);
+    unsigned *done = pool.alloc<unsigned>((size_t)kDoneSlots * kDoneStride);  // per-block-group counters
     unsigned *big_count = reinterpret_cast<unsigned *>(ibuf + 2);
 
     AMG_HIP(hipMemsetAsync(ibuf, 0, 16 * sizeof(int), stream));
@@ -518,7 +518,7 @@ void amg_hierarchy::build(const amg_csr &A)
         AMG_TRACE_MSG("level %d: n=%d nnz=%d G=%d aggregation", l, n, nnz, G);
         const uint32_t s_l = (uint32_t)splitmix64(opt.seed, (uint64_t)l);
         launch_priorities(n, lev[l].rp_nat, s_l, key, owner, stream);
-        AMG_HIP(hipMemsetAsync(done, 0, sizeof(unsigned), stream));
+        AMG_HIP(hipMemsetAsync(done, 0, sizeof(unsigned) * kDoneSlots * kDoneStride, stream));
         // hub rows (longer than 8 G) of this level, served by whole blocks in the passes
         const int lim = 8 * G;
         launch_long_rows(n, lev[l].rp_nat, lim, tptr, nullptr, tptr + n, scan_tmp, stream);
@@ -537,7 +537,7 @@ void amg_hierarchy::build(const amg_csr &A)
             for (int b = 0; b < kPassBatch; b++) {
                 launch_mis_pass(n, lev[l].rp_nat, lev[l].ci_nat, key, m1, owner, opt.max_aggregate, G, done,
                                 big_rows, nhub, lim, stream);
-                AMG_HIP(hipMemcpyAsync(after + b, done, sizeof(unsigned), hipMemcpyDeviceToDevice, stream));
+                launch_sum_slots(done, after + b, stream);
             }
             to_host(after_h, after, kPassBatch);
             for (int b = 0; b < kPassBatch && processed < (unsigned)n; b++) {
@@ -609,7 +609,7 @@ void amg_hierarchy::build(const amg_csr &A)
     }
     sync();
     for (void *ptr : std::initializer_list<void *>{key, m1, owner, cid, centre_of, size, pairs, cnt, tptr, tcol, tval,
-                                                  big_rows, scan_tmp})
+                                                  big_rows, scan_tmp, done})
         pool.release(ptr);
 
     // coarsest level: exact solve.  Unknowns with no off-diagonal entry in their row

@@ -348,7 +348,20 @@ __global__ void __launch_bounds__(kBlock) k_mis_select_claim(int n, const int *_
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0 && block_done) atomicAdd(done, block_done);
+    if (threadIdx.x == 0 && block_done) atomicAdd(done + (blockIdx.x % kDoneSlots) * kDoneStride, block_done);
+}
+
+// *out = sum of the kDoneSlots counters (one block of kDoneSlots threads).
+__global__ void __launch_bounds__(kDoneSlots) k_sum_slots(const unsigned *__restrict__ slots, unsigned *__restrict__ out)
+{
+    __shared__ unsigned sh[kDoneSlots];
+    sh[threadIdx.x] = slots[threadIdx.x * kDoneStride];
+    __syncthreads();
+    for (int h = kDoneSlots / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 // ------------------------------------------------------------------ numbering (Sec. 5.1)
@@ -1195,6 +1208,12 @@ void launch_mis_pass(int n, const int *rp, const int *ci, uint64_t *key, uint64_
     const int grid = nhb + grid_for((int64_t)n * G);
     AMG_LAUNCH_G(G, k_mis_max1, grid, s, n, rp, ci, key, m1, hubs, nhub, lim);
     AMG_LAUNCH_G(G, k_mis_select_claim, grid, s, n, rp, ci, key, m1, owner, cap, done_counter, hubs, nhub, lim);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_sum_slots(const unsigned *slots, unsigned *out, hipStream_t s)
+{
+    k_sum_slots<<<1, kDoneSlots, 0, s>>>(slots, out);
     AMG_HIP(hipGetLastError());
 }
 
