@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(kBlock) k_member_fill(int nc, const int *__res
 // each segment of equal J is summed sequentially in position order, which is the
 // order of a row-by-row accumulation over (s, t).
 
-constexpr int kWaveCap = 512;  // pairs one wavefront sorts in LDS
+constexpr int kWaveCap = 256;  // pairs one wavefront sorts in LDS (18 KB of LDS per block: 8 blocks per CU)
 constexpr int kWavesPerBlock = kBlock / kWave;
 
 __global__ void __launch_bounds__(kBlock) k_coarse_rows(int nc, const int *__restrict__ rp,
