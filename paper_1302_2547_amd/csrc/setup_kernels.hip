@@ -1292,7 +1292,7 @@ void launch_coarse_big_rows_acc(int nbig, const int *big_rows, int nc, const int
 void launch_coarse_compact(int nc, const int *tptr, const int *tcol, const double *tval, const int *crp, int *cci,
                            double *cva, double weight, double *cminv, hipStream_t s)
 {
-    const int G = wide(nc) ? kWave : 1;
+    const int G = wide(nc) ? kWave : 8;  // coarse rows hold ~10-20 entries
     AMG_LAUNCH_G(G, k_coarse_compact, grid_for((int64_t)nc * G), s, nc, tptr, tcol, tval, crp, cci, cva, weight, cminv);
     AMG_HIP(hipGetLastError());
 }
