@@ -1081,8 +1081,9 @@ void amg_hierarchy::run_iter(int ncol)
 // stay valid.
 // ---------------------------------------------------------------- lane-count autotuner
 // On levels of at least kSmallLevel rows (bandwidth-bound) the lanes per row of A (G,
-// used by the SpMVs and smoothers) and of the super-rows (Gs, used by the restriction)
-// are chosen by measurement: each candidate launch of the post-smoother and of the
+// used by the SpMVs and smoothers) and of the super-rows (Gs, used by the restriction),
+// or on a level with a sliced copy the row tiles per block of its sweeps (tpb), are
+// chosen by measurement: each candidate launch of the post-smoother and of the
 // restriction is timed with HIP events on the hierarchy's stream (one warm-up launch,
 // then kTuneReps), and the fastest wins.  The rows table does not depend on the choice
 // (rows beyond its hub threshold are served by chunks whatever G is).  Choices are cached
@@ -1167,11 +1168,13 @@ void amg_hierarchy::autotune_level(int l, int ncol)
         return best;
     };
     if (F.sell.ptr) {
-        // sliced copy: tiles per block of the post-smoother with its inner product
-        // (the partials go to a dot site the solve rewrites before reading)
+        // sliced copy: tiles per block (candidates g = 2..16 give g / 2 = 1..8) of the
+        // post-smoother with its inner product; the partials go to a dot site that
+        // the solve rewrites before reading it.  The restriction reads the same copy.
         Sell &S = F.sell;
         const DotBuf scratch = l == 0 ? d_zq : F.d_c1;
-        S.tpb = pick(2, 8.0, S.tpb, [&](int g) {
+        const double max_candidate = 8.0;  // pick() skips g > 2 * 8 + 2
+        S.tpb = pick(2, max_candidate, 2 * S.tpb, [&](int g) {
             S.tpb = g / 2;
             launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rv, F.agg_pos, F.cagg, 0, CK.c1, nullptr, nullptr,
                                   KDots{}, out, rv, scratch, flag, F.G, stream, ainv, C.n, ncol, F.xs, &S, FK.sva);
@@ -1182,8 +1185,6 @@ void amg_hierarchy::autotune_level(int l, int ncol)
             launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rv, F.agg_pos, F.cagg, 0, CK.c1, nullptr, nullptr,
                                   KDots{}, out, nullptr, DotBuf{}, flag, g, stream, ainv, C.n, ncol, F.xs);
         });
-    }
-    if (!F.sell.ptr) {  // (a sliced level restricts from its sliced copy)
         F.Gs = pick(1, (double)F.nnz / C.n, F.Gs, [&](int g) {
             launch_restrict<T>(F.S, F.n, F.sci, FK.wv, rv, CK.rc, g, stream, nullptr, DotBuf{}, ncol);
         });
