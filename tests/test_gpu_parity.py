@@ -460,3 +460,33 @@ def test_time_smoother_needs_a_kcycle(amg):
     assert h.level_slots(0) > 0 and avg_us > 0
     assert alg == 12.0 * nnz + 4.0 * (n + 1) + 36.0 * n + 16.0 * nc
     h.close()
+
+
+def test_wide_slice_keeps_csr(amg):
+    """A level of at least 100k rows with one row of more than 64 entries (a vertex
+    joined to 200 others on top of a grid) would need a slice of that width: the
+    level keeps CSR only, and the K-cycle and the solve still match the oracle."""
+    import scipy.sparse as sp
+    rp, ci, va = inputs.grid_laplacian((400, 300), jitter=0.2, seed=12)
+    n = len(rp) - 1
+    a = sp.csr_matrix((va, ci, rp), shape=(n, n))
+    star = sp.coo_matrix((-np.ones(200), (np.zeros(200, dtype=np.int64), np.arange(1, 201))), shape=(n, n))
+    lap = star + star.T
+    lap = lap - sp.diags(np.asarray(lap.sum(axis=1)).ravel())
+    a = (a + lap).tocsr()
+    a.sort_indices()
+    rp2, ci2, va2 = a.indptr.astype(np.int32), a.indices.astype(np.int32), a.data.astype(np.float64)
+    assert np.diff(rp2).max() > 64
+    h, ref = setup_both(amg, rp2, ci2, va2)
+    assert h.level_slots(0) == 0
+    r = inputs.rhs(n, 23)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.kcycle(dev(r), z)
+    zo = ref.kcycle(r)
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-10 * np.abs(zo).max())
+    b = inputs.rhs(n, 24)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, info = h.solve(dev(b), x, tol=1e-8)
+    res = b - oracle.spmv(rp2, ci2, va2, x.cpu().numpy())
+    assert st == amg.AMG_OK and np.linalg.norm(res) / np.linalg.norm(b) <= 1e-8
+    h.close()
