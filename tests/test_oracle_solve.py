@@ -194,3 +194,85 @@ def test_indefinite_input_is_detected():
         return
     _, st, _, _, _ = h.solve(inputs.rhs(100, 2), tol=1e-10)
     assert st == oracle.ERR_BREAKDOWN
+
+
+# --- exact pins of the inner flexible-CG steps of the K-cycle (Sec. 4.3) -------------------
+#
+# Two flexible-CG steps from zero on A_c e = g, the second direction A_c-orthogonalised
+# against the first (truncation 1), leave e equal to the A_c-Galerkin solution on the
+# span of the two preconditioned vectors: e = V (V^T A_c V)^-1 V^T g with V = [c1, c2],
+# c1 = B g and c2 = B (g - alpha A_c c1), alpha = (c1, g) / (c1, A_c c1).  The
+# references below use that characterisation (a 2 x 2 dense solve) instead of the
+# CG recurrences, so a wrong or missing orthogonalisation, a sign error in the inner
+# residual or a wrong step length changes the result.
+
+def dense_hierarchy(h):
+    levels = [h.level(l) for l in range(h.num_levels)]
+    mats = [dense(L.row_ptr, L.col, L.val) for L in levels]
+    prols = [prolongation(L.agg, levels[l + 1].n) for l, L in enumerate(levels[:-1])]
+    return levels, mats, prols
+
+
+def kcycle_galerkin(levels, mats, prols, k, r, nu):
+    """K-cycle on level k written with the Galerkin characterisation of its inner steps."""
+    a, m = mats[k], levels[k].minv
+    last = len(levels) - 1
+    if k == last:
+        return np.linalg.solve(a, r)
+    p = prols[k]
+    x = m * r
+    g = p.T @ (r - a @ x)
+    ac = mats[k + 1]
+    if k + 1 == last:
+        e = np.linalg.solve(ac, g)
+    else:
+        c1 = kcycle_galerkin(levels, mats, prols, k + 1, g, nu)
+        if nu == 1:
+            e = (c1 @ g) / (c1 @ ac @ c1) * c1
+        else:
+            alpha = (c1 @ g) / (c1 @ ac @ c1)
+            c2 = kcycle_galerkin(levels, mats, prols, k + 1, g - alpha * (ac @ c1), nu)
+            v = np.column_stack([c1, c2])
+            e = v @ np.linalg.solve(v.T @ ac @ v, v.T @ g)
+    x = x + p @ e
+    return x + m * (r - a @ x)
+
+
+def test_three_level_nu2_kcycle_is_galerkin_on_the_krylov_pair():
+    """Three levels: K(1, .) is the fixed two-grid matrix B1, so the two inner steps
+    give the A1-Galerkin solution on span{B1 g, B1 A1 B1 g} (a Krylov space)."""
+    rp, ci, va = inputs.grid_laplacian((12, 12), jitter=0.2, seed=5)
+    h = oracle.Hierarchy(rp, ci, va, coarsest_size=20, kcycle_inner=2)
+    assert h.num_levels == 3
+    levels, (a0, a1, a2), (p0, p1) = dense_hierarchy(h)
+    b1 = two_grid_matrix(a1, levels[1].minv, p1, np.linalg.inv(a2))
+    m0 = np.diag(levels[0].minv)
+    for seed in (3, 4):
+        r = inputs.rhs(levels[0].n, seed)
+        x1 = m0 @ r
+        g = p0.T @ (r - a0 @ x1)
+        v = np.column_stack([b1 @ g, b1 @ a1 @ b1 @ g])
+        e = v @ np.linalg.solve(v.T @ a1 @ v, v.T @ g)
+        x2 = x1 + p0 @ e
+        expect = x2 + m0 @ (r - a0 @ x2)
+        got = h.kcycle(r)
+        np.testing.assert_allclose(got, expect, rtol=0, atol=1e-12 * np.abs(expect).max())
+        # one inner step only would be a different vector
+        e1 = (v[:, 0] @ g) / (v[:, 0] @ a1 @ v[:, 0]) * v[:, 0]
+        x2b = x1 + p0 @ e1
+        assert np.abs(x2b + m0 @ (r - a0 @ x2b) - expect).max() > 1e-6 * np.abs(expect).max()
+
+
+@pytest.mark.parametrize("dims,coarsest,nu", [((10, 9, 8), 10, 2), ((20, 20), 4, 2), ((20, 20), 4, 1),
+                                              ((16, 16), 8, 2)])
+def test_deep_kcycle_matches_the_galerkin_recursion(dims, coarsest, nu):
+    """Four to six levels: the oracle's K-cycle equals the recursion whose inner
+    steps are Galerkin solutions on the span of the recursive directions."""
+    rp, ci, va = inputs.grid_laplacian(dims, jitter=0.2, seed=5)
+    h = oracle.Hierarchy(rp, ci, va, coarsest_size=coarsest, kcycle_inner=nu)
+    assert h.num_levels >= 4
+    levels, mats, prols = dense_hierarchy(h)
+    for seed in (1, 2):
+        r = inputs.rhs(levels[0].n, seed)
+        expect = kcycle_galerkin(levels, mats, prols, 0, r, nu)
+        np.testing.assert_allclose(h.kcycle(r), expect, rtol=0, atol=1e-12 * np.abs(expect).max())
