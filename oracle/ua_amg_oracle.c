@@ -363,6 +363,7 @@ typedef struct {
     orc_level lev[ORC_MAX_LEVELS];
     double *chol; /* lower Cholesky factor of the coarsest matrix, dense row-major */
     int nu;       /* inner flexible-CG steps per coarse level visit */
+    double theta; /* K-cycle threshold: later inner steps are skipped once ||rr|| < theta ||g|| */
     double setup_ms;
     int breakdown;
 } orc_hierarchy;
@@ -376,6 +377,7 @@ typedef struct {
     int kcycle_inner;     /* nu */
     int smoother;         /* 0: l1-Jacobi, 1: damped Jacobi */
     double jacobi_weight; /* omega of the damped Jacobi smoother */
+    double kcycle_threshold; /* theta >= 0; 0 = always nu inner steps */
 } orc_options;
 
 static void free_level(orc_level *L, int own_matrix)
@@ -462,6 +464,7 @@ void orc_default_options(orc_options *o)
     o->kcycle_inner = 2;
     o->smoother = 0;
     o->jacobi_weight = 2.0 / 3.0;
+    o->kcycle_threshold = 0.0;
 }
 
 /* Alg. 1, setup phase.  Copies the input matrix. */
@@ -472,13 +475,15 @@ int orc_setup(int n, int nnz, const int *rp, const int *ci, const double *va,
     *out = NULL;
     if (!opt || opt->max_levels < 1 || opt->max_levels > ORC_MAX_LEVELS || opt->kcycle_inner < 1 ||
         opt->coarsest_size < 1 || opt->max_aggregate < 0 || opt->max_aggregate == 1 || opt->smoother < 0 ||
-        opt->smoother > 1 || !(opt->jacobi_weight > 0.0) || !isfinite(opt->jacobi_weight))
+        opt->smoother > 1 || !(opt->jacobi_weight > 0.0) || !isfinite(opt->jacobi_weight) ||
+        !(opt->kcycle_threshold >= 0.0) || !isfinite(opt->kcycle_threshold))
         return ORC_ERR_ARG;
     int st = orc_check_csr(n, nnz, rp, ci, va);
     if (st) return st;
     orc_hierarchy *h = (orc_hierarchy *)calloc(1, sizeof(orc_hierarchy));
     if (!h) return ORC_ERR_NOMEM;
     h->nu = opt->kcycle_inner;
+    h->theta = opt->kcycle_threshold;
     orc_level *L0 = &h->lev[0];
     L0->n = n;
     L0->nnz = nnz;
@@ -572,7 +577,10 @@ int orc_level_export(const orc_hierarchy *h, int l, int *agg, int *rp, int *ci, 
 static void kcycle(orc_hierarchy *h, int k, const double *r, double *x);
 
 /* nu steps of flexible CG on level c for A_c e = g from e = 0, each step
- * preconditioned by the K-cycle of level c; the result is left in lev[c].e. */
+ * preconditioned by the K-cycle of level c; the result is left in lev[c].e.
+ * With a threshold theta > 0 the steps after the first stop as soon as the inner
+ * residual is small enough, ||rr||_2 < theta ||g||_2 (compared as squares): the
+ * K-cycle's test of whether a second Krylov step is worth its recursive cost. */
 static void inner_fcg(orc_hierarchy *h, int c, const double *g)
 {
     orc_level *C = &h->lev[c];
@@ -582,7 +590,9 @@ static void inner_fcg(orc_hierarchy *h, int c, const double *g)
         C->e[i] = 0.0;
         C->rr[i] = g[i];
     }
+    const double gg = h->theta > 0.0 ? dot(n, g, g) : 0.0;
     for (int j = 0; j < h->nu; j++) {
+        if (j > 0 && h->theta > 0.0 && dot(n, C->rr, C->rr) < h->theta * h->theta * gg) return;
         kcycle(h, c, C->rr, C->w);                    /* w = B_c rr */
         orc_spmv(n, C->rp, C->ci, C->va, C->w, C->aw); /* A_c w */
         if (j == 0) {

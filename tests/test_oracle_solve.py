@@ -276,3 +276,60 @@ def test_deep_kcycle_matches_the_galerkin_recursion(dims, coarsest, nu):
         r = inputs.rhs(levels[0].n, seed)
         expect = kcycle_galerkin(levels, mats, prols, 0, r, nu)
         np.testing.assert_allclose(h.kcycle(r), expect, rtol=0, atol=1e-12 * np.abs(expect).max())
+
+
+def kcycle_galerkin_threshold(levels, mats, prols, k, r, theta, skips):
+    """As kcycle_galerkin with nu = 2, except that the second inner direction is
+    dropped when the inner residual after the first step satisfies
+    ||g - alpha A c1|| < theta ||g||; skips counts those visits."""
+    a, m = mats[k], levels[k].minv
+    last = len(levels) - 1
+    p = prols[k]
+    x = m * r
+    g = p.T @ (r - a @ x)
+    ac = mats[k + 1]
+    if k + 1 == last:
+        e = np.linalg.solve(ac, g)
+    else:
+        c1 = kcycle_galerkin_threshold(levels, mats, prols, k + 1, g, theta, skips)
+        alpha = (c1 @ g) / (c1 @ ac @ c1)
+        rt = g - alpha * (ac @ c1)
+        if rt @ rt < theta * theta * (g @ g):
+            skips[0] += 1
+            e = alpha * c1
+        else:
+            c2 = kcycle_galerkin_threshold(levels, mats, prols, k + 1, rt, theta, skips)
+            v = np.column_stack([c1, c2])
+            e = v @ np.linalg.solve(v.T @ ac @ v, v.T @ g)
+    x = x + p @ e
+    return x + m * (r - a @ x)
+
+
+def test_kcycle_threshold_readings():
+    """K-cycle threshold theta (Sec. 4.3's cycle, in the form that tests whether a
+    second inner step pays): theta = 0 is the default cycle bit for bit; a huge theta
+    always stops after one step, i.e. nu = 1 bit for bit; in between the oracle takes
+    the second step exactly where the Galerkin recursion with the same test does."""
+    rp, ci, va = inputs.grid_laplacian((10, 9, 8), jitter=0.2, seed=5)
+    r = inputs.rhs(len(rp) - 1, 3)
+    base = oracle.Hierarchy(rp, ci, va, coarsest_size=10).kcycle(r)
+    zero = oracle.Hierarchy(rp, ci, va, coarsest_size=10, kcycle_threshold=0.0).kcycle(r)
+    assert np.array_equal(base, zero)
+    one = oracle.Hierarchy(rp, ci, va, coarsest_size=10, kcycle_inner=1).kcycle(r)
+    huge = oracle.Hierarchy(rp, ci, va, coarsest_size=10, kcycle_threshold=1e300).kcycle(r)
+    assert np.array_equal(one, huge)
+    levels, mats, prols = dense_hierarchy(oracle.Hierarchy(rp, ci, va, coarsest_size=10))
+    assert [L.n for L in levels] == [720, 284, 56, 15, 4]   # inner pairs on levels 1-3: at most 7 tests
+    for theta in (0.1, 0.3, 0.7):
+        h = oracle.Hierarchy(rp, ci, va, coarsest_size=10, kcycle_threshold=theta)
+        skips = [0]
+        expect = kcycle_galerkin_threshold(levels, mats, prols, 0, r, theta, skips)
+        np.testing.assert_allclose(h.kcycle(r), expect, rtol=0, atol=1e-12 * np.abs(expect).max())
+        assert 0 < skips[0] < 7   # both branches of the test are taken
+
+
+def test_kcycle_threshold_is_validated():
+    rp, ci, va = inputs.grid_laplacian((8, 8))
+    for bad in (-0.1, float("nan"), float("inf")):
+        with pytest.raises(RuntimeError, match="status 1"):
+            oracle.Hierarchy(rp, ci, va, kcycle_threshold=bad)
