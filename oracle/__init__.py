@@ -38,7 +38,7 @@ class _Options(ctypes.Structure):
                 ("stall_ratio", ctypes.c_double), ("max_aggregate", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("kcycle_inner", ctypes.c_int),
                 ("smoother", ctypes.c_int), ("jacobi_weight", ctypes.c_double),
-                ("kcycle_threshold", ctypes.c_double)]
+                ("kcycle_threshold", ctypes.c_double), ("skip_ratio", ctypes.c_double)]
 
 SMOOTHERS = {"l1": 0, "jacobi": 1}
 
@@ -206,7 +206,8 @@ class Hierarchy:
     """Oracle hierarchy (Alg. 1 setup); owns C memory, freed on close()/del."""
 
     def __init__(self, rp, ci, va, coarsest_size=64, max_levels=40, stall_ratio=0.9, max_aggregate=0,
-                 seed=0x5EED5EED, kcycle_inner=2, smoother="l1", jacobi_weight=2.0 / 3.0, kcycle_threshold=0.0):
+                 seed=0x5EED5EED, kcycle_inner=2, smoother="l1", jacobi_weight=2.0 / 3.0, kcycle_threshold=0.0,
+                 skip_ratio=0.0):
         lib = _load()
         rp, ci, va = _csr(rp, ci, va)
         opt = _Options()
@@ -215,6 +216,7 @@ class Hierarchy:
         opt.max_aggregate, opt.seed, opt.kcycle_inner = max_aggregate, seed & (2**64 - 1), kcycle_inner
         opt.smoother, opt.jacobi_weight = SMOOTHERS[smoother], jacobi_weight
         opt.kcycle_threshold = kcycle_threshold
+        opt.skip_ratio = skip_ratio
         self._h = ctypes.c_void_p()
         st = lib.orc_setup(len(rp) - 1, len(ci), rp, ci, va, ctypes.byref(opt), ctypes.byref(self._h))
         if st:

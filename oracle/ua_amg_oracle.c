@@ -378,6 +378,7 @@ typedef struct {
     int smoother;         /* 0: l1-Jacobi, 1: damped Jacobi */
     double jacobi_weight; /* omega of the damped Jacobi smoother */
     double kcycle_threshold; /* theta >= 0; 0 = always nu inner steps */
+    double skip_ratio;       /* aggregate twice when n_l / n_c < skip_ratio (Sec. 3.3); 0 = never */
 } orc_options;
 
 static void free_level(orc_level *L, int own_matrix)
@@ -465,6 +466,29 @@ void orc_default_options(orc_options *o)
     o->smoother = 0;
     o->jacobi_weight = 2.0 / 3.0;
     o->kcycle_threshold = 0.0;
+    o->skip_ratio = 0.0;
+}
+
+/* One aggregation (Alg. 2 with the priorities of eq. (3.2) and the numbering of
+ * Sec. 5.1) of the graph of a level; `index` selects rand()'s stream.  Returns the
+ * number of aggregates (or -status) and the coarse column of every vertex. */
+static int aggregate(int n, const int *rp, const int *ci, const orc_options *opt, int index, int **agg_out,
+                     int *passes_out)
+{
+    uint64_t *key = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    int *owner = (int *)malloc(sizeof(int) * (size_t)n);
+    int *agg = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!key || !owner || !agg) { free(key); free(owner); free(agg); return -ORC_ERR_NOMEM; }
+    orc_priorities(n, rp, ci, opt->seed, index, key);
+    int passes = orc_paa(n, rp, ci, key, opt->max_aggregate, owner, NULL);
+    free(key);
+    if (passes < 0) { free(owner); free(agg); return passes; }
+    int nc = orc_number(n, owner, agg);
+    free(owner);
+    if (nc < 0) { free(agg); return nc; }
+    *agg_out = agg;
+    *passes_out = passes;
+    return nc;
 }
 
 /* Alg. 1, setup phase.  Copies the input matrix. */
@@ -476,7 +500,8 @@ int orc_setup(int n, int nnz, const int *rp, const int *ci, const double *va,
     if (!opt || opt->max_levels < 1 || opt->max_levels > ORC_MAX_LEVELS || opt->kcycle_inner < 1 ||
         opt->coarsest_size < 1 || opt->max_aggregate < 0 || opt->max_aggregate == 1 || opt->smoother < 0 ||
         opt->smoother > 1 || !(opt->jacobi_weight > 0.0) || !isfinite(opt->jacobi_weight) ||
-        !(opt->kcycle_threshold >= 0.0) || !isfinite(opt->kcycle_threshold))
+        !(opt->kcycle_threshold >= 0.0) || !isfinite(opt->kcycle_threshold) || !(opt->skip_ratio >= 0.0) ||
+        !isfinite(opt->skip_ratio))
         return ORC_ERR_ARG;
     int st = orc_check_csr(n, nnz, rp, ci, va);
     if (st) return st;
@@ -497,32 +522,53 @@ int orc_setup(int n, int nnz, const int *rp, const int *ci, const double *va,
     memcpy(L0->va, va, sizeof(double) * (size_t)nnz);
 
     int l = 0;
+    int aggregations = 0; /* rand() of eq. (3.2) is drawn per aggregation, counted from 0 */
     while (h->lev[l].n > opt->coarsest_size && l + 1 < opt->max_levels) {
         orc_level *F = &h->lev[l];
-        uint64_t *key = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)F->n);
-        int *owner = (int *)malloc(sizeof(int) * (size_t)F->n);
-        F->agg = (int *)malloc(sizeof(int) * (size_t)F->n);
-        if (!key || !owner || !F->agg) { free(key); free(owner); orc_free(h); return ORC_ERR_NOMEM; }
-        orc_priorities(F->n, F->rp, F->ci, opt->seed, l, key);
-        int passes = orc_paa(F->n, F->rp, F->ci, key, opt->max_aggregate, owner, NULL);
-        free(key);
-        if (passes < 0) { free(owner); orc_free(h); return -passes; }
-        F->passes = passes;
-        int nc = orc_number(F->n, owner, F->agg);
-        free(owner);
+        int passes = 0;
+        int nc = aggregate(F->n, F->rp, F->ci, opt, aggregations, &F->agg, &passes);
         if (nc < 0) { orc_free(h); return -nc; }
         if ((double)nc > opt->stall_ratio * (double)F->n) { /* coarsening stalled */
             free(F->agg);
             F->agg = NULL;
-            F->passes = 0;
             break;
         }
+        aggregations++;
+        F->passes = passes;
         orc_level *C = &h->lev[l + 1];
         st = orc_coarse_operator(F->n, F->rp, F->ci, F->va, F->agg, nc, &C->rp, &C->ci, &C->va);
         if (st) { orc_free(h); return st; }
         C->n = nc;
         C->nnz = C->rp[nc];
         h->nlev = l + 2;
+        /* Sec. 3.3: a small coarsening ratio is compensated by applying the
+         * aggregation a second time, to the coarse graph just built, and keeping only
+         * the result: level l's aggregates become the unions of the second
+         * aggregation's groups, and the intermediate level is not kept.  Not done
+         * when the intermediate level is already coarse enough to end the hierarchy,
+         * or when the second aggregation stalls. */
+        if (opt->skip_ratio > 0.0 && (double)F->n < opt->skip_ratio * (double)nc && nc > opt->coarsest_size &&
+            l + 2 < opt->max_levels) {
+            int *agg2 = NULL, passes2 = 0;
+            int nc2 = aggregate(C->n, C->rp, C->ci, opt, aggregations, &agg2, &passes2);
+            if (nc2 < 0) { orc_free(h); return -nc2; }
+            if ((double)nc2 <= opt->stall_ratio * (double)C->n) {
+                aggregations++;
+                int *rp2 = NULL, *ci2 = NULL;
+                double *va2 = NULL;
+                st = orc_coarse_operator(C->n, C->rp, C->ci, C->va, agg2, nc2, &rp2, &ci2, &va2);
+                if (st) { free(agg2); orc_free(h); return st; }
+                for (int i = 0; i < F->n; i++) F->agg[i] = agg2[F->agg[i]]; /* P = P1 P2 */
+                F->passes += passes2;
+                free(C->rp); free(C->ci); free(C->va);
+                C->rp = rp2;
+                C->ci = ci2;
+                C->va = va2;
+                C->n = nc2;
+                C->nnz = rp2[nc2];
+            }
+            free(agg2);
+        }
         l++;
     }
     for (int k = 0; k < h->nlev; k++) {

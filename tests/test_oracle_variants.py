@@ -92,3 +92,85 @@ def test_invalid_jacobi_weight_is_rejected():
     for w in (0.0, -1.0, float("nan")):
         with pytest.raises(RuntimeError):
             oracle.Hierarchy(rp, ci, va, smoother="jacobi", jacobi_weight=w)
+
+
+# --- level skipping: the aggregation applied twice (Sec. 3.3) ------------------------------
+
+def prolongation(agg, nc):
+    p = np.zeros((len(agg), nc))
+    p[np.arange(len(agg)), agg] = 1.0
+    return p
+
+
+def levels_of(h):
+    return [h.level(l) for l in range(h.num_levels)]
+
+
+@pytest.mark.parametrize("case", ["grid3d_int", "rgg_int"])
+def test_level_skipping_galerkin_with_composed_prolongation(case):
+    """Each kept coarse matrix is exactly P^T A P with P the (composed) piecewise-
+    constant prolongation of its fine level (integer weights: no rounding), and a
+    level whose first aggregation coarsened by less than the ratio was aggregated
+    again unless the stop rule or the stall rule prevented it."""
+    if case == "grid3d_int":
+        rp, ci, va = inputs.grid_laplacian((14, 13, 12), jitter=0.0)
+        va = va * 3.0
+    else:
+        rp, ci, va = inputs.random_graph_laplacian(400, 0.012, seed=7, integer_weights=True, shift=1.0)
+    ratio = 2.5
+    # a size limit t = 2 coarsens by at most 2 (Sec. 3.3's motivation for aggregating twice)
+    h = oracle.Hierarchy(rp, ci, va, coarsest_size=8, max_aggregate=2, skip_ratio=ratio)
+    plain = oracle.Hierarchy(rp, ci, va, coarsest_size=8, max_aggregate=2)
+    lv = levels_of(h)
+    assert h.num_levels < plain.num_levels   # at least one level was skipped
+    for l in range(h.num_levels - 1):
+        a = dense(lv[l].row_ptr, lv[l].col, lv[l].val)
+        p = prolongation(lv[l].agg, lv[l + 1].n)
+        assert np.array_equal(dense(lv[l + 1].row_ptr, lv[l + 1].col, lv[l + 1].val), p.T @ a @ p)
+        assert sorted(set(lv[l].agg.tolist())) == list(range(lv[l + 1].n))
+
+
+def test_level_skipping_is_two_consecutive_aggregations():
+    """Applying the aggregation twice is skipping a level: with priorities drawn per
+    aggregation, the skipping hierarchy's coarse level equals the level two below in
+    the plain hierarchy (matrix bit for bit), and its aggregates are the plain
+    aggregates of the intermediate level composed with the fine ones."""
+    rp, ci, va = inputs.grid_laplacian((24, 22, 20), jitter=0.1, seed=2)
+    ratio = 2.4
+    plain = levels_of(oracle.Hierarchy(rp, ci, va, coarsest_size=16, max_aggregate=3))
+    skip = levels_of(oracle.Hierarchy(rp, ci, va, coarsest_size=16, max_aggregate=3, skip_ratio=ratio))
+    ratios = [plain[l].n / plain[l + 1].n for l in range(len(plain) - 1)]
+    assert min(ratios) < ratio < max(ratios)   # some levels are skipped, some kept
+    # walk the plain hierarchy, skipping where the ratio is small (not into the coarsest)
+    l, k = 0, 0
+    skipped = 0
+    while l < len(plain) - 1:
+        if ratios[l] < ratio and l + 2 < len(plain) and plain[l + 1].n > 16:
+            assert np.array_equal(skip[k].agg, plain[l + 1].agg[plain[l].agg])
+            nxt = l + 2
+            skipped += 1
+        else:
+            assert np.array_equal(skip[k].agg, plain[l].agg)
+            nxt = l + 1
+        k += 1
+        for f in ("row_ptr", "col", "val"):
+            assert np.array_equal(getattr(skip[k], f), getattr(plain[nxt], f))
+        l = nxt
+    assert k == len(skip) - 1 and skipped >= 1
+
+
+def test_level_skipping_solves_and_off_is_default():
+    rp, ci, va = inputs.grid_laplacian((9, 8, 7), jitter=0.1, seed=1)
+    a = dense(rp, ci, va)
+    b = inputs.rhs(a.shape[0], 5)
+    base = oracle.Hierarchy(rp, ci, va, coarsest_size=6)
+    off = oracle.Hierarchy(rp, ci, va, coarsest_size=6, skip_ratio=0.0)
+    for l in range(base.num_levels):
+        assert np.array_equal(base.level(l).val, off.level(l).val)
+    h = oracle.Hierarchy(rp, ci, va, coarsest_size=6, skip_ratio=3.0)
+    assert h.num_levels < base.num_levels
+    x, st, it, rel, _ = h.solve(b, tol=1e-12, max_iters=300)
+    assert st == oracle.OK and rel <= 1e-12
+    np.testing.assert_allclose(x, np.linalg.solve(a, b), rtol=0, atol=1e-9)
+    with pytest.raises(RuntimeError, match="status 1"):
+        oracle.Hierarchy(rp, ci, va, skip_ratio=-1.0)
