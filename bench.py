@@ -146,6 +146,22 @@ def traffic_from(args):
     print(json.dumps(out))
 
 
+def solve_floor_bytes(sizes, nu=2):
+    """Algorithmic HBM bytes of one outer iteration (int32 indices, FP64 values, each
+    vector read or written once per sweep): on the finest level three sweeps of A
+    (restriction, post-smoothing, q = A p) at 12 B per entry + 4 B row pointer and
+    three vectors per row, plus 14 vectors of the outer flexible CG; a coarse level k
+    < L takes 6 sweeps per coarse correction (two K-cycle visits of two sweeps each,
+    two products with A) and is corrected nu^(k-1) times per iteration."""
+    L = len(sizes) - 1
+    n0, nnz0 = sizes[0][0], sizes[0][1]
+    total = 3 * (12 * nnz0 + 28 * n0) + 14 * 8 * n0
+    for k in range(1, L):
+        n, nnz = sizes[k][0], sizes[k][1]
+        total += 6 * nu ** (k - 1) * (12 * nnz + 28 * n)
+    return total
+
+
 def serve_bench(args):
     """Replays the request stream in real time and reports served solves/s and
     latency percentiles (one JSON line)."""
@@ -356,6 +372,10 @@ def main():
         "timed_region_s": round(total_s, 3),
         "roofline": roofline, "cpu_baseline": cpu,
     }
+    floor_ms = solve_floor_bytes(sizes) * statistics.median(iters) / (HBM_PEAK_GBS * 1e9) * 1e3
+    out["solve_floor"] = {"ms": round(floor_ms, 3), "frac": round(floor_ms / statistics.median(solves), 4),
+                          "model": "algorithmic bytes of every sweep of every K-cycle visit and of the outer "
+                                   "iteration at 8 TB/s, times the iterations (solve_floor_bytes)"}
     if K > 1:
         out["rhs_per_s"] = round(K / (ms * 1e-3), 2)
         out["solve_ms_per_rhs"] = round(statistics.median(solves) / K, 3)

@@ -83,6 +83,13 @@ typedef struct {
                                 /* of levels >= 100k rows and keep the fastest (cached per  */
                                 /* level shape and right-hand-side count; default);         */
                                 /* 0: lanes from the mean row length                        */
+    double kcycle_threshold;    /* theta >= 0 of the K-cycle (Sec. 4.3): the second inner    */
+                                /* step of a coarse visit is skipped when the residual after */
+                                /* the first is below theta times the restricted residual   */
+                                /* (Euclidean norms); 0 = always kcycle_inner steps (def.)  */
+    double skip_ratio;          /* level skipping (Sec. 3.3): a level whose aggregation      */
+                                /* coarsens by less than this ratio is aggregated twice and */
+                                /* the intermediate level dropped; 0 = never (default)      */
 } amg_options;
 
 typedef struct {
@@ -108,7 +115,12 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt, amg_hierarchy **o
  * the K-cycle of Sec. 4.3-4.4, stopping when the true relative residual
  * ||b - A x|| / ||b|| <= tol.  b and x are device vectors of length n; x holds the
  * initial guess on entry and the solution on return (written on AMG_OK and
- * AMG_ERR_NOT_CONVERGED).  info (may be NULL) is filled on those two statuses. */
+ * AMG_ERR_NOT_CONVERGED).  info (may be NULL) is filled on those two statuses.
+ * The K-cycle visits level k nu^k times (nu = kcycle_inner); a hierarchy whose
+ * cycle would make more than 65,536 level visits per application (nu = 2 and more
+ * than 17 levels) is refused with AMG_ERR_UNSUPPORTED before any launch (raise
+ * coarsest_size, lower max_levels or take nu = 1).  The same holds for
+ * amg_solve_batch and amg_kcycle. */
 amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, amg_solve_info *info);
 
 /* Solves A X = B for nrhs right-hand sides at once (1 <= nrhs <= opt.max_rhs): every

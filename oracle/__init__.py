@@ -23,14 +23,23 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 OK, ERR_ARG, ERR_MATRIX, ERR_NOMEM, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_INTERNAL = 0, 1, 2, 3, 5, 6, 7
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (no fast-math, no FP contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+_SAN_LIB = os.path.join(_HERE, "liboracle_san.so")
+# checking build: AddressSanitizer + UndefinedBehaviorSanitizer, any report aborts
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (no fast-math, no FP contraction).  With
+    sanitize, a separate instrumented library (load it with the sanitizer runtime
+    preloaded and UA_AMG_ORACLE_LIB pointing at it)."""
+    lib = _SAN_LIB if sanitize else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_POSIX_C_SOURCE=199309L", "-fPIC", "-shared",
-                               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+                               "-ffp-contract=off", "-fno-fast-math", "-Wall"] + (SANITIZE_FLAGS if sanitize else [])
+                              + ["-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 class _Options(ctypes.Structure):
@@ -53,7 +62,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    lib = ctypes.CDLL(build())
+    lib = ctypes.CDLL(os.environ.get("UA_AMG_ORACLE_LIB") or build())
     c_int, c_double, c_void_p, c_u64 = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_uint64
     lib.orc_splitmix64.argtypes = [c_u64, c_u64]
     lib.orc_splitmix64.restype = c_u64

@@ -124,6 +124,11 @@ void launch_member_counts(int nc, const int *rp, const int *ci, const int *owner
                           int *pairs, hipStream_t s);
 void launch_member_fill(int nc, const int *rp, const int *ci, const int *owner, const int *centre_of,
                         const int *aptr, int *members, hipStream_t s);
+// level skipping: size[J] = sum of |G1_I| over the members I of G2_J; then the member
+// lists of the composed aggregates (aptr = exclusive scan of size)
+void launch_compose_sizes(int nc2, const int *aptr2, const int *members2, const int *aptr1, int *size, hipStream_t s);
+void launch_compose_members(int nc2, const int *aptr2, const int *members2, const int *aptr1, const int *members1,
+                            const int *aptr, int *members, hipStream_t s);
 void launch_coarse_rows(int nc, const int *rp, const int *ci, const double *va, const int *agg, const int *aptr,
                         const int *members, const int *tptr, int *tcol, double *tval, int *cnt, int *big_rows,
                         unsigned *big_count, hipStream_t s);

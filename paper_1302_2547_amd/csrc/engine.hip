@@ -329,6 +329,19 @@ struct amg_hierarchy {
     };
     std::map<int, Graphs> graphs;  // per batch width (an entry without graphs: launch eagerly)
     static constexpr int kMaxGraphDepth = 12;
+    // Level visits of one K-cycle application: level k is visited nu^k times (nu
+    // inner flexible-CG steps per coarse visit), so a deep hierarchy with nu = 2
+    // grows as 2^L.  Solves of hierarchies beyond this budget are refused.
+    static constexpr double kMaxKcycleVisits = 65536.0;
+    double kcycle_visits() const
+    {
+        double v = 0.0, w = 1.0;
+        for (int k = 0; k + 1 < levels(); k++) {
+            v += w;
+            w *= opt.kcycle_inner;
+        }
+        return v;
+    }
     double *host = nullptr;  // pinned: readbacks
     int *host_i = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -510,13 +523,15 @@ void amg_hierarchy::build(const amg_csr &A)
                             stream);
 
     const int acc_cap = coarse_acc_capacity();
-    // Alg. 1: coarsen while n_l > n_0 and fewer than L levels exist
-    int l = 0;
-    while (lev[l].n > opt.coarsest_size && l + 1 < opt.max_levels) {
+    // One aggregation of level l (Alg. 2, numbering of Sec. 5.1) and its coarse level
+    // (eq. (2.4)), appended to the hierarchy; rand() of eq. (3.2) takes the stream of
+    // aggregation number `index`.  Returns false, appending nothing, when the
+    // aggregation keeps more than stall_ratio * n_l aggregates.
+    auto coarsen = [&](int l, int index) -> bool {
         const int n = lev[l].n, nnz = lev[l].nnz;
         const int G = lanes_for((double)nnz / n, n);
         AMG_TRACE_MSG("level %d: n=%d nnz=%d G=%d aggregation", l, n, nnz, G);
-        const uint32_t s_l = (uint32_t)splitmix64(opt.seed, (uint64_t)l);
+        const uint32_t s_l = (uint32_t)splitmix64(opt.seed, (uint64_t)index);
         launch_priorities(n, lev[l].rp_nat, s_l, key, owner, stream);
         AMG_HIP(hipMemsetAsync(done, 0, sizeof(unsigned) * kDoneSlots * kDoneStride, stream));
         // hub rows (longer than 8 G) of this level, served by whole blocks in the passes
@@ -552,7 +567,7 @@ void amg_hierarchy::build(const amg_csr &A)
         launch_centre_flags(n, owner, cid, stream);
         scan(cid, cid, n, ibuf + 3, scan_tmp);
         const int nc = read_int(ibuf + 3);
-        if ((double)nc > opt.stall_ratio * (double)n) break;  // coarsening stalled: level l is the coarsest
+        if ((double)nc > opt.stall_ratio * (double)n) return false;  // coarsening stalled
         Level &F = lev[l];
         F.passes = passes;
         F.agg_nat = pool.alloc<int>(n);
@@ -605,6 +620,46 @@ void amg_hierarchy::build(const amg_csr &A)
         launch_coarse_compact(nc, tptr, tcol, tval, C.rp_nat, C.ci_nat, C.va_nat, smoother_weight(), C.minv_nat,
                               stream);
         lev.push_back(C);
+        return true;
+    };
+    // Alg. 1: coarsen while n_l > n_0 and fewer than L levels exist (a stalled
+    // aggregation leaves level l as the coarsest).  With skip_ratio (Sec. 3.3), a level
+    // whose aggregation coarsened by less than the ratio is aggregated a second time,
+    // from the coarse level just built, and that intermediate level is dropped: level
+    // l keeps the composed aggregates P = P1 P2, and A_{l+1} = P2^T (P1^T A_l P1) P2.
+    int l = 0, aggregations = 0;
+    while (lev[l].n > opt.coarsest_size && l + 1 < opt.max_levels) {
+        if (!coarsen(l, aggregations)) break;
+        aggregations++;
+        const int n = lev[l].n, nc = lev[l + 1].n;
+        if (opt.skip_ratio > 0.0 && (double)n < opt.skip_ratio * (double)nc && nc > opt.coarsest_size &&
+            l + 2 < opt.max_levels) {
+            if (!coarsen(l + 1, aggregations)) {  // the intermediate level stalls: it is the coarsest
+                l++;
+                break;
+            }
+            aggregations++;
+            Level &F = lev[l], &M = lev[l + 1];
+            const int nc2 = lev[l + 2].n;
+            AMG_TRACE_MSG("level %d: coarsening ratio %.2f, aggregated twice (%d -> %d -> %d)", l, (double)n / nc, n,
+                          nc, nc2);
+            int *agg = pool.alloc<int>(n);
+            launch_gather_int(n, M.agg_nat, F.agg_nat, agg, stream);  // agg[i] = agg2[agg1[i]]
+            int *aptr = pool.alloc<int>(nc2 + 1);
+            launch_compose_sizes(nc2, M.aptr_nat, M.members_nat, F.aptr_nat, size, stream);
+            scan(size, aptr, nc2, aptr + nc2, scan_tmp);
+            int *members = pool.alloc<int>(n);
+            launch_compose_members(nc2, M.aptr_nat, M.members_nat, F.aptr_nat, F.members_nat, aptr, members, stream);
+            sync();
+            for (void *ptr : std::initializer_list<void *>{F.agg_nat, F.aptr_nat, F.members_nat, M.rp_nat, M.ci_nat,
+                                                          M.va_nat, M.minv_nat, M.agg_nat, M.aptr_nat, M.members_nat})
+                pool.release(ptr);
+            F.agg_nat = agg;
+            F.aptr_nat = aptr;
+            F.members_nat = members;
+            F.passes += M.passes;
+            lev.erase(lev.begin() + (l + 1));
+        }
         l++;
     }
     sync();
@@ -1396,6 +1451,8 @@ void amg_default_options(amg_options *opt)
     opt->smoother = AMG_SMOOTHER_L1;
     opt->jacobi_weight = 2.0 / 3.0;
     opt->autotune = 1;
+    opt->kcycle_threshold = 0.0;
+    opt->skip_ratio = 0.0;
 }
 
 amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy **out)
@@ -1411,8 +1468,10 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy 
     if (opt.coarsest_size < 1 || opt.max_levels < 1 || opt.max_levels > 64 || !(opt.stall_ratio > 0.0) ||
         !(opt.stall_ratio <= 1.0) || opt.max_aggregate < 0 || opt.max_aggregate == 1 || opt.max_iters < 0 ||
         opt.max_coarsest < 1 || opt.max_rhs < 1 || opt.max_rhs > 1024 || !(opt.jacobi_weight > 0.0) ||
-        !std::isfinite(opt.jacobi_weight))
+        !std::isfinite(opt.jacobi_weight) || !(opt.kcycle_threshold >= 0.0) || !std::isfinite(opt.kcycle_threshold) ||
+        !(opt.skip_ratio >= 0.0) || !std::isfinite(opt.skip_ratio))
         return AMG_ERR_INVALID_ARGUMENT;
+    if (opt.kcycle_threshold > 0.0) return AMG_ERR_UNSUPPORTED;
     if (opt.smoother != AMG_SMOOTHER_L1 && opt.smoother != AMG_SMOOTHER_JACOBI) return AMG_ERR_UNSUPPORTED;
     if (opt.kcycle_inner != 1 && opt.kcycle_inner != 2) return AMG_ERR_UNSUPPORTED;
     if (opt.precision != AMG_PREC_FP64 && opt.precision != AMG_PREC_FP32_INNER) return AMG_ERR_UNSUPPORTED;
@@ -1444,6 +1503,7 @@ amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, a
 {
     if (!h || !b || !x || !(tol > 0.0) || !std::isfinite(tol)) return AMG_ERR_INVALID_ARGUMENT;
     if (!device_array(b) || !device_array(x)) return AMG_ERR_INVALID_ARGUMENT;
+    if (h->kcycle_visits() > amg_hierarchy::kMaxKcycleVisits) return AMG_ERR_UNSUPPORTED;
     return guarded([&]() { return h->solve(1, b, h->lev[0].n, x, h->lev[0].n, tol, info); });
 }
 
@@ -1454,6 +1514,7 @@ amg_status amg_solve_batch(amg_hierarchy *h, int32_t nrhs, const double *B, int3
     const int n = h->lev[0].n;
     if (nrhs < 1 || nrhs > h->opt.max_rhs || ldb < n || ldx < n) return AMG_ERR_INVALID_ARGUMENT;
     if (!device_array(B) || !device_array(X)) return AMG_ERR_INVALID_ARGUMENT;
+    if (h->kcycle_visits() > amg_hierarchy::kMaxKcycleVisits) return AMG_ERR_UNSUPPORTED;
     return guarded([&]() { return h->solve(nrhs, B, ldb, X, ldx, tol, info); });
 }
 
@@ -1587,6 +1648,7 @@ amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z)
 {
     if (!h || !r || !z) return AMG_ERR_INVALID_ARGUMENT;
     if (!device_array(r) || !device_array(z)) return AMG_ERR_INVALID_ARGUMENT;
+    if (h->kcycle_visits() > amg_hierarchy::kMaxKcycleVisits) return AMG_ERR_UNSUPPORTED;
     return guarded([&]() {
         const Level &F = h->lev[0];
         h->autotune(1);

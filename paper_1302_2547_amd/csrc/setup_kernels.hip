@@ -442,6 +442,39 @@ __global__ void __launch_bounds__(kBlock) k_member_fill(int nc, const int *__res
     }
 }
 
+// Level skipping (Sec. 3.3): the aggregates of the composed aggregation P = P1 P2
+// are the unions of the first aggregation's groups over each group J of the second.
+// Their members are listed group after group, in the second aggregation's member
+// order (any order inside an aggregate serves the solve layout).
+__global__ void __launch_bounds__(kBlock) k_compose_sizes(int nc2, const int *__restrict__ aptr2,
+                                                          const int *__restrict__ members2,
+                                                          const int *__restrict__ aptr1, int *__restrict__ size)
+{
+    const int J = blockIdx.x * kBlock + threadIdx.x;
+    if (J >= nc2) return;
+    int s = 0;
+    for (int k = aptr2[J]; k < aptr2[J + 1]; k++) {
+        const int I = members2[k];
+        s += aptr1[I + 1] - aptr1[I];
+    }
+    size[J] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_compose_members(int nc2, const int *__restrict__ aptr2,
+                                                            const int *__restrict__ members2,
+                                                            const int *__restrict__ aptr1,
+                                                            const int *__restrict__ members1,
+                                                            const int *__restrict__ aptr, int *__restrict__ members)
+{
+    const int J = blockIdx.x * kBlock + threadIdx.x;
+    if (J >= nc2) return;
+    int q = aptr[J];
+    for (int k = aptr2[J]; k < aptr2[J + 1]; k++) {
+        const int I = members2[k];
+        for (int m = aptr1[I]; m < aptr1[I + 1]; m++) members[q++] = members1[m];
+    }
+}
+
 // ------------------------------------------------------------------ eq. (2.4)
 //
 // Coarse row I gathers the pairs (agg[t], a_st) of its members' rows, in member
@@ -1234,6 +1267,19 @@ void launch_member_counts(int nc, const int *rp, const int *ci, const int *owner
 {
     const int G = wide(nc) ? kWave : 1;
     AMG_LAUNCH_G(G, k_member_counts, grid_for((int64_t)nc * G), s, nc, rp, ci, owner, centre_of, size, pairs);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_compose_sizes(int nc2, const int *aptr2, const int *members2, const int *aptr1, int *size, hipStream_t s)
+{
+    k_compose_sizes<<<grid_for(nc2), kBlock, 0, s>>>(nc2, aptr2, members2, aptr1, size);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_compose_members(int nc2, const int *aptr2, const int *members2, const int *aptr1, const int *members1,
+                            const int *aptr, int *members, hipStream_t s)
+{
+    k_compose_members<<<grid_for(nc2), kBlock, 0, s>>>(nc2, aptr2, members2, aptr1, members1, aptr, members);
     AMG_HIP(hipGetLastError());
 }
 

@@ -30,7 +30,7 @@ def setup_both(amg, rp, ci, va, **opt):
     print(f"[parity] n={len(rp) - 1} nnz={len(ci)} opt={opt}", flush=True)
     h = amg.Hierarchy(dev(rp), dev(ci), dev(va), **opt)
     oopt = {k: v for k, v in opt.items() if k in ("coarsest_size", "max_levels", "stall_ratio", "max_aggregate",
-                                                   "seed", "kcycle_inner")}
+                                                   "seed", "kcycle_inner", "kcycle_threshold", "skip_ratio")}
     ref = oracle.Hierarchy(rp, ci, va, **oopt)
     return h, ref
 
@@ -490,3 +490,102 @@ def test_wide_slice_keeps_csr(amg):
     res = b - oracle.spmv(rp2, ci2, va2, x.cpu().numpy())
     assert st == amg.AMG_OK and np.linalg.norm(res) / np.linalg.norm(b) <= 1e-8
     h.close()
+
+
+def test_single_level_hierarchy(amg):
+    """n <= n_0: Alg. 1 builds no coarse level, and the exact coarsest solve is the
+    whole preconditioner (one outer iteration)."""
+    rp, ci, va = inputs.grid_laplacian((20, 15), jitter=0.2, seed=4)
+    n = len(rp) - 1
+    h, ref = setup_both(amg, rp, ci, va, coarsest_size=1000)
+    assert h.num_levels == ref.num_levels == 1
+    assert_same_hierarchy(h, ref)
+    r = inputs.rhs(n, 6)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.kcycle(dev(r), z)
+    zo = ref.kcycle(r)
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-12 * np.abs(zo).max())
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, info = h.solve(dev(r), x, tol=1e-10)
+    xo, st_o, it_o, rel_o, _ = ref.solve(r, tol=1e-10)
+    assert st == amg.AMG_OK and st_o == oracle.OK and info.iterations == it_o == 1
+    rel = np.linalg.norm(r - oracle.spmv(rp, ci, va, x.cpu().numpy())) / np.linalg.norm(r)
+    assert rel <= 1e-10
+    np.testing.assert_allclose(x.cpu().numpy(), xo, rtol=0, atol=1e-10 * np.abs(xo).max())
+
+
+def test_deep_hierarchy_launched_eagerly(amg):
+    """15 levels (1D path, coarsest size 1) is deeper than the K-cycle graph is
+    captured for, so its 2^14 - 1 level visits per application are launched one by
+    one; the result must still be the oracle's K-cycle."""
+    rp, ci, va = inputs.grid_laplacian((20000,), jitter=0.2, seed=3)
+    n = len(rp) - 1
+    h, ref = setup_both(amg, rp, ci, va, coarsest_size=1)
+    assert h.num_levels == ref.num_levels == 15
+    assert_same_hierarchy(h, ref)
+    r = inputs.rhs(n, 5)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.kcycle(dev(r), z)
+    zo = ref.kcycle(r)
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-10 * np.abs(zo).max())
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, info = h.solve(dev(r), x, tol=1e-8)
+    _, st_o, it_o, _, _ = ref.solve(r, tol=1e-8)
+    rel = np.linalg.norm(r - oracle.spmv(rp, ci, va, x.cpu().numpy())) / np.linalg.norm(r)
+    print(f"[parity] deep: gpu iters={info.iterations} oracle iters={it_o} rel={rel:.2e}", flush=True)
+    assert st == amg.AMG_OK and rel <= 1e-8 and abs(info.iterations - it_o) <= 2
+
+
+def test_kcycle_visit_budget_refuses_before_launching(amg):
+    """19 levels with two inner steps would make 2^18 - 1 level visits per K-cycle:
+    amg_solve and amg_kcycle refuse with AMG_ERR_UNSUPPORTED and leave x alone; one
+    inner step (18 visits) is accepted and matches the oracle."""
+    rp, ci, va = inputs.grid_laplacian((300000,), jitter=0.2, seed=3)
+    n = len(rp) - 1
+    h = amg.Hierarchy(dev(rp), dev(ci), dev(va), coarsest_size=1)
+    assert h.num_levels == 19
+    b = dev(inputs.rhs(n, 2))
+    x = torch.full((n,), 3.0, dtype=torch.float64, device="cuda")
+    st, _ = h.solve(b, x, tol=1e-8, raise_on_error=False)
+    assert st == amg.AMG_ERR_UNSUPPORTED and bool((x == 3.0).all())
+    with pytest.raises(amg.AmgError) as e:
+        h.kcycle(b, x)
+    assert e.value.status == amg.AMG_ERR_UNSUPPORTED and bool((x == 3.0).all())
+    h.close()
+    h1, ref1 = setup_both(amg, rp, ci, va, coarsest_size=1, kcycle_inner=1)
+    r = inputs.rhs(n, 7)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h1.kcycle(dev(r), z)
+    zo = ref1.kcycle(r)
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-10 * np.abs(zo).max())
+
+
+@pytest.mark.parametrize("case,opt", [("grid2d_128_t2", dict(max_aggregate=2, skip_ratio=2.5, coarsest_size=400)),
+                                      ("grid3d_40_jitter", dict(skip_ratio=2.0, coarsest_size=1)),
+                                      ("rgg_20k", dict(skip_ratio=3.5))])
+def test_level_skipping_matches_oracle(amg, case, opt):
+    """Sec. 3.3's aggregation applied twice where the coarsening ratio is small: the
+    GPU hierarchy (composed aggregates, coarse values) equals the oracle's bit for
+    bit, the K-cycle matches, and the solve converges."""
+    if case == "grid2d_128_t2":
+        rp, ci, va = inputs.grid_laplacian((128, 128))
+    elif case == "grid3d_40_jitter":
+        rp, ci, va = inputs.grid_laplacian((40, 40, 40), jitter=0.1, seed=2)
+    else:
+        rp, ci, va = CASES[case]()
+    n = len(rp) - 1
+    h, ref = setup_both(amg, rp, ci, va, **opt)
+    plain = oracle.Hierarchy(rp, ci, va, **{k: v for k, v in opt.items() if k != "skip_ratio"})
+    print(f"[parity] {case}: {plain.num_levels} levels plain, {ref.num_levels} with skipping", flush=True)
+    assert ref.num_levels < plain.num_levels
+    assert_same_hierarchy(h, ref)
+    r = inputs.rhs(n, 8)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.kcycle(dev(r), z)
+    zo = ref.kcycle(r)
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-10 * np.abs(zo).max())
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, info = h.solve(dev(r), x, tol=1e-9)
+    _, st_o, it_o, _, _ = ref.solve(r, tol=1e-9)
+    rel = np.linalg.norm(r - oracle.spmv(rp, ci, va, x.cpu().numpy())) / np.linalg.norm(r)
+    assert st == amg.AMG_OK and rel <= 1e-9 and abs(info.iterations - it_o) <= 2
