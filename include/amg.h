@@ -147,6 +147,19 @@ amg_status amg_solve_batch(amg_hierarchy *h, int32_t nrhs, const double *B, int3
 int64_t amg_grid_laplacian_nnz(int32_t dim, const int32_t *dims);
 amg_status amg_grid_laplacian(int32_t dim, const int32_t *dims, double jitter, uint64_t seed, int32_t *row_ptr,
                               int32_t *col_idx, double *values, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops that forbid hipMalloc): the same grid Laplacian as
+ * amg_grid_laplacian, bit for bit, with no allocation of any kind.  The scan of the
+ * row pointers uses a scratch array that the library holds in static device memory
+ * (256 KiB per GPU, kept until the process ends), so grids are limited to
+ * 134,217,728 (2^27) unknowns; larger valid grids return AMG_ERR_UNSUPPORTED before
+ * any device work.  Asynchronous: the arrays are written in order on `stream`, which
+ * must belong to the current device; the call does not wait.  Every call on one GPU
+ * shares that GPU's scratch, so calls whose work overlaps on the device (different
+ * streams without ordering between them) race and must not be made; calls ordered
+ * on one stream are safe.  Argument errors as amg_grid_laplacian. */
+amg_status amg_grid_laplacian_noalloc(int32_t dim, const int32_t *dims, double jitter, uint64_t seed,
+                                      int32_t *row_ptr, int32_t *col_idx, double *values, void *stream);
 /* out[i] = 2 u_i - 1 with u_i the i-th SplitMix64 uniform of `seed` (device array of n,
  * ordered on `stream`, asynchronous). */
 amg_status amg_uniform_rhs(int64_t n, uint64_t seed, double *out, void *stream);

@@ -64,6 +64,8 @@ _sig = {
     "amg_free": (None, [_P]),
     "amg_grid_laplacian_nnz": (ctypes.c_int64, [ctypes.c_int32, _I32P]),
     "amg_grid_laplacian": (ctypes.c_int, [ctypes.c_int32, _I32P, ctypes.c_double, ctypes.c_uint64, _P, _P, _P, _P]),
+    "amg_grid_laplacian_noalloc": (ctypes.c_int, [ctypes.c_int32, _I32P, ctypes.c_double, ctypes.c_uint64, _P, _P,
+                                                   _P, _P]),
     "amg_uniform_rhs": (ctypes.c_int, [ctypes.c_int64, ctypes.c_uint64, _P, _P]),
     "amg_release_cached_memory": (None, []),
     "amg_num_levels": (ctypes.c_int, [_P, _I32P]),

@@ -314,6 +314,12 @@ void launch_restriction_weights(int n, const int *rp, const int *ci, const doubl
 int64_t grid_nnz(int d, const int *dims);
 void launch_grid_laplacian(int d, const int *dims, double jitter, uint64_t seed, int *rp, int *ci, double *va,
                            int *scan_tmp, hipStream_t s);
+// The same without allocating: the scan scratch is a static device array of the
+// library (grids of at most kNoAllocMaxRows unknowns; larger ones throw
+// AMG_ERR_UNSUPPORTED before any launch).  Asynchronous on s.
+constexpr int64_t kNoAllocMaxRows = 134217728;  // 2^27
+void launch_grid_laplacian_noalloc(int d, const int *dims, double jitter, uint64_t seed, int *rp, int *ci,
+                                   double *va, hipStream_t s);
 void launch_uniform_rhs(int64_t n, uint64_t seed, double *out, hipStream_t s);
 
 }  // namespace amg

@@ -1561,6 +1561,18 @@ amg_status amg_grid_laplacian(int32_t dim, const int32_t *dims, double jitter, u
     });
 }
 
+amg_status amg_grid_laplacian_noalloc(int32_t dim, const int32_t *dims, double jitter, uint64_t seed,
+                                      int32_t *row_ptr, int32_t *col_idx, double *values, void *stream)
+{
+    if (amg_grid_laplacian_nnz(dim, dims) < 0 || !std::isfinite(jitter) || !(jitter >= 0.0 && jitter < 1.0) ||
+        !device_array(row_ptr) || !device_array(col_idx) || !device_array(values))
+        return AMG_ERR_INVALID_ARGUMENT;
+    return guarded([&]() {
+        amg::launch_grid_laplacian_noalloc(dim, dims, jitter, seed, row_ptr, col_idx, values, (hipStream_t)stream);
+        return AMG_OK;
+    });
+}
+
 amg_status amg_uniform_rhs(int64_t n, uint64_t seed, double *out, void *stream)
 {
     if (n < 1 || !device_array(out)) return AMG_ERR_INVALID_ARGUMENT;

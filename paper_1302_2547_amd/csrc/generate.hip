@@ -5,7 +5,10 @@
 // generator of the Python package: the same counter-based SplitMix64 draws, the
 // same slot order of each row, the diagonal summed in that order, and every
 // product and sum rounded on its own (no contraction into fused multiply-adds).
+#include "amg.h"
 #include "amg_internal.h"
+
+#include <mutex>
 
 // hipcc contracts a * b + c into fused multiply-adds by default; every expression
 // of this file must round each product and sum on its own.
@@ -148,6 +151,53 @@ void launch_grid_laplacian(int d, const int *dims, double jitter, uint64_t seed,
     scan_exclusive(rp, rp, n, rp + n, scan_tmp, s);
     k_grid_fill<<<blocks_for(n), kBlock, 0, s>>>(g, n, rp, ci, va);
     AMG_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ no-allocation variant
+// The scan of the row pointers needs scan_tmp_ints(n) ints of scratch (one block
+// total per 2048 rows).  The variant for callers that cannot allocate takes them
+// from this array, which every GPU holds for the life of the process: grids of up
+// to kNoAllocMaxRows unknowns.  Host code never passes the array's name to a
+// kernel (in host code it is a host-side stand-in, not a device address); it
+// uses the device address looked up once per GPU below.
+constexpr int64_t kNoAllocScratchInts = 65537;  // 256 KiB + 4 B
+static_assert(kNoAllocMaxRows == (kNoAllocScratchInts - 1) * 2048, "one block total per 2048 rows");
+static __device__ __align__(256) int scratch[kNoAllocScratchInts];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+int *scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's copy of `scratch` (the current device's),
+// looked up at the first call on that device.
+int *scratch_address()
+{
+    int dev = 0;
+    AMG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw Error(AMG_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            throw Error(AMG_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed");
+        }
+        scratch_ptr[dev] = static_cast<int *>(ptr);
+    }
+    return scratch_ptr[dev];
+}
+}  // namespace
+
+void launch_grid_laplacian_noalloc(int d, const int *dims, double jitter, uint64_t seed, int *rp, int *ci,
+                                   double *va, hipStream_t s)
+{
+    int64_t n = 1;
+    for (int a = 0; a < d; a++) n *= dims[a];
+    if (n > kNoAllocMaxRows || (int64_t)scan_tmp_ints(n) > kNoAllocScratchInts)
+        throw Error(AMG_ERR_UNSUPPORTED, "grid larger than the no-allocation scratch");
+    launch_grid_laplacian(d, dims, jitter, seed, rp, ci, va, scratch_address(), s);
 }
 
 void launch_uniform_rhs(int64_t n, uint64_t seed, double *out, hipStream_t s)
