@@ -358,10 +358,32 @@ typedef struct {
     double *tmp, *rc, *e, *rr, *w, *aw, *d, *ad, *dp, *adp, *x, *r, *p, *q, *z;
 } orc_level;
 
+/* Lower Cholesky factor L of the coarsest matrix, kept as the lists of its nonzero
+ * entries: row i's entries left of the diagonal (ascending column) and column i's
+ * entries below it (ascending row), plus the diagonal.  The substitutions visit
+ * them in the order a dense loop would and skip only exact zeros, whose products
+ * change no nonzero sum (the coarsest level of a random graph is mostly isolated
+ * vertices, whose rows and columns of L are empty). */
+typedef struct {
+    int n;
+    double *diag;
+    int *rptr, *rcol;  /* row i: rcol[rptr[i] .. rptr[i+1]) < i */
+    double *rval;
+    int *cptr, *crow;  /* column i: crow[cptr[i] .. cptr[i+1]) > i */
+    double *cval;
+} orc_factor;
+
+static void free_factor(orc_factor *f)
+{
+    free(f->diag); free(f->rptr); free(f->rcol); free(f->rval);
+    free(f->cptr); free(f->crow); free(f->cval);
+    memset(f, 0, sizeof(*f));
+}
+
 typedef struct {
     int nlev;
     orc_level lev[ORC_MAX_LEVELS];
-    double *chol; /* lower Cholesky factor of the coarsest matrix, dense row-major */
+    orc_factor chol; /* Cholesky factor of the coarsest matrix */
     int nu;       /* inner flexible-CG steps per coarse level visit */
     double theta; /* K-cycle threshold: later inner steps are skipped once ||rr|| < theta ||g|| */
     double setup_ms;
@@ -397,7 +419,7 @@ void orc_free(orc_hierarchy *h)
 {
     if (!h) return;
     for (int l = 0; l < h->nlev; l++) free_level(&h->lev[l], 1);
-    free(h->chol);
+    free_factor(&h->chol);
     free(h);
 }
 
@@ -413,8 +435,8 @@ static int alloc_work(orc_level *L)
     return ORC_OK;
 }
 
-/* Dense Cholesky A = L L^T of the CSR matrix (row-major lower factor). */
-static int dense_cholesky(int n, const int *rp, const int *ci, const double *va, double **out)
+/* Dense Cholesky A = L L^T of the CSR matrix, then the nonzero entries of L. */
+static int dense_cholesky(int n, const int *rp, const int *ci, const double *va, orc_factor *out)
 {
     double *a = (double *)calloc((size_t)n * (size_t)n, sizeof(double));
     if (!a) return ORC_ERR_NOMEM;
@@ -435,23 +457,63 @@ static int dense_cholesky(int n, const int *rp, const int *ci, const double *va,
             a[(size_t)i * n + j] = t / ljj;
         }
     }
+    orc_factor f;
+    memset(&f, 0, sizeof(f));
+    f.n = n;
+    size_t nz = 0;
     for (int i = 0; i < n; i++)
-        for (int j = i + 1; j < n; j++) a[(size_t)i * n + j] = 0.0;
-    *out = a;
+        for (int k = 0; k < i; k++) nz += a[(size_t)i * n + k] != 0.0;
+    f.diag = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    f.rptr = (int *)calloc((size_t)n + 1, sizeof(int));
+    f.cptr = (int *)calloc((size_t)n + 1, sizeof(int));
+    f.rcol = (int *)malloc(sizeof(int) * (nz + 1));
+    f.crow = (int *)malloc(sizeof(int) * (nz + 1));
+    f.rval = (double *)malloc(sizeof(double) * (nz + 1));
+    f.cval = (double *)malloc(sizeof(double) * (nz + 1));
+    if (!f.diag || !f.rptr || !f.cptr || !f.rcol || !f.crow || !f.rval || !f.cval) {
+        free(a);
+        free_factor(&f);
+        return ORC_ERR_NOMEM;
+    }
+    size_t e = 0;
+    for (int i = 0; i < n; i++) {
+        f.diag[i] = a[(size_t)i * n + i];
+        for (int k = 0; k < i; k++)
+            if (a[(size_t)i * n + k] != 0.0) {
+                f.rcol[e] = k;
+                f.rval[e] = a[(size_t)i * n + k];
+                e++;
+            }
+        f.rptr[i + 1] = (int)e;
+    }
+    e = 0;
+    for (int i = 0; i < n; i++) {
+        for (int k = i + 1; k < n; k++)
+            if (a[(size_t)k * n + i] != 0.0) {
+                f.crow[e] = k;
+                f.cval[e] = a[(size_t)k * n + i];
+                e++;
+            }
+        f.cptr[i + 1] = (int)e;
+    }
+    free(a);
+    *out = f;
     return ORC_OK;
 }
 
-static void cholesky_solve(int n, const double *l, const double *b, double *x)
+/* L L^T x = b: forward substitution by rows of L, back substitution by columns. */
+static void cholesky_solve(const orc_factor *f, const double *b, double *x)
 {
+    const int n = f->n;
     for (int i = 0; i < n; i++) {
         double s = b[i];
-        for (int k = 0; k < i; k++) s -= l[(size_t)i * n + k] * x[k];
-        x[i] = s / l[(size_t)i * n + i];
+        for (int p = f->rptr[i]; p < f->rptr[i + 1]; p++) s -= f->rval[p] * x[f->rcol[p]];
+        x[i] = s / f->diag[i];
     }
     for (int i = n - 1; i >= 0; i--) {
         double s = x[i];
-        for (int k = i + 1; k < n; k++) s -= l[(size_t)k * n + i] * x[k];
-        x[i] = s / l[(size_t)i * n + i];
+        for (int p = f->cptr[i]; p < f->cptr[i + 1]; p++) s -= f->cval[p] * x[f->crow[p]];
+        x[i] = s / f->diag[i];
     }
 }
 
@@ -673,7 +735,7 @@ static void kcycle(orc_hierarchy *h, int k, const double *r, double *x)
     int n = F->n;
     int L = h->nlev - 1;
     if (k == L) { /* only reached when the hierarchy has a single level */
-        cholesky_solve(n, h->chol, r, x);
+        cholesky_solve(&h->chol, r, x);
         return;
     }
     orc_level *C = &h->lev[k + 1];
@@ -686,7 +748,7 @@ static void kcycle(orc_hierarchy *h, int k, const double *r, double *x)
     /* coarse-grid correction */
     const double *e;
     if (k + 1 == L) {
-        cholesky_solve(C->n, h->chol, C->rc, C->e);
+        cholesky_solve(&h->chol, C->rc, C->e);
         e = C->e;
     } else {
         inner_fcg(h, k + 1, C->rc);
