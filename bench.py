@@ -50,6 +50,12 @@ def parse():
     ap.add_argument("--smoother", choices=["l1", "jacobi"], default="l1",
                     help="l1-Jacobi (default) or damped Jacobi (Sec. 4.1)")
     ap.add_argument("--jacobi-weight", type=float, default=2.0 / 3.0, help="omega of the damped Jacobi smoother")
+    ap.add_argument("--kcycle-threshold", type=float, default=0.0,
+                    help="K-cycle threshold theta (Sec. 4.3): the second inner step is skipped where the inner "
+                         "residual fell below theta times the coarse residual (0: always two steps)")
+    ap.add_argument("--skip-ratio", type=float, default=0.0,
+                    help="level skipping (Sec. 3.3): aggregate twice where a level coarsens by less than this "
+                         "ratio (0: never, the plain method)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--smoother-reps", type=int, default=50)
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "post_smooth_128cubed_traffic.json"))
@@ -240,7 +246,7 @@ def main():
     n, nnz = len(rp) - 1, len(ci)
     prec = amg.AMG_PREC_FP32_INNER if args.precision == "fp32_inner" else amg.AMG_PREC_FP64
     smo = dict(smoother=amg.AMG_SMOOTHER_JACOBI if args.smoother == "jacobi" else amg.AMG_SMOOTHER_L1,
-               jacobi_weight=args.jacobi_weight)
+               jacobi_weight=args.jacobi_weight, skip_ratio=args.skip_ratio, kcycle_threshold=args.kcycle_threshold)
     b = inputs.rhs(n, 1)
     gen_s = time.perf_counter() - t0
     d_rp, d_ci, d_va = (torch.from_numpy(a).to(dev) for a in (rp, ci, va))
@@ -336,7 +342,8 @@ def main():
     if not args.no_cpu_baseline and args.workload == "grid" and K == 1:
         import oracle
         tc = time.perf_counter()
-        ref = oracle.Hierarchy(rp, ci, va, smoother=args.smoother, jacobi_weight=args.jacobi_weight)
+        ref = oracle.Hierarchy(rp, ci, va, smoother=args.smoother, jacobi_weight=args.jacobi_weight,
+                               skip_ratio=args.skip_ratio, kcycle_threshold=args.kcycle_threshold)
         _, st, it_o, rel_o, solve_ms = ref.solve(b, tol=args.tol)
         cpu_ms = ref.setup_ms + solve_ms
         ref.close()
@@ -357,7 +364,9 @@ def main():
     workload = (problem + f", FP64 CSR, {rhs_text}, x0=0, tol {args.tol:g}; UA-AMG K-cycle (nu=2) + flexible CG, "
                 + ("l1-Jacobi" if args.smoother == "l1" else f"damped Jacobi (omega {args.jacobi_weight:g})")
                 + " 1+1, coarsest <= 64" + ("" if args.precision == "fp64" else "; K-cycle values and vectors "
-                                                   "in FP32"))
+                                                   "in FP32")
+                + (f"; level skipping below coarsening ratio {args.skip_ratio:g}" if args.skip_ratio else "")
+                + (f"; K-cycle threshold {args.kcycle_threshold:g}" if args.kcycle_threshold else ""))
     out = {
         "metric": METRIC, "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak",

@@ -207,6 +207,13 @@ amg_status amg_spmv(amg_hierarchy *h, int32_t level, const double *x, double *y)
  * (Sec. 4.3), device vectors of length n in the natural numbering. */
 amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z);
 
+/* Z = B R for nrhs columns at once (1 <= nrhs <= opt.max_rhs), every kernel serving
+ * all columns in one launch as in amg_solve_batch: column c of R at R + c * ldr and
+ * of Z at Z + c * ldz (ldr, ldz >= n), device memory, natural numbering.  Each column
+ * takes its own decisions (the K-cycle threshold), so column c equals amg_kcycle on
+ * it alone. */
+amg_status amg_kcycle_batch(amg_hierarchy *h, int32_t nrhs, const double *R, int32_t ldr, double *Z, int32_t ldz);
+
 /* Average device time in microseconds of the finest level's post-smoothing step
  * as the solve runs it (prolongation of the coarse correction + one smoothing
  * sweep, Sec. 4.2-4.3, with the inner product (z, A p) of the outer flexible CG

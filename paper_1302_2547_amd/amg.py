@@ -75,6 +75,7 @@ _sig = {
     "amg_export_level": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "amg_spmv": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     "amg_kcycle": (ctypes.c_int, [_P, _P, _P]),
+    "amg_kcycle_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, ctypes.c_int32]),
     "amg_time_smoother": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
     "amg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -230,6 +231,12 @@ class Hierarchy:
 
     def kcycle(self, r, z):
         self._check(amg_kcycle(self._h, _ptr(r), _ptr(z)), "amg_kcycle")
+
+    def kcycle_batch(self, R, Z):
+        """R, Z: (nrhs, n) contiguous float64 device tensors."""
+        if R.dim() != 2 or R.shape != Z.shape or R.shape[1] != self.n:
+            raise ValueError("R and Z must both be (nrhs, n)")
+        self._check(amg_kcycle_batch(self._h, R.shape[0], _ptr(R), self.n, _ptr(Z), self.n), "amg_kcycle_batch")
 
     def time_smoother(self, reps: int = 20):
         us, by = ctypes.c_double(), ctypes.c_double()

@@ -180,6 +180,9 @@ void launch_spmv(Rows R, const int *ci, const double *va, const double *x, doubl
 // ncol > 1 runs a batch of right-hand sides in one launch (gridDim.y = column):
 // each level's vectors are stored column after column (leading dimension = the
 // level's size) and every dot site holds one kDotCol block per column.
+// gate (device, one int per column, or NULL): with the K-cycle threshold, the
+// launchers of a second inner step and of everything nested in it take that step's
+// gate, and their kernels do nothing for a column whose gate is 0.
 //
 // y = A x (y may be NULL); d[0] = (x, A x), d[1] = (x, w1) if w1, d[2] = (x, w2) if w2
 // (omy, non-NULL only with at most two other products, adds (omy, A x) last.)
@@ -188,7 +191,7 @@ void launch_spmv(Rows R, const int *ci, const double *va, const double *x, doubl
 template <class T>
 DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, const T *w1, const T *w2, int G,
                         DotBuf buf, hipStream_t s, const double *omy = nullptr, int ncol = 1,
-                        const Sell *sl = nullptr, const T *sva = nullptr);
+                        const Sell *sl = nullptr, const T *sva = nullptr, const int *gate = nullptr);
 // r = b - A x; d[0] = (b, b), d[1] = (r, r)
 DotSet launch_residual(Rows R, const int *ci, const double *va, const double *b, const double *x, double *r, int G,
                        DotBuf buf, hipStream_t s, int ncol = 1);
@@ -198,14 +201,14 @@ void launch_reduce(const DotRef &ref, double *out, hipStream_t s, int ncol = 1, 
 // With om, also the partials of (om, rc) into buf (returned; else a null reference).
 template <class T>
 DotRef launch_restrict(Rows S, int nf, const int *ci, const T *wv, const T *r, T *rc, int G, hipStream_t s,
-                       const double *om = nullptr, DotBuf buf = DotBuf{}, int ncol = 1);
+                       const double *om = nullptr, DotBuf buf = DotBuf{}, int ncol = 1, const int *gate = nullptr);
 // rc = P^T (r - A M^-1 r) on a level with a sliced copy S (values sva): the
 // pre-smoothing residual t (FP64, n per right-hand side, scratch) row by row, then
 // the sums of t over the aggregates: rc[J] = sum of t[idx[p]] (t[p] when idx is
 // NULL) for positions p in seg[J] .. seg[J+1] of the level's nested order.
 template <class T>
 void launch_sell_restrict(const Sell &S, const T *sva, const T *minv, const T *r, double *t, int nc, const int *seg,
-                          const int *idx, T *rc, hipStream_t s, int ncol = 1);
+                          const int *idx, T *rc, hipStream_t s, int ncol = 1, const int *gate = nullptr);
 // rc = W r with r = rt formed on the fly as rt = rcf - (alpha1/rho1) v1 (the
 // inner residual of the parent's first flexible-CG step), rt also stored
 template <class T>
@@ -217,7 +220,7 @@ DotRef launch_restrict_rt(Rows S, int nf, const int *ci, const T *wv, const T *r
 template <class T>
 void launch_post_direct(Rows R, const int *ci, const T *va, const T *minv, const T *r, const T *v1, KDots kd,
                         DotRef om_r, DotRef om_v1, const double *ainv, T *xout, T *rt_out, int *flag, int G,
-                        bool rt_mode, hipStream_t s, int ncol = 1);
+                        bool rt_mode, hipStream_t s, int ncol = 1, const int *gate = nullptr);
 // A small level whose coarse level is one unknown, laid out for a whole coarse
 // correction (two flexible-CG steps, Sec. 4.4) in one block of kTailThreads
 // threads per right-hand side.  Thread t owns rows t + u kTailThreads
@@ -252,24 +255,39 @@ bool build_tail_layout(int n, const int *rp, const int *ci, const double *va, st
 // coarse solve, prolongation, post-smoothing).  Writes c1 and c2 and the five
 // products as reduced values: d1[0] = rho1 = (c1, A c1), d1[1] = alpha1 = (c1, rc),
 // d2[0] = beta = (c2, A c2), d2[1] = gamma = (c2, v1), d2[2] = alpha2 = (c2, rt).
+// theta2 > 0 (the squared K-cycle threshold): when (rt, rt) < theta2 (rc, rc) the
+// second step is skipped (c2 = 0, d2 = 0, so the caller's coefficients reduce to
+// the first step's).
 template <class T>
 void launch_tail_visit(const TailLayout &L, const T *va, const T *minv, const double *om, const double *ainv,
-                       const T *rc, T *c1, T *c2, double *d1, double *d2, int *flag, hipStream_t s, int ncol = 1);
+                       const T *rc, T *c1, T *c2, double *d1, double *d2, int *flag, hipStream_t s, int ncol = 1,
+                       const int *gate = nullptr, double theta2 = 0.0);
 // rt = rc - (alpha1/rho1) v1
 template <class T>
 void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, hipStream_t s, int ncol = 1);
+// The same under the K-cycle threshold (Sec. 4.3): also the partials of (rc, rc),
+// (rt, rt) and, with om, (om, rt) (returned; else a null reference), then
+// gate_out[c] = 1 when column c's enclosing step runs (gate) and
+// (rt, rt) >= theta2 (rc, rc), else 0.
+template <class T>
+DotRef launch_inner_residual_theta(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, const double *om,
+                                   DotBuf buf, double theta2, const int *gate, int *gate_out, hipStream_t s,
+                                   int ncol = 1);
 // post-smoothing with the coarse correction folded in (mode 0: e = edirect;
 // 1: e = (alpha1/rho1) c1; 2: e = a1 c1 + a2 c2; 3: e = ainv * edirect, a dense
 // coarsest solve of size nc <= kInlineCoarse done in the kernel); returns
 // (out, wdot) if wdot.  nc is the coarse level's size (the leading dimension of
 // edirect, c1, c2).  xtmp (FP64, n per right-hand side, or NULL): on levels of at
 // least kSmallLevel rows the step is then split in two launches through it, the
-// second served from the sliced ELLPACK copy sl (values sva) when given.
+// second served from the sliced ELLPACK copy sl (values sva) when given.  second
+// (mode 2, or NULL): the gate of the second inner step; a column whose gate is 0
+// takes the mode 1 correction.
 template <class T>
 DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, const T *r, const int *agg_pos,
                           const int *cagg, int mode, const T *edirect, const T *c1, const T *c2, KDots kd, T *xout,
                           const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv, int nc,
-                          int ncol = 1, double *xtmp = nullptr, const Sell *sl = nullptr, const T *sva = nullptr);
+                          int ncol = 1, double *xtmp = nullptr, const Sell *sl = nullptr, const T *sva = nullptr,
+                          const int *gate = nullptr, const int *second = nullptr);
 // Exact solve on a coarsest level of n unknowns: rows with no off-diagonal entry (and
 // no entry in their column) are decoupled, x_i = r_i / a_ii (dinv[k] = 1 / a_ii for
 // row didx[k], k < nd); the other m rows idx[0..m) (ascending; NULL: all rows, m = n)

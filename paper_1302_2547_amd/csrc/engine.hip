@@ -269,6 +269,10 @@ struct Level {
     // work vectors and dot sites when this level is the coarse level of a visit
     double *rc = nullptr, *rt = nullptr, *c1 = nullptr, *c2 = nullptr, *v1 = nullptr;
     DotBuf d_c1{}, d_c2{};  // (c1, A c1), (c1, rc) [, (om, A c1)] and (c2, A c2), (c2, v1), (c2, rt)
+    // K-cycle threshold: (rc, rc), (rt, rt) [, (om, rt)] of the first inner step and
+    // the gate of the second (one int per right-hand side; NULL without threshold)
+    DotBuf d_th{};
+    int *gate2 = nullptr;
     // Level whose coarse level is a single unknown: the restriction is the row
     // vector om^T, applied as inner products written by the producers of rc / v1.
     double *omega = nullptr;
@@ -459,7 +463,8 @@ struct amg_hierarchy {
         KDots kd;
     };
     template <class T>
-    DotRef kcycle(int k, const T *r, T *x, const T *wdot, const RtSource<T> *rts, int ncol);
+    DotRef kcycle(int k, const T *r, T *x, const T *wdot, const RtSource<T> *rts, int ncol,
+                  const int *gate = nullptr);
     void run_kcycle(int ncol);
     void run_first(int ncol);
     void run_iter(int ncol);
@@ -848,6 +853,12 @@ void amg_hierarchy::finalize_layout()
             F.v1 = pool.alloc<double>((size_t)F.n * nr);
             F.d_c1 = dot_buf();
             F.d_c2 = dot_buf();
+            if (opt.kcycle_threshold > 0.0 && l < L) {
+                F.d_th = dot_buf();
+                F.gate2 = pool.alloc<int>(nr);
+                const std::vector<int> ones(nr, 1);
+                to_dev(F.gate2, ones.data(), nr);
+            }
         }
     }
     // single coarse unknown below level L-1 (L >= 2): om_j = sum over the entries
@@ -985,7 +996,8 @@ void amg_hierarchy::build_sell()
 // preconditioned by K_{k+1}), prolongation + post-smoothing.  When wdot is given
 // the returned reference holds (x, wdot).
 template <class T>
-DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtSource<T> *rts, int ncol)
+DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtSource<T> *rts, int ncol,
+                             const int *gate)
 {
     using namespace amg;
     const int L = levels() - 1;
@@ -1002,38 +1014,44 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
         // (rts: rr = rt is formed from the parent's first inner step and stored)
         if (rts) {
             launch_post_direct<T>(F.A, F.ci, FK.va, FK.minv, rts->rcf, rts->v1, rts->kd, F.om_rc, F.om_v1, ainv, xx,
-                                  const_cast<T *>(rr), flag, F.G, true, stream, ncol);
+                                  const_cast<T *>(rr), flag, F.G, true, stream, ncol, gate);
         } else {
             launch_post_direct<T>(F.A, F.ci, FK.va, FK.minv, rr, nullptr, KDots{}, F.om_rc, DotRef{}, ainv, xx,
-                                  nullptr, flag, F.G, false, stream, ncol);
+                                  nullptr, flag, F.G, false, stream, ncol, gate);
         }
         return DotRef{nullptr, 0};
     }
     Level &C = lev[k + 1];
     const KArrays<T> &CK = C.karr<T>();
+    // K-cycle threshold (Sec. 4.3): the second inner step on C runs for a column
+    // only while ||rt|| >= theta ||rc||, decided on the device (the launches stay
+    // the same, so the cycle is still one static graph)
+    const double theta = opt.kcycle_threshold;
     // C small with a single unknown below: the whole coarse correction in one block,
     // which forms (om, rc) itself
     const bool tail = C.tail.n > 0;
     const double *om = tail ? nullptr : C.omega;
-    if (rts) {  // rr = rt is formed here from the parent's first inner step
+    if (rts) {  // rr = rt is formed here from the parent's first inner step (never with a threshold)
         C.om_rc = launch_restrict_rt<T>(F.S, F.n, F.sci, FK.wv, rts->rcf, rts->v1, rts->kd, const_cast<T *>(rr),
                                         CK.rc, flag, F.Gs, stream, om, C.d_om, ncol);
     } else if (F.sell.ptr && !om) {  // sliced level: row sweep, then sums per aggregate
         const int *idx = k == 0 && !uperm ? F.perm : nullptr;  // the finest level's rows are in natural order
-        launch_sell_restrict<T>(F.sell, FK.sva, FK.minv, rr, F.xs, C.n, F.seg_ptr, idx, CK.rc, stream, ncol);
+        launch_sell_restrict<T>(F.sell, FK.sva, FK.minv, rr, F.xs, C.n, F.seg_ptr, idx, CK.rc, stream, ncol, gate);
         C.om_rc = DotRef{nullptr, 0};
     } else {
-        C.om_rc = launch_restrict<T>(F.S, F.n, F.sci, FK.wv, rr, CK.rc, F.Gs, stream, om, C.d_om, ncol);
+        C.om_rc = launch_restrict<T>(F.S, F.n, F.sci, FK.wv, rr, CK.rc, F.Gs, stream, om, C.d_om, ncol, gate);
     }
     KDots kd{};
     int mode;
     const T *edirect = nullptr;
+    const int *second = nullptr;  // gate of the second inner step (threshold only)
     if (tail) {
         const T *tva;
         if constexpr (std::is_same<T, double>::value) tva = C.tail_va;
         else tva = C.tail_va32;
         double *d1 = C.d_c1.final_out, *d2 = C.d_c2.final_out;
-        launch_tail_visit<T>(C.tail, tva, CK.minv, C.omega, ainv, CK.rc, CK.c1, CK.c2, d1, d2, flag, stream, ncol);
+        launch_tail_visit<T>(C.tail, tva, CK.minv, C.omega, ainv, CK.rc, CK.c1, CK.c2, d1, d2, flag, stream, ncol,
+                             gate, theta * theta);
         kd = KDots{DotRef{d1, 1}, DotRef{d1 + 1, 1}, DotRef{d2, 1}, DotRef{d2 + 1, 1}, DotRef{d2 + 2, 1}};
         mode = 2;
     } else if (k + 1 == L) {
@@ -1046,14 +1064,28 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
             edirect = CK.c1;
         }
     } else {
-        kcycle<T>(k + 1, CK.rc, CK.c1, nullptr, nullptr, ncol);
+        kcycle<T>(k + 1, CK.rc, CK.c1, nullptr, nullptr, ncol, gate);
         const DotSet s1 = launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c1, CK.v1, CK.rc, nullptr, C.G, C.d_c1, stream,
-                                              C.omega, ncol, C.sl(), CK.sva);
+                                              C.omega, ncol, C.sl(), CK.sva, gate);
         kd.rho1 = s1.d[0];
         kd.alpha1 = s1.d[1];
         if (C.omega) C.om_v1 = s1.d[2];
         mode = 1;
-        if (opt.kcycle_inner == 2) {
+        if (opt.kcycle_inner == 2 && theta > 0.0) {
+            // rt with the test's products, then the gate of the second step, under
+            // which that step and everything nested in it run
+            const DotRef om_rt = launch_inner_residual_theta<T>(C.n, CK.rc, CK.v1, kd, CK.rt, flag, C.omega, C.d_th,
+                                                                theta * theta, gate, C.gate2, stream, ncol);
+            if (C.omega) C.om_rc = om_rt;  // the restriction of rt for C's visit
+            kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, nullptr, ncol, C.gate2);
+            const DotSet s2 = launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c2, nullptr, CK.v1, CK.rt, C.G, C.d_c2,
+                                                  stream, nullptr, ncol, C.sl(), CK.sva, C.gate2);
+            kd.beta = s2.d[0];
+            kd.gamma = s2.d[1];
+            kd.alpha2 = s2.d[2];
+            mode = 2;
+            second = C.gate2;
+        } else if (opt.kcycle_inner == 2) {
             if (C.n < kSmallLevel || C.omega) {  // fold the inner residual into the next restriction
                 const RtSource<T> src{CK.rc, CK.v1, kd};
                 kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, &src, ncol);
@@ -1072,7 +1104,7 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
     if (k == 0) kd0 = kd;
     return launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rr, F.agg_pos, F.cagg, mode, edirect, CK.c1, CK.c2, kd, xx,
                                  wdot, k == 0 ? d_zq : DotBuf{}, flag, F.G, stream, ainv, C.n, ncol, F.xs, F.sl(),
-                                 FK.sva);
+                                 FK.sva, gate, second);
 }
 
 // One outer iteration is split in three replayable pieces:
@@ -1471,7 +1503,6 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy 
         !std::isfinite(opt.jacobi_weight) || !(opt.kcycle_threshold >= 0.0) || !std::isfinite(opt.kcycle_threshold) ||
         !(opt.skip_ratio >= 0.0) || !std::isfinite(opt.skip_ratio))
         return AMG_ERR_INVALID_ARGUMENT;
-    if (opt.kcycle_threshold > 0.0) return AMG_ERR_UNSUPPORTED;
     if (opt.smoother != AMG_SMOOTHER_L1 && opt.smoother != AMG_SMOOTHER_JACOBI) return AMG_ERR_UNSUPPORTED;
     if (opt.kcycle_inner != 1 && opt.kcycle_inner != 2) return AMG_ERR_UNSUPPORTED;
     if (opt.precision != AMG_PREC_FP64 && opt.precision != AMG_PREC_FP32_INNER) return AMG_ERR_UNSUPPORTED;
@@ -1656,27 +1687,47 @@ amg_status amg_spmv(amg_hierarchy *h, int32_t level, const double *x, double *y)
     });
 }
 
-amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z)
+}  // extern "C"
+
+namespace {
+amg_status kcycle_columns(amg_hierarchy *h, int ncol, const double *r, int ldr, double *z, int ldz)
 {
-    if (!h || !r || !z) return AMG_ERR_INVALID_ARGUMENT;
-    if (!device_array(r) || !device_array(z)) return AMG_ERR_INVALID_ARGUMENT;
     if (h->kcycle_visits() > amg_hierarchy::kMaxKcycleVisits) return AMG_ERR_UNSUPPORTED;
     return guarded([&]() {
         const Level &F = h->lev[0];
-        h->autotune(1);
-        h->capture_graphs(1);
+        h->autotune(ncol);
+        h->capture_graphs(ncol);
         AMG_HIP(hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
-        amg::launch_gather(F.n, r, h->uperm, h->r, h->stream);
-        if (h->mixed) {  // the mixed K-cycle reads (r, r) from scal[0]
-            const DotRef rr = amg::launch_dot(F.n, h->r, h->r, h->d_res, h->stream);
-            amg::launch_reduce(rr, h->scal, h->stream);
+        amg::launch_gather(F.n, r, h->uperm, h->r, h->stream, ncol, ldr, F.n);
+        if (h->mixed) {  // the mixed K-cycle reads (r, r) of column c from scal[c * kScalCol]
+            const DotRef rr = amg::launch_dot(F.n, h->r, h->r, h->d_res, h->stream, ncol);
+            amg::launch_reduce(rr, h->scal, h->stream, ncol);
         }
-        h->run_kcycle(1);
-        amg::launch_scatter(F.n, h->z, h->uperm, z, h->stream);
+        h->run_kcycle(ncol);
+        amg::launch_scatter(F.n, h->z, h->uperm, z, h->stream, ncol, F.n, ldz);
         AMG_HIP(hipMemcpyAsync(h->host_i, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         h->sync();
         return h->host_i[0] ? AMG_ERR_BREAKDOWN : AMG_OK;
     });
+}
+}  // namespace
+
+extern "C" {
+
+amg_status amg_kcycle(amg_hierarchy *h, const double *r, double *z)
+{
+    if (!h || !r || !z) return AMG_ERR_INVALID_ARGUMENT;
+    if (!device_array(r) || !device_array(z)) return AMG_ERR_INVALID_ARGUMENT;
+    return kcycle_columns(h, 1, r, h->lev[0].n, z, h->lev[0].n);
+}
+
+amg_status amg_kcycle_batch(amg_hierarchy *h, int32_t nrhs, const double *R, int32_t ldr, double *Z, int32_t ldz)
+{
+    if (!h || !R || !Z) return AMG_ERR_INVALID_ARGUMENT;
+    const int n = h->lev[0].n;
+    if (nrhs < 1 || nrhs > h->opt.max_rhs || ldr < n || ldz < n) return AMG_ERR_INVALID_ARGUMENT;
+    if (!device_array(R) || !device_array(Z)) return AMG_ERR_INVALID_ARGUMENT;
+    return kcycle_columns(h, nrhs, R, ldr, Z, ldz);
 }
 
 amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, double *bytes)

@@ -97,6 +97,14 @@ __device__ inline double *colp(double *part)
     return part ? part + (size_t)blockIdx.y * kDotCol : part;
 }
 
+// K-cycle threshold (Sec. 4.3): a kernel of a second inner step that the
+// threshold test skipped for this right-hand side (gate[column] == 0) returns at
+// once.  The whole grid of a column takes the same branch.  gate NULL: always runs.
+__device__ inline bool gated_off(const int *gate)
+{
+    return gate && gate[blockIdx.y] == 0;
+}
+
 // Sum over the block; every thread receives the same value (fixed order).
 __device__ inline double block_sum(double v)
 {
@@ -384,8 +392,9 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dots(Rows R, const int *__restr
                                                       const T *__restrict__ va, const T *__restrict__ x,
                                                       T *__restrict__ y, const T *__restrict__ w1,
                                                       const T *__restrict__ w2, const double *__restrict__ om,
-                                                      double *__restrict__ part)
+                                                      double *__restrict__ part, const int *__restrict__ gate)
 {
+    if (gated_off(gate)) return;
     constexpr int NT = ND + (OMY ? 1 : 0);
     x = colv(x, R.n);
     y = colv(y, R.n);
@@ -458,8 +467,9 @@ __global__ void __launch_bounds__(kBlock) k_residual(Rows R, const int *__restri
 constexpr int kReduceThreads = 1024;
 __global__ void __launch_bounds__(kReduceThreads) k_reduce_partials(int nd, const double *__restrict__ part,
                                                                     int count, double *__restrict__ out,
-                                                                    int out_stride)
+                                                                    int out_stride, const int *__restrict__ gate)
 {
+    if (gated_off(gate)) return;
     part += (size_t)blockIdx.y * kDotCol;
     out += (size_t)blockIdx.y * out_stride;
     __shared__ double sh[kReduceThreads / kWave];
@@ -496,8 +506,9 @@ template <class T, int G, bool LAT, bool OM>
 __global__ void __launch_bounds__(kBlock) k_restrict(Rows S, int nf, const int *__restrict__ ci,
                                                      const T *__restrict__ wv, const T *__restrict__ r,
                                                      T *__restrict__ rc, const double *__restrict__ om,
-                                                     double *__restrict__ part)
+                                                     double *__restrict__ part, const int *__restrict__ gate)
 {
+    if (gated_off(gate)) return;
     r = colv(r, nf);
     rc = colv(rc, S.n);
     part = colp(part);
@@ -524,13 +535,20 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Rows S, int nf, const int *
 struct KCoef {
     double a1, a2;
     bool bad;
+    bool two;  // the second step's direction c2 enters the correction (it was not skipped)
 };
 
+// second (may be NULL): the gate of the second inner step; where it is 0 for this
+// right-hand side the threshold test skipped that step and mode 2 reads as mode 1.
 template <bool PREFETCH = true>
-__device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd)
+__device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd, const int *second = nullptr)
 {
-    KCoef c{0.0, 0.0, false};
+    KCoef c{0.0, 0.0, false, mode == 2};
     if (mode == 0 || mode == 3) return c;
+    if (mode == 2 && second && second[blockIdx.y] == 0) {
+        mode = 1;  // c2 was never formed for this column: it must not be read
+        c.two = false;
+    }
     double rho1, alpha1, beta = 0.0, gamma = 0.0, alpha2 = 0.0;
     if (mode == 2) {
         const DotRef refs[5] = {kd.rho1, kd.alpha1, kd.beta, kd.gamma, kd.alpha2};
@@ -635,6 +653,52 @@ __global__ void __launch_bounds__(kBlock) k_inner_residual(int n, const T *__res
         rt[i] = (T)((double)rc[i] - c.a1 * (double)v1[i]);
 }
 
+// The same with the threshold test's inputs: partials of (rc, rc), (rt, rt) and,
+// with om, (om, rt) (the restriction of rt when the next level down is a single
+// unknown).  Runs under the gate of the enclosing step.
+template <class T, bool OM>
+__global__ void __launch_bounds__(kBlock) k_inner_residual_theta(int n, const T *__restrict__ rc,
+                                                                 const T *__restrict__ v1, KDots kd,
+                                                                 T *__restrict__ rt, int *__restrict__ flag,
+                                                                 const double *__restrict__ om,
+                                                                 double *__restrict__ part,
+                                                                 const int *__restrict__ gate)
+{
+    if (gated_off(gate)) return;
+    rc = colv(rc, n);
+    v1 = colv(v1, n);
+    rt = colv(rt, n);
+    part = colp(part);
+    const KCoef c = kcycle_coefficients<true>(1, kd);
+    if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
+    constexpr int ND = OM ? 3 : 2;
+    double d[ND] = {};
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double g = (double)rc[i];
+        const T t = (T)(g - c.a1 * (double)v1[i]);
+        rt[i] = t;
+        d[0] += g * g;
+        d[1] += (double)t * (double)t;
+        if (OM) d[2 % ND] += om[i] * (double)t;
+    }
+    store_partials<ND>(d, part);
+}
+
+// Threshold test of one inner flexible-CG step (Sec. 4.3): the second step runs
+// for a right-hand side only if the enclosing step runs and ||rt|| >= theta ||rc||
+// (compared as squares, as the oracle does).  One block per right-hand side.
+__global__ void __launch_bounds__(kBlock) k_theta_gate(DotRef rcrc, DotRef rtrt, double theta2,
+                                                       const int *__restrict__ parent, int *__restrict__ gate)
+{
+    const bool run = !(parent && parent[blockIdx.y] == 0);
+    double v[2] = {0.0, 0.0};
+    if (run) {
+        const DotRef refs[2] = {rcrc, rtrt};
+        dot_values<2>(refs, v);
+    }
+    if (threadIdx.x == 0) gate[blockIdx.y] = run && !(v[1] < theta2 * v[0]) ? 1 : 0;
+}
+
 // Prolongation + post-smoothing: x = M^-1 r + P e (the pre-smoothed iterate plus
 // the coarse correction) is formed on the fly for every column (cagg[p], when
 // given, is the coarse unknown of column ci[p] stored per entry: on small,
@@ -654,8 +718,10 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
                                                         const T *__restrict__ c2, KDots kd,
                                                         T *__restrict__ xout, const T *__restrict__ wdot,
                                                         double *__restrict__ part, int *__restrict__ flag,
-                                                        const double *__restrict__ ainv, int nc)
+                                                        const double *__restrict__ ainv, int nc,
+                                                        const int *__restrict__ gate, const int *__restrict__ second)
 {
+    if (gated_off(gate)) return;
     r = colv(r, R.n);
     xout = colv(xout, R.n);
     wdot = colv(wdot, R.n);
@@ -664,11 +730,12 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
     c2 = colv(c2, nc);
     part = colp(part);
     double a1 = 0.0, a2 = 0.0;
+    bool two = MODE == 2;
     __shared__ double e_sh[MODE == 3 ? kInlineCoarse : 1];
     auto corr = [&](int J) -> double {
         if (MODE == 0) return (double)edirect[J];
         if (MODE == 3) return e_sh[J];
-        if (MODE == 1) return a1 * (double)c1[J];
+        if (MODE == 1 || !two) return a1 * (double)c1[J];
         return a1 * (double)c1[J] + a2 * (double)c2[J];
     };
     struct Pre {
@@ -683,10 +750,11 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
     visit_rows<G, CAGG>(
         R,
         [&]() {
-            const KCoef c = kcycle_coefficients<CAGG>(MODE, kd);  // CAGG marks small levels
+            const KCoef c = kcycle_coefficients<CAGG>(MODE, kd, second);  // CAGG marks small levels
             if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
             a1 = c.a1;
             a2 = c.a2;
+            two = c.two;
             if (MODE == 3) {  // e = A_coarsest^-1 rc, computed by every block into LDS
                 // wavefront w forms rows w, w + 4, ...; lane j holds column j
                 constexpr int kRows = kInlineCoarse / (kBlock / kWave);
@@ -739,20 +807,24 @@ __global__ void __launch_bounds__(kBlock) k_smooth_start(int n, const T *__restr
                                                          const T *__restrict__ edirect,
                                                          const T *__restrict__ c1,
                                                          const T *__restrict__ c2, KDots kd,
-                                                         double *__restrict__ x, int *__restrict__ flag, int nc)
+                                                         double *__restrict__ x, int *__restrict__ flag, int nc,
+                                                         const int *__restrict__ gate,
+                                                         const int *__restrict__ second)
 {
+    if (gated_off(gate)) return;
     r = colv(r, n);
     x = colv(x, n);
     edirect = colv(edirect, nc);
     c1 = colv(c1, nc);
     c2 = colv(c2, nc);
-    const KCoef c = kcycle_coefficients<false>(MODE, kd);
+    const KCoef c = kcycle_coefficients<false>(MODE, kd, second);
     if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const int J = agg_pos[i];
         double e;
         if (MODE == 0) e = (double)edirect[J];
         else if (MODE == 1) e = c.a1 * (double)c1[J];
+        else if (!c.two) e = c.a1 * (double)c1[J];
         else e = c.a1 * (double)c1[J] + c.a2 * (double)c2[J];
         x[i] = (double)minv[i] * (double)r[i] + e;
     }
@@ -764,8 +836,10 @@ __global__ void __launch_bounds__(kBlock) k_smooth_finish(Rows R, const int *__r
                                                           const T *__restrict__ minv,
                                                           const T *__restrict__ r,
                                                           const double *__restrict__ x, T *__restrict__ xout,
-                                                          const T *__restrict__ wdot, double *__restrict__ part)
+                                                          const T *__restrict__ wdot, double *__restrict__ part,
+                                                          const int *__restrict__ gate)
 {
+    if (gated_off(gate)) return;
     r = colv(r, R.n);
     x = colv(x, R.n);
     xout = colv(xout, R.n);
@@ -848,8 +922,10 @@ __global__ void __launch_bounds__(kBlock) k_sell_smooth_finish(int n, int tpb, c
                                                                const int *__restrict__ sc, const T *__restrict__ sv,
                                                                const T *__restrict__ minv, const T *__restrict__ r,
                                                                const double *__restrict__ x, T *__restrict__ xout,
-                                                               const T *__restrict__ wdot, double *__restrict__ part)
+                                                               const T *__restrict__ wdot, double *__restrict__ part,
+                                                               const int *__restrict__ gate)
 {
+    if (gated_off(gate)) return;
     r = colv(r, n);
     x = colv(x, n);
     xout = colv(xout, n);
@@ -873,8 +949,9 @@ __global__ void __launch_bounds__(kBlock) k_sell_spmv_dots(int n, int tpb, const
                                                            const int *__restrict__ sc, const T *__restrict__ sv,
                                                            const T *__restrict__ x, T *__restrict__ y,
                                                            const T *__restrict__ w1, const T *__restrict__ w2,
-                                                           double *__restrict__ part)
+                                                           double *__restrict__ part, const int *__restrict__ gate)
 {
+    if (gated_off(gate)) return;
     x = colv(x, n);
     y = colv(y, n);
     w1 = colv(w1, n);
@@ -904,8 +981,10 @@ __global__ void __launch_bounds__(kBlock) k_sell_presmooth_residual(int n, int t
                                                                     const int *__restrict__ sc,
                                                                     const T *__restrict__ sv,
                                                                     const T *__restrict__ minv,
-                                                                    const T *__restrict__ r, double *__restrict__ t)
+                                                                    const T *__restrict__ r, double *__restrict__ t,
+                                                                    const int *__restrict__ gate)
 {
+    if (gated_off(gate)) return;
     r = colv(r, n);
     t = colv(t, n);
     sell_tiles(n, tpb, sptr, [&](int i, int beg, int w, int lane) {
@@ -924,8 +1003,10 @@ constexpr int kSegUnroll = 8;
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_segment_sum(int nc, const int *__restrict__ seg,
                                                         const int *__restrict__ idx, int nf,
-                                                        const double *__restrict__ t, T *__restrict__ rc)
+                                                        const double *__restrict__ t, T *__restrict__ rc,
+                                                        const int *__restrict__ gate)
 {
+    if (gated_off(gate)) return;
     t = colv(t, nf);
     rc = colv(rc, nc);
     for (int J = blockIdx.x * kBlock + threadIdx.x; J < nc; J += gridDim.x * kBlock) {
@@ -963,8 +1044,10 @@ __global__ void __launch_bounds__(kBlock) k_post_direct(Rows R, const int *__res
                                                         const T *__restrict__ r, const T *__restrict__ v1,
                                                         KDots kd, DotRef om_r, DotRef om_v1,
                                                         const double *__restrict__ ainv, T *__restrict__ xout,
-                                                        T *__restrict__ rt_out, int *__restrict__ flag)
+                                                        T *__restrict__ rt_out, int *__restrict__ flag,
+                                                        const int *__restrict__ gate)
 {
+    if (gated_off(gate)) return;
     r = colv(r, R.n);
     v1 = colv(v1, R.n);
     xout = colv(xout, R.n);
@@ -1045,8 +1128,10 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const
                                                              const double *__restrict__ ainv,
                                                              const T *__restrict__ rc, T *__restrict__ c1,
                                                              T *__restrict__ c2, double *__restrict__ d1,
-                                                             double *__restrict__ d2, int *__restrict__ flag)
+                                                             double *__restrict__ d2, int *__restrict__ flag,
+                                                             const int *__restrict__ gate, double theta2)
 {
+    if (gated_off(gate)) return;
     constexpr int R = kTailRows, W = kTailWidth, S = kTailSlots, NL = kTailLong;
     __shared__ double xs[R * kTailThreads];  // the vector being multiplied
     __shared__ double rs[R * kTailThreads];  // rc (first step), then rt (second step)
@@ -1086,6 +1171,7 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const
         rs[i] = rv[u];
         ms[i] = mv[u];
         q[0] += o[u] * rv[u];
+        q[1] += rv[u] * rv[u];  // (rc, rc) for the threshold test
     }
     const double acinv = ainv[0];
     // y = (A xs) at the owned rows; the sums of long rows are block sums (whose
@@ -1132,8 +1218,15 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const
         }
     };
     // first step: c1 = K(rc) with e = (om, rc) / a_c
-    double om_r[1] = {q[0]};
-    tail_sums<1>(om_r);
+    double om_r[1] = {q[0]}, rcrc = 0.0;
+    if (theta2 > 0.0) {
+        double v2[2] = {q[0], q[1]};
+        tail_sums<2>(v2);
+        om_r[0] = v2[0];
+        rcrc = v2[1];
+    } else {
+        tail_sums<1>(om_r);
+    }
     const double e1 = acinv * om_r[0];
     double x[R], y[R], c[R];
 #pragma unroll
@@ -1176,6 +1269,7 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const
     const double al = (bad || zero) ? 0.0 : alpha1 / rho1;
     // second step: rt = rc - (alpha1/rho1) v1, c2 = K(rt) with e = (om, rt) / a_c
     const double e2 = acinv * (om_r[0] - al * q[2]);
+    double rtrt[1] = {0.0};
 #pragma unroll
     for (int u = 0; u < R; u++) {
         const int i = t + u * kTailThreads;
@@ -1183,6 +1277,23 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const
         x[u] = ms[i] * rr + e2;
         rs[i] = rr;
         xs[i] = x[u];
+        if (i < n) rtrt[0] += (double)(T)rr * (double)(T)rr;
+    }
+    if (theta2 > 0.0) {  // threshold test (Sec. 4.3): skip the second step, c2 = 0
+        tail_sums<1>(rtrt);
+        if (rtrt[0] < theta2 * rcrc) {
+#pragma unroll
+            for (int u = 0; u < R; u++) {
+                const int i = t + u * kTailThreads;
+                if (i < n) c2[i] = (T)0.0;
+            }
+            if (t == 0) {
+                d1[0] = rho1;
+                d1[1] = alpha1;
+                d2[0] = d2[1] = d2[2] = 0.0;
+            }
+            return;
+        }
     }
     __syncthreads();
     apply(y);  // A x
@@ -1407,10 +1518,10 @@ inline int rows_grid(const Rows &R, int G, int cap)
 constexpr int kConsumerReduceMax = 1024;
 
 void reduce_if_large(int nd, double *part, int count, double *final_out, hipStream_t s, int ncol,
-                     int limit = kConsumerReduceMax)
+                     int limit = kConsumerReduceMax, const int *gate = nullptr)
 {
     if (count > limit && final_out) {
-        k_reduce_partials<<<dim3(1, ncol), kReduceThreads, 0, s>>>(nd, part, count, final_out, kDotCol);
+        k_reduce_partials<<<dim3(1, ncol), kReduceThreads, 0, s>>>(nd, part, count, final_out, kDotCol, gate);
         AMG_HIP(hipGetLastError());
     }
 }
@@ -1470,7 +1581,8 @@ inline int sell_grid(const Sell &S, bool dot, int *tpb)
 
 template <class T>
 DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, const T *w1, const T *w2, int G,
-                        DotBuf buf, hipStream_t s, const double *omy, int ncol, const Sell *sl, const T *sva)
+                        DotBuf buf, hipStream_t s, const double *omy, int ncol, const Sell *sl, const T *sva,
+                        const int *gate)
 {
     const int nd = w2 ? 3 : (w1 ? 2 : 1);
     if (sl) {
@@ -1478,14 +1590,14 @@ DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, co
         int tpb = 1;
         const dim3 grid(sell_grid(*sl, true, &tpb), ncol);
 #define AMG_SELL_DOTS(ND) \
-    k_sell_spmv_dots<T, ND><<<grid, kBlock, 0, s>>>(sl->n, tpb, sl->ptr, sl->ci, sva, x, y, w1, w2, buf.part)
+    k_sell_spmv_dots<T, ND><<<grid, kBlock, 0, s>>>(sl->n, tpb, sl->ptr, sl->ci, sva, x, y, w1, w2, buf.part, gate)
         if (nd == 1) AMG_SELL_DOTS(1);
         else if (nd == 2) AMG_SELL_DOTS(2);
         else AMG_SELL_DOTS(3);
 #undef AMG_SELL_DOTS
         AMG_HIP(hipGetLastError());
         const int count = (int)grid.x;
-        reduce_if_large(nd, buf.part, count, buf.final_out, s, ncol, 1);
+        reduce_if_large(nd, buf.part, count, buf.final_out, s, ncol, 1, gate);
         DotSet out{};
         for (int d = 0; d < nd; d++) out.d[d] = finished(buf.part, count, buf.final_out, d, 1);
         return out;
@@ -1494,7 +1606,7 @@ DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, co
     if (omy && nd == 3) throw Error(4, "spmv_dots: at most three products");
 #define AMG_SPMV_DOTS(ND, LAT, OMY)                                                                        \
     AMG_SWITCH_G(G, (k_spmv_dots<T, kG, ND, LAT, OMY><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, omy, \
-                                                                               buf.part)))
+                                                                               buf.part, gate)))
     const bool lat = R.n < kSmallLevel;
     if (omy) {
         if (nd == 1) {
@@ -1525,7 +1637,7 @@ DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, co
     AMG_HIP(hipGetLastError());
     const int nt = nd + (omy ? 1 : 0);
     const int count = (int)grid.x + R.nlong;
-    reduce_if_large(nt, buf.part, count, buf.final_out, s, ncol);
+    reduce_if_large(nt, buf.part, count, buf.final_out, s, ncol, kConsumerReduceMax, gate);
     DotSet out{};
     for (int d = 0; d < nt; d++) out.d[d] = finished(buf.part, count, buf.final_out, d);
     return out;
@@ -1546,26 +1658,29 @@ DotSet launch_residual(Rows R, const int *ci, const double *va, const double *b,
 
 void launch_reduce(const DotRef &ref, double *out, hipStream_t s, int ncol, int out_stride)
 {
-    k_reduce_partials<<<dim3(1, ncol), kReduceThreads, 0, s>>>(1, ref.part, ref.count, out, out_stride);
+    k_reduce_partials<<<dim3(1, ncol), kReduceThreads, 0, s>>>(1, ref.part, ref.count, out, out_stride, nullptr);
     AMG_HIP(hipGetLastError());
 }
 
 template <class T>
 DotRef launch_restrict(Rows S, int nf, const int *ci, const T *wv, const T *r, T *rc, int G, hipStream_t s,
-                       const double *om, DotBuf buf, int ncol)
+                       const double *om, DotBuf buf, int ncol, const int *gate)
 {
     const dim3 grid(rows_grid(S, G, om ? kMaxDotBlocks : (1 << 20)), ncol);
     if (om) {
-        AMG_SWITCH_G(G, (k_restrict<T, kG, true, true><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part)));
+        AMG_SWITCH_G(G, (k_restrict<T, kG, true, true><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part,
+                                                                                gate)));
     } else if (S.n < kSmallLevel) {
-        AMG_SWITCH_G(G, (k_restrict<T, kG, true, false><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part)));
+        AMG_SWITCH_G(G, (k_restrict<T, kG, true, false><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part,
+                                                                                 gate)));
     } else {
-        AMG_SWITCH_G(G, (k_restrict<T, kG, false, false><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part)));
+        AMG_SWITCH_G(G, (k_restrict<T, kG, false, false><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part,
+                                                                                  gate)));
     }
     AMG_HIP(hipGetLastError());
     if (!om) return DotRef{nullptr, 0};
     const int count = (int)grid.x + S.nlong;
-    reduce_if_large(1, buf.part, count, buf.final_out, s, ncol);
+    reduce_if_large(1, buf.part, count, buf.final_out, s, ncol, kConsumerReduceMax, gate);
     return finished(buf.part, count, buf.final_out, 0);
 }
 
@@ -1577,16 +1692,33 @@ void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int
 }
 
 template <class T>
+DotRef launch_inner_residual_theta(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, const double *om,
+                                   DotBuf buf, double theta2, const int *gate, int *gate_out, hipStream_t s, int ncol)
+{
+    const dim3 grid(grid_for(n, 4096), ncol);
+    if (om) k_inner_residual_theta<T, true><<<grid, kBlock, 0, s>>>(n, rc, v1, kd, rt, flag, om, buf.part, gate);
+    else k_inner_residual_theta<T, false><<<grid, kBlock, 0, s>>>(n, rc, v1, kd, rt, flag, om, buf.part, gate);
+    AMG_HIP(hipGetLastError());
+    const int nd = om ? 3 : 2, count = (int)grid.x;
+    reduce_if_large(nd, buf.part, count, buf.final_out, s, ncol, kConsumerReduceMax, gate);
+    k_theta_gate<<<dim3(1, ncol), kBlock, 0, s>>>(finished(buf.part, count, buf.final_out, 0),
+                                                  finished(buf.part, count, buf.final_out, 1), theta2, gate, gate_out);
+    AMG_HIP(hipGetLastError());
+    return om ? finished(buf.part, count, buf.final_out, 2) : DotRef{nullptr, 0};
+}
+
+template <class T>
 DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, const T *r, const int *agg_pos,
                           const int *cagg, int mode, const T *edirect, const T *c1, const T *c2, KDots kd, T *xout,
                           const T *wdot, DotBuf buf, int *flag, int G, hipStream_t s, const double *ainv, int nc,
-                          int ncol, double *xtmp, const Sell *sl, const T *sva)
+                          int ncol, double *xtmp, const Sell *sl, const T *sva, const int *gate, const int *second)
 {
     const bool dot = wdot != nullptr;
     const dim3 grid(rows_grid(R, G, dot ? kMaxDotBlocks : (1 << 20)), ncol);
     if (xtmp && !cagg && R.n >= kSmallLevel && mode >= 0 && mode <= 2) {  // two launches, see k_smooth_start
         const dim3 g1(grid_for(R.n, 1 << 16), ncol);
-#define AMG_START(M) k_smooth_start<T, M><<<g1, kBlock, 0, s>>>(R.n, minv, r, agg_pos, edirect, c1, c2, kd, xtmp, flag, nc)
+#define AMG_START(M) \
+    k_smooth_start<T, M><<<g1, kBlock, 0, s>>>(R.n, minv, r, agg_pos, edirect, c1, c2, kd, xtmp, flag, nc, gate, second)
         switch (mode) {
         case 0: AMG_START(0); break;
         case 1: AMG_START(1); break;
@@ -1599,27 +1731,27 @@ DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, con
             const dim3 gs(sell_grid(*sl, dot, &tpb), ncol);
             if (dot) {
                 k_sell_smooth_finish<T, true><<<gs, kBlock, 0, s>>>(sl->n, tpb, sl->ptr, sl->ci, sva, minv, r, xtmp,
-                                                                    xout, wdot, buf.part);
+                                                                    xout, wdot, buf.part, gate);
             } else {
                 k_sell_smooth_finish<T, false><<<gs, kBlock, 0, s>>>(sl->n, tpb, sl->ptr, sl->ci, sva, minv, r, xtmp,
-                                                                     xout, wdot, buf.part);
+                                                                     xout, wdot, buf.part, gate);
             }
             AMG_HIP(hipGetLastError());
             if (!dot) return DotRef{nullptr, 0};
-            reduce_if_large(1, buf.part, (int)gs.x, buf.final_out, s, ncol, 1);
+            reduce_if_large(1, buf.part, (int)gs.x, buf.final_out, s, ncol, 1, gate);
             return finished(buf.part, (int)gs.x, buf.final_out, 0, 1);
         }
         if (dot) {
             AMG_SWITCH_G(G, (k_smooth_finish<T, kG, true><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, xtmp, xout, wdot,
-                                                                                buf.part)));
+                                                                                buf.part, gate)));
         } else {
             AMG_SWITCH_G(G, (k_smooth_finish<T, kG, false><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, xtmp, xout, wdot,
-                                                                                 buf.part)));
+                                                                                 buf.part, gate)));
         }
         AMG_HIP(hipGetLastError());
         if (!dot) return DotRef{nullptr, 0};
         const int count = (int)grid.x + R.nlong;
-        reduce_if_large(1, buf.part, count, buf.final_out, s, ncol);
+        reduce_if_large(1, buf.part, count, buf.final_out, s, ncol, kConsumerReduceMax, gate);
         return finished(buf.part, count, buf.final_out, 0);
     }
 #define AMG_POST(M, D)                                                                                         \
@@ -1627,11 +1759,11 @@ DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, con
         if (cagg) {                                                                                            \
             AMG_SWITCH_G(G, (k_post_smooth<T, kG, M, D, true><<<grid, kBlock, 0, s>>>(                         \
                                 R, ci, va, minv, r, agg_pos, cagg, edirect, c1, c2, kd, xout, wdot, buf.part, flag,  \
-                                ainv, nc)));                                                                   \
+                                ainv, nc, gate, second)));                                                     \
         } else {                                                                                               \
             AMG_SWITCH_G(G, (k_post_smooth<T, kG, M, D, false><<<grid, kBlock, 0, s>>>(                        \
                                 R, ci, va, minv, r, agg_pos, cagg, edirect, c1, c2, kd, xout, wdot, buf.part, flag,  \
-                                ainv, nc)));                                                                   \
+                                ainv, nc, gate, second)));                                                     \
         }                                                                                                      \
     } while (0)
     switch (mode) {
@@ -1647,19 +1779,19 @@ DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, con
     AMG_HIP(hipGetLastError());
     if (!dot) return DotRef{nullptr, 0};
     const int count = (int)grid.x + R.nlong;
-    reduce_if_large(1, buf.part, count, buf.final_out, s, ncol);
+    reduce_if_large(1, buf.part, count, buf.final_out, s, ncol, kConsumerReduceMax, gate);
     return finished(buf.part, count, buf.final_out, 0);
 }
 
 template <class T>
 void launch_sell_restrict(const Sell &S, const T *sva, const T *minv, const T *r, double *t, int nc, const int *seg,
-                          const int *idx, T *rc, hipStream_t s, int ncol)
+                          const int *idx, T *rc, hipStream_t s, int ncol, const int *gate)
 {
     int tpb = 1;
     const dim3 grid(sell_grid(S, false, &tpb), ncol);
-    k_sell_presmooth_residual<T><<<grid, kBlock, 0, s>>>(S.n, tpb, S.ptr, S.ci, sva, minv, r, t);
+    k_sell_presmooth_residual<T><<<grid, kBlock, 0, s>>>(S.n, tpb, S.ptr, S.ci, sva, minv, r, t, gate);
     AMG_HIP(hipGetLastError());
-    k_segment_sum<T><<<dim3(grid_for(nc), ncol), kBlock, 0, s>>>(nc, seg, idx, S.n, t, rc);
+    k_segment_sum<T><<<dim3(grid_for(nc), ncol), kBlock, 0, s>>>(nc, seg, idx, S.n, t, rc, gate);
     AMG_HIP(hipGetLastError());
 }
 
@@ -1685,24 +1817,26 @@ DotRef launch_restrict_rt(Rows S, int nf, const int *ci, const T *wv, const T *r
 template <class T>
 void launch_post_direct(Rows R, const int *ci, const T *va, const T *minv, const T *r, const T *v1, KDots kd,
                         DotRef om_r, DotRef om_v1, const double *ainv, T *xout, T *rt_out, int *flag, int G,
-                        bool rt_mode, hipStream_t s, int ncol)
+                        bool rt_mode, hipStream_t s, int ncol, const int *gate)
 {
     const dim3 grid(rows_grid(R, G, 1 << 20), ncol);
     if (rt_mode) {
         AMG_SWITCH_G(G, (k_post_direct<T, kG, true><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, v1, kd, om_r, om_v1,
-                                                                             ainv, xout, rt_out, flag)));
+                                                                             ainv, xout, rt_out, flag, gate)));
     } else {
         AMG_SWITCH_G(G, (k_post_direct<T, kG, false><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, v1, kd, om_r, om_v1,
-                                                                              ainv, xout, rt_out, flag)));
+                                                                              ainv, xout, rt_out, flag, gate)));
     }
     AMG_HIP(hipGetLastError());
 }
 
 template <class T>
 void launch_tail_visit(const TailLayout &L, const T *va, const T *minv, const double *om, const double *ainv,
-                       const T *rc, T *c1, T *c2, double *d1, double *d2, int *flag, hipStream_t s, int ncol)
+                       const T *rc, T *c1, T *c2, double *d1, double *d2, int *flag, hipStream_t s, int ncol,
+                       const int *gate, double theta2)
 {
-    k_tail_visit<T><<<dim3(1, ncol), kTailThreads, 0, s>>>(L, va, minv, om, ainv, rc, c1, c2, d1, d2, flag);
+    k_tail_visit<T><<<dim3(1, ncol), kTailThreads, 0, s>>>(L, va, minv, om, ainv, rc, c1, c2, d1, d2, flag, gate,
+                                                           theta2);
     AMG_HIP(hipGetLastError());
 }
 
@@ -1789,24 +1923,28 @@ void launch_to_float(int64_t n, const double *src, float *dst, hipStream_t s)
 
 #define AMG_INSTANTIATE(T)                                                                                           \
     template DotSet launch_spmv_dots<T>(Rows, const int *, const T *, const T *, T *, const T *, const T *, int,     \
-                                        DotBuf, hipStream_t, const double *, int, const Sell *, const T *);         \
+                                        DotBuf, hipStream_t, const double *, int, const Sell *, const T *,          \
+                                        const int *);                                                               \
     template DotRef launch_restrict<T>(Rows, int, const int *, const T *, const T *, T *, int, hipStream_t,          \
-                                       const double *, DotBuf, int);                                                \
+                                       const double *, DotBuf, int, const int *);                                   \
     template void launch_sell_restrict<T>(const Sell &, const T *, const T *, const T *, double *, int, const int *, \
-                                          const int *, T *, hipStream_t, int);                                      \
+                                          const int *, T *, hipStream_t, int, const int *);                         \
     template void launch_inner_residual<T>(int, const T *, const T *, KDots, T *, int *, hipStream_t, int);         \
+    template DotRef launch_inner_residual_theta<T>(int, const T *, const T *, KDots, T *, int *, const double *,    \
+                                                   DotBuf, double, const int *, int *, hipStream_t, int);           \
     template DotRef launch_post_smooth<T>(Rows, const int *, const T *, const T *, const T *, const int *,          \
                                           const int *, int, const T *, const T *, const T *, KDots, T *, const T *, \
                                           DotBuf, int *, int, hipStream_t, const double *, int, int, double *,      \
-                                          const Sell *, const T *);                                                 \
+                                          const Sell *, const T *, const int *, const int *);                       \
     template DotRef launch_restrict_rt<T>(Rows, int, const int *, const T *, const T *, const T *, KDots, T *, T *, \
                                           int *, int, hipStream_t, const double *, DotBuf, int);                    \
     template void launch_post_direct<T>(Rows, const int *, const T *, const T *, const T *, const T *, KDots,       \
                                         DotRef, DotRef, const double *, T *, T *, int *, int, bool, hipStream_t,    \
-                                        int);                                                                       \
+                                        int, const int *);                                                          \
     template void launch_coarse_solve<T>(const CoarseSolve &, const T *, T *, hipStream_t, int);                   \
     template void launch_tail_visit<T>(const TailLayout &, const T *, const T *, const double *, const double *,    \
-                                       const T *, T *, T *, double *, double *, int *, hipStream_t, int);
+                                       const T *, T *, T *, double *, double *, int *, hipStream_t, int,            \
+                                       const int *, double);
 AMG_INSTANTIATE(double)
 AMG_INSTANTIATE(float)
 #undef AMG_INSTANTIATE

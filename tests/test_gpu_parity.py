@@ -589,3 +589,85 @@ def test_level_skipping_matches_oracle(amg, case, opt):
     _, st_o, it_o, _, _ = ref.solve(r, tol=1e-9)
     rel = np.linalg.norm(r - oracle.spmv(rp, ci, va, x.cpu().numpy())) / np.linalg.norm(r)
     assert st == amg.AMG_OK and rel <= 1e-9 and abs(info.iterations - it_o) <= 2
+
+
+@pytest.mark.parametrize("case,opt,theta", [
+    (case, opt, theta)
+    for case, opt, thetas in [("grid3d_24_jitter", {}, (0.25, 0.6)), ("grid3d_24_jitter", dict(coarsest_size=1), (0.25, 0.6)),
+                              ("rgg_20k", {}, (0.4, 0.6)), ("grid2d_77x50_jitter", dict(coarsest_size=8), (0.25, 0.6))]
+    for theta in thetas])
+def test_kcycle_threshold_matches_oracle(amg, case, opt, theta):
+    """The K-cycle threshold of Sec. 4.3: the second inner step on a coarse level is
+    skipped where ||rt|| < theta ||rc||, decided on the device per visit.  One cycle
+    matches the oracle's element by element and the solve converges like it.
+    coarsest_size=1 puts the skip test inside the one-block kernel of the level above
+    the single coarse unknown."""
+    rp, ci, va = CASES[case]()
+    n = len(rp) - 1
+    h, ref = setup_both(amg, rp, ci, va, kcycle_threshold=theta, **opt)
+    assert_same_hierarchy(h, ref)
+    r = inputs.rhs(n, 21)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.kcycle(dev(r), z)
+    zo = ref.kcycle(r)
+    full = oracle.Hierarchy(rp, ci, va, **opt).kcycle(r)
+    print(f"[parity] threshold {theta}: |z - z_full| / |z_full| = "
+          f"{np.abs(zo - full).max() / np.abs(full).max():.2e}", flush=True)
+    assert np.abs(zo - full).max() > 1e-6 * np.abs(full).max()  # some second step was skipped
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-10 * np.abs(zo).max())
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, info = h.solve(dev(r), x, tol=1e-9)
+    _, st_o, it_o, _, _ = ref.solve(r, tol=1e-9)
+    rel = np.linalg.norm(r - oracle.spmv(rp, ci, va, x.cpu().numpy())) / np.linalg.norm(r)
+    assert st == amg.AMG_OK and rel <= 1e-9 and abs(info.iterations - it_o) <= 2
+
+
+def test_kcycle_threshold_limits(amg):
+    """theta so large that every second step is skipped gives the one-step cycle
+    (kcycle_inner = 1) bit for bit on the GPU; theta = 0 leaves the default cycle."""
+    rp, ci, va = CASES["grid3d_24_jitter"]()
+    n = len(rp) - 1
+    r = dev(inputs.rhs(n, 22))
+    out = {}
+    for name, opt in [("huge", dict(kcycle_threshold=1e300)), ("one", dict(kcycle_inner=1)),
+                      ("zero", dict(kcycle_threshold=0.0)), ("default", {})]:
+        h = amg.Hierarchy(dev(rp), dev(ci), dev(va), **opt)
+        z = torch.empty(n, dtype=torch.float64, device="cuda")
+        h.kcycle(r, z)
+        out[name] = z.cpu().numpy()
+        h.close()
+    np.testing.assert_array_equal(out["huge"], out["one"])
+    np.testing.assert_array_equal(out["zero"], out["default"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_inner"])
+def test_kcycle_threshold_batch_columns_decide_alone(amg, precision):
+    """Every column of a batch takes its own skip decisions: one batched K-cycle
+    gives, column by column, bitwise what the single-column K-cycle gives (and the
+    oracle's cycle within the precision's bound), although the columns skip
+    different steps."""
+    rp, ci, va = CASES["grid3d_24_jitter"]()
+    n = len(rp) - 1
+    prec = amg.AMG_PREC_FP64 if precision == "fp64" else amg.AMG_PREC_FP32_INNER
+    bound = 1e-10 if precision == "fp64" else 2e-5
+    theta = 0.4
+    R = np.stack([inputs.rhs(n, 40 + k) for k in range(3)])
+    R[1] = oracle.spmv(rp, ci, va, R[1])  # a smoother right-hand side: other decisions
+    h = amg.Hierarchy(dev(rp), dev(ci), dev(va), kcycle_threshold=theta, max_rhs=3, precision=prec)
+    ref = oracle.Hierarchy(rp, ci, va, kcycle_threshold=theta)
+    Z = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    h.kcycle_batch(dev(R), Z)
+    Zg = Z.cpu().numpy()
+    for c in range(3):
+        z1 = torch.empty(n, dtype=torch.float64, device="cuda")
+        h.kcycle(dev(R[c]), z1)
+        np.testing.assert_array_equal(Zg[c], z1.cpu().numpy())
+        zo = ref.kcycle(R[c])
+        np.testing.assert_allclose(Zg[c], zo, rtol=0, atol=bound * np.abs(zo).max())
+    # and the batch solve reaches the tolerance in every column
+    X = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+    st, infos = h.solve_batch(dev(R), X, tol=1e-9)
+    assert st == amg.AMG_OK
+    for c in range(3):
+        rel = np.linalg.norm(R[c] - oracle.spmv(rp, ci, va, X[c].cpu().numpy())) / np.linalg.norm(R[c])
+        assert rel <= 1e-9
