@@ -61,6 +61,13 @@ def parse():
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "post_smooth_128cubed_traffic.json"))
     ap.add_argument("--traffic-probe", action="store_true",
                     help="launch a 256 MiB copy and the finest post-smoother only (run under rocprofv3 --pmc)")
+    ap.add_argument("--level-profile", action="store_true",
+                    help="set up and solve twice on one hierarchy (run under rocprofv3 --kernel-trace)")
+    ap.add_argument("--level-table", metavar="TRACE_DB",
+                    help="per-level table of the last solve of a --level-profile trace (rocprofv3 database)")
+    ap.add_argument("--level-json", metavar="PATH",
+                    help="with --level-table: also write the top kernel by time and the per-level shares "
+                         "(read back by the benchmark line while the solve sources are unchanged)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="turn two rocprofv3 --pmc databases of --traffic-probe into --traffic-file")
     return ap.parse_args()
@@ -101,6 +108,106 @@ def traffic_probe(args):
     h.solve(t(b), x, tol=args.tol)
     us, alg = h.time_smoother(5)
     print(json.dumps({"probe": "done", "avg_us": us, "alg_bytes": alg}), flush=True)
+
+
+def level_profile(args):
+    """One setup, a first solve (lane autotuning, graph capture) and a second solve on
+    the same hierarchy: the kernel trace's last solve is what --level-table reads."""
+    import torch
+
+    from paper_1302_2547_amd import amg, inputs
+    dev = torch.device("cuda:0")
+    N = args.grid
+    rp, ci, va = inputs.grid_laplacian((N, N, N), jitter=args.jitter, seed=2)
+    b = inputs.rhs(len(rp) - 1, 1)
+    t = lambda a: torch.from_numpy(a).to(dev)
+    h = amg.Hierarchy(t(rp), t(ci), t(va), skip_ratio=args.skip_ratio, kcycle_threshold=args.kcycle_threshold)
+    x = torch.zeros(len(b), dtype=torch.float64, device=dev)
+    h.solve(t(b), x, tol=args.tol)
+    x.zero_()
+    st, info = h.solve(t(b), x, tol=args.tol)
+    torch.cuda.synchronize()
+    print(json.dumps({"levels": [list(h.level_sizes(l)) for l in range(h.num_levels)],
+                      "iterations": info.iterations, "solve_ms": info.solve_ms}), flush=True)
+    h.close()
+
+
+LEVEL_KINDS = (("k_fcg_", "outer iteration"), ("k_residual", "outer iteration"), ("k_gather ", "outer iteration"),
+               ("k_scatter", "outer iteration"), ("copyBuffer", "outer iteration"), ("fillBuffer", "outer iteration"))
+
+
+def level_table(args):
+    """Per-level cost of the K-cycle from a kernel trace: the dispatches of the last
+    solve (from its first gather of b to the end), grouped by kernel and grid size.
+    The K-cycle visits level l 2^l times per application, so a group launched 2^l
+    times per outer iteration belongs to level l (the products with A on a coarse
+    level l, two per visit of level l-1, also come 2^l times); a partial-sum
+    reduction belongs to the launch before it."""
+    import math
+    import sqlite3
+    con = sqlite3.connect(args.level_table)
+    rows = list(con.execute("select name, grid_x, start, end from kernels order by start"))
+    gathers = [i for i, r in enumerate(rows) if "::k_gather(" in r[0]]
+    rows = rows[gathers[-2]:]  # the last solve gathers b and x first
+    iters = sum(1 for r in rows if "k_fcg_update" in r[0])
+    groups, prev = {}, None
+    for name, gx, t0, t1 in rows:
+        short = name.replace("void ", "").replace("amg::(anonymous namespace)::", "").split("(")[0]
+        key = prev + " +reduce" if "k_reduce_partials" in name and prev else f"{short} [grid {gx}]"
+        if "k_reduce_partials" not in name:
+            prev = key
+        g = groups.setdefault(key, [0, 0.0])
+        g[0] += 1
+        g[1] += (t1 - t0) / 1e3
+    solve_us = sum(g[1] for g in groups.values())
+    # the level of a group is read from the launches per iteration of its family and
+    # grid together: the two inner steps of a visit use two variants of one kernel
+    # (restriction with the inner residual formed on the fly, products with two or
+    # three inner products), each launched half as often
+    def family(key):
+        base = key.split(" +reduce")[0]
+        name, grid = base.split(" [")
+        return name.split("<")[0].replace("_rt", ""), grid
+    fam_calls = {}
+    for key, (calls, us) in groups.items():
+        if " +reduce" not in key:
+            fam_calls[family(key)] = fam_calls.get(family(key), 0) + calls
+    table = []
+    for key, (calls, us) in groups.items():
+        per_k = fam_calls.get(family(key), calls) / iters
+        outer = any(tag in key for tag, _ in LEVEL_KINDS)
+        lev = None if outer else (round(math.log2(per_k)) if per_k >= 1 and 2 ** round(math.log2(per_k)) == per_k
+                                  else None)
+        table.append((key, calls, calls / iters, us / calls, us / iters, lev))
+    by_level = {}
+    for key, calls, per_k, us_call, us_iter, lev in table:
+        b = by_level.setdefault(lev, [0.0, 0.0])
+        b[0] += per_k
+        b[1] += us_iter
+    print(f"iterations {iters}, kernel time of the solve {solve_us / 1e3:.2f} ms "
+          f"({solve_us / iters:.0f} us per iteration)\n")
+    print("| level | visits per iteration | launches per iteration | kernel us per iteration | us per visit | share |")
+    print("|---:|---:|---:|---:|---:|---:|")
+    for lev in sorted(by_level, key=lambda v: (v is None, v if v is not None else 0)):
+        launches, us = by_level[lev]
+        name = "outer / other" if lev is None else str(lev)
+        visits = "" if lev is None else str(2 ** lev)
+        per_visit = "" if lev is None else f"{us / 2 ** lev:.1f}"
+        print(f"| {name} | {visits} | {launches:.0f} | {us:.0f} | {per_visit} | {us / (solve_us / iters):.1%} |")
+    if args.level_json:
+        top = max(table, key=lambda r: r[4])
+        with open(args.level_json, "w") as f:
+            json.dump({"source": source_digest(), "grid": args.grid, "iterations": iters,
+                       "kernel_us_per_iteration": round(solve_us / iters, 1),
+                       "top_kernel": {"name": top[0], "level": top[5], "share": round(top[4] / (solve_us / iters), 4),
+                                      "us_per_launch": round(top[3], 2), "launches_per_iteration": top[2]},
+                       "levels": {("outer" if k is None else str(k)): round(v[1] / (solve_us / iters), 4)
+                                  for k, v in by_level.items()}},
+                      f, indent=1)
+    print("\n| kernel [grid] | level | launches per iteration | us per launch | us per iteration |")
+    print("|---|---:|---:|---:|---:|")
+    for key, calls, per_k, us_call, us_iter, lev in sorted(table, key=lambda r: -r[4]):
+        print(f"| `{key}` | {'' if lev is None else lev} | {per_k:g} | {us_call:.2f} | {us_iter:.1f} |")
 
 
 def traffic_from(args):
@@ -224,6 +331,10 @@ def main():
         return traffic_probe(args)
     if args.traffic_from:
         return traffic_from(args)
+    if args.level_profile:
+        return level_profile(args)
+    if args.level_table:
+        return level_table(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -381,6 +492,14 @@ def main():
         "timed_region_s": round(total_s, 3),
         "roofline": roofline, "cpu_baseline": cpu,
     }
+    level_file = os.path.join(ROOT, "profiles", "ua_amg_128cubed_levels.json")
+    if os.path.exists(level_file) and args.workload == "grid" and K == 1 and args.precision == "fp64":
+        with open(level_file) as f:
+            lv = json.load(f)
+        if lv.get("source") == source_digest() and lv.get("grid") == N and not args.skip_ratio and \
+                not args.kcycle_threshold:
+            out["top_kernel"] = dict(lv["top_kernel"], source="profiles/ua_amg_128cubed_levels.md (rocprofv3 "
+                                                                   "kernel trace of the same sources)")
     floor_ms = solve_floor_bytes(sizes) * statistics.median(iters) / (HBM_PEAK_GBS * 1e9) * 1e3
     out["solve_floor"] = {"ms": round(floor_ms, 3), "frac": round(floor_ms / statistics.median(solves), 4),
                           "model": "algorithmic bytes of every sweep of every K-cycle visit and of the outer "
