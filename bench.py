@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--kcycle-threshold", type=float, default=0.0,
                     help="K-cycle threshold theta (Sec. 4.3): the second inner step is skipped where the inner "
                          "residual fell below theta times the coarse residual (0: always two steps)")
+    ap.add_argument("--post-fused", type=int, default=-1, choices=[-1, 0, 1],
+                    help="post-smoothing of sliced levels: -1 timed (default), 0 two launches, 1 one sweep")
     ap.add_argument("--skip-ratio", type=float, default=0.0,
                     help="level skipping (Sec. 3.3): aggregate twice where a level coarsens by less than this "
                          "ratio (0: never, the plain method)")
@@ -357,7 +359,8 @@ def main():
     n, nnz = len(rp) - 1, len(ci)
     prec = amg.AMG_PREC_FP32_INNER if args.precision == "fp32_inner" else amg.AMG_PREC_FP64
     smo = dict(smoother=amg.AMG_SMOOTHER_JACOBI if args.smoother == "jacobi" else amg.AMG_SMOOTHER_L1,
-               jacobi_weight=args.jacobi_weight, skip_ratio=args.skip_ratio, kcycle_threshold=args.kcycle_threshold)
+               jacobi_weight=args.jacobi_weight, skip_ratio=args.skip_ratio, kcycle_threshold=args.kcycle_threshold,
+               post_fused=args.post_fused)
     b = inputs.rhs(n, 1)
     gen_s = time.perf_counter() - t0
     d_rp, d_ci, d_va = (torch.from_numpy(a).to(dev) for a in (rp, ci, va))

@@ -90,6 +90,10 @@ typedef struct {
     double skip_ratio;          /* level skipping (Sec. 3.3): a level whose aggregation      */
                                 /* coarsens by less than this ratio is aggregated twice and */
                                 /* the intermediate level dropped; 0 = never (default)      */
+    int32_t post_fused;         /* post-smoothing of a level with a sliced copy: 0 = two    */
+                                /* launches (the iterate stored), 1 = one sweep forming the */
+                                /* iterate per entry, -1 = timed at the first solve with    */
+                                /* autotune (default; two launches without).  Same result.  */
 } amg_options;
 
 typedef struct {

@@ -41,7 +41,8 @@ class amg_options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("max_coarsest", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p),
                 ("max_rhs", ctypes.c_int32), ("smoother", ctypes.c_int32), ("jacobi_weight", ctypes.c_double),
-                ("autotune", ctypes.c_int32), ("kcycle_threshold", ctypes.c_double), ("skip_ratio", ctypes.c_double)]
+                ("autotune", ctypes.c_int32), ("kcycle_threshold", ctypes.c_double), ("skip_ratio", ctypes.c_double),
+                ("post_fused", ctypes.c_int32)]
 
 
 class amg_solve_info(ctypes.Structure):

@@ -74,6 +74,7 @@ struct Sell {
     int n = 0, nslices = 0, tpb = 1;
     const int *ptr = nullptr;
     const int *ci = nullptr;
+    bool fused = false;  // post-smoothing in one sweep (see k_sell_post_fused)
 };
 constexpr double kSellMaxPadding = 1.25;  // padded / actual entries beyond which a level keeps CSR only
 constexpr int kSellMaxWidth = 64;         // widest slice accepted (entries per row)

@@ -985,7 +985,7 @@ void amg_hierarchy::build_sell()
         int *sci = pool.alloc<int>((size_t)slots);
         F.sell_va = pool.alloc<double>((size_t)slots);
         launch_sell_fill(F.n, ns, F.rp, F.ci, F.va, dptr, sci, F.sell_va, stream);
-        F.sell = Sell{F.n, ns, 1, dptr, sci};
+        F.sell = Sell{F.n, ns, 1, dptr, sci, opt.post_fused == 1};
         F.sell_slots = (size_t)slots;
         AMG_TRACE_MSG("level %d: sliced copy, %lld slots for %d entries (widest %d)", l, (long long)slots, F.nnz, wmax);
     }
@@ -1261,11 +1261,26 @@ void amg_hierarchy::autotune_level(int l, int ncol)
         Sell &S = F.sell;
         const DotBuf scratch = l == 0 ? d_zq : F.d_c1;
         const double max_candidate = 8.0;  // pick() skips g > 2 * 8 + 2
+        const bool fused = S.fused;
+        S.fused = false;
         S.tpb = pick(2, max_candidate, 2 * S.tpb, [&](int g) {
             S.tpb = g / 2;
             launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rv, F.agg_pos, F.cagg, 0, CK.c1, nullptr, nullptr,
                                   KDots{}, out, rv, scratch, flag, F.G, stream, ainv, C.n, ncol, F.xs, &S, FK.sva);
         }) / 2;
+        S.fused = fused;
+        if (opt.post_fused < 0) {
+            // then one sweep (candidate 4) against two launches (2), as the K-cycle runs
+            // the step: both coarse directions (the coefficients are read from a reduced
+            // dot site whose values do not matter here)
+            const DotRef any{scratch.final_out, 1};
+            const KDots kd{any, any, any, any, any};
+            S.fused = pick(3, 1.0, 2, [&](int g) {
+                S.fused = g == 4;
+                launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rv, F.agg_pos, F.cagg, 2, nullptr, CK.c1, CK.c2, kd,
+                                      out, rv, scratch, flag, F.G, stream, ainv, C.n, ncol, F.xs, &S, FK.sva);
+            }) == 4;
+        }
     } else {
         // post-smoother with a directly given correction (no inner products read or written)
         F.G = pick(0, (double)F.nnz / F.n, F.G, [&](int g) {
@@ -1276,8 +1291,8 @@ void amg_hierarchy::autotune_level(int l, int ncol)
             launch_restrict<T>(F.S, F.n, F.sci, FK.wv, rv, CK.rc, g, stream, nullptr, DotBuf{}, ncol);
         });
     }
-    AMG_TRACE_MSG("autotune level %d (%d right-hand sides): G=%d Gs=%d tiles per block=%d", l, ncol, F.G, F.Gs,
-                  F.sell.tpb);
+    AMG_TRACE_MSG("autotune level %d (%d right-hand sides): G=%d Gs=%d tiles per block=%d post-smoothing in %s", l,
+                  ncol, F.G, F.Gs, F.sell.tpb, F.sell.fused ? "one sweep" : "two launches");
 }
 
 void amg_hierarchy::autotune(int ncol)
@@ -1485,6 +1500,7 @@ void amg_default_options(amg_options *opt)
     opt->autotune = 1;
     opt->kcycle_threshold = 0.0;
     opt->skip_ratio = 0.0;
+    opt->post_fused = -1;
 }
 
 amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy **out)
@@ -1501,7 +1517,7 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy 
         !(opt.stall_ratio <= 1.0) || opt.max_aggregate < 0 || opt.max_aggregate == 1 || opt.max_iters < 0 ||
         opt.max_coarsest < 1 || opt.max_rhs < 1 || opt.max_rhs > 1024 || !(opt.jacobi_weight > 0.0) ||
         !std::isfinite(opt.jacobi_weight) || !(opt.kcycle_threshold >= 0.0) || !std::isfinite(opt.kcycle_threshold) ||
-        !(opt.skip_ratio >= 0.0) || !std::isfinite(opt.skip_ratio))
+        !(opt.skip_ratio >= 0.0) || !std::isfinite(opt.skip_ratio) || opt.post_fused < -1 || opt.post_fused > 1)
         return AMG_ERR_INVALID_ARGUMENT;
     if (opt.smoother != AMG_SMOOTHER_L1 && opt.smoother != AMG_SMOOTHER_JACOBI) return AMG_ERR_UNSUPPORTED;
     if (opt.kcycle_inner != 1 && opt.kcycle_inner != 2) return AMG_ERR_UNSUPPORTED;

@@ -735,8 +735,10 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
     auto corr = [&](int J) -> double {
         if (MODE == 0) return (double)edirect[J];
         if (MODE == 3) return e_sh[J];
-        if (MODE == 1 || !two) return a1 * (double)c1[J];
-        return a1 * (double)c1[J] + a2 * (double)c2[J];
+        if (MODE == 1) return a1 * (double)c1[J];
+        // both loads issue unconditionally; a skipped second step's c2 is not used
+        const double v1 = (double)c1[J], v2 = (double)c2[J];
+        return two ? a1 * v1 + a2 * v2 : a1 * v1;
     };
     struct Pre {
         double mr, rr, wd;
@@ -824,8 +826,10 @@ __global__ void __launch_bounds__(kBlock) k_smooth_start(int n, const T *__restr
         double e;
         if (MODE == 0) e = (double)edirect[J];
         else if (MODE == 1) e = c.a1 * (double)c1[J];
-        else if (!c.two) e = c.a1 * (double)c1[J];
-        else e = c.a1 * (double)c1[J] + c.a2 * (double)c2[J];
+        else {
+            const double v1 = (double)c1[J], v2 = (double)c2[J];
+            e = c.two ? c.a1 * v1 + c.a2 * v2 : c.a1 * v1;
+        }
         x[i] = (double)minv[i] * (double)r[i] + e;
     }
 }
@@ -936,6 +940,57 @@ __global__ void __launch_bounds__(kBlock) k_sell_smooth_finish(int n, int tpb, c
         const double mr = (double)minv[i], rr = (double)r[i], xr = x[i];
         const double wd = DOT ? (double)wdot[i] : 0.0;
         const double o = xr + mr * (rr - sell_row(sc, sv, beg, w, t, [&](int j) { return x[j]; }));
+        xout[i] = (T)o;
+        if (DOT) d[0] += o * wd;
+    });
+    if (DOT) store_partials<1>(d, part);
+}
+
+// Prolongation + post-smoothing of a sliced level in one sweep: every row forms
+// its iterate x_i = M^-1 r_i + (P e)_i, and every entry the iterate of its column
+// the same way, so x never goes to memory (three gathers per entry -- minv, r and
+// the aggregate position -- and the coarse values, instead of one gather of the
+// stored iterate and its write and read-back).  The products and their order are
+// those of k_smooth_start + k_sell_smooth_finish, so the result is the same.
+template <class T, int MODE, bool DOT>
+__global__ void __launch_bounds__(kBlock) k_sell_post_fused(int n, int tpb, const int *__restrict__ sptr,
+                                                            const int *__restrict__ sc, const T *__restrict__ sv,
+                                                            const T *__restrict__ minv, const T *__restrict__ r,
+                                                            const int *__restrict__ agg_pos,
+                                                            const T *__restrict__ edirect, const T *__restrict__ c1,
+                                                            const T *__restrict__ c2, KDots kd, int nc,
+                                                            T *__restrict__ xout, const T *__restrict__ wdot,
+                                                            double *__restrict__ part, int *__restrict__ flag,
+                                                            const int *__restrict__ gate,
+                                                            const int *__restrict__ second)
+{
+    if (gated_off(gate)) return;
+    r = colv(r, n);
+    xout = colv(xout, n);
+    wdot = colv(wdot, n);
+    edirect = colv(edirect, nc);
+    c1 = colv(c1, nc);
+    c2 = colv(c2, nc);
+    part = colp(part);
+    const KCoef c = kcycle_coefficients<false>(MODE, kd, second);
+    if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
+    auto xval = [&](int j) -> double {  // as k_smooth_start forms x_j
+        const int J = agg_pos[j];
+        double e;
+        if (MODE == 0) e = (double)edirect[J];
+        else if (MODE == 1) e = c.a1 * (double)c1[J];
+        else {
+            const double v1 = (double)c1[J], v2 = (double)c2[J];
+            e = c.two ? c.a1 * v1 + c.a2 * v2 : c.a1 * v1;
+        }
+        return (double)minv[j] * (double)r[j] + e;
+    };
+    double d[1] = {0.0};
+    sell_tiles(n, tpb, sptr, [&](int i, int beg, int w, int t) {
+        const double mr = (double)minv[i], rr = (double)r[i];
+        const double wd = DOT ? (double)wdot[i] : 0.0;
+        const double xi = xval(i);
+        const double o = xi + mr * (rr - sell_row(sc, sv, beg, w, t, xval));
         xout[i] = (T)o;
         if (DOT) d[0] += o * wd;
     });
@@ -1715,6 +1770,23 @@ DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, con
 {
     const bool dot = wdot != nullptr;
     const dim3 grid(rows_grid(R, G, dot ? kMaxDotBlocks : (1 << 20)), ncol);
+    if (sl && sl->fused && !cagg && R.n >= kSmallLevel && mode >= 0 && mode <= 2) {  // one sweep
+        int tpb = 1;
+        const dim3 gs(sell_grid(*sl, dot, &tpb), ncol);
+#define AMG_FUSED(M, D)                                                                                            \
+    k_sell_post_fused<T, M, D><<<gs, kBlock, 0, s>>>(sl->n, tpb, sl->ptr, sl->ci, sva, minv, r, agg_pos, edirect, c1, \
+                                                     c2, kd, nc, xout, wdot, buf.part, flag, gate, second)
+        switch (mode) {
+        case 0: if (dot) { AMG_FUSED(0, true); } else { AMG_FUSED(0, false); } break;
+        case 1: if (dot) { AMG_FUSED(1, true); } else { AMG_FUSED(1, false); } break;
+        default: if (dot) { AMG_FUSED(2, true); } else { AMG_FUSED(2, false); } break;
+        }
+#undef AMG_FUSED
+        AMG_HIP(hipGetLastError());
+        if (!dot) return DotRef{nullptr, 0};
+        reduce_if_large(1, buf.part, (int)gs.x, buf.final_out, s, ncol, 1, gate);
+        return finished(buf.part, (int)gs.x, buf.final_out, 0, 1);
+    }
     if (xtmp && !cagg && R.n >= kSmallLevel && mode >= 0 && mode <= 2) {  // two launches, see k_smooth_start
         const dim3 g1(grid_for(R.n, 1 << 16), ncol);
 #define AMG_START(M) \

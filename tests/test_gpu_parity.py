@@ -671,3 +671,32 @@ def test_kcycle_threshold_batch_columns_decide_alone(amg, precision):
     for c in range(3):
         rel = np.linalg.norm(R[c] - oracle.spmv(rp, ci, va, X[c].cpu().numpy())) / np.linalg.norm(R[c])
         assert rel <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_inner"])
+def test_one_sweep_post_smoothing_equals_two_launches(amg, precision):
+    """On levels with a sliced copy the post-smoothing step runs either as two
+    launches (the iterate stored, then the sweep) or as one sweep that forms every
+    column's iterate per entry (post_fused); the autotuner picks the faster.  Both
+    give the same bits: a K-cycle, a threshold K-cycle and whole solves."""
+    rp, ci, va = SLICED["grid3d_47x53x41_jitter"]()
+    n = len(rp) - 1
+    prec = amg.AMG_PREC_FP64 if precision == "fp64" else amg.AMG_PREC_FP32_INNER
+    r, b = dev(inputs.rhs(n, 31)), dev(inputs.rhs(n, 32))
+    out = {}
+    for form in (0, 1, -1):
+        for theta in (0.0, 0.4):
+            h = amg.Hierarchy(dev(rp), dev(ci), dev(va), precision=prec, post_fused=form, kcycle_threshold=theta)
+            assert h.level_slots(0) > 0
+            z = torch.empty(n, dtype=torch.float64, device="cuda")
+            h.kcycle(r, z)
+            x = torch.zeros(n, dtype=torch.float64, device="cuda")
+            st, info = h.solve(b, x, tol=1e-9)
+            assert st == amg.AMG_OK
+            out[form, theta] = (z.cpu().numpy(), x.cpu().numpy(), info.iterations)
+            h.close()
+    for theta in (0.0, 0.4):
+        for form in (1, -1):
+            np.testing.assert_array_equal(out[form, theta][0], out[0, theta][0])
+            np.testing.assert_array_equal(out[form, theta][1], out[0, theta][1])
+            assert out[form, theta][2] == out[0, theta][2]
