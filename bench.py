@@ -55,6 +55,8 @@ def parse():
                          "residual fell below theta times the coarse residual (0: always two steps)")
     ap.add_argument("--post-fused", type=int, default=-1, choices=[-1, 0, 1],
                     help="post-smoothing of sliced levels: -1 timed (default), 0 two launches, 1 one sweep")
+    ap.add_argument("--batch-cols", type=int, default=0, choices=[0, 1, 2, 4, 8],
+                    help="batched sweeps of large CSR levels: columns per block (0: timed, 1: one column per block)")
     ap.add_argument("--skip-ratio", type=float, default=0.0,
                     help="level skipping (Sec. 3.3): aggregate twice where a level coarsens by less than this "
                          "ratio (0: never, the plain method)")
@@ -360,7 +362,7 @@ def main():
     prec = amg.AMG_PREC_FP32_INNER if args.precision == "fp32_inner" else amg.AMG_PREC_FP64
     smo = dict(smoother=amg.AMG_SMOOTHER_JACOBI if args.smoother == "jacobi" else amg.AMG_SMOOTHER_L1,
                jacobi_weight=args.jacobi_weight, skip_ratio=args.skip_ratio, kcycle_threshold=args.kcycle_threshold,
-               post_fused=args.post_fused)
+               post_fused=args.post_fused, batch_cols=args.batch_cols)
     b = inputs.rhs(n, 1)
     gen_s = time.perf_counter() - t0
     d_rp, d_ci, d_va = (torch.from_numpy(a).to(dev) for a in (rp, ci, va))

@@ -94,6 +94,11 @@ typedef struct {
                                 /* launches (the iterate stored), 1 = one sweep forming the */
                                 /* iterate per entry, -1 = timed at the first solve with    */
                                 /* autotune (default; two launches without).  Same result.  */
+    int32_t batch_cols;         /* batched solves on levels >= 100k rows kept in CSR: the    */
+                                /* right-hand sides one block serves, each entry loaded     */
+                                /* once for all of them (CSR SpMM): 1, 2, 4 or 8; 0 = timed */
+                                /* at the first batched solve with autotune, else 4 (def.). */
+                                /* Same result for every choice.                            */
 } amg_options;
 
 typedef struct {

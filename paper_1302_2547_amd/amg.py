@@ -42,7 +42,7 @@ class amg_options(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p),
                 ("max_rhs", ctypes.c_int32), ("smoother", ctypes.c_int32), ("jacobi_weight", ctypes.c_double),
                 ("autotune", ctypes.c_int32), ("kcycle_threshold", ctypes.c_double), ("skip_ratio", ctypes.c_double),
-                ("post_fused", ctypes.c_int32)]
+                ("post_fused", ctypes.c_int32), ("batch_cols", ctypes.c_int32)]
 
 
 class amg_solve_info(ctypes.Structure):

@@ -58,7 +58,12 @@ struct Rows {
     const int *long_first;
     double *chunk_sum;
     unsigned *arrive;
+    // right-hand sides served by one block in batched sweeps of levels of at least
+    // kSmallLevel rows (1: one column per block; 2, 4, 8: each entry loaded once for
+    // that many columns)
+    int cb;
 };
+constexpr int kMaxColumnsPerBlock = 8;
 
 // Sliced ELLPACK copy of a level's matrix, for the sweeps of levels of at least
 // kSmallLevel rows whose row lengths vary little (a 3D stencil: 4..7 entries).

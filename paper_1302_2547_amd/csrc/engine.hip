@@ -808,6 +808,7 @@ void amg_hierarchy::finalize_layout()
         F.G = lanes_for((double)F.nnz / F.n, F.n);
         const bool natural = l == 0 && L >= 1;  // see below
         F.A = make_rows(F.n, natural ? F.rp_nat : F.rp, F.G, tmp, scan_tmp);
+        F.A.cb = opt.batch_cols > 0 ? opt.batch_cols : 4;
         AMG_TRACE_MSG("layout level %d: G=%d hub rows=%d chunks=%d", l, F.G, F.A.nlong, F.A.nchunks);
         if (l < L) {
             const int nc = lev[l + 1].n;
@@ -815,6 +816,7 @@ void amg_hierarchy::finalize_layout()
             launch_gather_int(nc + 1, F.rp, F.seg_ptr, F.srp, stream);
             F.Gs = lanes_for((double)F.nnz / nc, nc);
             F.S = make_rows(nc, F.srp, F.Gs, tmp, scan_tmp);
+            F.S.cb = F.A.cb;
             AMG_TRACE_MSG("layout level %d: super-rows Gs=%d hub rows=%d chunks=%d", l, F.Gs, F.S.nlong, F.S.nchunks);
             F.wv = pool.alloc<double>(F.nnz);
             launch_restriction_weights(F.n, F.rp, F.ci, F.va, F.minv, F.wv, stream);
@@ -1290,9 +1292,22 @@ void amg_hierarchy::autotune_level(int l, int ncol)
         F.Gs = pick(1, (double)F.nnz / C.n, F.Gs, [&](int g) {
             launch_restrict<T>(F.S, F.n, F.sci, FK.wv, rv, CK.rc, g, stream, nullptr, DotBuf{}, ncol);
         });
+        if (ncol > 1 && opt.batch_cols == 0) {
+            // columns per block of the batched sweeps (candidates g = 2..16 give g / 2 =
+            // 1..8): the post-smoother and the restriction, each reading the matrix once
+            // per group of columns
+            const int cb = pick(4, 8.0, 2 * F.A.cb, [&](int g) {
+                F.A.cb = F.S.cb = g / 2;
+                launch_post_smooth<T>(F.A, F.ci, FK.va, FK.minv, rv, F.agg_pos, F.cagg, 0, CK.c1, nullptr, nullptr,
+                                      KDots{}, out, nullptr, DotBuf{}, flag, F.G, stream, ainv, C.n, ncol, F.xs);
+                launch_restrict<T>(F.S, F.n, F.sci, FK.wv, rv, CK.rc, F.Gs, stream, nullptr, DotBuf{}, ncol);
+            }) / 2;
+            F.A.cb = F.S.cb = cb;
+        }
     }
-    AMG_TRACE_MSG("autotune level %d (%d right-hand sides): G=%d Gs=%d tiles per block=%d post-smoothing in %s", l,
-                  ncol, F.G, F.Gs, F.sell.tpb, F.sell.fused ? "one sweep" : "two launches");
+    AMG_TRACE_MSG("autotune level %d (%d right-hand sides): G=%d Gs=%d tiles per block=%d post-smoothing in %s, "
+                  "%d columns per block", l, ncol, F.G, F.Gs, F.sell.tpb, F.sell.fused ? "one sweep" : "two launches",
+                  F.A.cb);
 }
 
 void amg_hierarchy::autotune(int ncol)
@@ -1501,6 +1516,7 @@ void amg_default_options(amg_options *opt)
     opt->kcycle_threshold = 0.0;
     opt->skip_ratio = 0.0;
     opt->post_fused = -1;
+    opt->batch_cols = 0;
 }
 
 amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy **out)
@@ -1517,7 +1533,9 @@ amg_status amg_setup(const amg_csr *A, const amg_options *opt_in, amg_hierarchy 
         !(opt.stall_ratio <= 1.0) || opt.max_aggregate < 0 || opt.max_aggregate == 1 || opt.max_iters < 0 ||
         opt.max_coarsest < 1 || opt.max_rhs < 1 || opt.max_rhs > 1024 || !(opt.jacobi_weight > 0.0) ||
         !std::isfinite(opt.jacobi_weight) || !(opt.kcycle_threshold >= 0.0) || !std::isfinite(opt.kcycle_threshold) ||
-        !(opt.skip_ratio >= 0.0) || !std::isfinite(opt.skip_ratio) || opt.post_fused < -1 || opt.post_fused > 1)
+        !(opt.skip_ratio >= 0.0) || !std::isfinite(opt.skip_ratio) || opt.post_fused < -1 || opt.post_fused > 1 ||
+        !(opt.batch_cols == 0 || opt.batch_cols == 1 || opt.batch_cols == 2 || opt.batch_cols == 4 ||
+          opt.batch_cols == 8))
         return AMG_ERR_INVALID_ARGUMENT;
     if (opt.smoother != AMG_SMOOTHER_L1 && opt.smoother != AMG_SMOOTHER_JACOBI) return AMG_ERR_UNSUPPORTED;
     if (opt.kcycle_inner != 1 && opt.kcycle_inner != 2) return AMG_ERR_UNSUPPORTED;

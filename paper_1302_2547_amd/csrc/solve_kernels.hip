@@ -233,7 +233,7 @@ __device__ inline int xcd_block(int b, int nb)
 // wavefront loads them together) and finishes the row.  done(row, sum, k) runs
 // in one thread.
 template <class Done>
-__device__ inline void finish_chunk(const Rows &R, int c, const Chunk &ch, double s, Done done)
+__device__ inline void finish_chunk(const Rows &R, int c, const Chunk &ch, double s, Done done, int col = -1)
 {
     if (threadIdx.x >= kWave) return;
     const int lane = threadIdx.x;
@@ -247,9 +247,10 @@ __device__ inline void finish_chunk(const Rows &R, int c, const Chunk &ch, doubl
     // write-back: the store's completion is awaited (vector memory counter) before
     // the count is raised, and the last arrival reads the sums only after its
     // count returned.  Nothing else is read afterwards, so no acquire either.
-    // every right-hand side of a batched launch (blockIdx.y) has its own sums and counters
-    double *chunk_sum = R.chunk_sum + (size_t)blockIdx.y * R.nchunks;
-    unsigned *arrive = R.arrive + (size_t)blockIdx.y * R.nlong;
+    // every right-hand side of a batched launch (blockIdx.y, or col) has its own sums and counters
+    if (col < 0) col = blockIdx.y;
+    double *chunk_sum = R.chunk_sum + (size_t)col * R.nchunks;
+    unsigned *arrive = R.arrive + (size_t)col * R.nlong;
     unsigned prev = 0;
     if (lane == 0) {
         __hip_atomic_store(&chunk_sum[c], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -867,6 +868,191 @@ __global__ void __launch_bounds__(kBlock) k_smooth_finish(Rows R, const int *__r
             }
         });
     if (DOT) store_partials<1>(dsum, part);
+}
+
+
+// ------------------------------------------------------------------ batched sweeps (SpMM)
+// On large levels a batch of right-hand sides is served CB columns per block
+// (blockIdx.y = column group): each entry's column index and value are loaded once
+// and applied to every column of the group, so the matrix is read ceil(ncol / CB)
+// times instead of ncol times (column-major vectors, leading dimension = the level's
+// size).  Rows, lanes (G per row, lane-strided entries, group_sum) and blocks are
+// those of the one-column kernels, so every column's sums and partials are formed in
+// the same order and the results are the same bits.  Columns past ncol in the last
+// group repeat the first column of the group and are discarded.
+template <int CB>
+__device__ inline int mm_columns(int ncol, int *c0)
+{
+    *c0 = blockIdx.y * CB;
+    const int left = ncol - *c0;
+    return left < CB ? left : CB;
+}
+
+// The row loop of visit_rows (large levels) for CB columns: acc(p, s) adds entry
+// p's contribution to the CB sums s; fin(row, s, k) finishes the row for every
+// column (k: hub row index, -1 for an ordinary row), called by one lane.
+template <int G, int CB, class Acc, class Fin>
+__device__ inline void visit_rows_mm(const Rows &R, Acc acc, Fin fin)
+{
+    const int nlb = R.nchunks < kLongBlocks ? R.nchunks : kLongBlocks;
+    if ((int)blockIdx.x < nlb) {
+        for (int c = blockIdx.x; c < R.nchunks; c += nlb) {
+            const Chunk ch = R.chunks[c];
+            double s[CB] = {};
+            for (int p = ch.beg + (int)threadIdx.x; p < ch.end; p += kBlock) acc(p, s);
+            block_sums<CB>(s);
+            fin(c, ch, s);
+        }
+        return;
+    }
+    const int sub = threadIdx.x % G;
+    const int nrb = gridDim.x - nlb;
+    const int ngroups = nrb * (kBlock / G);
+    const int rb = xcd_block(blockIdx.x - nlb, nrb);
+    for (int row = (rb * kBlock + threadIdx.x) / G; row < R.n; row += ngroups) {
+        const int b = R.ptr[row], e = R.ptr[row + 1];
+        if (e - b > R.lim) continue;  // hub row: served by the chunk blocks
+        double s[CB] = {};
+        for (int p = b + sub; p < e; p += G) acc(p, s);
+#pragma unroll
+        for (int k = 0; k < CB; k++) s[k] = group_sum<G>(s[k]);
+        if (sub == 0) fin(row, Chunk{-1, 0, 0, -1}, s);
+    }
+}
+
+// k_spmv_dots for CB columns: y = A x and the partials of (x, A x), (x, w1), (x, w2)
+template <class T, int G, int ND, int CB>
+__global__ void __launch_bounds__(kBlock) k_spmm_dots(Rows R, const int *__restrict__ ci,
+                                                      const T *__restrict__ va, const T *__restrict__ x,
+                                                      T *__restrict__ y, const T *__restrict__ w1,
+                                                      const T *__restrict__ w2, double *__restrict__ part, int ncol)
+{
+    int c0;
+    const int nc = mm_columns<CB>(ncol, &c0);
+    const size_t n = (size_t)R.n;
+    const int nb = gridDim.x;
+    auto col = [&](int k) { return (size_t)(c0 + (k < nc ? k : 0)); };
+    double d[CB][ND] = {};
+    auto row_done = [&](int row, int k, double s, int hub) {
+        const size_t o = col(k) * n + row;
+        if (y) y[o] = (T)s;
+        const double xr = (double)x[o];
+        double t[ND];
+        t[0] = xr * s;
+        if (ND > 1) t[1 % ND] = xr * (double)w1[o];
+        if (ND > 2) t[2 % ND] = xr * (double)w2[o];
+        if (hub < 0) {
+#pragma unroll
+            for (int j = 0; j < ND; j++) d[k][j] += t[j];
+        } else {
+            double *pc = part + col(k) * kDotCol;
+#pragma unroll
+            for (int j = 0; j < ND; j++) pc[j * kPartStride + nb + hub] = t[j];
+        }
+    };
+    visit_rows_mm<G, CB>(
+        R,
+        [&](int p, double (&s)[CB]) {
+            const int j = ci[p];
+            const double a = (double)va[p];
+#pragma unroll
+            for (int k = 0; k < CB; k++) s[k] += a * (double)x[col(k) * n + j];
+        },
+        [&](int row, const Chunk &ch, double (&s)[CB]) {
+            if (ch.k < 0) {
+#pragma unroll
+                for (int k = 0; k < CB; k++)
+                    if (k < nc) row_done(row, k, s[k], -1);
+                return;
+            }
+#pragma unroll
+            for (int k = 0; k < CB; k++)
+                if (k < nc) finish_chunk(R, row, ch, s[k], [&](int r, double t, int hub) { row_done(r, k, t, hub); },
+                                         c0 + k);
+        });
+#pragma unroll
+    for (int k = 0; k < CB; k++)
+        if (k < nc) store_partials<ND>(d[k], part + col(k) * kDotCol);
+}
+
+// k_restrict (large levels) for CB columns: rc = W r over the super-rows
+template <class T, int G, int CB>
+__global__ void __launch_bounds__(kBlock) k_restrict_mm(Rows S, int nf, const int *__restrict__ ci,
+                                                        const T *__restrict__ wv, const T *__restrict__ r,
+                                                        T *__restrict__ rc, int ncol)
+{
+    int c0;
+    const int nc = mm_columns<CB>(ncol, &c0);
+    auto col = [&](int k) { return (size_t)(c0 + (k < nc ? k : 0)); };
+    visit_rows_mm<G, CB>(
+        S,
+        [&](int p, double (&s)[CB]) {
+            const int j = ci[p];
+            const double w = (double)wv[p];
+#pragma unroll
+            for (int k = 0; k < CB; k++) s[k] += w * (double)r[col(k) * nf + j];
+        },
+        [&](int Q, const Chunk &ch, double (&s)[CB]) {
+#pragma unroll
+            for (int k = 0; k < CB; k++) {
+                if (k >= nc) continue;
+                if (ch.k < 0) rc[col(k) * S.n + Q] = (T)s[k];
+                else finish_chunk(S, Q, ch, s[k], [&](int q, double t, int) {
+                    rc[col(k) * S.n + q] = (T)t;
+                }, c0 + k);
+            }
+        });
+}
+
+// k_smooth_finish for CB columns: out = x + M^-1 (r - A x), partials of (out, wdot)
+template <class T, int G, bool DOT, int CB>
+__global__ void __launch_bounds__(kBlock) k_smooth_finish_mm(Rows R, const int *__restrict__ ci,
+                                                             const T *__restrict__ va, const T *__restrict__ minv,
+                                                             const T *__restrict__ r, const double *__restrict__ x,
+                                                             T *__restrict__ xout, const T *__restrict__ wdot,
+                                                             double *__restrict__ part, int ncol)
+{
+    int c0;
+    const int nc = mm_columns<CB>(ncol, &c0);
+    const size_t n = (size_t)R.n;
+    const int nb = gridDim.x;
+    auto col = [&](int k) { return (size_t)(c0 + (k < nc ? k : 0)); };
+    double d[CB][1] = {};
+    auto row_done = [&](int row, int k, double s, int hub) {
+        const size_t o = col(k) * n + row;
+        const double out = x[o] + (double)minv[row] * ((double)r[o] - s);
+        xout[o] = (T)out;
+        if (DOT) {
+            const double t = out * (double)wdot[o];
+            if (hub < 0) d[k][0] += t;
+            else part[col(k) * kDotCol + nb + hub] = t;
+        }
+    };
+    visit_rows_mm<G, CB>(
+        R,
+        [&](int p, double (&s)[CB]) {
+            const int j = ci[p];
+            const double a = (double)va[p];
+#pragma unroll
+            for (int k = 0; k < CB; k++) s[k] += a * x[col(k) * n + j];
+        },
+        [&](int row, const Chunk &ch, double (&s)[CB]) {
+            if (ch.k < 0) {
+#pragma unroll
+                for (int k = 0; k < CB; k++)
+                    if (k < nc) row_done(row, k, s[k], -1);
+                return;
+            }
+#pragma unroll
+            for (int k = 0; k < CB; k++)
+                if (k < nc) finish_chunk(R, row, ch, s[k], [&](int q, double t, int hub) { row_done(q, k, t, hub); },
+                                         c0 + k);
+        });
+    if (DOT) {
+#pragma unroll
+        for (int k = 0; k < CB; k++)
+            if (k < nc) store_partials<1>(d[k], part + col(k) * kDotCol);
+    }
 }
 
 // ------------------------------------------------------------------ sliced ELLPACK sweeps
@@ -1657,12 +1843,32 @@ DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, co
         for (int d = 0; d < nd; d++) out.d[d] = finished(buf.part, count, buf.final_out, d, 1);
         return out;
     }
+    const bool lat = R.n < kSmallLevel;
+    if (ncol > 1 && !lat && !omy && !gate && R.cb > 1) {  // batched: CB columns per block
+        const dim3 gm(rows_grid(R, G, kMaxDotBlocks), (ncol + R.cb - 1) / R.cb);
+#define AMG_SPMM(ND, CB)                                                                                             \
+    AMG_SWITCH_G(G, (k_spmm_dots<T, kG, ND, CB><<<gm, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, buf.part, ncol)))
+#define AMG_SPMM_CB(ND)                    \
+    switch (R.cb) {                        \
+    case 2: AMG_SPMM(ND, 2); break;        \
+    case 4: AMG_SPMM(ND, 4); break;        \
+    default: AMG_SPMM(ND, 8); break;       \
+    }
+        if (nd == 1) { AMG_SPMM_CB(1) } else if (nd == 2) { AMG_SPMM_CB(2) } else { AMG_SPMM_CB(3) }
+#undef AMG_SPMM_CB
+#undef AMG_SPMM
+        AMG_HIP(hipGetLastError());
+        const int count = (int)gm.x + R.nlong;
+        reduce_if_large(nd, buf.part, count, buf.final_out, s, ncol, kConsumerReduceMax, gate);
+        DotSet out{};
+        for (int d = 0; d < nd; d++) out.d[d] = finished(buf.part, count, buf.final_out, d);
+        return out;
+    }
     const dim3 grid(rows_grid(R, G, kMaxDotBlocks), ncol);
     if (omy && nd == 3) throw Error(4, "spmv_dots: at most three products");
 #define AMG_SPMV_DOTS(ND, LAT, OMY)                                                                        \
     AMG_SWITCH_G(G, (k_spmv_dots<T, kG, ND, LAT, OMY><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, omy, \
                                                                                buf.part, gate)))
-    const bool lat = R.n < kSmallLevel;
     if (omy) {
         if (nd == 1) {
             AMG_SPMV_DOTS(1, true, true);
@@ -1721,6 +1927,18 @@ template <class T>
 DotRef launch_restrict(Rows S, int nf, const int *ci, const T *wv, const T *r, T *rc, int G, hipStream_t s,
                        const double *om, DotBuf buf, int ncol, const int *gate)
 {
+    if (ncol > 1 && !om && !gate && S.n >= kSmallLevel && S.cb > 1) {  // batched: CB columns per block
+        const dim3 gm(rows_grid(S, G, 1 << 20), (ncol + S.cb - 1) / S.cb);
+#define AMG_RMM(CB) AMG_SWITCH_G(G, (k_restrict_mm<T, kG, CB><<<gm, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, ncol)))
+        switch (S.cb) {
+        case 2: AMG_RMM(2); break;
+        case 4: AMG_RMM(4); break;
+        default: AMG_RMM(8); break;
+        }
+#undef AMG_RMM
+        AMG_HIP(hipGetLastError());
+        return DotRef{nullptr, 0};
+    }
     const dim3 grid(rows_grid(S, G, om ? kMaxDotBlocks : (1 << 20)), ncol);
     if (om) {
         AMG_SWITCH_G(G, (k_restrict<T, kG, true, true><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part,
@@ -1813,7 +2031,18 @@ DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, con
             reduce_if_large(1, buf.part, (int)gs.x, buf.final_out, s, ncol, 1, gate);
             return finished(buf.part, (int)gs.x, buf.final_out, 0, 1);
         }
-        if (dot) {
+        if (ncol > 1 && !gate && R.cb > 1) {  // batched: CB columns per block
+            const dim3 gm(grid.x, (ncol + R.cb - 1) / R.cb);
+#define AMG_FMM(D, CB)                                                                                              \
+    AMG_SWITCH_G(G, (k_smooth_finish_mm<T, kG, D, CB><<<gm, kBlock, 0, s>>>(R, ci, va, minv, r, xtmp, xout, wdot, \
+                                                                            buf.part, ncol)))
+            switch (R.cb) {
+            case 2: if (dot) { AMG_FMM(true, 2); } else { AMG_FMM(false, 2); } break;
+            case 4: if (dot) { AMG_FMM(true, 4); } else { AMG_FMM(false, 4); } break;
+            default: if (dot) { AMG_FMM(true, 8); } else { AMG_FMM(false, 8); } break;
+            }
+#undef AMG_FMM
+        } else if (dot) {
             AMG_SWITCH_G(G, (k_smooth_finish<T, kG, true><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, xtmp, xout, wdot,
                                                                                 buf.part, gate)));
         } else {

@@ -136,3 +136,40 @@ def test_batch_with_multi_chunk_hub_rows(amg):
             assert rel <= tol and infos[c].iterations <= it_o + 3
         h.close()
         ref.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_spmm_columns_per_block_same_bits(amg, precision):
+    """On levels of at least 100k rows kept in CSR (the random graph's finest levels) a
+    batch is swept CB columns per block, each matrix entry loaded once for all of them
+    (CSR SpMM).  Every choice of CB (1 = one column per block) gives the same bits, for a
+    batched K-cycle and for whole batched solves; 5 columns leave the last group ragged."""
+    rp, ci, va = inputs.rgg_laplacian(150000, seed=13, weight_range=(0.5, 1.5))
+    n, k = len(rp) - 1, 5
+    R = dev(rhs_block(n, k))
+    out = {}
+    # lanes per row from the mean row length (autotune off), so that every run sums in
+    # the same order; then the timed choice (autotune on) against one column per block
+    # with the lanes timed the same way
+    for cb, tune in ((1, 0), (2, 0), (4, 0), (8, 0), (0, 1), (1, 1)):
+        print(f"[batch] spmm columns per block {cb} autotune {tune} precision {precision}", flush=True)
+        h = amg.Hierarchy(dev(rp), dev(ci), dev(va), max_rhs=k, precision=precision, batch_cols=cb, autotune=tune)
+        assert h.level_slots(0) == 0  # CSR, so the batched sweeps are the SpMM kernels
+        Z = torch.empty((k, n), dtype=torch.float64, device="cuda")
+        h.kcycle_batch(R, Z)
+        X = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+        st, infos = h.solve_batch(R, X, tol=1e-8)
+        assert st == amg.AMG_OK
+        out[cb, tune] = (Z.cpu().numpy(), X.cpu().numpy(), [i.iterations for i in infos])
+        h.close()
+    for key, ref in (((2, 0), (1, 0)), ((4, 0), (1, 0)), ((8, 0), (1, 0)), ((0, 1), (1, 1))):
+        np.testing.assert_array_equal(out[key][0], out[ref][0])
+        np.testing.assert_array_equal(out[key][1], out[ref][1])
+        assert out[key][2] == out[ref][2]
+    # and each column of the batched K-cycle equals that column alone
+    h = amg.Hierarchy(dev(rp), dev(ci), dev(va), max_rhs=k, precision=precision, autotune=0)
+    for c in range(k):
+        z = torch.empty(n, dtype=torch.float64, device="cuda")
+        h.kcycle(R[c].contiguous(), z)
+        np.testing.assert_array_equal(out[1, 0][0][c], z.cpu().numpy())
+    h.close()
