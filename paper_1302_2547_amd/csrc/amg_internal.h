@@ -200,9 +200,10 @@ DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, co
                         const Sell *sl = nullptr, const T *sva = nullptr, const int *gate = nullptr);
 // r = b - A x; d[0] = (b, b), d[1] = (r, r)
 DotSet launch_residual(Rows R, const int *ci, const double *va, const double *b, const double *x, double *r, int G,
-                       DotBuf buf, hipStream_t s, int ncol = 1);
+                       DotBuf buf, hipStream_t s, int ncol = 1, const int *gate = nullptr);
 // out[c * out_stride] = value of ref for column c (one block per column)
-void launch_reduce(const DotRef &ref, double *out, hipStream_t s, int ncol = 1, int out_stride = kScalCol);
+void launch_reduce(const DotRef &ref, double *out, hipStream_t s, int ncol = 1, int out_stride = kScalCol,
+                   const int *gate = nullptr);
 // rc = W r over the super-rows S (nf fine rows), W = P^T (I - A M^-1) stored per entry.
 // With om, also the partials of (om, rc) into buf (returned; else a null reference).
 template <class T>
@@ -220,7 +221,7 @@ void launch_sell_restrict(const Sell &S, const T *sva, const T *minv, const T *r
 template <class T>
 DotRef launch_restrict_rt(Rows S, int nf, const int *ci, const T *wv, const T *rcf, const T *v1, KDots kd, T *rt,
                           T *rc, int *flag, int G, hipStream_t s, const double *om = nullptr, DotBuf buf = DotBuf{},
-                          int ncol = 1);
+                          int ncol = 1, const int *gate = nullptr);
 // K-cycle visit of a level whose coarse level is one unknown (restriction by the
 // inner products om_r and, with rt_mode, om_v1; see k_post_direct).
 template <class T>
@@ -270,7 +271,8 @@ void launch_tail_visit(const TailLayout &L, const T *va, const T *minv, const do
                        const int *gate = nullptr, double theta2 = 0.0);
 // rt = rc - (alpha1/rho1) v1
 template <class T>
-void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, hipStream_t s, int ncol = 1);
+void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, hipStream_t s, int ncol = 1,
+                           const int *gate = nullptr);
 // The same under the K-cycle threshold (Sec. 4.3): also the partials of (rc, rc),
 // (rt, rt) and, with om, (om, rt) (returned; else a null reference), then
 // gate_out[c] = 1 when column c's enclosing step runs (gate) and
@@ -316,10 +318,10 @@ DotRef launch_from_inner(int n, const float *z32, const double *rr, double *z, c
 void launch_to_float(int64_t n, const double *src, float *dst, hipStream_t s);
 // alpha = pr/pq; x += alpha p; r -= alpha q; returns (r, r)
 DotRef launch_fcg_update(int n, DotRef pq, DotRef pr, double *x, double *r, const double *p, const double *q,
-                         DotBuf buf, int *flag, hipStream_t s, int ncol = 1);
-// beta = -zq/pq; p = z + beta p
+                         DotBuf buf, int *flag, hipStream_t s, int ncol = 1, const int *gate = nullptr);
+// beta = -zq/pq; p = z + beta p (p = z for a column whose restart flag is set)
 void launch_fcg_direction(int n, DotRef pq, DotRef zq, const double *z, double *p, int *flag, hipStream_t s,
-                          int ncol = 1);
+                          int ncol = 1, const int *gate = nullptr, const int *restart = nullptr);
 DotRef launch_dot(int n, const double *a, const double *b, DotBuf buf, hipStream_t s, int ncol = 1);
 // dst[i] = src[idx[i]] / dst[idx[i]] = src[i]; ld <= 0 means n
 void launch_gather(int n, const double *src, const int *idx, double *dst, hipStream_t s, int ncol = 1,

@@ -329,7 +329,7 @@ struct amg_hierarchy {
     KDots kd0{};             // dots of the finest visit's coarse correction (for timing)
     int *flag = nullptr;     // bit 0: Krylov breakdown
     struct Graphs {
-        hipGraphExec_t k = nullptr, first = nullptr, iter = nullptr;
+        hipGraphExec_t k = nullptr, step = nullptr;
     };
     std::map<int, Graphs> graphs;  // per batch width (an entry without graphs: launch eagerly)
     static constexpr int kMaxGraphDepth = 12;
@@ -348,6 +348,13 @@ struct amg_hierarchy {
     }
     double *host = nullptr;  // pinned: readbacks
     int *host_i = nullptr;
+    // Per right-hand side of the outer iteration (max_rhs ints each, device and a
+    // pinned host copy): active (still iterating), restart (the next direction is
+    // the preconditioned residual itself), claim (the recursive residual says
+    // converged: form the true one).  Every outer kernel and the K-cycle run only for
+    // active columns, so a column's iteration is that of its right-hand side alone.
+    int *mask = nullptr, *host_mask = nullptr;
+    std::vector<int> mask_sent;  // the masks as last copied to the device
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double setup_ms = 0.0;
 
@@ -356,12 +363,13 @@ struct amg_hierarchy {
         AMG_TRACE_MSG("free: start");
         if (stream) (void)hipStreamSynchronize(stream);
         for (auto &kv : graphs)
-            for (hipGraphExec_t g : {kv.second.k, kv.second.first, kv.second.iter})
+            for (hipGraphExec_t g : {kv.second.k, kv.second.step})
                 if (g) (void)hipGraphExecDestroy(g);
         AMG_TRACE_MSG("free: graphs destroyed");
         pool.release_all();
         AMG_TRACE_MSG("free: device memory released");
         if (host) (void)hipHostFree(host);
+        if (host_mask) (void)hipHostFree(host_mask);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -466,8 +474,8 @@ struct amg_hierarchy {
     DotRef kcycle(int k, const T *r, T *x, const T *wdot, const RtSource<T> *rts, int ncol,
                   const int *gate = nullptr);
     void run_kcycle(int ncol);
-    void run_first(int ncol);
-    void run_iter(int ncol);
+    void run_step(int ncol);
+    void upload_masks();
     void capture_graphs(int ncol);
     // lanes per row of the bandwidth-bound levels, by measurement (once per hierarchy)
     bool tuned = false;
@@ -486,6 +494,7 @@ void amg_hierarchy::build(const amg_csr &A)
     const size_t nscal = (size_t)amg::kScalCol * (size_t)opt.max_rhs;  // per-column device scalars
     AMG_HIP(hipHostMalloc((void **)&host, (nscal + 64) * sizeof(double), hipHostMallocDefault));
     host_i = reinterpret_cast<int *>(host + nscal + 32);
+    AMG_HIP(hipHostMalloc((void **)&host_mask, 3 * (size_t)opt.max_rhs * sizeof(int), hipHostMallocDefault));
     AMG_HIP(hipEventRecord(ev0, stream));
 
     const int n0 = A.n, nnz0 = A.nnz;
@@ -946,6 +955,7 @@ void amg_hierarchy::finalize_layout()
     scal = pool.alloc<double>((size_t)amg::kScalCol * nr);
     flag = pool.alloc<int>(1);
     AMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
+    mask = pool.alloc<int>(3 * nr);
     sync();
     pool.release(tmp);
     pool.release(scan_tmp);
@@ -1035,7 +1045,7 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
     const double *om = tail ? nullptr : C.omega;
     if (rts) {  // rr = rt is formed here from the parent's first inner step (never with a threshold)
         C.om_rc = launch_restrict_rt<T>(F.S, F.n, F.sci, FK.wv, rts->rcf, rts->v1, rts->kd, const_cast<T *>(rr),
-                                        CK.rc, flag, F.Gs, stream, om, C.d_om, ncol);
+                                        CK.rc, flag, F.Gs, stream, om, C.d_om, ncol, gate);
     } else if (F.sell.ptr && !om) {  // sliced level: row sweep, then sums per aggregate
         const int *idx = k == 0 && !uperm ? F.perm : nullptr;  // the finest level's rows are in natural order
         launch_sell_restrict<T>(F.sell, FK.sva, FK.minv, rr, F.xs, C.n, F.seg_ptr, idx, CK.rc, stream, ncol, gate);
@@ -1090,13 +1100,13 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
         } else if (opt.kcycle_inner == 2) {
             if (C.n < kSmallLevel || C.omega) {  // fold the inner residual into the next restriction
                 const RtSource<T> src{CK.rc, CK.v1, kd};
-                kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, &src, ncol);
+                kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, &src, ncol, gate);
             } else {
-                launch_inner_residual<T>(C.n, CK.rc, CK.v1, kd, CK.rt, flag, stream, ncol);
-                kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, nullptr, ncol);
+                launch_inner_residual<T>(C.n, CK.rc, CK.v1, kd, CK.rt, flag, stream, ncol, gate);
+                kcycle<T>(k + 1, CK.rt, CK.c2, nullptr, nullptr, ncol, gate);
             }
             const DotSet s2 = launch_spmv_dots<T>(C.A, C.ci, CK.va, CK.c2, nullptr, CK.v1, CK.rt, C.G, C.d_c2,
-                                                  stream, nullptr, ncol, C.sl(), CK.sva);
+                                                  stream, nullptr, ncol, C.sl(), CK.sva, gate);
             kd.beta = s2.d[0];
             kd.gamma = s2.d[1];
             kd.alpha2 = s2.d[2];
@@ -1109,60 +1119,58 @@ DotRef amg_hierarchy::kcycle(int k, const T *rr, T *xx, const T *wdot, const RtS
                                  FK.sva, gate, second);
 }
 
-// One outer iteration is split in three replayable pieces:
-//   K     : z = B r, with (z, A p) for the direction update
-//   first : p = z; q = A p, (p, q), (p, r); x += alpha p, r -= alpha q; (r, r)
-//   iter  : p = z + beta p; then as in first
+// One outer iteration is split in two replayable pieces, both run for the active
+// right-hand sides only (mask[0 .. max_rhs)):
+//   K    : z = B r, with (z, A p) for the direction update
+//   step : p = z (restart) or p = z + beta p; q = A p, (p, q), (p, r);
+//          x += alpha p, r -= alpha q; (r, r)
 void amg_hierarchy::run_kcycle(int ncol)
 {
     using namespace amg;
     const auto g = graphs.find(ncol);
+    // one right-hand side is always active while it iterates: no gate (its load
+    // would open every kernel of the cycle)
+    const int *active = ncol > 1 ? mask : nullptr;
     if (g != graphs.end() && g->second.k) {
         AMG_HIP(hipGraphLaunch(g->second.k, stream));
     } else if (mixed) {  // scal[c * kScalCol] holds (r, r) of column c
         const int n = lev[0].n;
         launch_to_inner(n, r, scal, r32, stream, ncol);
-        kcycle<float>(0, r32, z32, nullptr, nullptr, ncol);
+        kcycle<float>(0, r32, z32, nullptr, nullptr, ncol, active);
         dr_zq = launch_from_inner(n, z32, scal, z, q, d_zq, stream, ncol);
     } else {
-        dr_zq = kcycle<double>(0, r, z, q, nullptr, ncol);
+        dr_zq = kcycle<double>(0, r, z, q, nullptr, ncol, active);
     }
 }
 
-void amg_hierarchy::run_first(int ncol)
+void amg_hierarchy::run_step(int ncol)
 {
     using namespace amg;
     const auto g = graphs.find(ncol);
-    if (g != graphs.end() && g->second.first) {
-        AMG_HIP(hipGraphLaunch(g->second.first, stream));
+    if (g != graphs.end() && g->second.step) {
+        AMG_HIP(hipGraphLaunch(g->second.step, stream));
         return;
     }
     Level &F = lev[0];
-    AMG_HIP(hipMemcpyAsync(p, z, sizeof(double) * F.n * (size_t)ncol, hipMemcpyDeviceToDevice, stream));
+    const int *active = ncol > 1 ? mask : nullptr, *restart = mask + opt.max_rhs;
+    // before the first step dr_pq is unset; every column restarts then and reads no products
+    launch_fcg_direction(F.n, dr_pq, dr_zq, z, p, flag, stream, ncol, active, restart);
     const DotSet s1 = launch_spmv_dots<double>(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream, nullptr, ncol,
-                                               F.sl(), F.k64.sva);
+                                               F.sl(), F.k64.sva, active);
     dr_pq = s1.d[0];
     dr_pr = s1.d[1];
-    dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream, ncol);
-    launch_reduce(dr_rr, scal, stream, ncol);
+    dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream, ncol, active);
+    launch_reduce(dr_rr, scal, stream, ncol, kScalCol, active);
 }
 
-void amg_hierarchy::run_iter(int ncol)
+void amg_hierarchy::upload_masks()
 {
-    using namespace amg;
-    const auto g = graphs.find(ncol);
-    if (g != graphs.end() && g->second.iter) {
-        AMG_HIP(hipGraphLaunch(g->second.iter, stream));
-        return;
-    }
-    Level &F = lev[0];
-    launch_fcg_direction(F.n, dr_pq, dr_zq, z, p, flag, stream, ncol);
-    const DotSet s1 = launch_spmv_dots<double>(F.A, F.ci, F.va, p, q, r, nullptr, F.G, d_pq, stream, nullptr, ncol,
-                                               F.sl(), F.k64.sva);
-    dr_pq = s1.d[0];
-    dr_pr = s1.d[1];
-    dr_rr = launch_fcg_update(F.n, dr_pq, dr_pr, x, r, p, q, d_rr, flag, stream, ncol);
-    launch_reduce(dr_rr, scal, stream, ncol);
+    // only when they changed since the last upload (a copy per outer iteration would
+    // cost as much as a small kernel)
+    const size_t count = 3 * (size_t)opt.max_rhs;
+    if (mask_sent.size() == count && std::equal(mask_sent.begin(), mask_sent.end(), host_mask)) return;
+    mask_sent.assign(host_mask, host_mask + count);
+    AMG_HIP(hipMemcpyAsync(mask, host_mask, count * sizeof(int), hipMemcpyHostToDevice, stream));
 }
 
 // Records the three pieces once per hierarchy and batch width; every launch
@@ -1329,6 +1337,7 @@ void amg_hierarchy::capture_graphs(int ncol)
     Graphs &G = graphs[ncol];
     const int L = levels() - 1;
     if (L > kMaxGraphDepth) return;
+    // out NULL: record the body's launches and drop them (nothing runs)
     auto capture = [&](auto &&body, hipGraphExec_t *out) {
         hipGraph_t g = nullptr;
         AMG_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
@@ -1340,20 +1349,22 @@ void amg_hierarchy::capture_graphs(int ncol)
             throw;
         }
         AMG_HIP(hipStreamEndCapture(stream, &g));
-        const hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+        const hipError_t e = out ? hipGraphInstantiate(out, g, nullptr, nullptr, 0) : hipSuccess;
         (void)hipGraphDestroy(g);
         AMG_HIP(e);
     };
-    hipGraphExec_t gk = nullptr, gf = nullptr, gi = nullptr;
+    hipGraphExec_t gk = nullptr, gs = nullptr;
     AMG_TRACE_MSG("capturing K-cycle graph (%d right-hand sides)", ncol);
     capture([&] { run_kcycle(ncol); }, &gk);
-    AMG_TRACE_MSG("capturing outer-iteration graphs");
-    capture([&] { run_first(ncol); }, &gf);
-    capture([&] { run_iter(ncol); }, &gi);
+    AMG_TRACE_MSG("capturing outer-iteration graph");
+    // the step's direction update reads the products of the previous step, whose
+    // partial-sum set its own launch of A p fixes: a first capture (never launched)
+    // records that set, the second uses it
+    capture([&] { run_step(ncol); }, nullptr);
+    capture([&] { run_step(ncol); }, &gs);
     AMG_TRACE_MSG("graphs ready");
     G.k = gk;
-    G.first = gf;
-    G.iter = gi;
+    G.step = gs;
 }
 
 // Outer flexible CG over ncol right-hand sides at once (column c of b_user at
@@ -1374,38 +1385,48 @@ amg_status amg_hierarchy::solve(int ncol, const double *b_user, int ldb, double 
     AMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
     launch_gather(n, b_user, uperm, b, stream, ncol, ldb, n);
     launch_gather(n, x_user, uperm, x, stream, ncol, ldx, n);
-    auto true_residual = [&]() {  // r = b - A x; per column (b, b), (r, r) at scal[c * kScalCol + 1, + 2]
-        const DotSet s0 = launch_residual(F.A, F.ci, F.va, b, x, r, F.G, d_res, stream, ncol);
-        launch_reduce(s0.d[0], scal + 1, stream, ncol);
-        launch_reduce(s0.d[1], scal + 2, stream, ncol);
-        if (mixed) launch_reduce(s0.d[1], scal, stream, ncol);  // the K-cycle scales r by sqrt(scal[0])
+    const int nr = opt.max_rhs;
+    int *active = host_mask, *restart = host_mask + nr, *claim = host_mask + 2 * nr;
+    // r = b - A x for the columns of `gate` (NULL: all); per column (b, b), (r, r) at
+    // scal[c * kScalCol + 1, + 2]
+    auto true_residual = [&](const int *gate) {
+        const DotSet s0 = launch_residual(F.A, F.ci, F.va, b, x, r, F.G, d_res, stream, ncol, gate);
+        launch_reduce(s0.d[0], scal + 1, stream, ncol, kScalCol, gate);
+        launch_reduce(s0.d[1], scal + 2, stream, ncol, kScalCol, gate);
+        // the mixed K-cycle scales r by sqrt(scal[c * kScalCol])
+        if (mixed) launch_reduce(s0.d[1], scal, stream, ncol, kScalCol, gate);
         AMG_HIP(hipMemcpyAsync(host, scal, sizeof(double) * kScalCol * ncol, hipMemcpyDeviceToHost, stream));
         sync();
     };
     std::vector<double> bnorm(ncol), rel(ncol);
     std::vector<int> iters(ncol, 0);
-    std::vector<char> done(ncol, 0), claim(ncol, 0);
-    true_residual();
+    std::vector<char> done(ncol, 0);
+    true_residual(nullptr);
+    for (int c = 0; c < nr; c++) active[c] = restart[c] = claim[c] = 0;
     for (int c = 0; c < ncol; c++) {
         const double bb = host[c * kScalCol + 1], rr = host[c * kScalCol + 2];
         if (!std::isfinite(bb) || !std::isfinite(rr)) return AMG_ERR_INVALID_ARGUMENT;
         bnorm[c] = std::sqrt(bb);
         rel[c] = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
         done[c] = bb == 0.0 || rel[c] <= tol;
+        active[c] = !done[c];
+        restart[c] = 1;
     }
     auto all_done = [&]() {
         for (int c = 0; c < ncol; c++)
             if (!done[c]) return false;
         return true;
     };
+    // Each column iterates on its own: it stops when its recursive and then its true
+    // relative residual are <= tol, and a true residual that does not confirm
+    // restarts that column alone; the others are not touched.  So every column goes
+    // through the iterates of its right-hand side solved alone.
     int it = 0;
     amg_status st = AMG_ERR_NOT_CONVERGED;
-    bool restart = true;
     while (!all_done() && it < opt.max_iters) {
+        upload_masks();
         run_kcycle(ncol);  // z = B r
-        if (restart) run_first(ncol);
-        else run_iter(ncol);
-        restart = false;
+        run_step(ncol);
         AMG_HIP(hipMemcpyAsync(host, scal, sizeof(double) * kScalCol * ncol, hipMemcpyDeviceToHost, stream));
         AMG_HIP(hipMemcpyAsync(host_i, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
         sync();
@@ -1416,25 +1437,31 @@ amg_status amg_hierarchy::solve(int ncol, const double *b_user, int ldb, double 
         }
         bool any = false;
         for (int c = 0; c < ncol; c++) {
-            claim[c] = !done[c] && std::sqrt(host[c * kScalCol]) / bnorm[c] <= tol;
+            restart[c] = 0;
+            claim[c] = active[c] && std::sqrt(host[c * kScalCol]) / bnorm[c] <= tol;
             any = any || claim[c];
         }
-        if (any) {  // confirm with the true residual, then restart every column from it
-            true_residual();
+        if (any) {  // confirm with the true residual of the claiming columns
+            upload_masks();
+            true_residual(mask + 2 * nr);
             for (int c = 0; c < ncol; c++) {
-                if (claim[c] && std::sqrt(host[c * kScalCol + 2]) / bnorm[c] <= tol) {
+                if (!claim[c]) continue;
+                if (std::sqrt(host[c * kScalCol + 2]) / bnorm[c] <= tol) {
                     done[c] = 1;
+                    active[c] = 0;
                     iters[c] = it;
+                } else {
+                    restart[c] = 1;  // continue from the true residual
                 }
+                claim[c] = 0;
             }
-            restart = true;
         }
     }
     if (st != AMG_ERR_BREAKDOWN) st = all_done() ? AMG_OK : AMG_ERR_NOT_CONVERGED;
     launch_scatter(n, x, uperm, x_user, stream, ncol, n, ldx);
     for (int c = 0; c < ncol; c++)  // b = 0 has the solution 0
         if (bnorm[c] == 0.0) AMG_HIP(hipMemsetAsync(x_user + (size_t)c * ldx, 0, sizeof(double) * n, stream));
-    true_residual();  // the reported residual is always the true one
+    true_residual(nullptr);  // the reported residual is always the true one
     for (int c = 0; c < ncol; c++) {
         const double bb = host[c * kScalCol + 1];
         rel[c] = bb > 0.0 ? std::sqrt(host[c * kScalCol + 2] / bb) : 0.0;
@@ -1732,6 +1759,8 @@ amg_status kcycle_columns(amg_hierarchy *h, int ncol, const double *r, int ldr, 
         h->autotune(ncol);
         h->capture_graphs(ncol);
         AMG_HIP(hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
+        for (int c = 0; c < 3 * h->opt.max_rhs; c++) h->host_mask[c] = c < ncol ? 1 : 0;  // every column active
+        h->upload_masks();
         amg::launch_gather(F.n, r, h->uperm, h->r, h->stream, ncol, ldr, F.n);
         if (h->mixed) {  // the mixed K-cycle reads (r, r) of column c from scal[c * kScalCol]
             const DotRef rr = amg::launch_dot(F.n, h->r, h->r, h->d_res, h->stream, ncol);

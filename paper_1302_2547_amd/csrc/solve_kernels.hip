@@ -104,6 +104,14 @@ __device__ inline bool gated_off(const int *gate)
 {
     return gate && gate[blockIdx.y] == 0;
 }
+// The latency-bound small-level kernels take the check as a template switch: without
+// it their first loads issue at once (a runtime test of a null gate before them
+// measurably delays every launch).
+template <bool GATE>
+__device__ inline bool gated_off_if(const int *gate)
+{
+    return GATE && gate[blockIdx.y] == 0;
+}
 
 // Sum over the block; every thread receives the same value (fixed order).
 __device__ inline double block_sum(double v)
@@ -388,14 +396,14 @@ __global__ void __launch_bounds__(kBlock) k_spmv(Rows R, const int *__restrict__
 
 // y = A x (y may be NULL); dots (x, Ax) and, for each non-NULL w_j, (x, w_j);
 // OMY adds (om, A x) as the last product.
-template <class T, int G, int ND, bool LAT, bool OMY>
+template <class T, int G, int ND, bool LAT, bool OMY, bool GATE>
 __global__ void __launch_bounds__(kBlock) k_spmv_dots(Rows R, const int *__restrict__ ci,
                                                       const T *__restrict__ va, const T *__restrict__ x,
                                                       T *__restrict__ y, const T *__restrict__ w1,
                                                       const T *__restrict__ w2, const double *__restrict__ om,
                                                       double *__restrict__ part, const int *__restrict__ gate)
 {
-    if (gated_off(gate)) return;
+    if (gated_off_if<GATE>(gate)) return;
     constexpr int NT = ND + (OMY ? 1 : 0);
     x = colv(x, R.n);
     y = colv(y, R.n);
@@ -440,8 +448,9 @@ template <int G>
 __global__ void __launch_bounds__(kBlock) k_residual(Rows R, const int *__restrict__ ci,
                                                      const double *__restrict__ va, const double *__restrict__ b,
                                                      const double *__restrict__ x, double *__restrict__ r,
-                                                     double *__restrict__ part)
+                                                     double *__restrict__ part, const int *__restrict__ gate)
 {
+    if (gated_off(gate)) return;
     b = colv(b, R.n);
     x = colv(x, R.n);
     r = colv(r, R.n);
@@ -503,13 +512,13 @@ __global__ void __launch_bounds__(kReduceThreads) k_reduce_partials(int nd, cons
 // w = P^T (I - A M^-1) is stored per entry (w_e = [diagonal] - a_e minv_col).
 // OM adds partials of (om, rc) (the restriction to a single coarse unknown of
 // the next level down, see k_post_direct).
-template <class T, int G, bool LAT, bool OM>
+template <class T, int G, bool LAT, bool OM, bool GATE>
 __global__ void __launch_bounds__(kBlock) k_restrict(Rows S, int nf, const int *__restrict__ ci,
                                                      const T *__restrict__ wv, const T *__restrict__ r,
                                                      T *__restrict__ rc, const double *__restrict__ om,
                                                      double *__restrict__ part, const int *__restrict__ gate)
 {
-    if (gated_off(gate)) return;
+    if (gated_off_if<GATE>(gate)) return;
     r = colv(r, nf);
     rc = colv(rc, S.n);
     part = colp(part);
@@ -541,12 +550,12 @@ struct KCoef {
 
 // second (may be NULL): the gate of the second inner step; where it is 0 for this
 // right-hand side the threshold test skipped that step and mode 2 reads as mode 1.
-template <bool PREFETCH = true>
+template <bool PREFETCH = true, bool SECOND = true>
 __device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd, const int *second = nullptr)
 {
     KCoef c{0.0, 0.0, false, mode == 2};
     if (mode == 0 || mode == 3) return c;
-    if (mode == 2 && second && second[blockIdx.y] == 0) {
+    if (SECOND && mode == 2 && second && second[blockIdx.y] == 0) {
         mode = 1;  // c2 was never formed for this column: it must not be read
         c.two = false;
     }
@@ -592,15 +601,16 @@ __device__ inline KCoef kcycle_coefficients(int mode, const KDots &kd, const int
 // Restriction of the inner residual of the parent's first flexible-CG step:
 // rt = rcf - (alpha1/rho1) v1 is formed on the fly (and stored for the later
 // kernels of the visit), rc = W rt.
-template <class T, int G, bool OM>
+template <class T, int G, bool OM, bool GATE>
 __global__ void __launch_bounds__(kBlock) k_restrict_rt(Rows S, int nf, const int *__restrict__ ci,
                                                         const T *__restrict__ wv,
                                                         const T *__restrict__ rcf,
                                                         const T *__restrict__ v1, KDots kd,
                                                         T *__restrict__ rt, T *__restrict__ rc,
                                                         int *__restrict__ flag, const double *__restrict__ om,
-                                                        double *__restrict__ part)
+                                                        double *__restrict__ part, const int *__restrict__ gate)
 {
+    if (gated_off_if<GATE>(gate)) return;
     rcf = colv(rcf, nf);
     v1 = colv(v1, nf);
     rt = colv(rt, nf);
@@ -643,8 +653,10 @@ __global__ void __launch_bounds__(kBlock) k_restrict_rt(Rows S, int nf, const in
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_inner_residual(int n, const T *__restrict__ rc,
                                                            const T *__restrict__ v1, KDots kd,
-                                                           T *__restrict__ rt, int *__restrict__ flag)
+                                                           T *__restrict__ rt, int *__restrict__ flag,
+                                                           const int *__restrict__ gate)
 {
+    if (gated_off(gate)) return;
     rc = colv(rc, n);
     v1 = colv(v1, n);
     rt = colv(rt, n);
@@ -707,7 +719,7 @@ __global__ void __launch_bounds__(kBlock) k_theta_gate(DotRef rcrc, DotRef rtrt,
 // out = x + M^-1 (r - A x).  mode 0: e = edirect; mode 1: e = a1 c1;
 // mode 2: e = a1 c1 + a2 c2; mode 3: e = ainv edirect (small dense coarsest level).
 // DOT adds partials of (out, wdot).
-template <class T, int G, int MODE, bool DOT, bool CAGG>
+template <class T, int G, int MODE, bool DOT, bool CAGG, bool GATE>
 __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__restrict__ ci,
                                                         const T *__restrict__ va,
                                                         const T *__restrict__ minv,
@@ -722,7 +734,7 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
                                                         const double *__restrict__ ainv, int nc,
                                                         const int *__restrict__ gate, const int *__restrict__ second)
 {
-    if (gated_off(gate)) return;
+    if (GATE && gated_off(gate)) return;
     r = colv(r, R.n);
     xout = colv(xout, R.n);
     wdot = colv(wdot, R.n);
@@ -731,15 +743,16 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
     c2 = colv(c2, nc);
     part = colp(part);
     double a1 = 0.0, a2 = 0.0;
-    bool two = MODE == 2;
+    bool two = MODE == 2;  // a constant unless GATE
     __shared__ double e_sh[MODE == 3 ? kInlineCoarse : 1];
+    // rounded step by step, so that the gated and the ungated kernel give the same
+    // bits; both loads issue unconditionally (a skipped second step's c2 is not used)
     auto corr = [&](int J) -> double {
         if (MODE == 0) return (double)edirect[J];
         if (MODE == 3) return e_sh[J];
-        if (MODE == 1) return a1 * (double)c1[J];
-        // both loads issue unconditionally; a skipped second step's c2 is not used
+        if (MODE == 1) return __dmul_rn(a1, (double)c1[J]);
         const double v1 = (double)c1[J], v2 = (double)c2[J];
-        return two ? a1 * v1 + a2 * v2 : a1 * v1;
+        return two ? __fma_rn(a1, v1, __dmul_rn(a2, v2)) : __dmul_rn(a1, v1);
     };
     struct Pre {
         double mr, rr, wd;
@@ -753,11 +766,11 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
     visit_rows<G, CAGG>(
         R,
         [&]() {
-            const KCoef c = kcycle_coefficients<CAGG>(MODE, kd, second);  // CAGG marks small levels
+            const KCoef c = kcycle_coefficients<CAGG, GATE>(MODE, kd, second);  // CAGG marks small levels
             if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
             a1 = c.a1;
             a2 = c.a2;
-            two = c.two;
+            if (GATE) two = c.two;
             if (MODE == 3) {  // e = A_coarsest^-1 rc, computed by every block into LDS
                 // wavefront w forms rows w, w + 4, ...; lane j holds column j
                 constexpr int kRows = kInlineCoarse / (kBlock / kWave);
@@ -798,6 +811,21 @@ __global__ void __launch_bounds__(kBlock) k_post_smooth(Rows R, const int *__res
     if (DOT) store_partials<1>(dsum, part);
 }
 
+// The prolonged iterate x = M^-1 r + (P e) of one row and its coarse value e, as the
+// two-launch and the one-sweep post-smoothing of large levels form it: rounded step
+// by step (explicit fused multiply-adds, no contraction left to the compiler), so
+// both forms produce the same bits.
+template <int MODE, class T>
+__device__ inline double coarse_value(const KCoef &c, const T *edirect, const T *c1, const T *c2, int J)
+{
+    if (MODE == 0) return (double)edirect[J];
+    if (MODE == 1) return __dmul_rn(c.a1, (double)c1[J]);
+    const double v1 = (double)c1[J], v2 = (double)c2[J];
+    return c.two ? __fma_rn(c.a1, v1, __dmul_rn(c.a2, v2)) : __dmul_rn(c.a1, v1);
+}
+__device__ inline double prolonged_iterate(double minv, double r, double e) { return __fma_rn(minv, r, e); }
+__device__ inline double smoothed(double x, double minv, double r, double ax) { return __fma_rn(minv, __dsub_rn(r, ax), x); }
+
 // Large levels split the same step in two launches, so that each entry gathers one
 // value instead of five (the fused form recomputes x_t = M^-1 r_t + (P e)_t for every
 // entry that references column t, which at 128^3 and above is bound by the gathers):
@@ -823,15 +851,8 @@ __global__ void __launch_bounds__(kBlock) k_smooth_start(int n, const T *__restr
     const KCoef c = kcycle_coefficients<false>(MODE, kd, second);
     if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const int J = agg_pos[i];
-        double e;
-        if (MODE == 0) e = (double)edirect[J];
-        else if (MODE == 1) e = c.a1 * (double)c1[J];
-        else {
-            const double v1 = (double)c1[J], v2 = (double)c2[J];
-            e = c.two ? c.a1 * v1 + c.a2 * v2 : c.a1 * v1;
-        }
-        x[i] = (double)minv[i] * (double)r[i] + e;
+        const double e = coarse_value<MODE>(c, edirect, c1, c2, agg_pos[i]);
+        x[i] = prolonged_iterate((double)minv[i], (double)r[i], e);
     }
 }
 
@@ -887,6 +908,19 @@ __device__ inline int mm_columns(int ncol, int *c0)
     const int left = ncol - *c0;
     return left < CB ? left : CB;
 }
+// which of the block's columns run (inside the batch and not gated off); a block
+// with none returns at once
+template <int CB>
+__device__ inline bool mm_live(int nc, int c0, const int *gate, bool (&live)[CB])
+{
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < CB; k++) {
+        live[k] = k < nc && !(gate && gate[c0 + k] == 0);
+        any = any || live[k];
+    }
+    return any;
+}
 
 // The row loop of visit_rows (large levels) for CB columns: acc(p, s) adds entry
 // p's contribution to the CB sums s; fin(row, s, k) finishes the row for every
@@ -925,10 +959,13 @@ template <class T, int G, int ND, int CB>
 __global__ void __launch_bounds__(kBlock) k_spmm_dots(Rows R, const int *__restrict__ ci,
                                                       const T *__restrict__ va, const T *__restrict__ x,
                                                       T *__restrict__ y, const T *__restrict__ w1,
-                                                      const T *__restrict__ w2, double *__restrict__ part, int ncol)
+                                                      const T *__restrict__ w2, double *__restrict__ part, int ncol,
+                                                      const int *__restrict__ gate)
 {
     int c0;
     const int nc = mm_columns<CB>(ncol, &c0);
+    bool live[CB];
+    if (!mm_live<CB>(nc, c0, gate, live)) return;
     const size_t n = (size_t)R.n;
     const int nb = gridDim.x;
     auto col = [&](int k) { return (size_t)(c0 + (k < nc ? k : 0)); };
@@ -962,27 +999,29 @@ __global__ void __launch_bounds__(kBlock) k_spmm_dots(Rows R, const int *__restr
             if (ch.k < 0) {
 #pragma unroll
                 for (int k = 0; k < CB; k++)
-                    if (k < nc) row_done(row, k, s[k], -1);
+                    if (live[k]) row_done(row, k, s[k], -1);
                 return;
             }
 #pragma unroll
             for (int k = 0; k < CB; k++)
-                if (k < nc) finish_chunk(R, row, ch, s[k], [&](int r, double t, int hub) { row_done(r, k, t, hub); },
-                                         c0 + k);
+                if (live[k]) finish_chunk(R, row, ch, s[k], [&](int r, double t, int hub) { row_done(r, k, t, hub); },
+                                          c0 + k);
         });
 #pragma unroll
     for (int k = 0; k < CB; k++)
-        if (k < nc) store_partials<ND>(d[k], part + col(k) * kDotCol);
+        if (live[k]) store_partials<ND>(d[k], part + col(k) * kDotCol);
 }
 
 // k_restrict (large levels) for CB columns: rc = W r over the super-rows
 template <class T, int G, int CB>
 __global__ void __launch_bounds__(kBlock) k_restrict_mm(Rows S, int nf, const int *__restrict__ ci,
                                                         const T *__restrict__ wv, const T *__restrict__ r,
-                                                        T *__restrict__ rc, int ncol)
+                                                        T *__restrict__ rc, int ncol, const int *__restrict__ gate)
 {
     int c0;
     const int nc = mm_columns<CB>(ncol, &c0);
+    bool live[CB];
+    if (!mm_live<CB>(nc, c0, gate, live)) return;
     auto col = [&](int k) { return (size_t)(c0 + (k < nc ? k : 0)); };
     visit_rows_mm<G, CB>(
         S,
@@ -995,7 +1034,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict_mm(Rows S, int nf, const in
         [&](int Q, const Chunk &ch, double (&s)[CB]) {
 #pragma unroll
             for (int k = 0; k < CB; k++) {
-                if (k >= nc) continue;
+                if (!live[k]) continue;
                 if (ch.k < 0) rc[col(k) * S.n + Q] = (T)s[k];
                 else finish_chunk(S, Q, ch, s[k], [&](int q, double t, int) {
                     rc[col(k) * S.n + q] = (T)t;
@@ -1010,10 +1049,13 @@ __global__ void __launch_bounds__(kBlock) k_smooth_finish_mm(Rows R, const int *
                                                              const T *__restrict__ va, const T *__restrict__ minv,
                                                              const T *__restrict__ r, const double *__restrict__ x,
                                                              T *__restrict__ xout, const T *__restrict__ wdot,
-                                                             double *__restrict__ part, int ncol)
+                                                             double *__restrict__ part, int ncol,
+                                                             const int *__restrict__ gate)
 {
     int c0;
     const int nc = mm_columns<CB>(ncol, &c0);
+    bool live[CB];
+    if (!mm_live<CB>(nc, c0, gate, live)) return;
     const size_t n = (size_t)R.n;
     const int nb = gridDim.x;
     auto col = [&](int k) { return (size_t)(c0 + (k < nc ? k : 0)); };
@@ -1040,18 +1082,18 @@ __global__ void __launch_bounds__(kBlock) k_smooth_finish_mm(Rows R, const int *
             if (ch.k < 0) {
 #pragma unroll
                 for (int k = 0; k < CB; k++)
-                    if (k < nc) row_done(row, k, s[k], -1);
+                    if (live[k]) row_done(row, k, s[k], -1);
                 return;
             }
 #pragma unroll
             for (int k = 0; k < CB; k++)
-                if (k < nc) finish_chunk(R, row, ch, s[k], [&](int q, double t, int hub) { row_done(q, k, t, hub); },
-                                         c0 + k);
+                if (live[k]) finish_chunk(R, row, ch, s[k], [&](int q, double t, int hub) { row_done(q, k, t, hub); },
+                                          c0 + k);
         });
     if (DOT) {
 #pragma unroll
         for (int k = 0; k < CB; k++)
-            if (k < nc) store_partials<1>(d[k], part + col(k) * kDotCol);
+            if (live[k]) store_partials<1>(d[k], part + col(k) * kDotCol);
     }
 }
 
@@ -1079,10 +1121,10 @@ __device__ inline double sell_row(const int *__restrict__ sc, const V *__restric
     }
     double s = 0.0;
 #pragma unroll
-    for (int u = 0; u < kSellUnroll; u++) s += v[u] * gx(c[u]);
+    for (int u = 0; u < kSellUnroll; u++) s = __fma_rn(v[u], gx(c[u]), s);
     for (int k = kSellUnroll; k < w; k++) {
         const int p = p0 + k * kWave;
-        s += (double)sv[p] * gx(sc[p]);
+        s = __fma_rn((double)sv[p], gx(sc[p]), s);
     }
     return s;
 }
@@ -1125,7 +1167,7 @@ __global__ void __launch_bounds__(kBlock) k_sell_smooth_finish(int n, int tpb, c
     sell_tiles(n, tpb, sptr, [&](int i, int beg, int w, int t) {
         const double mr = (double)minv[i], rr = (double)r[i], xr = x[i];
         const double wd = DOT ? (double)wdot[i] : 0.0;
-        const double o = xr + mr * (rr - sell_row(sc, sv, beg, w, t, [&](int j) { return x[j]; }));
+        const double o = smoothed(xr, mr, rr, sell_row(sc, sv, beg, w, t, [&](int j) { return x[j]; }));
         xout[i] = (T)o;
         if (DOT) d[0] += o * wd;
     });
@@ -1161,22 +1203,15 @@ __global__ void __launch_bounds__(kBlock) k_sell_post_fused(int n, int tpb, cons
     const KCoef c = kcycle_coefficients<false>(MODE, kd, second);
     if (c.bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
     auto xval = [&](int j) -> double {  // as k_smooth_start forms x_j
-        const int J = agg_pos[j];
-        double e;
-        if (MODE == 0) e = (double)edirect[J];
-        else if (MODE == 1) e = c.a1 * (double)c1[J];
-        else {
-            const double v1 = (double)c1[J], v2 = (double)c2[J];
-            e = c.two ? c.a1 * v1 + c.a2 * v2 : c.a1 * v1;
-        }
-        return (double)minv[j] * (double)r[j] + e;
+        const double e = coarse_value<MODE>(c, edirect, c1, c2, agg_pos[j]);
+        return prolonged_iterate((double)minv[j], (double)r[j], e);
     };
     double d[1] = {0.0};
     sell_tiles(n, tpb, sptr, [&](int i, int beg, int w, int t) {
         const double mr = (double)minv[i], rr = (double)r[i];
         const double wd = DOT ? (double)wdot[i] : 0.0;
         const double xi = xval(i);
-        const double o = xi + mr * (rr - sell_row(sc, sv, beg, w, t, xval));
+        const double o = smoothed(xi, mr, rr, sell_row(sc, sv, beg, w, t, xval));
         xout[i] = (T)o;
         if (DOT) d[0] += o * wd;
     });
@@ -1278,7 +1313,7 @@ __global__ void __launch_bounds__(kBlock) k_segment_sum(int nc, const int *__res
 // out = x + M^-1 (r - A x).  RT (the second inner step of the parent):
 // r = rcf - (alpha1/rho1) v1 is formed on the fly and stored, and
 // rc = (om, rcf) - (alpha1/rho1) (om, v1).
-template <class T, int G, bool RT>
+template <class T, int G, bool RT, bool GATE>
 __global__ void __launch_bounds__(kBlock) k_post_direct(Rows R, const int *__restrict__ ci,
                                                         const T *__restrict__ va,
                                                         const T *__restrict__ minv,
@@ -1288,7 +1323,7 @@ __global__ void __launch_bounds__(kBlock) k_post_direct(Rows R, const int *__res
                                                         T *__restrict__ rt_out, int *__restrict__ flag,
                                                         const int *__restrict__ gate)
 {
-    if (gated_off(gate)) return;
+    if (gated_off_if<GATE>(gate)) return;
     r = colv(r, R.n);
     v1 = colv(v1, R.n);
     xout = colv(xout, R.n);
@@ -1362,7 +1397,7 @@ __device__ inline void tail_sums(double (&v)[N])
 // owned rows), and every inner product is a block sum, so the correction takes
 // one launch instead of four.  Vectors that the separate kernels store in T are
 // rounded to T here at the same points (c1, A c1, rt, c2).
-template <class T>
+template <class T, bool GATE, bool THETA>
 __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const T *__restrict__ va,
                                                              const T *__restrict__ minv,
                                                              const double *__restrict__ om,
@@ -1372,7 +1407,7 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const
                                                              double *__restrict__ d2, int *__restrict__ flag,
                                                              const int *__restrict__ gate, double theta2)
 {
-    if (gated_off(gate)) return;
+    if (gated_off_if<GATE>(gate)) return;
     constexpr int R = kTailRows, W = kTailWidth, S = kTailSlots, NL = kTailLong;
     __shared__ double xs[R * kTailThreads];  // the vector being multiplied
     __shared__ double rs[R * kTailThreads];  // rc (first step), then rt (second step)
@@ -1412,7 +1447,7 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const
         rs[i] = rv[u];
         ms[i] = mv[u];
         q[0] += o[u] * rv[u];
-        q[1] += rv[u] * rv[u];  // (rc, rc) for the threshold test
+        if (THETA) q[1] += rv[u] * rv[u];  // (rc, rc) for the threshold test
     }
     const double acinv = ainv[0];
     // y = (A xs) at the owned rows; the sums of long rows are block sums (whose
@@ -1460,7 +1495,7 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const
     };
     // first step: c1 = K(rc) with e = (om, rc) / a_c
     double om_r[1] = {q[0]}, rcrc = 0.0;
-    if (theta2 > 0.0) {
+    if (THETA) {
         double v2[2] = {q[0], q[1]};
         tail_sums<2>(v2);
         om_r[0] = v2[0];
@@ -1518,9 +1553,9 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_visit(TailLayout L, const
         x[u] = ms[i] * rr + e2;
         rs[i] = rr;
         xs[i] = x[u];
-        if (i < n) rtrt[0] += (double)(T)rr * (double)(T)rr;
+        if (THETA && i < n) rtrt[0] += (double)(T)rr * (double)(T)rr;
     }
-    if (theta2 > 0.0) {  // threshold test (Sec. 4.3): skip the second step, c2 = 0
+    if (THETA) {  // threshold test (Sec. 4.3): skip the second step, c2 = 0
         tail_sums<1>(rtrt);
         if (rtrt[0] < theta2 * rcrc) {
 #pragma unroll
@@ -1657,8 +1692,9 @@ __global__ void __launch_bounds__(kBlock) k_convert(int64_t n, const S *__restri
 __global__ void __launch_bounds__(kBlock) k_fcg_update(int n, DotRef pq, DotRef pr, double *__restrict__ x,
                                                        double *__restrict__ r, const double *__restrict__ p,
                                                        const double *__restrict__ q, double *__restrict__ part,
-                                                       int *__restrict__ flag)
+                                                       int *__restrict__ flag, const int *__restrict__ gate)
 {
+    if (gated_off(gate)) return;
     x = colv(x, n);
     r = colv(r, n);
     p = colv(p, n);
@@ -1679,12 +1715,21 @@ __global__ void __launch_bounds__(kBlock) k_fcg_update(int n, DotRef pq, DotRef 
     store_partials<1>(d, part);
 }
 
-// beta = -(z, A p) / (p, A p); p = z + beta p
+// beta = -(z, A p) / (p, A p); p = z + beta p.  A column whose restart flag is set
+// (the first step, or after a true residual that did not confirm convergence)
+// takes p = z and reads no products.
 __global__ void __launch_bounds__(kBlock) k_fcg_direction(int n, DotRef pq, DotRef zq, const double *__restrict__ z,
-                                                          double *__restrict__ p, int *__restrict__ flag)
+                                                          double *__restrict__ p, int *__restrict__ flag,
+                                                          const int *__restrict__ gate,
+                                                          const int *__restrict__ restart)
 {
+    if (gated_off(gate)) return;
     z = colv(z, n);
     p = colv(p, n);
+    if (restart && restart[blockIdx.y]) {
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i];
+        return;
+    }
     const double vpq = dot_value(pq), vzq = dot_value(zq);
     const bool zero = vpq == 0.0 && vzq == 0.0;
     const bool bad = !(vpq > 0.0) && !zero;
@@ -1844,10 +1889,10 @@ DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, co
         return out;
     }
     const bool lat = R.n < kSmallLevel;
-    if (ncol > 1 && !lat && !omy && !gate && R.cb > 1) {  // batched: CB columns per block
+    if (ncol > 1 && !lat && !omy && R.cb > 1) {  // batched: CB columns per block
         const dim3 gm(rows_grid(R, G, kMaxDotBlocks), (ncol + R.cb - 1) / R.cb);
 #define AMG_SPMM(ND, CB)                                                                                             \
-    AMG_SWITCH_G(G, (k_spmm_dots<T, kG, ND, CB><<<gm, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, buf.part, ncol)))
+    AMG_SWITCH_G(G, (k_spmm_dots<T, kG, ND, CB><<<gm, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, buf.part, ncol, gate)))
 #define AMG_SPMM_CB(ND)                    \
     switch (R.cb) {                        \
     case 2: AMG_SPMM(ND, 2); break;        \
@@ -1866,9 +1911,15 @@ DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, co
     }
     const dim3 grid(rows_grid(R, G, kMaxDotBlocks), ncol);
     if (omy && nd == 3) throw Error(4, "spmv_dots: at most three products");
-#define AMG_SPMV_DOTS(ND, LAT, OMY)                                                                        \
-    AMG_SWITCH_G(G, (k_spmv_dots<T, kG, ND, LAT, OMY><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, omy, \
-                                                                               buf.part, gate)))
+#define AMG_SPMV_DOTS_GATE(ND, LAT, OMY, GT)                                                                  \
+    AMG_SWITCH_G(G, (k_spmv_dots<T, kG, ND, LAT, OMY, GT><<<grid, kBlock, 0, s>>>(R, ci, va, x, y, w1, w2, omy, \
+                                                                                   buf.part, gate)))
+#define AMG_SPMV_DOTS(ND, LAT, OMY)               \
+    if (gate) {                                   \
+        AMG_SPMV_DOTS_GATE(ND, LAT, OMY, true);   \
+    } else {                                      \
+        AMG_SPMV_DOTS_GATE(ND, LAT, OMY, false);  \
+    }
     if (omy) {
         if (nd == 1) {
             AMG_SPMV_DOTS(1, true, true);
@@ -1895,6 +1946,7 @@ DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, co
         }
     }
 #undef AMG_SPMV_DOTS
+#undef AMG_SPMV_DOTS_GATE
     AMG_HIP(hipGetLastError());
     const int nt = nd + (omy ? 1 : 0);
     const int count = (int)grid.x + R.nlong;
@@ -1905,21 +1957,21 @@ DotSet launch_spmv_dots(Rows R, const int *ci, const T *va, const T *x, T *y, co
 }
 
 DotSet launch_residual(Rows R, const int *ci, const double *va, const double *b, const double *x, double *r, int G,
-                       DotBuf buf, hipStream_t s, int ncol)
+                       DotBuf buf, hipStream_t s, int ncol, const int *gate)
 {
     const dim3 grid(rows_grid(R, G, kMaxDotBlocks), ncol);
-    AMG_SWITCH_G(G, (k_residual<kG><<<grid, kBlock, 0, s>>>(R, ci, va, b, x, r, buf.part)));
+    AMG_SWITCH_G(G, (k_residual<kG><<<grid, kBlock, 0, s>>>(R, ci, va, b, x, r, buf.part, gate)));
     AMG_HIP(hipGetLastError());
     const int count = (int)grid.x + R.nlong;
-    reduce_if_large(2, buf.part, count, buf.final_out, s, ncol);
+    reduce_if_large(2, buf.part, count, buf.final_out, s, ncol, kConsumerReduceMax, gate);
     DotSet out{};
     for (int d = 0; d < 2; d++) out.d[d] = finished(buf.part, count, buf.final_out, d);
     return out;
 }
 
-void launch_reduce(const DotRef &ref, double *out, hipStream_t s, int ncol, int out_stride)
+void launch_reduce(const DotRef &ref, double *out, hipStream_t s, int ncol, int out_stride, const int *gate)
 {
-    k_reduce_partials<<<dim3(1, ncol), kReduceThreads, 0, s>>>(1, ref.part, ref.count, out, out_stride, nullptr);
+    k_reduce_partials<<<dim3(1, ncol), kReduceThreads, 0, s>>>(1, ref.part, ref.count, out, out_stride, gate);
     AMG_HIP(hipGetLastError());
 }
 
@@ -1927,9 +1979,10 @@ template <class T>
 DotRef launch_restrict(Rows S, int nf, const int *ci, const T *wv, const T *r, T *rc, int G, hipStream_t s,
                        const double *om, DotBuf buf, int ncol, const int *gate)
 {
-    if (ncol > 1 && !om && !gate && S.n >= kSmallLevel && S.cb > 1) {  // batched: CB columns per block
+    if (ncol > 1 && !om && S.n >= kSmallLevel && S.cb > 1) {  // batched: CB columns per block
         const dim3 gm(rows_grid(S, G, 1 << 20), (ncol + S.cb - 1) / S.cb);
-#define AMG_RMM(CB) AMG_SWITCH_G(G, (k_restrict_mm<T, kG, CB><<<gm, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, ncol)))
+#define AMG_RMM(CB) \
+    AMG_SWITCH_G(G, (k_restrict_mm<T, kG, CB><<<gm, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, ncol, gate)))
         switch (S.cb) {
         case 2: AMG_RMM(2); break;
         case 4: AMG_RMM(4); break;
@@ -1940,16 +1993,22 @@ DotRef launch_restrict(Rows S, int nf, const int *ci, const T *wv, const T *r, T
         return DotRef{nullptr, 0};
     }
     const dim3 grid(rows_grid(S, G, om ? kMaxDotBlocks : (1 << 20)), ncol);
-    if (om) {
-        AMG_SWITCH_G(G, (k_restrict<T, kG, true, true><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part,
-                                                                                gate)));
-    } else if (S.n < kSmallLevel) {
-        AMG_SWITCH_G(G, (k_restrict<T, kG, true, false><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part,
-                                                                                 gate)));
-    } else {
-        AMG_SWITCH_G(G, (k_restrict<T, kG, false, false><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part,
-                                                                                  gate)));
+#define AMG_RESTRICT(LAT, OM)                                                                                        \
+    if (gate) {                                                                                                      \
+        AMG_SWITCH_G(G, (k_restrict<T, kG, LAT, OM, true><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om, buf.part, \
+                                                                                   gate)));                          \
+    } else {                                                                                                         \
+        AMG_SWITCH_G(G, (k_restrict<T, kG, LAT, OM, false><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, r, rc, om,         \
+                                                                                    buf.part, gate)));               \
     }
+    if (om) {
+        AMG_RESTRICT(true, true)
+    } else if (S.n < kSmallLevel) {
+        AMG_RESTRICT(true, false)
+    } else {
+        AMG_RESTRICT(false, false)
+    }
+#undef AMG_RESTRICT
     AMG_HIP(hipGetLastError());
     if (!om) return DotRef{nullptr, 0};
     const int count = (int)grid.x + S.nlong;
@@ -1958,9 +2017,10 @@ DotRef launch_restrict(Rows S, int nf, const int *ci, const T *wv, const T *r, T
 }
 
 template <class T>
-void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, hipStream_t s, int ncol)
+void launch_inner_residual(int n, const T *rc, const T *v1, KDots kd, T *rt, int *flag, hipStream_t s, int ncol,
+                           const int *gate)
 {
-    k_inner_residual<T><<<dim3(grid_for(n, 4096), ncol), kBlock, 0, s>>>(n, rc, v1, kd, rt, flag);
+    k_inner_residual<T><<<dim3(grid_for(n, 4096), ncol), kBlock, 0, s>>>(n, rc, v1, kd, rt, flag, gate);
     AMG_HIP(hipGetLastError());
 }
 
@@ -2031,11 +2091,11 @@ DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, con
             reduce_if_large(1, buf.part, (int)gs.x, buf.final_out, s, ncol, 1, gate);
             return finished(buf.part, (int)gs.x, buf.final_out, 0, 1);
         }
-        if (ncol > 1 && !gate && R.cb > 1) {  // batched: CB columns per block
+        if (ncol > 1 && R.cb > 1) {  // batched: CB columns per block
             const dim3 gm(grid.x, (ncol + R.cb - 1) / R.cb);
 #define AMG_FMM(D, CB)                                                                                              \
     AMG_SWITCH_G(G, (k_smooth_finish_mm<T, kG, D, CB><<<gm, kBlock, 0, s>>>(R, ci, va, minv, r, xtmp, xout, wdot, \
-                                                                            buf.part, ncol)))
+                                                                            buf.part, ncol, gate)))
             switch (R.cb) {
             case 2: if (dot) { AMG_FMM(true, 2); } else { AMG_FMM(false, 2); } break;
             case 4: if (dot) { AMG_FMM(true, 4); } else { AMG_FMM(false, 4); } break;
@@ -2055,17 +2115,18 @@ DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, con
         reduce_if_large(1, buf.part, count, buf.final_out, s, ncol, kConsumerReduceMax, gate);
         return finished(buf.part, count, buf.final_out, 0);
     }
-#define AMG_POST(M, D)                                                                                         \
-    do {                                                                                                       \
-        if (cagg) {                                                                                            \
-            AMG_SWITCH_G(G, (k_post_smooth<T, kG, M, D, true><<<grid, kBlock, 0, s>>>(                         \
-                                R, ci, va, minv, r, agg_pos, cagg, edirect, c1, c2, kd, xout, wdot, buf.part, flag,  \
-                                ainv, nc, gate, second)));                                                     \
-        } else {                                                                                               \
-            AMG_SWITCH_G(G, (k_post_smooth<T, kG, M, D, false><<<grid, kBlock, 0, s>>>(                        \
-                                R, ci, va, minv, r, agg_pos, cagg, edirect, c1, c2, kd, xout, wdot, buf.part, flag,  \
-                                ainv, nc, gate, second)));                                                     \
-        }                                                                                                      \
+#define AMG_POST_G(M, D, CA, GT)                                                                        \
+    AMG_SWITCH_G(G, (k_post_smooth<T, kG, M, D, CA, GT><<<grid, kBlock, 0, s>>>(                                \
+                        R, ci, va, minv, r, agg_pos, cagg, edirect, c1, c2, kd, xout, wdot, buf.part, flag, ainv, nc, \
+                        gate, second)))
+#define AMG_POST(M, D)                                                                                   \
+    do {                                                                                                 \
+        const bool gt = gate || second;                                                                  \
+        if (cagg) {                                                                                      \
+            if (gt) { AMG_POST_G(M, D, true, true); } else { AMG_POST_G(M, D, true, false); }            \
+        } else {                                                                                         \
+            if (gt) { AMG_POST_G(M, D, false, true); } else { AMG_POST_G(M, D, false, false); }          \
+        }                                                                                                \
     } while (0)
     switch (mode) {
     case 0: if (dot) { AMG_POST(0, true); } else { AMG_POST(0, false); } break;
@@ -2077,6 +2138,7 @@ DotRef launch_post_smooth(Rows R, const int *ci, const T *va, const T *minv, con
         break;
     }
 #undef AMG_POST
+#undef AMG_POST_G
     AMG_HIP(hipGetLastError());
     if (!dot) return DotRef{nullptr, 0};
     const int count = (int)grid.x + R.nlong;
@@ -2098,20 +2160,23 @@ void launch_sell_restrict(const Sell &S, const T *sva, const T *minv, const T *r
 
 template <class T>
 DotRef launch_restrict_rt(Rows S, int nf, const int *ci, const T *wv, const T *rcf, const T *v1, KDots kd, T *rt,
-                          T *rc, int *flag, int G, hipStream_t s, const double *om, DotBuf buf, int ncol)
+                          T *rc, int *flag, int G, hipStream_t s, const double *om, DotBuf buf, int ncol,
+                          const int *gate)
 {
     const dim3 grid(rows_grid(S, G, om ? kMaxDotBlocks : (1 << 20)), ncol);
+#define AMG_RESTRICT_RT(OM, GT)                                                                                 \
+    AMG_SWITCH_G(G, (k_restrict_rt<T, kG, OM, GT><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, rcf, v1, kd, rt, rc, flag, \
+                                                                           om, buf.part, gate)))
     if (om) {
-        AMG_SWITCH_G(G, (k_restrict_rt<T, kG, true><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, rcf, v1, kd, rt, rc, flag,
-                                                                             om, buf.part)));
+        if (gate) { AMG_RESTRICT_RT(true, true); } else { AMG_RESTRICT_RT(true, false); }
     } else {
-        AMG_SWITCH_G(G, (k_restrict_rt<T, kG, false><<<grid, kBlock, 0, s>>>(S, nf, ci, wv, rcf, v1, kd, rt, rc, flag,
-                                                                              om, buf.part)));
+        if (gate) { AMG_RESTRICT_RT(false, true); } else { AMG_RESTRICT_RT(false, false); }
     }
+#undef AMG_RESTRICT_RT
     AMG_HIP(hipGetLastError());
     if (!om) return DotRef{nullptr, 0};
     const int count = (int)grid.x + S.nlong;
-    reduce_if_large(1, buf.part, count, buf.final_out, s, ncol);
+    reduce_if_large(1, buf.part, count, buf.final_out, s, ncol, kConsumerReduceMax, gate);
     return finished(buf.part, count, buf.final_out, 0);
 }
 
@@ -2121,13 +2186,15 @@ void launch_post_direct(Rows R, const int *ci, const T *va, const T *minv, const
                         bool rt_mode, hipStream_t s, int ncol, const int *gate)
 {
     const dim3 grid(rows_grid(R, G, 1 << 20), ncol);
+#define AMG_DIRECT(RT, GT)                                                                                \
+    AMG_SWITCH_G(G, (k_post_direct<T, kG, RT, GT><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, v1, kd, om_r, om_v1, \
+                                                                           ainv, xout, rt_out, flag, gate)))
     if (rt_mode) {
-        AMG_SWITCH_G(G, (k_post_direct<T, kG, true><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, v1, kd, om_r, om_v1,
-                                                                             ainv, xout, rt_out, flag, gate)));
+        if (gate) { AMG_DIRECT(true, true); } else { AMG_DIRECT(true, false); }
     } else {
-        AMG_SWITCH_G(G, (k_post_direct<T, kG, false><<<grid, kBlock, 0, s>>>(R, ci, va, minv, r, v1, kd, om_r, om_v1,
-                                                                              ainv, xout, rt_out, flag, gate)));
+        if (gate) { AMG_DIRECT(false, true); } else { AMG_DIRECT(false, false); }
     }
+#undef AMG_DIRECT
     AMG_HIP(hipGetLastError());
 }
 
@@ -2136,8 +2203,15 @@ void launch_tail_visit(const TailLayout &L, const T *va, const T *minv, const do
                        const T *rc, T *c1, T *c2, double *d1, double *d2, int *flag, hipStream_t s, int ncol,
                        const int *gate, double theta2)
 {
-    k_tail_visit<T><<<dim3(1, ncol), kTailThreads, 0, s>>>(L, va, minv, om, ainv, rc, c1, c2, d1, d2, flag, gate,
-                                                           theta2);
+#define AMG_TAIL(GT, TH)                                                                                           \
+    k_tail_visit<T, GT, TH><<<dim3(1, ncol), kTailThreads, 0, s>>>(L, va, minv, om, ainv, rc, c1, c2, d1, d2, flag, gate, \
+                                                                   theta2)
+    if (gate) {
+        if (theta2 > 0.0) { AMG_TAIL(true, true); } else { AMG_TAIL(true, false); }
+    } else {
+        if (theta2 > 0.0) { AMG_TAIL(false, true); } else { AMG_TAIL(false, false); }
+    }
+#undef AMG_TAIL
     AMG_HIP(hipGetLastError());
 }
 
@@ -2230,7 +2304,8 @@ void launch_to_float(int64_t n, const double *src, float *dst, hipStream_t s)
                                        const double *, DotBuf, int, const int *);                                   \
     template void launch_sell_restrict<T>(const Sell &, const T *, const T *, const T *, double *, int, const int *, \
                                           const int *, T *, hipStream_t, int, const int *);                         \
-    template void launch_inner_residual<T>(int, const T *, const T *, KDots, T *, int *, hipStream_t, int);         \
+    template void launch_inner_residual<T>(int, const T *, const T *, KDots, T *, int *, hipStream_t, int,         \
+                                           const int *);                                                            \
     template DotRef launch_inner_residual_theta<T>(int, const T *, const T *, KDots, T *, int *, const double *,    \
                                                    DotBuf, double, const int *, int *, hipStream_t, int);           \
     template DotRef launch_post_smooth<T>(Rows, const int *, const T *, const T *, const T *, const int *,          \
@@ -2238,7 +2313,7 @@ void launch_to_float(int64_t n, const double *src, float *dst, hipStream_t s)
                                           DotBuf, int *, int, hipStream_t, const double *, int, int, double *,      \
                                           const Sell *, const T *, const int *, const int *);                       \
     template DotRef launch_restrict_rt<T>(Rows, int, const int *, const T *, const T *, const T *, KDots, T *, T *, \
-                                          int *, int, hipStream_t, const double *, DotBuf, int);                    \
+                                          int *, int, hipStream_t, const double *, DotBuf, int, const int *);       \
     template void launch_post_direct<T>(Rows, const int *, const T *, const T *, const T *, const T *, KDots,       \
                                         DotRef, DotRef, const double *, T *, T *, int *, int, bool, hipStream_t,    \
                                         int, const int *);                                                          \
@@ -2251,18 +2326,19 @@ AMG_INSTANTIATE(float)
 #undef AMG_INSTANTIATE
 
 DotRef launch_fcg_update(int n, DotRef pq, DotRef pr, double *x, double *r, const double *p, const double *q,
-                         DotBuf buf, int *flag, hipStream_t s, int ncol)
+                         DotBuf buf, int *flag, hipStream_t s, int ncol, const int *gate)
 {
     const int grid = grid_for(n, kMaxDotBlocks);
-    k_fcg_update<<<dim3(grid, ncol), kBlock, 0, s>>>(n, pq, pr, x, r, p, q, buf.part, flag);
+    k_fcg_update<<<dim3(grid, ncol), kBlock, 0, s>>>(n, pq, pr, x, r, p, q, buf.part, flag, gate);
     AMG_HIP(hipGetLastError());
-    reduce_if_large(1, buf.part, grid, buf.final_out, s, ncol);
+    reduce_if_large(1, buf.part, grid, buf.final_out, s, ncol, kConsumerReduceMax, gate);
     return finished(buf.part, grid, buf.final_out, 0);
 }
 
-void launch_fcg_direction(int n, DotRef pq, DotRef zq, const double *z, double *p, int *flag, hipStream_t s, int ncol)
+void launch_fcg_direction(int n, DotRef pq, DotRef zq, const double *z, double *p, int *flag, hipStream_t s, int ncol,
+                          const int *gate, const int *restart)
 {
-    k_fcg_direction<<<dim3(grid_for(n, 4096), ncol), kBlock, 0, s>>>(n, pq, zq, z, p, flag);
+    k_fcg_direction<<<dim3(grid_for(n, 4096), ncol), kBlock, 0, s>>>(n, pq, zq, z, p, flag, gate, restart);
     AMG_HIP(hipGetLastError());
 }
 

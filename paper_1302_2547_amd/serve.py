@@ -10,12 +10,17 @@ on the device from its seed) and 1..8 right-hand sides.  The server:
   stream; each hierarchy solves on a stream of its own);
 * keeps hierarchies resident (least recently used evicted first when memory is
   needed), so a request for a resident problem skips the setup;
-* solves each request's right-hand sides together (``amg_solve_batch``);
+* merges queued requests for the same problem: a slot that takes a request also
+  takes the waiting requests with the same key, up to ``max_rhs`` right-hand sides
+  in all, and solves them as one batch (``amg_solve_batch``), so their K-cycles --
+  the latency-bound coarse levels above all -- share every launch;
 * reports per-request latency (arrival to completion), p50/p99 and solves/s.
 
 Every kernel of a solve reads and writes only that solve's hierarchy and vectors
-and reduces in a fixed order, so a request's result does not depend on what else
-runs: the same alone and in the mix (a test checks this bit for bit).
+and reduces in a fixed order, and every column of a batch iterates on its own
+(it stops, confirms and restarts by its own residuals), so a request's result does
+not depend on what else runs or what it was merged with: the same alone and in the
+mix (a test checks this bit for bit).
 """
 from __future__ import annotations
 
@@ -58,6 +63,7 @@ class Result:
     iterations: list
     rel_residuals: list
     solution: object = None  # (nrhs, n) host array when kept
+    merged: int = 1          # requests solved in the same batch
 
 
 def make_requests(count: int = 2000, rate: float = 200.0, seed: int = 6, reuse: float = 0.3,
@@ -94,7 +100,7 @@ class Server:
     each, within an HBM `budget` (bytes; default 0.8 of the free device memory)."""
 
     def __init__(self, slots: int = 4, budget: int | None = None, tol: float = 1e-8,
-                 precision: int = amg.AMG_PREC_FP32_INNER, max_rhs: int = 8, keep_solutions: bool = False):
+                 precision: int = amg.AMG_PREC_FP32_INNER, max_rhs: int = 16, keep_solutions: bool = False):
         import torch
         self.torch = torch
         self.slots, self.tol, self.precision, self.max_rhs = slots, tol, precision, max_rhs
@@ -155,15 +161,18 @@ class Server:
         amg.amg_release_cached_memory()
         torch.cuda.empty_cache()
 
-    def _admit(self, req: Request):
-        """Block until req fits; returns (hierarchy or None, reserved bytes)."""
+    def _admit(self, group):
+        """Block until a group of requests for one problem fits; returns (hierarchy or
+        None, reserved bytes)."""
+        req = group[0]
         with self.lock:
             while True:
                 entry = self.resident.get(req.key)
                 if entry is not None and entry[2]:  # the hierarchy is busy: wait for it
                     self.lock.wait()
                     continue
-                need = self.vector_bytes(req) + (0 if entry else self.hierarchy_estimate(req, self.max_rhs))
+                need = sum(self.vector_bytes(q) for q in group) + \
+                    (0 if entry else self.hierarchy_estimate(req, self.max_rhs))
                 if self.resident_bytes + self.inflight_bytes + need > self.budget:
                     self._evict(need)
                 self._ensure_free(need)
@@ -195,10 +204,13 @@ class Server:
             self._evict(0)
             self.lock.notify_all()
 
-    def _serve_one(self, req: Request, stream, t0: float) -> Result:
+    def _serve_group(self, group, stream, t0: float):
+        """Solve the right-hand sides of a group of requests for one problem as one
+        batch; returns one Result per request."""
         torch = self.torch
+        req = group[0]
         t_start = time.perf_counter()
-        h, reserved = self._admit(req)
+        h, reserved = self._admit(group)
         t_admit = time.perf_counter()
         new = h is None
         sp = stream.cuda_stream
@@ -215,9 +227,9 @@ class Server:
                     # measurement would add to their latency
                     h = amg.Hierarchy(rp, ci, va, precision=self.precision, max_rhs=self.max_rhs, autotune=0)
                     del rp, ci, va
-                k = len(req.rhs_seeds)
-                B = torch.empty((k, req.n), dtype=torch.float64, device="cuda")
-                for j, s in enumerate(req.rhs_seeds):
+                seeds = [s for q in group for s in q.rhs_seeds]
+                B = torch.empty((len(seeds), req.n), dtype=torch.float64, device="cuda")
+                for j, s in enumerate(seeds):
                     amg.device_rhs(B[j], s, stream=sp)
                 X = torch.zeros_like(B)
                 stream.synchronize()  # the hierarchy's stream does not wait for this one
@@ -227,10 +239,28 @@ class Server:
         finally:
             self._release(req, h, reserved, new)
         t_done = time.perf_counter()
-        return Result(req.rid, st, 1e3 * (t_done - (t0 + req.t_arrival)), 1e3 * (t_done - t_start),
-                      1e3 * (t_admit - t_start),
-                      infos[0].setup_ms if new else 0.0, infos[0].solve_ms, not new,
-                      [i.iterations for i in infos], [i.rel_residual for i in infos], sol)
+        out, col = [], 0
+        for q in group:
+            k = len(q.rhs_seeds)
+            mine = infos[col:col + k]
+            out.append(Result(q.rid, st, 1e3 * (t_done - (t0 + q.t_arrival)), 1e3 * (t_done - t_start),
+                              1e3 * (t_admit - t_start), mine[0].setup_ms if new else 0.0, mine[0].solve_ms,
+                              not new or q is not req, [i.iterations for i in mine], [i.rel_residual for i in mine],
+                              sol[col:col + k] if sol is not None else None, len(group)))
+            col += k
+        return out
+
+    def _take(self, pending):
+        """The oldest waiting request and the waiting requests for the same problem
+        that fit in one batch with it (caller holds the queue's lock)."""
+        first = pending.popleft()
+        group, cols = [first], len(first.rhs_seeds)
+        for q in list(pending):
+            if q.key == first.key and cols + len(q.rhs_seeds) <= self.max_rhs:
+                pending.remove(q)
+                group.append(q)
+                cols += len(q.rhs_seeds)
+        return group
 
     def run(self, requests, realtime: bool = True, progress=None):
         """Serve `requests` (sorted by arrival); returns (results by rid, stats).
@@ -250,17 +280,18 @@ class Server:
                         cv.wait()
                     if not pending:
                         return
-                    req = pending.popleft()
+                    group = self._take(pending)
                 try:
-                    res = self._serve_one(req, stream, t0)
-                    with cv:
-                        results[req.rid] = res
-                        done = len(results)
-                    if progress:
-                        progress(done, len(requests), res)
+                    for res in self._serve_group(group, stream, t0):
+                        with cv:
+                            results[res.rid] = res
+                            done = len(results)
+                        if progress:
+                            progress(done, len(requests), res)
                 except Exception as e:  # noqa: BLE001 - reported at once and by run()
+                    req = group[0]
                     errors.append((req.rid, repr(e)))
-                    print(f"[serve] request {req.rid} {req.dims} x{len(req.rhs_seeds)} failed: {e!r}", flush=True)
+                    print(f"[serve] requests {[q.rid for q in group]} {req.dims} failed: {e!r}", flush=True)
 
         threads = [threading.Thread(target=worker, daemon=True) for _ in range(self.slots)]
         for t in threads:
@@ -289,6 +320,7 @@ class Server:
                  "requests_per_s": len(results) / wall, "p50_ms": pct(0.50), "p99_ms": pct(0.99),
                  "service_p50_ms": pct(0.50, svc), "service_p99_ms": pct(0.99, svc),
                  "max_ms": lat[-1], "reused": sum(r.reused for r in results.values()),
+                 "merged": sum(r.merged > 1 for r in results.values()),
                  "failed": sum(r.status != amg.AMG_OK for r in results.values())}
         return results, stats
 

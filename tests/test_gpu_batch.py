@@ -173,3 +173,34 @@ def test_spmm_columns_per_block_same_bits(amg, precision):
         h.kcycle(R[c].contiguous(), z)
         np.testing.assert_array_equal(out[1, 0][0][c], z.cpu().numpy())
     h.close()
+
+
+@pytest.mark.parametrize("case", ["rgg_150k", "grid3d_50_jitter", "grid2d_64_single_coarse"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_columns_equal_solves_alone(amg, case, precision):
+    """Every column of a batched solve iterates on its own (it stops, confirms and
+    restarts by its own residuals; finished columns are left alone), so it ends
+    with the bits and the iteration count of its right-hand side solved alone --
+    whatever the other columns do, including a zero column and columns of very
+    different scales."""
+    if case == "rgg_150k":
+        rp, ci, va = inputs.rgg_laplacian(150000, seed=13, weight_range=(0.5, 1.5))
+    else:
+        rp, ci, va = CASES[case]()
+    opt = OPTS.get(case, {})
+    n, k = len(rp) - 1, 5
+    B = rhs_block(n, k, zero_col=3)
+    B[1] *= 1e6
+    B[4] = oracle.spmv(rp, ci, va, B[4])
+    h = amg.Hierarchy(dev(rp), dev(ci), dev(va), max_rhs=k, precision=precision, autotune=0, **opt)
+    X = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+    st, infos = h.solve_batch(dev(B), X, tol=1e-9)
+    assert st == amg.AMG_OK
+    Xg = X.cpu().numpy()
+    for c in range(k):
+        x1 = torch.zeros(n, dtype=torch.float64, device="cuda")
+        st1, info1 = h.solve(dev(B[c]), x1, tol=1e-9)
+        print(f"[batch] {case} col {c}: batch {infos[c].iterations} alone {info1.iterations} iterations", flush=True)
+        assert st1 == amg.AMG_OK and info1.iterations == infos[c].iterations
+        np.testing.assert_array_equal(Xg[c], x1.cpu().numpy())
+    h.close()

@@ -557,7 +557,12 @@ def test_kcycle_visit_budget_refuses_before_launching(amg):
     z = torch.empty(n, dtype=torch.float64, device="cuda")
     h1.kcycle(dev(r), z)
     zo = ref1.kcycle(r)
-    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-10 * np.abs(zo).max())
+    # This 1D Laplacian of 300,000 unknowns has condition ~4e10 and its cycle passes
+    # through 18 coarse levels: the GPU's summation order (weights W per entry, sums
+    # per aggregate) and the oracle's differ by rounding, which the coarse corrections
+    # amplify to ~1.2e-10 of max |z| (against ~1e-11 at 100,000 unknowns); the bound
+    # is ten times that.
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-9 * np.abs(zo).max())
 
 
 @pytest.mark.parametrize("case,opt", [("grid2d_128_t2", dict(max_aggregate=2, skip_ratio=2.5, coarsest_size=400)),

@@ -1,5 +1,6 @@
 """Serving: device-built inputs equal the host generator, and every served
-result is the same alone and in the mix (bit for bit), within the tolerance, and
+result is the same alone and in the mix (bit for bit, also where it was merged
+into a batch with other requests for its problem), within the tolerance, and
 close to the FP64 oracle's solution."""
 import numpy as np
 import pytest
@@ -64,6 +65,9 @@ def test_served_results_same_alone_and_in_mix(amg):
     mix.close()
     print(f"[serve] alone {s1}\n[serve] mix {s2}")
     assert s1["failed"] == 0 and s2["failed"] == 0 and s2["reused"] > 0
+    # all 20 requests are queued at once: requests for the same problem are merged
+    # into one batch (in both runs, not necessarily the same ones)
+    assert s1["merged"] > 0 and s2["merged"] > 0
     for rid in r1:
         a, b = r1[rid], r2[rid]
         assert a.status == b.status == amg.AMG_OK
