@@ -165,6 +165,12 @@ void launch_permute_rows(int n, const int *rp_nat, const int *ci_nat, const doub
 void launch_agg_positions(int n, const int *perm_f, const int *agg_nat, const int *pos_c, int *agg_pos,
                           hipStream_t s);
 void launch_gather_int(int n, const int *src, const int *idx, int *dst, hipStream_t s);
+// om_t = sum over rows q holding column t of [q == t] - a_qt minv_t: the restriction
+// row vector of a level whose coarse level is one unknown
+void launch_single_unknown_weights(int n, const int *rp, const int *ci, const double *va, const double *minv,
+                                   double *om, hipStream_t s);
+// dinv[k] = 1 / va[pos[k]]
+void launch_reciprocals(int m, const int *pos, const double *va, double *dinv, hipStream_t s);
 // Rows of ptr longer than lim, ascending.  Call first with list == NULL: flags
 // (n ints) receive exclusive offsets and *count_dev the count; then call again with
 // the same flags and a list of that many ints.

@@ -463,7 +463,7 @@ struct amg_hierarchy {
 
     void build(const amg_csr &A);
     void finalize_layout();
-    void build_sell();
+    void build_sell(int l, const int *rp, const int *ci, const double *va);
     // the inner residual rt = rcf - (alpha1/rho1) v1 of a parent's first step
     template <class T>
     struct RtSource {
@@ -691,8 +691,8 @@ void amg_hierarchy::build(const amg_csr &A)
     AMG_TRACE_MSG("coarsest level %d: n=%d", levels() - 1, Lc.n);
     {
         const int n = Lc.n;
-        std::vector<int> crp(n + 1), cci, idx, didx;
-        std::vector<double> cva, dinv;
+        std::vector<int> crp(n + 1), cci, idx, didx, dpos;
+        std::vector<double> cva;
         int m = n;
         if (n > kInlineCoarse) {
             std::vector<int> rp(n + 1), ci(Lc.nnz), cnt(n, 0), pos(n, -1);
@@ -705,7 +705,7 @@ void amg_hierarchy::build(const amg_csr &A)
                 if (rp[i + 1] - rp[i] == 1 && ci[rp[i]] == i && cnt[i] == 1) {
                     if (!(va[rp[i]] > 0.0)) throw Error(AMG_ERR_BREAKDOWN, "coarsest matrix is not positive definite");
                     didx.push_back(i);
-                    dinv.push_back(1.0 / va[rp[i]]);
+                    dpos.push_back(rp[i]);
                 } else {
                     pos[i] = (int)idx.size();
                     idx.push_back(i);
@@ -726,11 +726,15 @@ void amg_hierarchy::build(const amg_csr &A)
         }
         if (m > opt.max_coarsest) throw Error(AMG_ERR_UNSUPPORTED, "coarsest level larger than max_coarsest");
         coarse = CoarseSolve{n, m, (int)didx.size(), nullptr, nullptr, nullptr, nullptr};
-        if (!didx.empty()) {
+        if (!didx.empty()) {  // decoupled unknowns: x_i = r_i / a_ii
             int *d_didx = pool.alloc<int>(didx.size());
-            double *d_dinv = pool.alloc<double>(dinv.size());
+            int *d_dpos = pool.alloc<int>(dpos.size());
+            double *d_dinv = pool.alloc<double>(didx.size());
             to_dev(d_didx, didx.data(), didx.size());
-            to_dev(d_dinv, dinv.data(), dinv.size());
+            to_dev(d_dpos, dpos.data(), dpos.size());
+            launch_reciprocals((int)dpos.size(), d_dpos, Lc.va_nat, d_dinv, stream);
+            sync();
+            pool.release(d_dpos);
             coarse.didx = d_didx;
             coarse.dinv = d_dinv;
         }
@@ -821,23 +825,48 @@ void amg_hierarchy::finalize_layout()
         AMG_TRACE_MSG("layout level %d: G=%d hub rows=%d chunks=%d", l, F.G, F.A.nlong, F.A.nchunks);
         if (l < L) {
             const int nc = lev[l + 1].n;
-            F.srp = pool.alloc<int>(nc + 1);
-            launch_gather_int(nc + 1, F.rp, F.seg_ptr, F.srp, stream);
-            F.Gs = lanes_for((double)F.nnz / nc, nc);
-            F.S = make_rows(nc, F.srp, F.Gs, tmp, scan_tmp);
-            F.S.cb = F.A.cb;
-            AMG_TRACE_MSG("layout level %d: super-rows Gs=%d hub rows=%d chunks=%d", l, F.Gs, F.S.nlong, F.S.nchunks);
-            F.wv = pool.alloc<double>(F.nnz);
-            launch_restriction_weights(F.n, F.rp, F.ci, F.va, F.minv, F.wv, stream);
+            // Levels of at least kSmallLevel rows may also hold a sliced ELLPACK copy
+            // (not the level above a single coarse unknown, whose visits take another
+            // path); their solve sweeps read only that copy, and their restriction is
+            // a row sweep plus sums per aggregate -- unless the coarse level below is
+            // the one above a single unknown, which restricts by inner products with
+            // the weights W.  Only the levels that restrict through W get the
+            // aggregate-grouped super-rows and W.
+            const bool single_below = [&] {
+                return L >= 2 && lev[L].n == 1 && lev[L - 1].nnz <= (1 << 24);
+            }();
+            const bool omega_here = single_below && l == L - 1;
+            const bool omega_below = single_below && l + 1 == L - 1;
+            if (!omega_here) {
+                if (natural) build_sell(l, F.rp_nat, F.ci_nat, F.va_nat);
+                else build_sell(l, F.rp, F.ci, F.va);
+            }
+            const bool super_rows = !F.sell.ptr || omega_below;
             F.sci = F.ci;
+            if (super_rows) {
+                F.srp = pool.alloc<int>(nc + 1);
+                launch_gather_int(nc + 1, F.rp, F.seg_ptr, F.srp, stream);
+                F.Gs = lanes_for((double)F.nnz / nc, nc);
+                F.S = make_rows(nc, F.srp, F.Gs, tmp, scan_tmp);
+                F.S.cb = F.A.cb;
+                AMG_TRACE_MSG("layout level %d: super-rows Gs=%d hub rows=%d chunks=%d", l, F.Gs, F.S.nlong,
+                              F.S.nchunks);
+                F.wv = pool.alloc<double>(F.nnz);
+                launch_restriction_weights(F.n, F.rp, F.ci, F.va, F.minv, F.wv, stream);
+            } else {
+                AMG_TRACE_MSG("layout level %d: sliced, no super-row copy", l);
+            }
             if (natural) {
                 // The finest level keeps the caller's numbering for A (the stencil's
                 // neighbours stay in nearby cache lines; the nested order scatters them
                 // and the finest sweeps fetched ~3x their bytes).  Only the restriction
                 // needs the aggregate-grouped super-rows: their entries keep the nested
                 // order built above, with the columns mapped back to natural indices.
-                int *sci = pool.alloc<int>(F.nnz);
-                launch_gather_int(F.nnz, F.perm, F.ci, sci, stream);  // sci[e] = perm[ci[e]]
+                int *sci = nullptr;
+                if (super_rows) {
+                    sci = pool.alloc<int>(F.nnz);
+                    launch_gather_int(F.nnz, F.perm, F.ci, sci, stream);  // sci[e] = perm[ci[e]]
+                }
                 launch_gather_int(F.n, lev[1].pos, F.agg_nat, F.agg_pos, stream);  // natural row -> coarse position
                 // released once the stream has drained (another hierarchy's stream
                 // may receive the blocks from the shared cache)
@@ -872,24 +901,20 @@ void amg_hierarchy::finalize_layout()
             }
         }
     }
-    // single coarse unknown below level L-1 (L >= 2): om_j = sum over the entries
-    // e of column j of w_e, summed in entry order on the host (small level)
+    // single coarse unknown below level L-1 (L >= 2): the restriction is the row
+    // vector om (launch_single_unknown_weights)
     if (L >= 2 && lev[L].n == 1 && lev[L - 1].nnz <= (1 << 24)) {
         Level &F = lev[L - 1];
+        F.omega = pool.alloc<double>(F.n);
+        launch_single_unknown_weights(F.n, F.rp, F.ci, F.va, F.minv, F.omega, stream);
+        F.d_om = dot_buf();
+        // the one-block coarse correction's layout is built on the host from the
+        // level's pattern (placement only, no arithmetic)
         std::vector<int> rp(F.n + 1), ci(F.nnz);
-        std::vector<double> va(F.nnz), mv(F.n), om(F.n, 0.0);
+        std::vector<double> va(F.nnz);
         to_host(rp.data(), F.rp, F.n + 1);
         to_host(ci.data(), F.ci, F.nnz);
         to_host(va.data(), F.va, F.nnz);
-        to_host(mv.data(), F.minv, F.n);
-        for (int q = 0; q < F.n; q++)
-            for (int e = rp[q]; e < rp[q + 1]; e++) {
-                const int t = ci[e];
-                om[t] += (t == q ? 1.0 : 0.0) - va[e] * mv[t];
-            }
-        F.omega = pool.alloc<double>(F.n);
-        to_dev(F.omega, om.data(), F.n);
-        F.d_om = dot_buf();
         AMG_TRACE_MSG("level %d: single coarse unknown below, restriction by inner products", L - 1);
         std::vector<uint16_t> tci;
         std::vector<double> tva;
@@ -909,7 +934,6 @@ void amg_hierarchy::finalize_layout()
             AMG_TRACE_MSG("level %d: one-block coarse correction (%d long rows)", L - 1, tl.nlong);
         }
     }
-    build_sell();
     for (int l = 0; l <= L; l++) {
         Level &F = lev[l];
         F.k64 = KArrays<double>{F.va, F.minv, F.wv, F.rc, F.rt, F.c1, F.c2, F.v1, F.sell_va};
@@ -966,15 +990,15 @@ void amg_hierarchy::finalize_layout()
 // fine level of a single coarse unknown, whose visits take another path), kept
 // where the padding stays within kSellMaxPadding of the entries and no slice is
 // wider than kSellMaxWidth; other levels (irregular graphs) keep CSR only.
-void amg_hierarchy::build_sell()
+void amg_hierarchy::build_sell(int l, const int *rp, const int *ci, const double *va)
 {
     using namespace amg;
-    for (int l = 0; l + 1 < levels(); l++) {
+    {
         Level &F = lev[l];
-        if (F.n < kSmallLevel || F.omega || F.n > (1 << 28)) continue;
+        if (F.n < kSmallLevel || F.n > (1 << 28)) return;
         const int ns = (F.n + kWave - 1) / kWave;
         int *w = pool.alloc<int>(ns);
-        launch_sell_widths(F.n, F.rp, w, stream);
+        launch_sell_widths(F.n, rp, w, stream);
         std::vector<int> hw(ns), ptr(ns + 1);
         to_host(hw.data(), w, ns);
         pool.release(w);
@@ -990,13 +1014,13 @@ void amg_hierarchy::build_sell()
         const bool fits = !pool.budget || pool.used + bytes <= pool.budget;
         if (wmax > kSellMaxWidth || slots > kSellMaxPadding * F.nnz || slots >= INT32_MAX || !fits) {
             AMG_TRACE_MSG("level %d: CSR only (sliced copy %lld slots, widest %d)", l, (long long)slots, wmax);
-            continue;
+            return;
         }
         int *dptr = pool.alloc<int>(ns + 1);
         to_dev(dptr, ptr.data(), ns + 1);
         int *sci = pool.alloc<int>((size_t)slots);
         F.sell_va = pool.alloc<double>((size_t)slots);
-        launch_sell_fill(F.n, ns, F.rp, F.ci, F.va, dptr, sci, F.sell_va, stream);
+        launch_sell_fill(F.n, ns, rp, ci, va, dptr, sci, F.sell_va, stream);
         F.sell = Sell{F.n, ns, 1, dptr, sci, opt.post_fused == 1};
         F.sell_slots = (size_t)slots;
         AMG_TRACE_MSG("level %d: sliced copy, %lld slots for %d entries (widest %d)", l, (long long)slots, F.nnz, wmax);

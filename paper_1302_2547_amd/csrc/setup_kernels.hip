@@ -1369,6 +1369,67 @@ void launch_cholesky_inverse(int n, double *a, double *inv, int *err, hipStream_
     AMG_HIP(hipGetLastError());
 }
 
+namespace {
+// om_t = sum over the rows q that hold column t of [q == t] - a_qt minv_t: the row
+// vector W = P^T (I - A M^-1) of a level whose coarse level is a single unknown
+// (P = all ones).  The rows holding column t are the columns of row t (the pattern
+// is symmetric); a_qt is found in row q by bisection.  One block per column: thread
+// k takes the entries k, k + kBlock, ... of row t (a hub column has thousands), and
+// the block adds the partial sums in a fixed order.
+__global__ void __launch_bounds__(kBlock) k_single_unknown_weights(int n, const int *__restrict__ rp,
+                                                                   const int *__restrict__ ci,
+                                                                   const double *__restrict__ va,
+                                                                   const double *__restrict__ minv,
+                                                                   double *__restrict__ om)
+{
+    __shared__ double sh[kBlock];
+    for (int t = blockIdx.x; t < n; t += gridDim.x) {
+        const double mt = minv[t];
+        double s = 0.0;
+        for (int e = rp[t] + (int)threadIdx.x; e < rp[t + 1]; e += kBlock) {
+            const int q = ci[e];
+            int lo = rp[q], hi = rp[q + 1] - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (ci[mid] < t) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < rp[q + 1] && ci[lo] == t) s += (q == t ? 1.0 : 0.0) - va[lo] * mt;
+        }
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) om[t] = sh[0];
+        __syncthreads();
+    }
+}
+
+// dinv[k] = 1 / va[pos[k]]: the exact solve of the coarsest level's decoupled unknowns
+__global__ void __launch_bounds__(kBlock) k_reciprocals(int m, const int *__restrict__ pos,
+                                                        const double *__restrict__ va, double *__restrict__ dinv)
+{
+    for (int k = blockIdx.x * kBlock + threadIdx.x; k < m; k += gridDim.x * kBlock) dinv[k] = 1.0 / va[pos[k]];
+}
+
+}  // namespace
+
+void launch_single_unknown_weights(int n, const int *rp, const int *ci, const double *va, const double *minv,
+                                   double *om, hipStream_t s)
+{
+    k_single_unknown_weights<<<n < 65536 ? n : 65536, kBlock, 0, s>>>(n, rp, ci, va, minv, om);
+    AMG_HIP(hipGetLastError());
+}
+
+void launch_reciprocals(int m, const int *pos, const double *va, double *dinv, hipStream_t s)
+{
+    if (m <= 0) return;
+    k_reciprocals<<<grid_for(m), kBlock, 0, s>>>(m, pos, va, dinv);
+    AMG_HIP(hipGetLastError());
+}
+
 void launch_identity(int n, int *v, hipStream_t s)
 {
     k_identity<<<grid_for(n), kBlock, 0, s>>>(n, v);
