@@ -287,12 +287,12 @@ def serve_bench(args):
     from paper_1302_2547_amd import amg, serve
     reqs = serve.make_requests(count=args.requests, rate=args.rate, seed=6)
     prec = amg.AMG_PREC_FP32_INNER if args.precision == "fp32_inner" else amg.AMG_PREC_FP64
-    warm = serve.Server(slots=args.slots, precision=prec)  # first use of every kernel, graphs, caches
+    warm = serve.Server(slots=args.slots, precision=prec, skip_ratio=args.skip_ratio)  # first use of kernels
     warm.run(serve.make_requests(count=8, rate=1e4, seed=99, n_range_2d=(1e4, 1e5), n_range_3d=(1e4, 1e5)),
              realtime=False)
     warm.close()
     torch.cuda.synchronize()
-    srv = serve.Server(slots=args.slots, precision=prec, tol=args.tol)
+    srv = serve.Server(slots=args.slots, precision=prec, tol=args.tol, skip_ratio=args.skip_ratio)
     print(f"[bench] serving {len(reqs)} requests over {reqs[-1].t_arrival:.1f} s of arrivals, "
           f"{args.slots} slots, budget {srv.budget / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     by_rid = {q.rid: q for q in reqs}
@@ -317,7 +317,10 @@ def serve_bench(args):
         "config": {"workload": f"{len(reqs)} solve requests, Poisson arrivals at {args.rate:g}/s (seed 6); each a 2D "
                                "(n log-uniform in [1e4, 2e6]) or 3D (n in [1e4, 4e6]) 5/7-point Laplacian, weights "
                                "1+0.1U[-1,1], 1-8 right-hand sides U[-1,1], 30% reuse a recent problem; built on the "
-                               f"device; tol {args.tol:g}; admission by HBM footprint, {args.slots} slots",
+                               f"device; tol {args.tol:g}; admission by HBM footprint, {args.slots} slots; "
+                               "queued requests for the same problem merged into one batch"
+                               + (f"; level skipping below coarsening ratio {args.skip_ratio:g}" if args.skip_ratio
+                                  else ""),
                    "precision": args.precision, "slots": args.slots, "parallelism": "single GPU"},
         "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2), "max_ms": round(st["max_ms"], 2),
         "service_p50_ms": round(st["service_p50_ms"], 2), "service_p99_ms": round(st["service_p99_ms"], 2),

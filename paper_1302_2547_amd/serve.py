@@ -100,10 +100,12 @@ class Server:
     each, within an HBM `budget` (bytes; default 0.8 of the free device memory)."""
 
     def __init__(self, slots: int = 4, budget: int | None = None, tol: float = 1e-8,
-                 precision: int = amg.AMG_PREC_FP32_INNER, max_rhs: int = 16, keep_solutions: bool = False):
+                 precision: int = amg.AMG_PREC_FP32_INNER, max_rhs: int = 16, keep_solutions: bool = False,
+                 skip_ratio: float = 0.0):
         import torch
         self.torch = torch
         self.slots, self.tol, self.precision, self.max_rhs = slots, tol, precision, max_rhs
+        self.skip_ratio = skip_ratio  # level skipping of the hierarchies (Sec. 3.3); 0: the plain method
         self.keep = keep_solutions
         if budget is None:
             free, _ = torch.cuda.mem_get_info()
@@ -225,7 +227,8 @@ class Server:
                     # is capturing
                     # no lane-count autotuning: most requests bring a new shape, and the
                     # measurement would add to their latency
-                    h = amg.Hierarchy(rp, ci, va, precision=self.precision, max_rhs=self.max_rhs, autotune=0)
+                    h = amg.Hierarchy(rp, ci, va, precision=self.precision, max_rhs=self.max_rhs, autotune=0,
+                                      skip_ratio=self.skip_ratio)
                     del rp, ci, va
                 seeds = [s for q in group for s in q.rhs_seeds]
                 B = torch.empty((len(seeds), req.n), dtype=torch.float64, device="cuda")
