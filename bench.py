@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--skip-ratio", type=float, default=0.0,
                     help="level skipping (Sec. 3.3): aggregate twice where a level coarsens by less than this "
                          "ratio (0: never, the plain method)")
+    ap.add_argument("--group-n", type=int, default=0,
+                    help="serve workload: problems of at most this many unknowns (FP64) are solved in grouped "
+                         "launches, one workgroup per right-hand side (0: never)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--smoother-reps", type=int, default=50)
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "post_smooth_128cubed_traffic.json"))
@@ -287,12 +290,14 @@ def serve_bench(args):
     from paper_1302_2547_amd import amg, serve
     reqs = serve.make_requests(count=args.requests, rate=args.rate, seed=6)
     prec = amg.AMG_PREC_FP32_INNER if args.precision == "fp32_inner" else amg.AMG_PREC_FP64
-    warm = serve.Server(slots=args.slots, precision=prec, skip_ratio=args.skip_ratio)  # first use of kernels
+    warm = serve.Server(slots=args.slots, precision=prec, skip_ratio=args.skip_ratio,
+                        group_n=args.group_n)  # first use of kernels
     warm.run(serve.make_requests(count=8, rate=1e4, seed=99, n_range_2d=(1e4, 1e5), n_range_3d=(1e4, 1e5)),
              realtime=False)
     warm.close()
     torch.cuda.synchronize()
-    srv = serve.Server(slots=args.slots, precision=prec, tol=args.tol, skip_ratio=args.skip_ratio)
+    srv = serve.Server(slots=args.slots, precision=prec, tol=args.tol, skip_ratio=args.skip_ratio,
+                       group_n=args.group_n)
     print(f"[bench] serving {len(reqs)} requests over {reqs[-1].t_arrival:.1f} s of arrivals, "
           f"{args.slots} slots, budget {srv.budget / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     by_rid = {q.rid: q for q in reqs}
@@ -320,13 +325,15 @@ def serve_bench(args):
                                f"device; tol {args.tol:g}; admission by HBM footprint, {args.slots} slots; "
                                "queued requests for the same problem merged into one batch"
                                + (f"; level skipping below coarsening ratio {args.skip_ratio:g}" if args.skip_ratio
-                                  else ""),
+                                  else "")
+                               + (f"; problems of at most {args.group_n} unknowns solved in grouped launches (one "
+                                  "workgroup per right-hand side, up to 256 per launch)" if args.group_n else ""),
                    "precision": args.precision, "slots": args.slots, "parallelism": "single GPU"},
         "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2), "max_ms": round(st["max_ms"], 2),
         "service_p50_ms": round(st["service_p50_ms"], 2), "service_p99_ms": round(st["service_p99_ms"], 2),
         "requests_per_s": round(st["requests_per_s"], 2), "wall_s": round(st["wall_s"], 2),
         "solves": st["solves"], "reused": st["reused"], "failed": st["failed"],
-        "merged_requests": st["merged"],
+        "merged_requests": st["merged"], "grouped_requests": st["grouped"],
         "median_setup_ms": med(setup), "median_solve_ms": med(solve), "median_queue_ms": med(queue),
         "roofline": None, "cpu_baseline": None,
     }

@@ -144,6 +144,52 @@ amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, a
 amg_status amg_solve_batch(amg_hierarchy *h, int32_t nrhs, const double *B, int32_t ldb, double *X, int32_t ldx,
                            double tol, amg_solve_info *info);
 
+/* ---- Grouped solves of small problems (one launch for many requests) ----
+ * One right-hand side of one hierarchy: solve A x = b of h.  column (0 <= column <
+ * h's max_rhs) names the set of h's work vectors the job uses; two jobs of one call
+ * on the same hierarchy must name different columns.  b and x are device vectors of
+ * h's n unknowns in the caller's numbering; x holds the initial guess on entry.
+ * b and x must not overlap. */
+typedef struct {
+    amg_hierarchy *h;
+    int32_t column;
+    const double *b;
+    double *x;
+} amg_group_job;
+
+/* Solves `count` jobs -- on different hierarchies, of different sizes and depths, or
+ * several right-hand sides of one -- in ONE kernel launch: one workgroup runs the
+ * whole outer flexible CG (Sec. 4.4) with its K-cycle preconditioner (Sec. 4.3, the
+ * hierarchy's kcycle_inner, kcycle_threshold and smoother) for one job, so the
+ * latency-bound small levels of concurrent requests share a dispatch instead of
+ * taking thousands each.  Meant for small problems (a workgroup sweeps a level at
+ * the bandwidth of one compute unit); the method and stopping rule are those of
+ * amg_solve (recursive relative residual <= tol, confirmed by the true residual,
+ * the iteration continuing from the true residual when it disagrees), with
+ * h's max_iters.  Each job's sums run in a fixed order that does not depend on the
+ * other jobs: a job gives the same bits alone and in any group.  The result is
+ * not bit-identical to amg_solve's (other summation orders), and agrees with it to
+ * the tolerance.
+ *   Requirements (else AMG_ERR_UNSUPPORTED before any launch): every hierarchy in
+ * AMG_PREC_FP64, with 2 to 16 levels and within the visit budget of amg_solve.
+ * Argument errors (NULL job arrays, b or x not device memory, a column out of
+ * range or repeated on one hierarchy, tol not finite and > 0): AMG_ERR_INVALID_ARGUMENT.
+ * The call waits for each hierarchy's own stream, launches on `stream` (hipStream_t;
+ * NULL: the stream of jobs[0].h), and returns when every job is done.  status[k]
+ * receives job k's status (AMG_OK, AMG_ERR_NOT_CONVERGED, AMG_ERR_BREAKDOWN, or
+ * AMG_ERR_INVALID_ARGUMENT for a non-finite b or x); info (may be NULL) receives
+ * count records (solve_ms: device time of the whole launch).  Returns AMG_OK when
+ * every job converged, else the first failing job's status.  The hierarchies must
+ * not be in use by other calls meanwhile. */
+amg_status amg_solve_group(int32_t count, const amg_group_job *jobs, double tol, void *stream, int32_t *status,
+                           amg_solve_info *info);
+
+/* x = B b for every job: one application of the K-cycle preconditioner of the
+ * job's hierarchy (Sec. 4.3) per job, run as in amg_solve_group (one workgroup per
+ * job, one launch).  Same requirements and argument rules; status[k] is AMG_OK or
+ * AMG_ERR_BREAKDOWN. */
+amg_status amg_kcycle_group(int32_t count, const amg_group_job *jobs, void *stream, int32_t *status);
+
 /* ---- Synthetic workload (the benchmarks' inputs, built in device memory) ----
  * The (2d+1)-point finite-difference Laplacian on the interior of a d-dimensional
  * grid (d = 1, 2, 3; dims[a] >= 1 interior nodes along axis a; unknowns numbered x

@@ -50,6 +50,10 @@ class amg_solve_info(ctypes.Structure):
                 ("solve_ms", ctypes.c_double)]
 
 
+class amg_group_job(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_void_p), ("column", ctypes.c_int32), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1302_2547_amd.build`")
 _lib = ctypes.CDLL(LIB_PATH)
@@ -77,6 +81,9 @@ _sig = {
     "amg_spmv": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     "amg_kcycle": (ctypes.c_int, [_P, _P, _P]),
     "amg_kcycle_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, ctypes.c_int32]),
+    "amg_solve_group": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(amg_group_job), ctypes.c_double, _P, _I32P,
+                                       ctypes.POINTER(amg_solve_info)]),
+    "amg_kcycle_group": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(amg_group_job), _P, _I32P]),
     "amg_time_smoother": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
     "amg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -155,6 +162,37 @@ class LevelExport:
     row_ptr: np.ndarray
     col: np.ndarray
     val: np.ndarray
+
+
+def _group_jobs(jobs):
+    arr = (amg_group_job * max(1, len(jobs)))()
+    for k, (h, column, b, x) in enumerate(jobs):
+        if b.numel() != h.n or x.numel() != h.n:
+            raise ValueError("b and x must have the hierarchy's n entries")
+        arr[k] = amg_group_job(h._h.value, column, _ptr(b), _ptr(x))
+    return arr
+
+
+def solve_group(jobs, tol: float = 1e-8, stream: int | None = None, raise_on_error: bool = True):
+    """One launch for many solves: jobs is a list of (Hierarchy, column, b, x) with
+    float64 device vectors; returns (status, per-job statuses, per-job infos)."""
+    arr = _group_jobs(jobs)
+    st_out = (ctypes.c_int32 * max(1, len(jobs)))()
+    infos = (amg_solve_info * max(1, len(jobs)))()
+    st = amg_solve_group(len(jobs), arr, tol, stream or 0, st_out, infos)
+    if raise_on_error and st != AMG_OK:
+        raise AmgError(st, "amg_solve_group")
+    return st, list(st_out)[:len(jobs)], list(infos)[:len(jobs)]
+
+
+def kcycle_group(jobs, stream: int | None = None):
+    """x = B b for every (Hierarchy, column, b, x) job, in one launch."""
+    arr = _group_jobs(jobs)
+    st_out = (ctypes.c_int32 * max(1, len(jobs)))()
+    st = amg_kcycle_group(len(jobs), arr, stream or 0, st_out)
+    if st != AMG_OK:
+        raise AmgError(st, "amg_kcycle_group")
+    return list(st_out)[:len(jobs)]
 
 
 class Hierarchy:

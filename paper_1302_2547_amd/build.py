@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libamg.so")
-SOURCES = ["scan.hip", "setup_kernels.hip", "solve_kernels.hip", "generate.hip", "engine.hip"]
+SOURCES = ["scan.hip", "setup_kernels.hip", "solve_kernels.hip", "group_solve.hip", "generate.hip",
+           "engine.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled (the compiler would otherwise form them
 # from ordinary float code)

@@ -354,4 +354,41 @@ void launch_grid_laplacian_noalloc(int d, const int *dims, double jitter, uint64
                                    double *va, hipStream_t s);
 void launch_uniform_rhs(int64_t n, uint64_t seed, double *out, hipStream_t s);
 
+// Grouped solves (group_solve.hip): one workgroup of kGroupBlock threads runs the
+// whole outer flexible CG with its K-cycle for one right-hand side of one hierarchy;
+// one launch serves any number of such jobs, on different problems.  Level arrays
+// are those of the solve layout (level 0 in the caller's numbering).
+constexpr int kGroupBlock = 1024;
+constexpr int kGroupMaxLevels = 16;
+struct GroupLevel {
+    int n, nnz;
+    int G;   // lanes per row of the row sweeps (1, 2, 4, 8 or 16)
+    int Gr;  // lanes per aggregate of the restriction (all but the coarsest)
+    const int *rp, *ci;
+    const double *va, *minv;
+    const int *agg;   // row -> coarse position (all but the coarsest)
+    const int *cagg;  // entry -> coarse position of its column (NULL: agg of the column)
+    const int *seg;   // rows of coarse position c: positions seg[c] .. seg[c+1]-1
+    const int *srp;   // entries of those rows: srp[c] .. srp[c+1]-1 (NULL: from rp and seg)
+    const int *perm;  // position -> row (NULL: the identity)
+    // this job's work vectors (levels >= 1): restricted residual, the two inner
+    // preconditioned directions, A c1
+    double *rc, *c1, *c2, *v1;
+};
+struct GroupJob {
+    int levels, max_iters, nu;
+    double tol, theta;
+    const double *b;
+    double *x;
+    double *r, *z, *p, *q;  // finest-level work vectors of this job
+    CoarseSolve cs;
+    GroupLevel lev[kGroupMaxLevels];
+};
+struct GroupResult {
+    int status, iterations;
+    double rel_residual;
+};
+// kcycle_only: x = K(b) (one K-cycle application per job) instead of the solve
+void launch_group_solve(const GroupJob *jobs, int count, int kcycle_only, GroupResult *res, hipStream_t s);
+
 }  // namespace amg

@@ -19,6 +19,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <tuple>
 #include <type_traits>
 #include <vector>
@@ -1851,6 +1852,154 @@ amg_status amg_time_smoother(amg_hierarchy *h, int32_t reps, double *avg_us, dou
                             ((h->mixed ? 3.0 : 4.0) * w + 4.0) * F.n + 2.0 * w * C.n;
         return AMG_OK;
     });
+}
+
+}  // extern "C"
+
+namespace {
+// Lanes per row of the one-workgroup sweeps: the power of two nearest below the
+// mean row length, at most 16.
+int group_lanes(double mean)
+{
+    int g = 1;
+    while (g < 16 && 2.0 * g <= mean) g *= 2;
+    return g;
+}
+
+amg_status group_call(int32_t count, const amg_group_job *jobs, double tol, void *stream, int kcycle_only,
+                      int32_t *status, amg_solve_info *info)
+{
+    using namespace amg;
+    if (count < 0 || (count > 0 && (!jobs || !status))) return AMG_ERR_INVALID_ARGUMENT;
+    if (!kcycle_only && (!(tol > 0.0) || !std::isfinite(tol))) return AMG_ERR_INVALID_ARGUMENT;
+    if (count == 0) return AMG_OK;
+    std::set<std::pair<const amg_hierarchy *, int>> seen;
+    std::set<amg_hierarchy *> hs;
+    for (int k = 0; k < count; k++) {
+        const amg_group_job &j = jobs[k];
+        if (!j.h || !device_array(j.b) || !device_array(j.x)) return AMG_ERR_INVALID_ARGUMENT;
+        if (j.column < 0 || j.column >= j.h->opt.max_rhs) return AMG_ERR_INVALID_ARGUMENT;
+        if (!seen.insert({j.h, j.column}).second) return AMG_ERR_INVALID_ARGUMENT;
+        if (j.h->mixed || j.h->levels() < 2 || j.h->levels() > kGroupMaxLevels) return AMG_ERR_UNSUPPORTED;
+        if (j.h->kcycle_visits() > amg_hierarchy::kMaxKcycleVisits) return AMG_ERR_UNSUPPORTED;
+        hs.insert(j.h);
+    }
+    return guarded([&]() -> amg_status {
+        std::vector<GroupJob> hj((size_t)count);
+        for (int k = 0; k < count; k++) {
+            const amg_group_job &j = jobs[k];
+            const amg_hierarchy &h = *j.h;
+            const size_t c = (size_t)j.column;
+            GroupJob &g = hj[(size_t)k];
+            std::memset(&g, 0, sizeof(g));
+            g.levels = h.levels();
+            g.max_iters = h.opt.max_iters;
+            g.nu = h.opt.kcycle_inner;
+            g.tol = tol;
+            g.theta = h.opt.kcycle_threshold;
+            g.b = j.b;
+            g.x = j.x;
+            const size_t n0 = (size_t)h.lev[0].n;
+            g.r = h.r + c * n0;
+            g.z = h.z + c * n0;
+            g.p = h.p + c * n0;
+            g.q = h.q + c * n0;
+            g.cs = h.coarse;
+            const int L = h.levels() - 1;
+            for (int l = 0; l <= L; l++) {
+                const Level &F = h.lev[l];
+                GroupLevel &G = g.lev[l];
+                G.n = F.n;
+                G.nnz = F.nnz;
+                G.G = group_lanes((double)F.nnz / F.n);
+                // the restriction's lane groups serve one aggregate: its members on the
+                // finest level (a gather of the residual), its rows' entries below
+                if (l < L) G.Gr = group_lanes((l == 0 ? (double)F.n : (double)F.nnz) / h.lev[l + 1].n);
+                G.rp = F.rp;
+                G.ci = F.ci;
+                G.va = F.va;
+                G.minv = F.minv;
+                if (l < L) {
+                    G.agg = F.agg_pos;
+                    G.cagg = F.cagg;
+                    G.seg = F.seg_ptr;
+                    G.srp = l == 0 ? nullptr : F.srp;  // the finest level's super-rows are in another order
+                    G.perm = l == 0 ? F.perm : nullptr;  // the finest level keeps the caller's numbering
+                }
+                if (l >= 1) {
+                    const size_t o = c * (size_t)F.n;
+                    G.rc = F.rc + o;
+                    G.c1 = F.c1 + o;
+                    G.c2 = F.c2 + o;
+                    G.v1 = F.v1 + o;
+                }
+            }
+        }
+        hipStream_t s = stream ? (hipStream_t)stream : jobs[0].h->stream;
+        for (amg_hierarchy *h : hs) h->sync();  // each hierarchy's own work is done before the launch
+        BlockCache &bc = BlockCache::get();
+        int dev = 0;
+        AMG_HIP(hipGetDevice(&dev));
+        const size_t jb = sizeof(GroupJob) * (size_t)count, rb = sizeof(GroupResult) * (size_t)count;
+        size_t got = 0;
+        void *blk = bc.take(BlockCache::size_class(jb + rb), &got);
+        if (!blk) throw Error(AMG_ERR_OUT_OF_MEMORY, "hipMalloc");
+        struct Give {
+            BlockCache &bc;
+            void *p;
+            size_t cls;
+            int dev;
+            ~Give() { bc.give(p, cls, dev); }
+        } give{bc, blk, got, dev};
+        GroupJob *d_jobs = static_cast<GroupJob *>(blk);
+        GroupResult *d_res = reinterpret_cast<GroupResult *>(static_cast<char *>(blk) + jb);
+        std::vector<GroupResult> res((size_t)count);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        AMG_HIP(hipEventCreate(&e0));
+        AMG_HIP(hipEventCreate(&e1));
+        struct Ev {
+            hipEvent_t a, b;
+            ~Ev()
+            {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } ev{e0, e1};
+        AMG_HIP(hipMemcpyAsync(d_jobs, hj.data(), jb, hipMemcpyHostToDevice, s));
+        AMG_HIP(hipEventRecord(e0, s));
+        launch_group_solve(d_jobs, count, kcycle_only, d_res, s);
+        AMG_HIP(hipEventRecord(e1, s));
+        AMG_HIP(hipMemcpyAsync(res.data(), d_res, rb, hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipStreamSynchronize(s));
+        float ms = 0.f;
+        AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        amg_status first = AMG_OK;
+        for (int k = 0; k < count; k++) {
+            status[k] = res[(size_t)k].status;
+            if (first == AMG_OK && res[(size_t)k].status != AMG_OK) first = (amg_status)res[(size_t)k].status;
+            if (info) {
+                info[k].iterations = res[(size_t)k].iterations;
+                info[k].rel_residual = res[(size_t)k].rel_residual;
+                info[k].setup_ms = jobs[k].h->setup_ms;
+                info[k].solve_ms = ms;
+            }
+        }
+        return first;
+    });
+}
+}  // namespace
+
+extern "C" {
+
+amg_status amg_solve_group(int32_t count, const amg_group_job *jobs, double tol, void *stream, int32_t *status,
+                           amg_solve_info *info)
+{
+    return group_call(count, jobs, tol, stream, 0, status, info);
+}
+
+amg_status amg_kcycle_group(int32_t count, const amg_group_job *jobs, void *stream, int32_t *status)
+{
+    return group_call(count, jobs, 0.0, stream, 1, status, nullptr);
 }
 
 const char *amg_status_string(amg_status s)

@@ -14,13 +14,21 @@ on the device from its seed) and 1..8 right-hand sides.  The server:
   takes the waiting requests with the same key, up to ``max_rhs`` right-hand sides
   in all, and solves them as one batch (``amg_solve_batch``), so their K-cycles --
   the latency-bound coarse levels above all -- share every launch;
+* optionally (``group_n`` > 0) solves small problems -- n <= group_n, FP64 --
+  through grouped launches: a slot that takes a small request also takes the
+  waiting small requests of any problem, up to ``group_jobs`` right-hand sides,
+  and solves all of them in ONE kernel launch (``amg_solve_group``: one workgroup
+  per right-hand side runs the whole solve), so the small-level work of
+  concurrent requests shares a dispatch;
 * reports per-request latency (arrival to completion), p50/p99 and solves/s.
 
 Every kernel of a solve reads and writes only that solve's hierarchy and vectors
 and reduces in a fixed order, and every column of a batch iterates on its own
 (it stops, confirms and restarts by its own residuals), so a request's result does
 not depend on what else runs or what it was merged with: the same alone and in the
-mix (a test checks this bit for bit).
+mix (a test checks this bit for bit).  A small request takes the grouped path
+whether it is alone or not (the choice depends on its size only), and a grouped
+job's result does not depend on the other jobs of its launch.
 """
 from __future__ import annotations
 
@@ -64,6 +72,7 @@ class Result:
     rel_residuals: list
     solution: object = None  # (nrhs, n) host array when kept
     merged: int = 1          # requests solved in the same batch
+    grouped: bool = False    # solved by a grouped launch
 
 
 def make_requests(count: int = 2000, rate: float = 200.0, seed: int = 6, reuse: float = 0.3,
@@ -101,11 +110,12 @@ class Server:
 
     def __init__(self, slots: int = 4, budget: int | None = None, tol: float = 1e-8,
                  precision: int = amg.AMG_PREC_FP32_INNER, max_rhs: int = 16, keep_solutions: bool = False,
-                 skip_ratio: float = 0.0):
+                 skip_ratio: float = 0.0, group_n: int = 0, group_jobs: int = 256):
         import torch
         self.torch = torch
         self.slots, self.tol, self.precision, self.max_rhs = slots, tol, precision, max_rhs
         self.skip_ratio = skip_ratio  # level skipping of the hierarchies (Sec. 3.3); 0: the plain method
+        self.group_n, self.group_jobs = group_n, group_jobs
         self.keep = keep_solutions
         if budget is None:
             free, _ = torch.cuda.mem_get_info()
@@ -188,6 +198,32 @@ class Server:
                     return None, need
                 self.lock.wait()
 
+    def _admit_nowait(self, group):
+        """As _admit, without waiting: (hierarchy or None, reserved bytes), or False
+        when the problem's hierarchy is busy or the memory is not there now."""
+        req = group[0]
+        with self.lock:
+            entry = self.resident.get(req.key)
+            if entry is not None and entry[2]:
+                return False
+            need = sum(self.vector_bytes(q) for q in group) + \
+                (0 if entry else self.hierarchy_estimate(req, self.max_rhs))
+            if self.resident_bytes + self.inflight_bytes + need > self.budget:
+                self._evict(need)
+            self._ensure_free(need)
+            alone = self.inflight_bytes == 0 and not any(e[2] for e in self.resident.values())
+            if self.resident_bytes + self.inflight_bytes + need > self.budget and not alone:
+                return False
+            self.inflight_bytes += need
+            if entry is not None:
+                entry[2] = True
+                self.resident.move_to_end(req.key)
+                return entry[0], need
+            return None, need
+
+    def _groupable(self, req: Request) -> bool:
+        return self.group_n > 0 and req.n <= self.group_n and self.precision == amg.AMG_PREC_FP64
+
     def _release(self, req: Request, h, reserved: int, new: bool):
         """Return a request's reservation; keep its hierarchy resident (h may be None
         when the setup failed)."""
@@ -253,10 +289,91 @@ class Server:
             col += k
         return out
 
+    def _serve_small(self, group, stream, t0: float, requeue):
+        """Solve small requests (of any problems) in one grouped launch; requests
+        whose hierarchy is busy, or whose memory is not free now, go back to the
+        queue.  Returns one Result per request solved."""
+        torch = self.torch
+        t_start = time.perf_counter()
+        by_key = collections.OrderedDict()
+        for q in group:
+            by_key.setdefault(q.key, []).append(q)
+        held, deferred = [], []
+        for reqs in by_key.values():
+            got = self._admit_nowait(reqs)
+            if got is False:
+                deferred += reqs
+            else:
+                held.append([reqs, got[0], got[1], got[0] is None])
+        if deferred:
+            requeue(deferred)
+        if not held:
+            with self.lock:
+                self.lock.wait(0.01)  # a busy hierarchy or full memory: let others finish first
+            return []
+        t_admit = time.perf_counter()
+        out = []
+        try:
+            sp = stream.cuda_stream
+            with torch.cuda.stream(stream):
+                jobs, spans = [], []
+                for ent in held:
+                    reqs, h, _, new = ent
+                    req = reqs[0]
+                    if new:
+                        rp, ci, va = amg.device_grid_laplacian(req.dims, 0.1, req.jitter_seed, stream=sp)
+                        h = amg.Hierarchy(rp, ci, va, precision=self.precision, max_rhs=self.max_rhs, autotune=0,
+                                          skip_ratio=self.skip_ratio)
+                        ent[1] = h
+                        del rp, ci, va
+                    seeds = [s for q in reqs for s in q.rhs_seeds]
+                    B = torch.empty((len(seeds), req.n), dtype=torch.float64, device="cuda")
+                    for j, s in enumerate(seeds):
+                        amg.device_rhs(B[j], s, stream=sp)
+                    X = torch.zeros_like(B)
+                    spans.append((len(jobs), B, X))
+                    jobs += [(h, c, B[c], X[c]) for c in range(len(seeds))]
+                stream.synchronize()
+                st, status, infos = amg.solve_group(jobs, tol=self.tol, stream=sp, raise_on_error=False)
+                t_done = time.perf_counter()
+                for (reqs, h, _, new), (j0, B, X) in zip(held, spans):
+                    sol = X.cpu().numpy() if self.keep else None
+                    col = 0
+                    for q in reqs:
+                        k = len(q.rhs_seeds)
+                        mine, ms = infos[j0 + col:j0 + col + k], status[j0 + col:j0 + col + k]
+                        bad = [v for v in ms if v != amg.AMG_OK]
+                        out.append(Result(q.rid, bad[0] if bad else amg.AMG_OK, 1e3 * (t_done - (t0 + q.t_arrival)),
+                                          1e3 * (t_done - t_start), 1e3 * (t_admit - t_start),
+                                          mine[0].setup_ms if new else 0.0, mine[0].solve_ms,
+                                          not new or q is not reqs[0], [i.iterations for i in mine],
+                                          [i.rel_residual for i in mine],
+                                          sol[col:col + k] if sol is not None else None, len(group), True))
+                        col += k
+                del jobs, spans
+        finally:
+            for reqs, h, reserved, new in held:
+                self._release(reqs[0], h, reserved, new)
+        return out
+
     def _take(self, pending):
         """The oldest waiting request and the waiting requests for the same problem
-        that fit in one batch with it (caller holds the queue's lock)."""
+        that fit in one batch with it; for a small request (grouped path), the
+        waiting small requests of any problem, up to group_jobs right-hand sides and
+        max_rhs per problem (caller holds the queue's lock)."""
         first = pending.popleft()
+        if self._groupable(first):
+            group, cols = [first], len(first.rhs_seeds)
+            per_key = {first.key: cols}
+            for q in list(pending):
+                k = len(q.rhs_seeds)
+                if not self._groupable(q) or cols + k > self.group_jobs or per_key.get(q.key, 0) + k > self.max_rhs:
+                    continue
+                pending.remove(q)
+                group.append(q)
+                cols += k
+                per_key[q.key] = per_key.get(q.key, 0) + k
+            return group
         group, cols = [first], len(first.rhs_seeds)
         for q in list(pending):
             if q.key == first.key and cols + len(q.rhs_seeds) <= self.max_rhs:
@@ -275,6 +392,12 @@ class Server:
         results, errors = {}, []
         t0 = time.perf_counter()
 
+        def requeue(reqs):
+            with cv:
+                for q in reversed(reqs):
+                    pending.appendleft(q)
+                cv.notify_all()
+
         def worker():
             stream = torch.cuda.Stream()
             while True:
@@ -285,7 +408,9 @@ class Server:
                         return
                     group = self._take(pending)
                 try:
-                    for res in self._serve_group(group, stream, t0):
+                    served = self._serve_small(group, stream, t0, requeue) if self._groupable(group[0]) \
+                        else self._serve_group(group, stream, t0)
+                    for res in served:
                         with cv:
                             results[res.rid] = res
                             done = len(results)
@@ -324,6 +449,7 @@ class Server:
                  "service_p50_ms": pct(0.50, svc), "service_p99_ms": pct(0.99, svc),
                  "max_ms": lat[-1], "reused": sum(r.reused for r in results.values()),
                  "merged": sum(r.merged > 1 for r in results.values()),
+                 "grouped": sum(r.grouped for r in results.values()),
                  "failed": sum(r.status != amg.AMG_OK for r in results.values())}
         return results, stats
 

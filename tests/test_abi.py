@@ -81,3 +81,28 @@ def test_options_struct_matches_header():
     block = block[:block.index("} amg_options;")]
     fields = re.findall(r"\b([a-z_]+);", block)
     assert fields == [f for f, _ in amg.amg_options._fields_]
+
+
+def test_group_job_struct_matches_header():
+    from paper_1302_2547_amd import amg
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    block = text[text.index("amg_hierarchy *h;"):]
+    block = block[:block.index("} amg_group_job;")]
+    fields = re.findall(r"\b([a-z_]+);", block)
+    assert fields == [f for f, _ in amg.amg_group_job._fields_]
+    assert ctypes.sizeof(amg.amg_group_job) == 32
+
+
+def test_group_argument_errors(lib):
+    """The grouped entry points check their arguments before any device work."""
+    from paper_1302_2547_amd import amg
+    st = (ctypes.c_int32 * 2)()
+    jobs = (amg.amg_group_job * 2)()
+    assert amg.amg_solve_group(0, None, 1e-8, None, None, None) == amg.AMG_OK
+    assert amg.amg_solve_group(-1, jobs, 1e-8, None, st, None) == amg.AMG_ERR_INVALID_ARGUMENT
+    assert amg.amg_solve_group(1, None, 1e-8, None, st, None) == amg.AMG_ERR_INVALID_ARGUMENT
+    assert amg.amg_solve_group(1, jobs, 1e-8, None, None, None) == amg.AMG_ERR_INVALID_ARGUMENT
+    assert amg.amg_solve_group(1, jobs, 1e-8, None, st, None) == amg.AMG_ERR_INVALID_ARGUMENT  # h NULL
+    assert amg.amg_solve_group(1, jobs, 0.0, None, st, None) == amg.AMG_ERR_INVALID_ARGUMENT
+    assert amg.amg_kcycle_group(1, jobs, None, st) == amg.AMG_ERR_INVALID_ARGUMENT
+    assert amg.amg_kcycle_group(0, None, None, None) == amg.AMG_OK

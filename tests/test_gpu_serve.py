@@ -102,3 +102,36 @@ def test_tiny_budget_still_serves_everything(amg):
     res, stats = srv.run(reqs, realtime=False)
     srv.close()
     assert stats["failed"] == 0 and len(res) == len(reqs)
+
+
+def test_grouped_serving_same_alone_and_in_mix(amg):
+    """Small problems through grouped launches (one workgroup per right-hand side,
+    many problems per launch): every result is the same bits with one slot (one
+    big launch) and with four (other groupings), reaches the tolerance and agrees
+    with the multi-launch path; a tiny budget still serves everything."""
+    from paper_1302_2547_amd import serve
+    reqs = small_stream()
+    runs = {}
+    for slots in (1, 4):
+        srv = serve.Server(slots=slots, keep_solutions=True, precision=amg.AMG_PREC_FP64, group_n=10**6)
+        runs[slots] = srv.run(reqs, realtime=False)
+        srv.close()
+    (r1, s1), (r4, s4) = runs[1], runs[4]
+    print(f"[serve] grouped, one slot {s1}\n[serve] grouped, four slots {s4}")
+    assert s1["failed"] == 0 and s4["failed"] == 0
+    assert s1["grouped"] == len(reqs) == s4["grouped"]
+    plain = serve.Server(slots=2, keep_solutions=True, precision=amg.AMG_PREC_FP64)
+    rp_, _ = plain.run(reqs, realtime=False)
+    plain.close()
+    for rid in r1:
+        a, b, c = r1[rid], r4[rid], rp_[rid]
+        assert a.status == b.status == amg.AMG_OK
+        assert max(a.rel_residuals) <= 1e-8
+        assert a.iterations == b.iterations
+        np.testing.assert_array_equal(a.solution, b.solution)
+        for x, y in zip(a.solution, c.solution):
+            assert np.abs(x - y).max() <= 1e-5 * np.abs(y).max()
+    srv = serve.Server(slots=3, budget=1 << 20, precision=amg.AMG_PREC_FP64, group_n=10**6)
+    res, stats = srv.run(small_stream(8), realtime=False)
+    srv.close()
+    assert stats["failed"] == 0 and len(res) == 8 and stats["grouped"] == 8

@@ -23,3 +23,29 @@ def test_stream_is_deterministic_and_shaped():
         assert lo / 2 <= r.n <= hi * 1.5
         assert len(set(r.dims)) == 1
     assert abs(sum(len(r.dims) == 2 for r in a) / len(a) - 0.5) < 0.15
+
+
+def test_take_groups_small_requests_of_any_problem():
+    """A slot that takes a small request also takes the waiting small requests of
+    other problems (up to group_jobs right-hand sides, max_rhs per problem); a
+    large request takes only waiting requests for its own problem."""
+    import collections
+
+    from paper_1302_2547_amd import amg
+    srv = serve.Server(budget=1 << 30, precision=amg.AMG_PREC_FP64, max_rhs=4, group_n=50000, group_jobs=10)
+    R = serve.Request
+    small_a = [R(0, 0.0, (100, 100), 1, (1, 2)), R(1, 0.0, (100, 100), 1, (3, 4)), R(2, 0.0, (100, 100), 1, (5,))]
+    small_b = [R(3, 0.0, (30, 30, 30), 2, (6, 7, 8))]
+    big = [R(4, 0.0, (1000, 1000), 3, (9,)), R(5, 0.0, (1000, 1000), 3, (10, 11))]
+    small_c = [R(6, 0.0, (150, 150), 4, (12, 13, 14, 15))]
+    pending = collections.deque(small_a + big[:1] + small_b + big[1:] + small_c)
+    g = srv._take(pending)
+    # a's first two fill its 4 columns; b's 3 columns; c's 4 would pass 10 in all
+    assert [q.rid for q in g] == [0, 1, 3]
+    assert [q.rid for q in pending] == [2, 4, 5, 6]
+    pending.rotate(-1)  # the large request first
+    g = srv._take(pending)
+    assert [q.rid for q in g] == [4, 5]
+    assert [q.rid for q in pending] == [6, 2]
+    off = serve.Server(budget=1 << 30, precision=amg.AMG_PREC_FP64, max_rhs=4)  # group_n 0: no grouping
+    assert [q.rid for q in off._take(collections.deque(small_a + small_b))] == [0, 1]
