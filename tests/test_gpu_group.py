@@ -1,8 +1,9 @@
 """GPU: grouped solves (amg_solve_group / amg_kcycle_group) against the oracle.
 
 One launch carries jobs on different hierarchies (grids, random graphs, a hub row,
-and the K-cycle variants: threshold, one inner step, damped Jacobi, level
-skipping, a single coarse unknown); each job's K-cycle must match the oracle's
+the K-cycle variants: threshold, one inner step, damped Jacobi, level skipping, a
+single coarse unknown, and a finest level of more than 100k rows); each job's
+K-cycle must match the oracle's
 element by element and each solve must reach the tolerance with the oracle's
 iteration count (+-1).  A job gives the same bits alone and in any group.
 """
@@ -47,6 +48,9 @@ CASES = {
     "grid2d_64_single": (lambda: inputs.grid_laplacian((64, 64)), {"coarsest_size": 1}),
     "grid2d_256": (lambda: inputs.grid_laplacian((256, 256), jitter=0.1, seed=11), {}),
     "grid3d_40": (lambda: inputs.grid_laplacian((40, 40, 40), jitter=0.1, seed=12), {}),
+    # a finest level of more than 100k rows: it also holds a sliced copy, and its
+    # entries have no per-entry coarse index (the group path reads the CSR arrays)
+    "grid3d_50": (lambda: inputs.grid_laplacian((50, 50, 50), jitter=0.1, seed=13), {}),
 }
 
 ORACLE_KEYS = ("coarsest_size", "kcycle_inner", "kcycle_threshold", "skip_ratio", "jacobi_weight")
