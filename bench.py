@@ -32,9 +32,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["grid", "rgg", "serve"], default="grid",
+    ap.add_argument("--workload", choices=["grid", "rgg", "serve", "group"], default="grid",
                     help="grid: 3D 7-point Laplacian (the headline); rgg: 2D random geometric graph Laplacian; "
-                         "serve: a stream of solve requests served with continuous batching")
+                         "serve: a stream of solve requests served with continuous batching; group: many small "
+                         "solves on one stream, on four threads and in one grouped launch")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests in the stream")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second (Poisson)")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent requests on the GPU")
@@ -349,6 +350,80 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def group_bench(args):
+    """Many small solves three ways, per size class: 64 problems (2D or 3D grid
+    Laplacians, n log-uniform in the class, 4 right-hand sides each) solved batch by
+    batch on one stream, on four host threads (as four serving slots), and all 256
+    right-hand sides in one grouped launch (amg_solve_group).  One JSON line."""
+    import math
+    import threading
+
+    import torch
+
+    from paper_1302_2547_amd import amg, inputs
+    classes = [(500, 2000), (2000, 8000), (8000, 32000), (32000, 128000)]
+    rows = []
+    for lo, hi in classes:
+        hs = []
+        for k in range(64):
+            u = inputs.uniform(91, [4 * k + j for j in range(4)])
+            d = 2 if u[0] < 0.5 else 3
+            n = math.exp(math.log(lo) + u[1] * (math.log(hi) - math.log(lo)))
+            dims = (max(2, int(round(n ** (1.0 / d)))),) * d
+            rp, ci, va = amg.device_grid_laplacian(dims, 0.1, 2000 + k)
+            h = amg.Hierarchy(rp, ci, va, max_rhs=4, autotune=0)
+            B = torch.empty((4, math.prod(dims)), dtype=torch.float64, device="cuda")
+            for j in range(4):
+                amg.device_rhs(B[j], 100 * (2000 + k) + j)
+            hs.append((h, B))
+        torch.cuda.synchronize()
+
+        def batches(part):
+            for h, B in part:
+                st, _ = h.solve_batch(B, torch.zeros_like(B), tol=args.tol)
+                assert st == amg.AMG_OK
+
+        batches(hs)  # first solves: graph capture
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        batches(hs)
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - t
+        threads = [threading.Thread(target=batches, args=(hs[i::4],)) for i in range(4)]
+        t = time.perf_counter()
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        torch.cuda.synchronize()
+        par = time.perf_counter() - t
+        jobs = [(h, c, B[c], torch.zeros(B.shape[1], dtype=torch.float64, device="cuda"))
+                for h, B in hs for c in range(4)]
+        amg.solve_group(jobs, tol=args.tol)
+        for j in jobs:
+            j[3].zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, status, infos = amg.solve_group(jobs, tol=args.tol)
+        grp = time.perf_counter() - t
+        assert st == amg.AMG_OK and max(i.rel_residual for i in infos) <= args.tol
+        rows.append({"n_range": [lo, hi], "rhs": len(jobs), "one_stream_ms": round(1e3 * seq, 1),
+                     "four_threads_ms": round(1e3 * par, 1), "grouped_launch_ms": round(1e3 * grp, 1)})
+        print(f"[bench] n in [{lo}, {hi}]: one stream {1e3 * seq:.0f} ms, four threads {1e3 * par:.0f} ms, "
+              f"one grouped launch {1e3 * grp:.0f} ms", file=sys.stderr, flush=True)
+        for h, _ in hs:
+            h.close()
+    best = rows[0]
+    out = {"metric": "ms to solve 64 small problems x 4 right-hand sides (tol %g)" % args.tol,
+           "value": best["grouped_launch_ms"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "64 grid Laplacians (2D or 3D, weights 1+0.1U[-1,1], n log-uniform per class), 4 "
+                                  "right-hand sides each: batch by batch on one stream, on four threads, and in one "
+                                  "grouped launch (one workgroup per right-hand side)"},
+           "classes": rows, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_probe:
@@ -365,6 +440,8 @@ def main():
         sys.exit(2)
     if args.workload == "serve":
         return serve_bench(args)
+    if args.workload == "group":
+        return group_bench(args)
     import numpy as np
     import torch
 
