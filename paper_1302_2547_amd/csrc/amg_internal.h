@@ -371,6 +371,15 @@ struct GroupLevel {
     const int *seg;   // rows of coarse position c: positions seg[c] .. seg[c+1]-1
     const int *srp;   // entries of those rows: srp[c] .. srp[c+1]-1 (NULL: from rp and seg)
     const int *perm;  // position -> row (NULL: the identity)
+    // hub rows (more than lim entries) of A, summed by the whole workgroup: hub row k
+    // is chunks[long_first[k]].row (the level's Rows lists); the same for the
+    // aggregates' entry ranges (srp) of the restriction
+    int lim, nlong;
+    const int *long_first;
+    const Chunk *chunks;
+    int slim, snlong;
+    const int *slong_first;
+    const Chunk *schunks;
     // this job's work vectors (levels >= 1): restricted residual, the two inner
     // preconditioned directions, A c1
     double *rc, *c1, *c2, *v1;

@@ -1919,6 +1919,15 @@ amg_status group_call(int32_t count, const amg_group_job *jobs, double tol, void
                 G.ci = F.ci;
                 G.va = F.va;
                 G.minv = F.minv;
+                G.lim = F.A.nlong > 0 ? F.A.lim : INT_MAX;
+                G.nlong = F.A.nlong;
+                G.long_first = F.A.long_first;
+                G.chunks = F.A.chunks;
+                const bool super_rows = l >= 1 && F.srp != nullptr && F.S.nlong > 0;
+                G.slim = super_rows ? F.S.lim : INT_MAX;
+                G.snlong = super_rows ? F.S.nlong : 0;
+                G.slong_first = super_rows ? F.S.long_first : nullptr;
+                G.schunks = super_rows ? F.S.chunks : nullptr;
                 if (l < L) {
                     G.agg = F.agg_pos;
                     G.cagg = F.cagg;

@@ -115,12 +115,15 @@ __device__ __forceinline__ void block_sum(double (&v)[ND], Red &red)
 // row data pre(i) is loaded with the row pointers, before the entries; rows past
 // n are clamped to row n - 1 (and get no entries) so that every load is valid.
 template <class EntryF, class PreF, class RowF>
-__device__ __forceinline__ void sweep(int n, const int *rp, const int *ci, int G, EntryF entry, PreF pre, RowF fin)
+__device__ __forceinline__ void sweep(const GroupLevel &F, Red &red, EntryF entry, PreF pre, RowF fin)
 {
     using P = decltype(pre(0));
+    const int n = F.n, G = F.G, lim = F.lim;
+    const int *rp = F.rp, *ci = F.ci;
     const int g = threadIdx.x & (G - 1), slot = threadIdx.x / G, step = kGB / G;
     for (int i0 = 0; i0 < n; i0 += kRows * step) {
         int e[kRows], end[kRows];
+        bool own[kRows];  // a row of this lane group (not a hub row, which the block sums below)
         double s[kRows];
         P pd[kRows];
 #pragma unroll
@@ -128,8 +131,9 @@ __device__ __forceinline__ void sweep(int n, const int *rp, const int *ci, int G
             const int raw = i0 + r * step + slot, i = min(raw, n - 1);
             const int b = rp[i], t = rp[i + 1];
             pd[r] = pre(i);
+            own[r] = raw < n && t - b <= lim;
             e[r] = b + g;
-            end[r] = raw < n ? t : 0;
+            end[r] = own[r] ? t : 0;
             s[r] = 0.0;
         }
         for (;;) {
@@ -149,8 +153,16 @@ __device__ __forceinline__ void sweep(int n, const int *rp, const int *ci, int G
         for (int r = 0; r < kRows; r++) {
             const double t = lanes_sum(s[r], G);
             const int raw = i0 + r * step + slot;
-            fin(min(raw, n - 1), t, raw < n && g == 0, pd[r]);
+            fin(min(raw, n - 1), t, own[r] && g == 0, pd[r]);
         }
+    }
+    // hub rows: every thread takes a share of the entries, then one block sum
+    for (int k = 0; k < F.nlong; k++) {
+        const int i = F.chunks[F.long_first[k]].row;
+        double v[1] = {0.0};
+        for (int p = rp[i] + (int)threadIdx.x; p < rp[i + 1]; p += kGB) v[0] += entry(p, ci[p]);
+        block_sum(v, red);
+        if (threadIdx.x == 0) fin(i, v[0], true, pre(i));
     }
 }
 
@@ -174,7 +186,7 @@ __device__ __forceinline__ void residual(const GroupLevel &F, const double *b, c
 {
     d[0] = d[1] = 0.0;
     sweep(
-        F.n, F.rp, F.ci, F.G, [&](int e, int j) { return F.va[e] * x[j]; }, [&](int i) { return b[i]; },
+        F, red, [&](int e, int j) { return F.va[e] * x[j]; }, [&](int i) { return b[i]; },
         [&](int i, double s, bool ok, double bi) {
             const double yi = bi - s;
             if (ok) y[i] = yi;
@@ -196,8 +208,7 @@ __device__ __forceinline__ double restrict_residual(const GroupLevel &F, const G
     double d[1] = {0.0};
     if (F.perm) {
         sweep(
-            F.n, F.rp, F.ci, F.G, [&](int e, int j) { return F.va[e] * (F.minv[j] * in(j)); },
-            [&](int i) { return in(i); },
+            F, red, [&](int e, int j) { return F.va[e] * (F.minv[j] * in(j)); }, [&](int i) { return in(i); },
             [&](int i, double s, bool ok, double ii) {
                 if (ok) tmp[i] = ii - s;
             });
@@ -237,17 +248,18 @@ __device__ __forceinline__ double restrict_residual(const GroupLevel &F, const G
     } else {
         for (int c0 = 0; c0 < nc; c0 += kRows * step) {
             int k[kRows], kend[kRows], e[kRows], eend[kRows];
+            bool own[kRows];  // an aggregate of this lane group (not a hub, which the block sums below)
             double s[kRows];
 #pragma unroll
             for (int r = 0; r < kRows; r++) {
                 const int raw = c0 + r * step + slot, c = min(raw, nc - 1);
-                const bool ok = raw < nc;
                 const int k0 = F.seg[c], k1 = F.seg[c + 1];
                 const int e0 = F.srp ? F.srp[c] : F.rp[k0], e1 = F.srp ? F.srp[c + 1] : F.rp[k1];
+                own[r] = raw < nc && e1 - e0 <= F.slim;
                 k[r] = k0 + g;
-                kend[r] = ok ? k1 : 0;
+                kend[r] = own[r] ? k1 : 0;
                 e[r] = e0 + g;
-                eend[r] = ok ? e1 : 0;
+                eend[r] = own[r] ? e1 : 0;
                 s[r] = 0.0;
             }
             for (;;) {
@@ -272,8 +284,23 @@ __device__ __forceinline__ double restrict_residual(const GroupLevel &F, const G
             for (int r = 0; r < kRows; r++) {
                 const double t = lanes_sum(s[r], G);
                 const int raw = c0 + r * step + slot;
-                if (raw < nc && g == 0) C.rc[raw] = t;
-                d[0] += raw < nc && g == 0 ? t * t : 0.0;
+                if (own[r] && g == 0) C.rc[raw] = t;
+                d[0] += own[r] && g == 0 ? t * t : 0.0;
+            }
+        }
+        // hub aggregates (more than slim entries): every thread takes a share
+        for (int h = 0; h < F.snlong; h++) {
+            const int c = F.schunks[F.slong_first[h]].row;
+            double v[1] = {0.0};
+            for (int q = F.seg[c] + (int)threadIdx.x; q < F.seg[c + 1]; q += kGB) v[0] += in(q);
+            for (int p = F.srp[c] + (int)threadIdx.x; p < F.srp[c + 1]; p += kGB) {
+                const int j = F.ci[p];
+                v[0] -= F.va[p] * (F.minv[j] * in(j));
+            }
+            block_sum(v, red);
+            if (threadIdx.x == 0) {
+                C.rc[c] = v[0];
+                d[0] += v[0] * v[0];
             }
         }
     }
@@ -322,11 +349,9 @@ __device__ __forceinline__ double post_smooth(const GroupLevel &F, const GroupLe
         if (q) d[0] += ok ? o * q[i] : 0.0;
     };
     if (F.cagg)
-        sweep(F.n, F.rp, F.ci, F.G, [&](int e, int j) { return F.va[e] * (F.minv[j] * in(j) + corr(F.cagg[e])); },
-              pre, fin);
+        sweep(F, red, [&](int e, int j) { return F.va[e] * (F.minv[j] * in(j) + corr(F.cagg[e])); }, pre, fin);
     else
-        sweep(F.n, F.rp, F.ci, F.G, [&](int e, int j) { return F.va[e] * (F.minv[j] * in(j) + corr(F.agg[j])); },
-              pre, fin);
+        sweep(F, red, [&](int e, int j) { return F.va[e] * (F.minv[j] * in(j) + corr(F.agg[j])); }, pre, fin);
     if (q) {
         block_sum(d, red);
         return d[0];
@@ -347,7 +372,7 @@ __device__ __forceinline__ void product_dots(const GroupLevel &F, const double *
 #pragma unroll
     for (int k = 0; k < ND; k++) d[k] = 0.0;
     sweep(
-        F.n, F.rp, F.ci, F.G, [&](int e, int j) { return F.va[e] * x[j]; },
+        F, red, [&](int e, int j) { return F.va[e] * x[j]; },
         [&](int i) { return DotRow{x[i], u[i], ND > 2 ? w[i] : 0.0}; },
         [&](int i, double s, bool ok, const DotRow &v) {
             if (y && ok) y[i] = s;
