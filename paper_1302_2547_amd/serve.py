@@ -33,6 +33,7 @@ job's result does not depend on the other jobs of its launch.
 from __future__ import annotations
 
 import collections
+import concurrent.futures
 import math
 import threading
 import time
@@ -315,17 +316,29 @@ class Server:
         out = []
         try:
             sp = stream.cuda_stream
+
+            def build(ent):  # a new problem's matrix and hierarchy, on a stream of its own
+                req = ent[0][0]
+                st = torch.cuda.Stream()
+                with torch.cuda.stream(st):
+                    rp, ci, va = amg.device_grid_laplacian(req.dims, 0.1, req.jitter_seed, stream=st.cuda_stream)
+                    ent[1] = amg.Hierarchy(rp, ci, va, precision=self.precision, max_rhs=self.max_rhs, autotune=0,
+                                           skip_ratio=self.skip_ratio)
+                st.synchronize()
+
+            # the setups of the group's new problems run side by side (host threads; the
+            # library's calls release the interpreter while they wait on the device)
+            fresh = [ent for ent in held if ent[3]]
+            if len(fresh) > 1:
+                with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(fresh))) as pool:
+                    list(pool.map(build, fresh))
+            elif fresh:
+                build(fresh[0])
             with torch.cuda.stream(stream):
                 jobs, spans = [], []
                 for ent in held:
                     reqs, h, _, new = ent
                     req = reqs[0]
-                    if new:
-                        rp, ci, va = amg.device_grid_laplacian(req.dims, 0.1, req.jitter_seed, stream=sp)
-                        h = amg.Hierarchy(rp, ci, va, precision=self.precision, max_rhs=self.max_rhs, autotune=0,
-                                          skip_ratio=self.skip_ratio)
-                        ent[1] = h
-                        del rp, ci, va
                     seeds = [s for q in reqs for s in q.rhs_seeds]
                     B = torch.empty((len(seeds), req.n), dtype=torch.float64, device="cuda")
                     for j, s in enumerate(seeds):
