@@ -23,6 +23,9 @@
 #include "amg_internal.h"
 
 #include <algorithm>
+#include <climits>
+#include <functional>
+#include <vector>
 
 namespace amg {
 namespace {
@@ -611,6 +614,9 @@ __device__ void tile_steps(uint64_t *t, int64_t base, int64_t size, int stride0,
     }
 }
 
+// phase 0: gather every row's pairs; rows of fewer than split_min padded keys are
+// then sorted and summed here (one block), the others only gathered.  phase 1:
+// the sums of those other rows, whose keys the whole-chip passes below sorted.
 __global__ void __launch_bounds__(kBigThreads) k_coarse_big_rows(const int *__restrict__ big_rows,
                                                                  const int64_t *__restrict__ scratch_off,
                                                                  uint64_t *skey, const int *__restrict__ rp,
@@ -620,7 +626,8 @@ __global__ void __launch_bounds__(kBigThreads) k_coarse_big_rows(const int *__re
                                                                  const int *__restrict__ aptr,
                                                                  const int *__restrict__ members,
                                                                  const int *__restrict__ tptr, int *__restrict__ tcol,
-                                                                 double *__restrict__ tval, int *__restrict__ cnt)
+                                                                 double *__restrict__ tval, int *__restrict__ cnt,
+                                                                 int phase, int64_t split_min)
 {
     __shared__ uint64_t tile[kTile];
     __shared__ int mbeg[kBigThreads], mexcl[kBigThreads];
@@ -632,6 +639,11 @@ __global__ void __launch_bounds__(kBigThreads) k_coarse_big_rows(const int *__re
     const int base = tptr[I];
     const int pc = tptr[I + 1] - base;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int64_t P = 1;
+    while (P < pc) P <<= 1;
+    const bool split = P >= split_min;
+    if (phase == 1 && !split) return;
+    if (phase == 0) {
     // gather: up to kBigThreads members at a time, block-wide prefix of row lengths
     int fill = 0;
     const int me = aptr[I + 1];
@@ -675,10 +687,9 @@ __global__ void __launch_bounds__(kBigThreads) k_coarse_big_rows(const int *__re
         fill += tot;
         __syncthreads();
     }
-    int64_t P = 1;
-    while (P < pc) P <<= 1;
     for (int64_t k = pc + threadIdx.x; k < P; k += kBigThreads) key[k] = ~0ull;
     __syncthreads();
+    if (split) return;  // sorted by the whole-chip passes, summed in phase 1
     const int tl = P < kTile ? (int)P : kTile;
     // 1) sort every tile completely (bitonic sizes up to the tile length)
     for (int64_t t0 = 0; t0 < P; t0 += tl) {
@@ -712,6 +723,7 @@ __global__ void __launch_bounds__(kBigThreads) k_coarse_big_rows(const int *__re
             __syncthreads();
         }
     }
+    }  // phase 0
     // 3) values in sorted order, head positions, then every segment of equal J
     //    summed in position order over a contiguous range
     double *sv = reinterpret_cast<double *>(skey + 2 * scratch_off[gridDim.x]) + scratch_off[blockIdx.x];
@@ -748,6 +760,64 @@ __global__ void __launch_bounds__(kBigThreads) k_coarse_big_rows(const int *__re
         tval[base + k] = s;
     }
     if (threadIdx.x == 0) cnt[I] = u;
+}
+
+// The sort of the longest big rows as passes over the whole chip (the keys are
+// unique, so any correct sort gives the one order the block sort gives): every
+// tile of kTile keys sorted in LDS by one block, then for every bitonic size above
+// kTile the strides of at least kTile as global compare-exchange passes and the
+// shorter ones again inside the tiles.
+constexpr int64_t kSplitMin = int64_t(1) << 17;
+constexpr int kSplitRows = 32;
+struct SplitRows {
+    int n;
+    int64_t off[kSplitRows];         // first key of the row in the scratch
+    int64_t P[kSplitRows];           // padded key count (a power of two >= kSplitMin)
+    int64_t tile0[kSplitRows + 1];   // prefix of P / kTile
+    int64_t pair0[kSplitRows + 1];   // prefix of P / 2
+};
+
+// size 0: sort every tile completely; size > kTile: the strides below kTile of that
+// bitonic size, in the tiles of rows of at least size keys
+__global__ void __launch_bounds__(kBigThreads) k_big_tile_sort(SplitRows S, uint64_t *skey, int64_t size)
+{
+    __shared__ uint64_t tile[kTile];
+    const int64_t b = blockIdx.x;
+    int r = 0;
+    while (r + 1 < S.n && S.tile0[r + 1] <= b) r++;
+    if (size > S.P[r]) return;
+    const int64_t t0 = (b - S.tile0[r]) * kTile;
+    uint64_t *key = skey + S.off[r];
+    for (int k = threadIdx.x; k < kTile; k += kBigThreads) tile[k] = key[t0 + k];
+    __syncthreads();
+    if (size == 0) {
+        for (int sz = 2; sz <= kTile; sz <<= 1) tile_steps(tile, t0, sz, sz >> 1, kTile);
+    } else {
+        tile_steps(tile, t0, size, kTile / 2, kTile);
+    }
+    for (int k = threadIdx.x; k < kTile; k += kBigThreads) key[t0 + k] = tile[k];
+}
+
+// one compare-exchange stride of a bitonic size, over every row of at least size keys
+__global__ void __launch_bounds__(kBlock) k_big_global_pass(SplitRows S, uint64_t *skey, int64_t size,
+                                                            int64_t stride)
+{
+    const int64_t items = S.pair0[S.n];
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < items; g += (int64_t)gridDim.x * kBlock) {
+        int r = 0;
+        while (r + 1 < S.n && S.pair0[r + 1] <= g) r++;
+        if (size > S.P[r]) continue;
+        const int64_t u = g - S.pair0[r];
+        const int64_t lo = 2 * stride * (u / stride) + (u % stride);
+        const int64_t hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        uint64_t *key = skey + S.off[r];
+        const uint64_t a = key[lo], c = key[hi];
+        if ((a > c) == up) {
+            key[lo] = c;
+            key[hi] = a;
+        }
+    }
 }
 
 // Big rows on coarse levels small enough for a dense accumulator in LDS: one
@@ -1310,8 +1380,48 @@ void launch_coarse_big_rows(int nbig, const int *big_rows, const int64_t *scratc
                             const int *members, const int *tptr, int *tcol, double *tval, int *cnt, hipStream_t s)
 {
     if (nbig <= 0) return;
+    // rows of at least kSplitMin padded keys (at most kSplitRows of them, the longest;
+    // the threshold is raised otherwise) are sorted by whole-chip passes
+    std::vector<int64_t> off(nbig + 1);
+    AMG_HIP(hipMemcpyAsync(off.data(), scratch_off, sizeof(int64_t) * (nbig + 1), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> lens;
+    for (int k = 0; k < nbig; k++) lens.push_back(off[k + 1] - off[k]);
+    std::vector<int64_t> sorted_lens = lens;
+    std::sort(sorted_lens.begin(), sorted_lens.end(), std::greater<int64_t>());
+    int64_t split_min = kSplitMin;
+    if ((int)sorted_lens.size() > kSplitRows && sorted_lens[kSplitRows] >= split_min)
+        split_min = sorted_lens[kSplitRows] * 2;  // powers of two: only lengths above the 33rd
+    SplitRows S{};
+    int64_t pmax = 0;
+    for (int k = 0; k < nbig && S.n < kSplitRows; k++) {
+        if (lens[k] < split_min) continue;
+        S.off[S.n] = off[k];
+        S.P[S.n] = lens[k];
+        S.tile0[S.n + 1] = S.tile0[S.n] + lens[k] / kTile;
+        S.pair0[S.n + 1] = S.pair0[S.n] + lens[k] / 2;
+        pmax = std::max(pmax, lens[k]);
+        S.n++;
+    }
+    if (S.n == 0) split_min = INT64_MAX;
     k_coarse_big_rows<<<nbig, kBigThreads, 0, s>>>(big_rows, scratch_off, skey, rp, ci, va, agg, aptr, members, tptr,
-                                                   tcol, tval, cnt);
+                                                   tcol, tval, cnt, 0, split_min);
+    AMG_HIP(hipGetLastError());
+    if (S.n == 0) return;
+    const int64_t tiles = S.tile0[S.n], pairs = S.pair0[S.n];
+    const int gp = (int)std::min<int64_t>((pairs + kBlock - 1) / kBlock, 1 << 16);
+    k_big_tile_sort<<<(unsigned)tiles, kBigThreads, 0, s>>>(S, skey, 0);
+    AMG_HIP(hipGetLastError());
+    for (int64_t size = 2 * (int64_t)kTile; size <= pmax; size <<= 1) {
+        for (int64_t stride = size >> 1; stride >= kTile; stride >>= 1) {
+            k_big_global_pass<<<gp, kBlock, 0, s>>>(S, skey, size, stride);
+            AMG_HIP(hipGetLastError());
+        }
+        k_big_tile_sort<<<(unsigned)tiles, kBigThreads, 0, s>>>(S, skey, size);
+        AMG_HIP(hipGetLastError());
+    }
+    k_coarse_big_rows<<<nbig, kBigThreads, 0, s>>>(big_rows, scratch_off, skey, rp, ci, va, agg, aptr, members, tptr,
+                                                   tcol, tval, cnt, 1, split_min);
     AMG_HIP(hipGetLastError());
 }
 
