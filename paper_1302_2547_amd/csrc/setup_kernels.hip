@@ -755,7 +755,15 @@ __global__ void __launch_bounds__(kBigThreads) k_coarse_big_rows(const int *__re
     for (int k = threadIdx.x; k < u; k += kBigThreads) {
         const int q = hp[k], qe = hp[k + 1];
         double s = 0.0;
-        for (int r = q; r < qe; r++) s += sv[r];
+        int r = q;
+        for (; r + 16 <= qe; r += 16) {  // loads in flight together, adds in order
+            double v[16];
+#pragma unroll
+            for (int j = 0; j < 16; j++) v[j] = sv[r + j];
+#pragma unroll
+            for (int j = 0; j < 16; j++) s += v[j];
+        }
+        for (; r < qe; r++) s += sv[r];
         tcol[base + k] = (int)(uint32_t)(key[q] >> 32);
         tval[base + k] = s;
     }
