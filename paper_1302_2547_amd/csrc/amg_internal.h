@@ -139,6 +139,8 @@ void launch_coarse_rows(int nc, const int *rp, const int *ci, const double *va, 
                         const int *members, const int *tptr, int *tcol, double *tval, int *cnt, int *big_rows,
                         unsigned *big_count, hipStream_t s);
 int coarse_wave_capacity();
+// true when the environment sets AMG_TRACE=1 (stage trace on stderr)
+bool trace_on();
 // Largest coarse level size whose dense accumulator fits in LDS beside the big-row
 // kernel's other shared arrays; rows of such levels need no global scratch.
 int coarse_acc_capacity();

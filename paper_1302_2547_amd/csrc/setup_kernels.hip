@@ -24,6 +24,8 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <functional>
 #include <vector>
 
@@ -1398,6 +1400,12 @@ void launch_coarse_big_rows(int nbig, const int *big_rows, const int64_t *scratc
     std::vector<int64_t> sorted_lens = lens;
     std::sort(sorted_lens.begin(), sorted_lens.end(), std::greater<int64_t>());
     int64_t split_min = kSplitMin;
+    // AMG_SPLIT_MIN_KEYS (a power of two >= kTile) lowers the threshold, so that the
+    // whole-chip passes can be checked on rows of moderate problems
+    if (const char *e = std::getenv("AMG_SPLIT_MIN_KEYS")) {
+        const long long v = std::atoll(e);
+        if (v >= kTile && (v & (v - 1)) == 0) split_min = v;
+    }
     if ((int)sorted_lens.size() > kSplitRows && sorted_lens[kSplitRows] >= split_min)
         split_min = sorted_lens[kSplitRows] * 2;  // powers of two: only lengths above the 33rd
     SplitRows S{};
@@ -1411,6 +1419,9 @@ void launch_coarse_big_rows(int nbig, const int *big_rows, const int64_t *scratc
         pmax = std::max(pmax, lens[k]);
         S.n++;
     }
+    if (trace_on())
+        std::fprintf(stderr, "[amg] coarse big rows: %d, %d of them (at least %lld keys) by whole-chip passes\n", nbig,
+                     S.n, (long long)split_min);
     if (S.n == 0) split_min = INT64_MAX;
     k_coarse_big_rows<<<nbig, kBigThreads, 0, s>>>(big_rows, scratch_off, skey, rp, ci, va, agg, aptr, members, tptr,
                                                    tcol, tval, cnt, 0, split_min);
