@@ -978,7 +978,7 @@ __global__ void __launch_bounds__(kBigThreads) k_coarse_big_rows_acc(const int *
             on = (uint64_t)__double_as_longlong(a) != kUntouched;
         }
         const uint64_t hm = __ballot(on);
-        __syncthreads();  // sh_out / sh_count of the previous round are read
+        __syncthreads();  // sh_out / sh_count of the previous iteration are read
         if (lane == 0) sh_count[w] = __popcll(hm);
         __syncthreads();
         int ob = sh_out, tot = 0;
