@@ -451,32 +451,60 @@ __global__ void __launch_bounds__(kBlock) k_member_fill(int nc, const int *__res
 // are the unions of the first aggregation's groups over each group J of the second.
 // Their members are listed group after group, in the second aggregation's member
 // order (any order inside an aggregate serves the solve layout).
+//
+// One wavefront per aggregate J of the second aggregation; lane j takes its middle
+// aggregate members2[k0 + j] (64 at a time, k0 = aptr2[J], aptr2[J] + 64, ...).
 __global__ void __launch_bounds__(kBlock) k_compose_sizes(int nc2, const int *__restrict__ aptr2,
                                                           const int *__restrict__ members2,
                                                           const int *__restrict__ aptr1, int *__restrict__ size)
 {
-    const int J = blockIdx.x * kBlock + threadIdx.x;
-    if (J >= nc2) return;
-    int s = 0;
-    for (int k = aptr2[J]; k < aptr2[J + 1]; k++) {
-        const int I = members2[k];
-        s += aptr1[I + 1] - aptr1[I];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t J = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave; J < nc2; J += waves) {
+        int s = 0;
+        const int ke = aptr2[J + 1];
+        for (int k = aptr2[J] + lane; k < ke; k += kWave) {
+            const int I = members2[k];
+            s += aptr1[I + 1] - aptr1[I];
+        }
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+        if (lane == 0) size[J] = s;
     }
-    size[J] = s;
 }
 
+// The fine members of J: those of its middle aggregates in their order, each one's in
+// its own order; a lane copies the members of its middle aggregate at the offset the
+// wavefront's prefix of their sizes gives.
 __global__ void __launch_bounds__(kBlock) k_compose_members(int nc2, const int *__restrict__ aptr2,
                                                             const int *__restrict__ members2,
                                                             const int *__restrict__ aptr1,
                                                             const int *__restrict__ members1,
                                                             const int *__restrict__ aptr, int *__restrict__ members)
 {
-    const int J = blockIdx.x * kBlock + threadIdx.x;
-    if (J >= nc2) return;
-    int q = aptr[J];
-    for (int k = aptr2[J]; k < aptr2[J + 1]; k++) {
-        const int I = members2[k];
-        for (int m = aptr1[I]; m < aptr1[I + 1]; m++) members[q++] = members1[m];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t J = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave; J < nc2; J += waves) {
+        int q = aptr[J];
+        const int ke = aptr2[J + 1];
+        for (int k0 = aptr2[J]; k0 < ke; k0 += kWave) {
+            const int k = k0 + lane;
+            int b = 0, len = 0;
+            if (k < ke) {
+                const int I = members2[k];
+                b = aptr1[I];
+                len = aptr1[I + 1] - b;
+            }
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int y = __shfl_up(incl, o, kWave);
+                if (lane >= o) incl += y;
+            }
+            const int at = q + incl - len;
+            for (int t = 0; t < len; t++) members[at + t] = members1[b + t];
+            q += __shfl(incl, kWave - 1, kWave);
+        }
     }
 }
 
@@ -1352,14 +1380,15 @@ void launch_member_counts(int nc, const int *rp, const int *ci, const int *owner
 
 void launch_compose_sizes(int nc2, const int *aptr2, const int *members2, const int *aptr1, int *size, hipStream_t s)
 {
-    k_compose_sizes<<<grid_for(nc2), kBlock, 0, s>>>(nc2, aptr2, members2, aptr1, size);
+    k_compose_sizes<<<grid_for((int64_t)nc2 * kWave), kBlock, 0, s>>>(nc2, aptr2, members2, aptr1, size);
     AMG_HIP(hipGetLastError());
 }
 
 void launch_compose_members(int nc2, const int *aptr2, const int *members2, const int *aptr1, const int *members1,
                             const int *aptr, int *members, hipStream_t s)
 {
-    k_compose_members<<<grid_for(nc2), kBlock, 0, s>>>(nc2, aptr2, members2, aptr1, members1, aptr, members);
+    k_compose_members<<<grid_for((int64_t)nc2 * kWave), kBlock, 0, s>>>(nc2, aptr2, members2, aptr1, members1, aptr,
+                                                                      members);
     AMG_HIP(hipGetLastError());
 }
 

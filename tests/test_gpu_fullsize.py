@@ -79,3 +79,24 @@ def test_grid_128cubed_kcycle(amg):
 def test_rgg_1m(amg):
     rp, ci, va = inputs.rgg_laplacian(1_000_000, mean_degree=8.0, seed=3)
     run_case(amg, rp, ci, va, inputs.rhs(len(rp) - 1, 1))
+
+
+def test_grid_128cubed_level_skipping(amg):
+    """The level-skipping configuration of the benchmark (coarsening ratio 2, Sec. 3.3)
+    at full size: the composed aggregations and the coarse values of the 128^3
+    hierarchy equal the oracle's bit for bit."""
+    rp, ci, va = inputs.grid_laplacian((128, 128, 128), jitter=0.1, seed=2)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    print("[fullsize] 128^3 level skipping", flush=True)
+    h = amg.Hierarchy(d(rp), d(ci), d(va), skip_ratio=2.0)
+    ref = oracle.Hierarchy(rp, ci, va, skip_ratio=2.0)
+    assert h.num_levels == ref.num_levels == 7
+    for l in range(h.num_levels):
+        g, o = h.export_level(l), ref.level(l)
+        assert (g.n, g.nnz, g.passes) == (o.n, o.nnz, o.passes), l
+        np.testing.assert_array_equal(g.agg, o.agg)
+        np.testing.assert_array_equal(g.row_ptr, o.row_ptr)
+        np.testing.assert_array_equal(g.col, o.col)
+        np.testing.assert_array_equal(g.val, o.val)
+    h.close()
+    ref.close()
